@@ -1,0 +1,145 @@
+"""Shading a batch of hits: uncached, and cached in deterministic snapshot mode.
+
+Sec. 3: at a cacheable node the cache is looked up first; on a hit the cached
+value is used and the sub-graph is skipped; otherwise the sub-graph is
+evaluated in the standard way and its value stored.  Sec. 1 and 3.2: values
+are inserted progressively while frames are rendered, and the table persists
+across frames.
+
+Snapshot semantics (a deterministic reading of the concurrent update of
+Sec. 3.3): a frame is one batch of hits.  Every lookup of frame f sees the
+table as it was after frame f - 1; the frame's insert candidates are then
+applied in ascending sequence number seq = (hit index, cacheable ordinal)
+with Algorithm 1, stamping writes with f + 1.
+"""
+from collections import Counter
+from typing import List, Optional
+
+import numpy as np
+
+from . import codec, graph, keys as K
+from .table import FIRST, Table
+
+
+def decode(enc, out_type):
+    if out_type == "COLOR":
+        return codec.rgb9e5_decode(np.asarray(enc, dtype=np.uint64))
+    return codec.float_decode(np.asarray(enc, dtype=np.uint64))
+
+
+def encode(value, out_type):
+    if out_type == "COLOR":
+        return codec.rgb9e5_encode(value)
+    return codec.float_encode(value)
+
+
+def shade_uncached(materials, textures, hits):
+    """Plain evaluation of every hit (cache disabled).  Returns dict of FP64 arrays."""
+    n = len(hits)
+    out = dict(base_color=np.zeros((n, 3)), roughness=np.zeros(n), normal=np.zeros((n, 3)))
+    mat = hits.material.astype(np.int64)
+    for m in np.unique(mat):
+        idx = np.nonzero(mat == m)[0]
+        if m >= len(materials):
+            o = graph.default_outputs(hits.normal[idx])
+        else:
+            o, _ = graph.evaluate(materials[m], hits.uv[idx], hits.normal[idx], textures)
+        for k in out:
+            out[k][idx] = o[k]
+    return out
+
+
+class FrameResult:
+    def __init__(self, n, kmax):
+        self.outputs = dict(base_color=np.zeros((n, 3)), roughness=np.zeros(n),
+                            normal=np.zeros((n, 3)))
+        self.found = np.zeros((n, kmax), dtype=bool)        # cache hit per (hit, ordinal)
+        self.bypass = np.zeros((n, kmax), dtype=bool)
+        self.valid = np.zeros((n, kmax), dtype=bool)        # ordinal exists for the hit's material
+        self.found_value = np.full((n, kmax, 3), np.nan)    # decoded value on a cache hit
+        self.stats = Counter()
+
+
+def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
+                         policy: str = FIRST, level_bias: int = 0,
+                         level_max: int = K.LEVEL_MAX_DEFAULT, min_subgraph_nodes: int = 2,
+                         kmax: int = 8, cacheables: Optional[list] = None) -> FrameResult:
+    """One snapshot-mode frame; mutates ``table`` into T_f and returns the frame's results."""
+    n = len(hits)
+    res = FrameResult(n, kmax)
+    mat = hits.material.astype(np.int64)
+    if cacheables is None:
+        cacheables = [graph.cacheable_outputs(m, min_subgraph_nodes) for m in materials]
+    candidates = []                                  # (hit, ordinal, cell, hash2, enc)
+    for m in np.unique(mat):
+        idx = np.nonzero(mat == m)[0]
+        if m >= len(materials):
+            o = graph.default_outputs(hits.normal[idx])
+            res.stats["invalid_material"] += len(idx)
+            for k in res.outputs:
+                res.outputs[k][idx] = o[k]
+            continue
+        material = materials[m]
+        cach = cacheables[m]
+        subst = {}
+        key_list = []
+        for c, (node, sock) in enumerate(cach):
+            ky = K.compute_keys(int(m), node, sock, hits.uv[idx], hits.duv[idx], table.n_cells,
+                                level_bias, level_max)
+            key_list.append(ky)
+            otype = graph.output_type(material, node, sock)
+            found = np.zeros(len(idx), dtype=bool)
+            encs = np.zeros(len(idx), dtype=np.uint64)
+            for j in range(len(idx)):
+                if ky.bypass[j]:
+                    continue
+                hit, enc = table.lookup(int(ky.cell[j]), int(ky.hash2[j]))
+                found[j] = hit
+                encs[j] = enc
+            res.valid[idx, c] = True
+            res.bypass[idx, c] = ky.bypass
+            res.found[idx, c] = found
+            res.stats["bypasses"] += int(ky.bypass.sum())
+            res.stats["probes"] += int((~ky.bypass).sum())
+            res.stats["hits"] += int(found.sum())
+            if found.any():
+                dv = decode(encs[found], otype)
+                if otype == "COLOR":
+                    res.found_value[idx[found], c, :] = dv
+                else:
+                    res.found_value[idx[found], c, 0] = dv
+                subst[(node, sock)] = (found, np.zeros((len(idx), 3)) if otype == "COLOR"
+                                       else np.zeros(len(idx)))
+                full = subst[(node, sock)][1]
+                full[found] = dv
+        out, values = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures, subst)
+        for k in res.outputs:
+            res.outputs[k][idx] = out[k]
+        for c, (node, sock) in enumerate(cach):
+            ky = key_list[c]
+            otype = graph.output_type(material, node, sock)
+            v = values[(node, sock)]
+            miss = np.nonzero(~res.found[idx, c] & ~ky.bypass)[0]
+            vals = v[miss]
+            fin = np.isfinite(vals) if vals.ndim == 1 else np.all(np.isfinite(vals), axis=1)
+            res.stats["nonfinite"] += int((~fin).sum())
+            miss, vals = miss[fin], vals[fin]
+            encs = encode(vals, otype)
+            for j, enc in zip(miss, encs):
+                candidates.append((int(idx[j]), c, int(ky.cell[j]), int(ky.hash2[j]), int(enc)))
+    res.stats["misses"] = res.stats["probes"] - res.stats["hits"]
+    res.stats["candidates"] = len(candidates)
+    candidates.sort(key=lambda t: (t[0], t[1]))
+    for h, c, cell, h2, enc in candidates:
+        res.stats[table.insert(cell, h2, enc, policy, frame)] += 1
+    return res
+
+
+def shade_snapshot(materials, textures, frames: List, table: Table, policy: str = FIRST,
+                   level_bias: int = 0, level_max: int = K.LEVEL_MAX_DEFAULT,
+                   min_subgraph_nodes: int = 2, kmax: int = 8, first_frame: int = 0):
+    """Progressive snapshot render of a list of hit batches; returns one FrameResult each."""
+    cach = [graph.cacheable_outputs(m, min_subgraph_nodes) for m in materials]
+    return [shade_snapshot_frame(materials, textures, h, table, first_frame + f, policy,
+                                 level_bias, level_max, min_subgraph_nodes, kmax, cach)
+            for f, h in enumerate(frames)]

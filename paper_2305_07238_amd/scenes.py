@@ -1,0 +1,502 @@
+"""Seeded synthetic scenes: material graph sets, textures and per-frame hit batches.
+
+This module only produces inputs.  It contains none of the caching method's
+arithmetic (no node evaluation, no key quantisation, no hashing of
+descriptors, no encoding): both the HIP path and the CPU oracle consume what
+it returns.  Every random draw goes through ``numpy.random.default_rng`` with
+an explicit seed sequence, so a (config, purpose, frame) triple always yields
+the same bytes.
+
+The paper's production scenes are not available; the workloads below stand in
+for them with the shapes the paper describes: thousands of node-based
+materials, networks of up to a few hundred nodes (Sec. 2), 1920x1080 frames
+rendered progressively at one sample per pixel per pass (Sec. 4).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# graph data model (plain data; the C-ABI mirrors it in pmc_node_desc)
+# ----------------------------------------------------------------------------
+
+OPS = ("UV_INPUT", "IMAGE_TEXTURE", "VALUE_NOISE", "PERLIN_NOISE", "MIX",
+       "MATH", "COLOR_RAMP", "NORMAL_MAP", "BSDF_OUTPUT")
+MATH_OPS = ("ADD", "MUL", "POW")
+
+# socket types of each op: inputs and outputs
+IN_TYPES = {
+    "UV_INPUT": (),
+    "IMAGE_TEXTURE": ("UV",),
+    "VALUE_NOISE": ("UV",),
+    "PERLIN_NOISE": ("UV",),
+    "MIX": ("FLOAT", "COLOR", "COLOR"),
+    "MATH": ("FLOAT", "FLOAT"),
+    "COLOR_RAMP": ("FLOAT",),
+    "NORMAL_MAP": ("COLOR", "FLOAT"),
+    "BSDF_OUTPUT": ("COLOR", "FLOAT", "VECTOR"),
+}
+OUT_TYPES = {
+    "UV_INPUT": ("UV",),
+    "IMAGE_TEXTURE": ("COLOR", "FLOAT"),
+    "VALUE_NOISE": ("FLOAT",),
+    "PERLIN_NOISE": ("FLOAT",),
+    "MIX": ("COLOR",),
+    "MATH": ("FLOAT",),
+    "COLOR_RAMP": ("COLOR", "FLOAT"),
+    "NORMAL_MAP": ("VECTOR",),
+    "BSDF_OUTPUT": (),
+}
+
+
+@dataclasses.dataclass
+class Input:
+    """One input socket: a link to (node, socket) of the same material, or a constant."""
+    node: int = -1                      # -1 = unconnected (use ``value``)
+    socket: int = 0
+    value: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+    @staticmethod
+    def link(node: int, socket: int = 0) -> "Input":
+        return Input(node=node, socket=socket)
+
+    @staticmethod
+    def const(*v: float) -> "Input":
+        vals = tuple(float(x) for x in v) + (0.0,) * (3 - len(v))
+        return Input(node=-1, socket=0, value=vals[:3])
+
+
+@dataclasses.dataclass
+class Node:
+    op: str
+    inputs: List[Input] = dataclasses.field(default_factory=list)
+    math_op: str = "ADD"                # MATH
+    clamp: bool = False                 # MATH
+    texture: int = 0                    # IMAGE_TEXTURE: index into the scene's texture list
+    freq: float = 0.0                   # noise base frequency f0
+    octaves: int = 1                    # noise octave count
+    seed: int = 0                       # noise seed
+    ramp_pos: Tuple[float, ...] = ()    # COLOR_RAMP: 8 ascending positions
+    ramp_rgba: Tuple[Tuple[float, float, float, float], ...] = ()  # COLOR_RAMP: 8 stops
+
+
+@dataclasses.dataclass
+class Material:
+    nodes: List[Node]
+
+    @property
+    def sink(self) -> int:
+        return next(i for i, n in enumerate(self.nodes) if n.op == "BSDF_OUTPUT")
+
+
+@dataclasses.dataclass
+class Hits:
+    """A batch of shading points (structure of arrays, host memory)."""
+    material: np.ndarray                # uint32 [n]
+    uv: np.ndarray                      # float32 [n, 2]
+    duv: np.ndarray                     # float32 [n, 4]: g1.x, g1.y, g2.x, g2.y
+    normal: np.ndarray                  # float32 [n, 3]
+
+    def __len__(self) -> int:
+        return int(self.material.shape[0])
+
+    def take(self, idx) -> "Hits":
+        return Hits(self.material[idx], self.uv[idx], self.duv[idx], self.normal[idx])
+
+    @staticmethod
+    def concat(parts: Sequence["Hits"]) -> "Hits":
+        return Hits(np.concatenate([p.material for p in parts]),
+                    np.concatenate([p.uv for p in parts]),
+                    np.concatenate([p.duv for p in parts]),
+                    np.concatenate([p.normal for p in parts]))
+
+
+@dataclasses.dataclass
+class CacheConfig:
+    slots: int                          # N_c * N_e
+    n_entries: int = 8                  # N_e
+    entry_bytes: int = 16
+    policy: str = "FIRST"               # FIRST (keep first value) or OVERWRITE
+
+    @property
+    def n_cells(self) -> int:
+        return self.slots // self.n_entries
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    materials: List[Material]
+    textures: List[np.ndarray]          # each uint8 [H, W, 4] (RGBA8, row 0 at v = 0)
+    frames: int
+    hits_per_frame: int
+    cache: CacheConfig
+    seed: int
+    _frame_fn: object = dataclasses.field(repr=False, default=None)
+
+    def frame(self, f: int) -> Hits:
+        """Hits of progressive pass ``f`` (deterministic)."""
+        return self._frame_fn(f)
+
+    def all_hits(self) -> Hits:
+        return Hits.concat([self.frame(f) for f in range(self.frames)])
+
+
+def _rng(*key: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(k) & 0xFFFFFFFF for k in key]))
+
+
+# purpose tags for seed sequences
+_P_GRAPH, _P_TEX, _P_OBJ, _P_JITTER, _P_MLP = 1, 2, 3, 4, 5
+
+
+# ----------------------------------------------------------------------------
+# tiny scene: one 8-node material, 64x64 px x 4 spp
+# ----------------------------------------------------------------------------
+
+def checker_texture(size: int = 256, block_shift: int = 5) -> np.ndarray:
+    """Grey checker: 230 where ((x>>5) ^ (y>>5)) is odd, else 26; alpha 255."""
+    y, x = np.mgrid[0:size, 0:size]
+    on = ((x >> block_shift) ^ (y >> block_shift)) & 1
+    img = np.empty((size, size, 4), np.uint8)
+    img[..., :3] = np.where(on, 230, 26)[..., None]
+    img[..., 3] = 255
+    return img
+
+
+def _ramp_stops(rng: np.random.Generator, min_gap: float = 0.08, max_slope: float = 1.5):
+    """8 ascending stops (first at 0, last at 1) whose colours change smoothly.
+
+    Each colour step is bounded by ``max_slope`` times the position gap, which
+    keeps the ramp's Lipschitz constant small (FP32 vs FP64 round-off is not
+    amplified by steep ramps)."""
+    while True:
+        inner = np.sort(rng.uniform(0.0, 1.0, 6))
+        pos = np.concatenate([[0.0], inner, [1.0]])
+        if np.all(np.diff(pos) >= min_gap):
+            break
+    rgba = np.empty((8, 4))
+    rgba[0] = rng.uniform(0.1, 0.9, 4)
+    for k in range(1, 8):
+        step = rng.uniform(-1, 1, 4) * max_slope * (pos[k] - pos[k - 1])
+        rgba[k] = np.clip(rgba[k - 1] + step, 0.0, 1.0)
+    pos32 = tuple(float(np.float32(p)) for p in pos)
+    rgba32 = tuple(tuple(float(np.float32(c)) for c in row) for row in rgba)
+    return pos32, rgba32
+
+
+def tiny_material(seed: int = 0) -> Material:
+    rng = _rng(seed, _P_GRAPH, 1)
+    pos, rgba = _ramp_stops(rng)
+    L, C = Input.link, Input.const
+    nodes = [
+        Node("UV_INPUT"),                                                      # n0
+        Node("IMAGE_TEXTURE", [L(0)], texture=0),                              # n1 checker
+        Node("VALUE_NOISE", [L(0)], freq=8.0, octaves=2, seed=7),             # n2
+        Node("MIX", [L(2, 0), L(1, 0), C(0.9, 0.6, 0.2)]),                     # n3
+        Node("COLOR_RAMP", [L(3, 0)], ramp_pos=pos, ramp_rgba=rgba),          # n4
+        Node("MATH", [L(4, 1), C(0.9)], math_op="MUL", clamp=True),           # n5
+        Node("MATH", [L(5, 0), C(0.05)], math_op="ADD", clamp=True),          # n6
+        Node("BSDF_OUTPUT", [L(4, 0), L(6, 0), C()]),                         # n7
+    ]
+    return Material(nodes)
+
+
+def tiny_scene(seed: int = 0, px: int = 64, spp: int = 4, slots: int = 1 << 16) -> Scene:
+    """1 material, 8 nodes, px x px pixels x spp samples (sample-major: frame = sample)."""
+    mat = tiny_material(seed)
+    tex = [checker_texture(256)]
+
+    def frame(f: int) -> Hits:
+        rng = _rng(seed, _P_JITTER, 1, f)
+        r = rng.integers(0, 1 << 16, size=(px, px, 2), dtype=np.int64)
+        py, pxx = np.mgrid[0:px, 0:px]
+        # u = (px + r * 2^-16) / px: exact in float32 (23 fractional bits suffice)
+        u = (pxx + r[..., 0] / 65536.0) / px
+        v = (py + r[..., 1] / 65536.0) / px
+        n = px * px
+        uv = np.stack([u.ravel(), v.ravel()], 1).astype(np.float32)
+        duv = np.tile(np.array([1.0 / px, 0.0, 0.0, 1.0 / px], np.float32), (n, 1))
+        normal = np.tile(np.array([0.0, 0.0, 1.0], np.float32), (n, 1))
+        return Hits(np.zeros(n, np.uint32), uv, duv, normal)
+
+    return Scene("tiny", [mat], tex, spp, px * px, CacheConfig(slots), seed, frame)
+
+
+# ----------------------------------------------------------------------------
+# random material networks
+# ----------------------------------------------------------------------------
+
+# target mix of body node types (the paper's networks are Blender-like node
+# graphs; these proportions are this workload's stand-in)
+_BODY_MIX = (("IMAGE_TEXTURE", 0.20), ("PERLIN_NOISE", 0.20), ("MIX", 0.20),
+             ("MATH", 0.25), ("COLOR_RAMP", 0.10), ("VALUE_NOISE", 0.05))
+_LEAVES = ("IMAGE_TEXTURE", "PERLIN_NOISE", "VALUE_NOISE")
+_INNER = ("MIX", "MATH", "COLOR_RAMP")
+
+
+def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
+                    p_normal_map: float = 0.5, p_share: float = 0.15) -> Material:
+    """A random node network with exactly ``n_nodes`` nodes, all reachable from the sink.
+
+    Built top-down from the BSDF sink: every open input slot is filled by a new
+    node while the node budget lasts, else by an existing node created later
+    than the slot's owner (sharing, which keeps the graph acyclic) or a
+    constant.  The creation order reversed is a topological order, so the
+    returned node list has every input before its consumers (UV_INPUT first,
+    BSDF_OUTPUT last)."""
+    n_nodes = max(int(n_nodes), 4)
+    budget = n_nodes - 2                        # minus UV_INPUT and the sink
+    created: List[dict] = []                    # creation order; index = creation id
+
+    def new(op, **kw):
+        created.append(dict(op=op, slots={}, **kw))
+        return len(created) - 1
+
+    sink = new("BSDF_OUTPUT")
+    open_slots: List[Tuple[int, int]] = [(sink, 0), (sink, 1)]
+    if budget >= 3 and rng.random() < p_normal_map:
+        nm = new("NORMAL_MAP", strength=float(np.float32(rng.uniform(0.5, 1.0))))
+        budget -= 1
+        created[sink]["slots"][2] = ("node", nm, 0)
+        open_slots.append((nm, 0))
+    else:
+        created[sink]["slots"][2] = ("const", (0.0, 0.0, 0.0))
+
+    types = [t for t, _ in _BODY_MIX]
+    probs = np.array([p for _, p in _BODY_MIX])
+    probs = probs / probs.sum()
+    inner_probs = np.array([p for t, p in _BODY_MIX if t in _INNER])
+    inner_probs = inner_probs / inner_probs.sum()
+    leaf_probs = np.array([p for t, p in _BODY_MIX if t in _LEAVES])
+    leaf_probs = leaf_probs / leaf_probs.sum()
+
+    def make_node(op):
+        kw = {}
+        if op == "IMAGE_TEXTURE":
+            kw["texture"] = int(rng.integers(0, n_textures))
+        elif op in ("PERLIN_NOISE", "VALUE_NOISE"):
+            kw["freq"] = float(rng.choice([2.0, 4.0, 8.0, 16.0]))
+            kw["octaves"] = 4 if op == "PERLIN_NOISE" else 2
+            kw["seed"] = int(rng.integers(0, 1 << 30))
+        elif op == "MATH":
+            mop = str(rng.choice(MATH_OPS))
+            lo, hi = {"ADD": (0.0, 0.5), "MUL": (0.5, 1.0), "POW": (1.0, 2.0)}[mop]
+            kw["math_op"] = mop
+            kw["b"] = float(np.float32(rng.uniform(lo, hi)))
+        elif op == "COLOR_RAMP":
+            kw["ramp"] = _ramp_stops(rng)
+        idx = new(op, **kw)
+        if op == "MIX":
+            open_slots.extend([(idx, 0), (idx, 1), (idx, 2)])
+        elif op in ("MATH", "COLOR_RAMP"):
+            open_slots.append((idx, 0))
+        return idx
+
+    def out_socket(op):
+        if op in ("IMAGE_TEXTURE", "COLOR_RAMP"):
+            return int(rng.random() < 0.3)          # mostly colour, sometimes alpha
+        return 0
+
+    while open_slots:
+        k = int(rng.integers(0, len(open_slots)))
+        owner, slot = open_slots.pop(k)
+        later = [i for i in range(owner + 1, len(created))
+                 if created[i]["op"] not in ("BSDF_OUTPUT", "NORMAL_MAP")]
+        if budget > 0:
+            if later and open_slots and rng.random() < p_share:
+                src = int(rng.choice(later))
+                created[owner]["slots"][slot] = ("node", src, out_socket(created[src]["op"]))
+                continue
+            if len(open_slots) == 0 and budget > 1:
+                op = str(rng.choice(_INNER, p=inner_probs))     # keep the graph growing
+            elif len(open_slots) >= budget:
+                op = str(rng.choice(_LEAVES, p=leaf_probs))     # close slots in time
+            else:
+                op = str(rng.choice(types, p=probs))
+            budget -= 1
+            src = make_node(op)
+            created[owner]["slots"][slot] = ("node", src, out_socket(op))
+        else:
+            if later and rng.random() < 0.7:
+                src = int(rng.choice(later))
+                created[owner]["slots"][slot] = ("node", src, out_socket(created[src]["op"]))
+            else:
+                created[owner]["slots"][slot] = ("const", tuple(
+                    float(np.float32(x)) for x in rng.uniform(0.1, 0.9, 3)))
+    uv_id = new("UV_INPUT")
+
+    # reverse creation order -> topological order
+    n = len(created)
+    order = list(range(n - 1, -1, -1))
+    remap = {c: i for i, c in enumerate(order)}
+    nodes: List[Node] = []
+    for c in order:
+        d = created[c]
+        op = d["op"]
+        if op in ("IMAGE_TEXTURE", "PERLIN_NOISE", "VALUE_NOISE"):
+            ins = [Input.link(remap[uv_id], 0)]
+        elif op == "UV_INPUT":
+            ins = []
+        else:
+            n_in = len(IN_TYPES[op])
+            ins = []
+            for s in range(n_in):
+                sv = d["slots"].get(s)
+                if op == "MATH" and s == 1:
+                    ins.append(Input.const(d["b"]))
+                elif op == "NORMAL_MAP" and s == 1:
+                    ins.append(Input.const(d["strength"]))
+                elif sv is None:
+                    ins.append(Input.const(0.5, 0.5, 0.5))
+                elif sv[0] == "node":
+                    ins.append(Input.link(remap[sv[1]], sv[2]))
+                else:
+                    ins.append(Input.const(*sv[1]))
+        node = Node(op, ins)
+        if op == "IMAGE_TEXTURE":
+            node.texture = d["texture"]
+        elif op in ("PERLIN_NOISE", "VALUE_NOISE"):
+            node.freq, node.octaves, node.seed = d["freq"], d["octaves"], d["seed"]
+        elif op == "MATH":
+            node.math_op, node.clamp = d["math_op"], True
+        elif op == "COLOR_RAMP":
+            node.ramp_pos, node.ramp_rgba = d["ramp"]
+        nodes.append(node)
+    assert nodes[-1].op == "BSDF_OUTPUT" and nodes[0].op == "UV_INPUT"
+    return Material(nodes)
+
+
+def texture_pool(seed: int, count: int, size: int = 1024) -> List[np.ndarray]:
+    """Procedural RGBA8 textures: checkers, stripes and blocky random noise."""
+    pool = []
+    y, x = np.mgrid[0:size, 0:size]
+    for t in range(count):
+        rng = _rng(seed, _P_TEX, t)
+        kind = t % 3
+        c0 = rng.integers(0, 256, 4)
+        c1 = rng.integers(0, 256, 4)
+        if kind == 0:
+            sh = int(rng.integers(3, 8))
+            on = (((x >> sh) ^ (y >> sh)) & 1)[..., None]
+            img = np.where(on, c1, c0)
+        elif kind == 1:
+            period = int(rng.integers(16, 128))
+            ang = rng.uniform(0, np.pi)
+            ph = (x * np.cos(ang) + y * np.sin(ang)) * (2 * np.pi / period)
+            w = (0.5 + 0.5 * np.sin(ph))[..., None]
+            img = np.rint(c0 + (c1.astype(np.float64) - c0) * w)
+        else:
+            sh = int(rng.integers(2, 6))
+            blocks = rng.integers(0, 256, ((size >> sh) + 1, (size >> sh) + 1, 4))
+            img = blocks[y >> sh, x >> sh]
+        pool.append(np.ascontiguousarray(img.astype(np.uint8)))
+    return pool
+
+
+def _zipf_choice(rng: np.random.Generator, n_items: int, size: int, s: float = 1.1) -> np.ndarray:
+    """Items drawn with P(rank r) proportional to r^-s; ranks mapped through a random permutation."""
+    w = np.arange(1, n_items + 1, dtype=np.float64) ** (-s)
+    rank = rng.choice(n_items, size=size, p=w / w.sum())
+    perm = rng.permutation(n_items)
+    return perm[rank]
+
+
+def _object_screen(seed: int, n_mats: int, width: int, height: int, obj: int, frames: int,
+                   scale=(1.0, 8.0), name: str = "scene"):
+    """Screen split into obj x obj pixel objects; each object has one material,
+    a UV scale and offset, an anisotropy and a normal.  Returns the frame function."""
+    gx, gy = width // obj, height // obj
+    n_obj = gx * gy
+    rng = _rng(seed, _P_OBJ, n_mats, width)
+    mat = _zipf_choice(rng, n_mats, n_obj).astype(np.uint32)
+    s = rng.uniform(scale[0], scale[1], n_obj)
+    off = rng.uniform(0.0, 1.0, (n_obj, 2))
+    aniso = rng.uniform(1.0, 2.0, n_obj)
+    # uniform direction on the upper hemisphere
+    z = rng.uniform(0.0, 1.0, n_obj)
+    phi = rng.uniform(0.0, 2 * np.pi, n_obj)
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    nrm = np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+
+    py, px = np.mgrid[0:gy * obj, 0:gx * obj]
+    oid = (py // obj) * gx + (px // obj)
+    xl = (px % obj).astype(np.float64)
+    yl = (py % obj).astype(np.float64)
+    oid = oid.ravel(); xl = xl.ravel(); yl = yl.ravel()
+    n = oid.shape[0]
+    # per-hit constants that do not change between frames
+    mat_h = mat[oid]
+    s_h = s[oid]
+    duv = np.zeros((n, 4), np.float32)
+    duv[:, 0] = s_h / obj
+    duv[:, 3] = aniso[oid] * s_h / obj
+    nrm_h = nrm[oid].astype(np.float32)
+
+    def frame(f: int) -> Hits:
+        jr = _rng(seed, _P_JITTER, n_mats, f)
+        j = jr.random((n, 2))
+        uv = np.empty((n, 2), np.float32)
+        uv[:, 0] = off[oid, 0] + s_h * (xl + j[:, 0]) / obj
+        uv[:, 1] = off[oid, 1] + s_h * (yl + j[:, 1]) / obj
+        return Hits(mat_h.copy(), uv, duv.copy(), nrm_h.copy())
+
+    return frame, n
+
+
+def mid_scene(seed: int = 0, n_mats: int = 64, width: int = 1920, height: int = 1080,
+              frames: int = 16, slots: int = 1 << 22, n_textures: int = 16,
+              tex_size: int = 1024, nodes=(8, 64)) -> Scene:
+    """64 materials of U{8..64} nodes, 120x120-px objects, Zipf(1.1) materials."""
+    rng = _rng(seed, _P_GRAPH, 2)
+    mats = [random_material(rng, int(rng.integers(nodes[0], nodes[1] + 1)), n_textures)
+            for _ in range(n_mats)]
+    tex = texture_pool(seed, n_textures, tex_size)
+    frame_fn, n = _object_screen(seed, n_mats, width, height, 120, frames, name="mid")
+    return Scene("mid", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn)
+
+
+def lognormal_sizes(rng, n, lo, hi, mu=3.0, sigma=1.0):
+    return np.clip(np.rint(rng.lognormal(mu, sigma, n)), lo, hi).astype(int)
+
+
+def batching_scene(seed: int = 0, n_mats: int = 1000, width: int = 1920, height: int = 1080,
+                   frames: int = 64, slots: int = 1 << 24, n_textures: int = 64,
+                   tex_size: int = 1024) -> Scene:
+    """1000 materials with lognormal(3, 1) sizes in [4, 400], 40x40-px objects."""
+    rng = _rng(seed, _P_GRAPH, 3)
+    sizes = lognormal_sizes(rng, n_mats, 4, 400)
+    mats = [random_material(rng, int(k), n_textures) for k in sizes]
+    tex = texture_pool(seed + 1, n_textures, tex_size)
+    frame_fn, n = _object_screen(seed, n_mats, width, height, 40, frames, name="batching")
+    return Scene("batching", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn)
+
+
+def scale_scene(seed: int = 0, n_mats: int = 4096, width: int = 3840, height: int = 2160,
+                frames: int = 128, slots: int = 1 << 26, n_textures: int = 64,
+                tex_size: int = 1024) -> Scene:
+    """4096 materials with lognormal sizes in [8, 400], 3840x2160, OVERWRITE table."""
+    rng = _rng(seed, _P_GRAPH, 5)
+    sizes = lognormal_sizes(rng, n_mats, 8, 400)
+    mats = [random_material(rng, int(k), n_textures) for k in sizes]
+    tex = texture_pool(seed + 2, n_textures, tex_size)
+    frame_fn, n = _object_screen(seed, n_mats, width, height, 40, frames, name="scale")
+    return Scene("scale", mats, tex, frames, n, CacheConfig(slots, policy="OVERWRITE"), seed,
+                 frame_fn)
+
+
+def mlp_init(seed: int, n_mats: int, fan=((32, 64), (64, 64), (64, 4))) -> List[List[np.ndarray]]:
+    """He-uniform initial weights (float32) per material: [W1, b1, W2, b2, W3, b3], W as [out, in]."""
+    out = []
+    for m in range(n_mats):
+        rng = _rng(seed, _P_MLP, m)
+        layers = []
+        for fi, fo in fan:
+            lim = np.sqrt(6.0 / fi)
+            layers.append(rng.uniform(-lim, lim, (fo, fi)).astype(np.float32))
+            layers.append(np.zeros(fo, np.float32))
+        out.append(layers)
+    return out
