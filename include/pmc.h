@@ -1,0 +1,281 @@
+/*
+ * pmc.h - C ABI of the progressive material cache library (libpmc.so).
+ *
+ * The library shades batches of ray hits with node-based material networks
+ * on one MI355X (gfx950).  Selected node outputs are looked up in, and
+ * progressively inserted into, a fixed-size device hash table keyed by
+ * material id, node id and a quantised UV texel, using two hashes: one picks
+ * the cell, the other verifies the key (Fujieda & Harada, "Progressive
+ * Material Caching", SIGGRAPH Asia 2022 TC: Sec. 2 network evaluation,
+ * Sec. 3 cacheable nodes, Sec. 3.1 descriptor and Eq. 1, Sec. 3.2 the two
+ * hashes, Sec. 3.3 and Algorithm 1 the lock-free update).
+ *
+ * Conventions for every entry point
+ *   - Return value: PMC_OK (0) or a negative pmc_status.  Nothing throws
+ *     across this boundary.  pmc_last_error() gives the message of the last
+ *     failing call on a context.
+ *   - Argument and graph errors are detected on the host before any work is
+ *     enqueued; nothing is enqueued when a call fails.
+ *   - Data errors inside a batch never abort: a material id at or beyond the
+ *     compiled count shades to default outputs and is counted; non-finite
+ *     UVs or gradients bypass the cache.
+ *   - Pointers named "device" are device memory (e.g. from hipMalloc or a
+ *     torch CUDA tensor) owned by the caller; "host" pointers are read (or
+ *     written) before the call returns, unless the entry point says it runs
+ *     asynchronously on the stream.
+ *   - Streams are passed as void* (a hipStream_t; NULL = the null stream).
+ *     Device work is enqueued on that stream only; calls return without
+ *     waiting unless stated.
+ *   - A context is not thread-safe.  Different contexts are independent.
+ */
+#ifndef PMC_H
+#define PMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMC_ABI_VERSION 1u
+
+typedef int32_t pmc_status;
+enum {
+    PMC_OK = 0,
+    PMC_ERR_INVALID = -1,      /* bad argument (null pointer, size, enum value) */
+    PMC_ERR_GRAPH = -2,        /* invalid material network (type, cycle, link) */
+    PMC_ERR_OOM = -3,          /* device or host allocation failed */
+    PMC_ERR_HIP = -4,          /* a HIP runtime call failed; message has hipGetErrorString */
+    PMC_ERR_UNSUPPORTED = -5,  /* valid request this build cannot serve */
+    PMC_ERR_STATE = -6         /* call order (e.g. shading before compiling) */
+};
+
+typedef struct pmc_ctx pmc_ctx;        /* opaque, library-owned */
+typedef struct pmc_cache pmc_cache;    /* opaque handle of one hash table */
+
+/* ------------------------------------------------------------------ graphs */
+
+/* Node operations (Sec. 2 leaves node types open; this is the library's set). */
+enum pmc_op {
+    PMC_OP_UV_INPUT = 0,       /* out 0: UV of the hit */
+    PMC_OP_IMAGE_TEXTURE = 1,  /* in 0: UV; out 0: COLOR, out 1: FLOAT alpha */
+    PMC_OP_VALUE_NOISE = 2,    /* in 0: UV; out 0: FLOAT */
+    PMC_OP_PERLIN_NOISE = 3,   /* in 0: UV; out 0: FLOAT */
+    PMC_OP_MIX = 4,            /* in: FLOAT fac, COLOR a, COLOR b; out 0: COLOR */
+    PMC_OP_MATH = 5,           /* in: FLOAT a, FLOAT b; out 0: FLOAT */
+    PMC_OP_COLOR_RAMP = 6,     /* in 0: FLOAT fac; out 0: COLOR, out 1: FLOAT alpha */
+    PMC_OP_NORMAL_MAP = 7,     /* in: COLOR, FLOAT strength; out 0: VECTOR (reads the hit normal) */
+    PMC_OP_BSDF_OUTPUT = 8     /* in: COLOR base colour, FLOAT roughness, VECTOR normal */
+};
+enum pmc_math_op { PMC_MATH_ADD = 0, PMC_MATH_MUL = 1, PMC_MATH_POW = 2 };
+#define PMC_NODE_CLAMP 1u      /* MATH: clamp the result to [0, 1] */
+
+/* One input socket: a link to (node, socket) of the same material, or a constant. */
+typedef struct pmc_input {
+    int32_t node;              /* source node index in the material, or -1 = unconnected */
+    uint32_t socket;           /* output socket of the source node */
+    float value[3];            /* constant when unconnected (FLOAT uses value[0]);
+                                  unconnected UV inputs read the hit UV and an
+                                  unconnected VECTOR input reads the hit normal */
+} pmc_input;                   /* 20 bytes */
+
+typedef struct pmc_node_desc {
+    uint32_t op;               /* enum pmc_op */
+    uint32_t variant;          /* MATH: enum pmc_math_op; IMAGE_TEXTURE: texture index */
+    uint32_t flags;            /* PMC_NODE_CLAMP */
+    uint32_t seed;             /* noise seed */
+    float freq;                /* noise base frequency f0 */
+    uint32_t octaves;          /* noise octave count (1..8) */
+    pmc_input in[3];
+    float ramp_pos[8];         /* COLOR_RAMP stop positions, ascending */
+    float ramp_rgba[8][4];     /* COLOR_RAMP stop colours */
+} pmc_node_desc;               /* 244 bytes */
+
+typedef struct pmc_texture_desc {
+    const uint32_t* texels;    /* host, width*height RGBA8 texels (byte 0 = R), row 0 at v = 0 */
+    uint32_t width, height;
+} pmc_texture_desc;
+
+typedef struct pmc_compile_opts {
+    uint32_t min_subgraph_nodes;   /* smallest cacheable sub-graph (nodes besides UV inputs); 0 = 2 */
+    uint32_t no_fold;              /* 1 = keep constant arithmetic nodes (no folding) */
+    uint32_t reserved[6];
+} pmc_compile_opts;
+
+#define PMC_MAX_CACHEABLE 8    /* cacheable outputs per material kept by the compiler */
+
+typedef struct pmc_material_info {
+    uint32_t n_nodes;          /* nodes given */
+    uint32_t n_live;           /* nodes reachable from the sink */
+    uint32_t n_folded;         /* constant nodes folded away (Sec. 2) */
+    uint32_t n_instr;          /* interpreter instructions emitted */
+    uint32_t n_regs;           /* per-lane float registers needed */
+    uint32_t n_cacheable;      /* cacheable outputs K (Sec. 3) */
+    uint32_t cacheable_node[PMC_MAX_CACHEABLE];
+    uint32_t cacheable_socket[PMC_MAX_CACHEABLE];
+    uint32_t subgraph_nodes[PMC_MAX_CACHEABLE];  /* sub-graph size of each, UV inputs excluded */
+    uint32_t cacheable_type[PMC_MAX_CACHEABLE];  /* 0 FLOAT (raw float32 code), 1 COLOR (RGB9E5) */
+} pmc_material_info;
+
+/* Create a context on HIP device `device`, or a host-only context when
+ * device == -1 (compile and inspect graphs only; every device call then
+ * returns PMC_ERR_STATE).  *out receives the context. */
+pmc_status pmc_create(int device, pmc_ctx** out);
+/* Destroy a context and everything it owns.  NULL is accepted. */
+void pmc_destroy(pmc_ctx* ctx);
+/* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
+const char* pmc_last_error(const pmc_ctx* ctx);
+/* ABI version (PMC_ABI_VERSION) and sizeof of the public structs, by index
+ * 0..7 (node_desc, input, texture_desc, compile_opts, material_info,
+ * cache_params, shade_params, stats); 0 for an unknown index. */
+uint32_t pmc_abi_version(void);
+size_t pmc_abi_sizeof(uint32_t which);
+
+/* Upload textures (copied into library-owned device memory; synchronous).
+ * Replaces any previous set.  Graphs refer to textures by index. */
+pmc_status pmc_set_textures(pmc_ctx* ctx, const pmc_texture_desc* tex, uint32_t n_tex);
+
+/* Compile a graph set (Sec. 2 stack-machine form; Sec. 3 cacheable marking).
+ * nodes: host array of all materials' nodes, material m owning
+ * nodes[node_offsets[m] .. node_offsets[m+1]); node indices inside a
+ * material are local.  Validates types, links and acyclicity
+ * (PMC_ERR_GRAPH, message names material and node), folds constant MATH /
+ * MIX / COLOR_RAMP nodes, marks cacheable outputs, computes the need masks
+ * and registers and, on a device context, uploads the program
+ * (synchronous).  Replaces any previous graph set.  opts may be NULL. */
+pmc_status pmc_compile_materials(pmc_ctx* ctx, const pmc_node_desc* nodes,
+                                 const uint32_t* node_offsets, uint32_t n_mats,
+                                 const pmc_compile_opts* opts);
+/* Compile report of one material (host). */
+pmc_status pmc_get_material_info(const pmc_ctx* ctx, uint32_t mat, pmc_material_info* out);
+
+/* ------------------------------------------------------------------ cache */
+
+enum pmc_policy {
+    PMC_POLICY_FIRST = 0,      /* keep the first inserted value (Sec. 3.2) */
+    PMC_POLICY_OVERWRITE = 1   /* evict the oldest-stamped entry of a full cell (16-byte entries) */
+};
+
+typedef struct pmc_cache_params {
+    uint64_t n_cells;          /* N_c >= 1 */
+    uint32_t n_entries;        /* N_e in 1..64 */
+    uint32_t entry_bytes;      /* 8: {u64 word}; 16: {u64 word, u32 stamp, u32 reserved=0} */
+    uint32_t policy;           /* enum pmc_policy */
+    int32_t level_bias;        /* integer offset added to floor(lambda) (Sec. 4 level offset) */
+    uint32_t level_max;        /* levels clamp to [0, level_max]; 0 = 20 */
+    uint32_t reserved;
+} pmc_cache_params;
+
+/* Create a table of n_cells * n_entries * entry_bytes bytes.  device_mem NULL:
+ * the library allocates it; else the caller's device buffer of at least that
+ * size (256-byte aligned) is used and stays caller-owned.  The table starts
+ * cleared (synchronous).  Word layout: hash2 << 32 | 32-bit encoded value;
+ * 0 = empty (Sec. 3.3). */
+pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* params, void* device_mem,
+                            pmc_cache** out);
+/* Destroy the handle (and the table if library-allocated).  NULL accepted. */
+void pmc_cache_destroy(pmc_cache* cache);
+/* Empty every entry (asynchronous on stream; a fill kernel, no memset node). */
+pmc_status pmc_cache_clear(pmc_cache* cache, void* stream);
+/* Device address and byte size of the table. */
+pmc_status pmc_cache_device_ptr(pmc_cache* cache, void** ptr, size_t* bytes);
+/* Copy the raw table to / from host memory (bytes must equal the table size);
+ * both wait for the stream to finish the copy before returning. */
+pmc_status pmc_cache_export(pmc_cache* cache, void* host_dst, size_t bytes, void* stream);
+pmc_status pmc_cache_import(pmc_cache* cache, const void* host_src, size_t bytes, void* stream);
+
+/* --------------------------------------------------------------- shading */
+
+typedef struct pmc_hits {      /* all device pointers, caller-owned, n entries each */
+    const uint32_t* material;  /* material id */
+    const float* uv;           /* [n][2] */
+    const float* duv;          /* [n][4]: g1.x, g1.y, g2.x, g2.y (ray-cone UV gradients, Sec. 3.1) */
+    const float* normal;       /* [n][3] unit shading normal */
+    uint64_t n;                /* hits; < 2^27 per call */
+} pmc_hits;
+
+typedef struct pmc_bsdf_out {  /* device pointers, caller-owned */
+    float* base_color;         /* [n][3] */
+    float* roughness;          /* [n] */
+    float* normal;             /* [n][3] */
+} pmc_bsdf_out;
+
+/* Optional per-(hit, ordinal) diagnostics, device pointers (may be NULL). */
+typedef struct pmc_debug_out {
+    uint8_t* state;            /* [n][8]: 0 miss, 1 cache hit, 2 bypass, 3 no such ordinal */
+    float* value;              /* [n][8][3]: decoded value on a cache hit (unspecified otherwise) */
+} pmc_debug_out;
+
+enum pmc_mode {
+    PMC_MODE_UNCACHED = 0,     /* plain evaluation; the table is not touched */
+    PMC_MODE_CACHED = 1,       /* lookups and lock-free inserts race freely (Sec. 3.3) */
+    PMC_MODE_SNAPSHOT = 2      /* lookups see the table as it was before the call; inserts
+                                  are applied afterwards in (hit, ordinal) order: deterministic */
+};
+enum pmc_flags {
+    PMC_FLAG_SORT = 1u,        /* sort hits by material first so each wave runs one program */
+    PMC_FLAG_PERSISTENT = 2u   /* persistent waves pull work from a queue */
+};
+
+typedef struct pmc_shade_params {
+    uint32_t mode;             /* enum pmc_mode */
+    uint32_t flags;            /* enum pmc_flags */
+    uint32_t frame;            /* progressive pass index (stamps = frame + 1) */
+    uint32_t chunk_waves;      /* persistent: 64-hit chunks taken per queue pop; 0 = 1 */
+    uint32_t blocks_per_cu;    /* persistent: resident blocks per CU; 0 = library choice */
+    uint32_t reserved[3];
+} pmc_shade_params;
+
+typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade */
+    uint64_t hits_shaded;      /* hits processed */
+    uint64_t probes;           /* lookups issued (cacheable outputs not bypassed) */
+    uint64_t cache_hits;       /* lookups that found their key */
+    uint64_t bypasses;         /* cacheable outputs that skipped the cache (non-finite input) */
+    uint64_t inserts;          /* successful inserts (CAS from 0, or snapshot writes) */
+    uint64_t cas_failures;     /* CAS that lost a race (nondeterministic mode) */
+    uint64_t present;          /* insert found its key already stored */
+    uint64_t cell_full;        /* insert found no free entry and did not evict */
+    uint64_t overwrites;       /* OVERWRITE evictions */
+    uint64_t nonfinite;        /* values not inserted because not finite */
+    uint64_t candidates;       /* snapshot insert candidates */
+    uint64_t nodes_executed;   /* lane-instructions executed by the interpreter */
+    uint64_t nodes_total;      /* lane-instructions of full (uncached) evaluation */
+    uint64_t invalid_material; /* hits with a material id out of range */
+    uint64_t reserved[2];
+} pmc_stats;
+
+/* Shade one batch (one progressive pass).  cache NULL or mode UNCACHED:
+ * plain evaluation.  stats: device pmc_stats to accumulate into (NULL ok).
+ * dbg: NULL, or device diagnostics buffers.  Asynchronous on stream. */
+pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                     const pmc_bsdf_out* out, const pmc_shade_params* params,
+                     pmc_stats* stats, const pmc_debug_out* dbg, void* stream);
+
+/* Per-(hit, ordinal) descriptor fields, for bit-exact checks (Sec. 3.1, Eq. 1,
+ * Sec. 3.2).  out: device array of n * 8 records; ordinals beyond the hit's
+ * material K get bypass = 2.  Asynchronous. */
+typedef struct pmc_key_record {
+    uint32_t cell;             /* Hash(desc) % N_c */
+    uint32_t hash2;            /* Hash2(desc), never 0 */
+    int32_t level;             /* virtual mip level after bias and clamp */
+    int32_t tx, ty;            /* virtual texel indices */
+    uint32_t bypass;           /* 0 keyed, 1 bypassed (non-finite / out of range), 2 no ordinal */
+} pmc_key_record;
+pmc_status pmc_debug_keys(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                          pmc_key_record* out, void* stream);
+
+/* Algorithm 1 on raw descriptors: for i < n, insert (k0[i], k1[i]) -> the
+ * 32-bit code enc[i] with one 64-bit compare-and-swap, all n concurrently.
+ * desc = the two 64-bit descriptor words.  Device arrays.  Asynchronous. */
+pmc_status pmc_cache_insert_raw(pmc_cache* cache, const uint64_t* k0, const uint64_t* k1,
+                                const uint32_t* enc, uint64_t n, uint32_t frame,
+                                pmc_stats* stats, void* stream);
+/* Lookup of raw descriptors: hit[i] = 1 and enc_out[i] = code when found. */
+pmc_status pmc_cache_lookup_raw(pmc_cache* cache, const uint64_t* k0, const uint64_t* k1,
+                                uint64_t n, uint32_t* enc_out, uint8_t* hit, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMC_H */

@@ -1,0 +1,154 @@
+"""Invariants that a lock-free (nondeterministic) cached run must satisfy.
+
+Sec. 3.3: several threads may shade samples with the same descriptor at once
+and insert with a compare-and-swap, so which sample's value a later lookup
+returns, and whether a lookup hits at all, depends on timing.  Many results
+are then correct.  A run is accepted when:
+  (i)   every value returned by a lookup is the encoded value of the same
+        cacheable output computed at some sample with the same descriptor
+        (Sec. 3: the stored value is a sub-graph result at an earlier sample);
+  (ii)  every live table entry carries the hash2 of a descriptor that was
+        inserted into that cell;
+  (iii) FIRST policy (Sec. 3.2): no hash2 appears twice in a cell, the live
+        entries of each cell form a prefix, and a stored word never changes
+        in later frames;
+  (iv)  the BSDF outputs equal plain evaluation with the returned values
+        substituted at the cacheable outputs.
+The functions return lists of violations (empty = accepted).
+"""
+from collections import defaultdict
+
+import numpy as np
+
+from . import codec, graph, keys as K
+
+
+def decoded_candidates(values, out_type):
+    """Decode(Encode(v)) of FP64 values: what the table can hold for them."""
+    if out_type == "COLOR":
+        return codec.rgb9e5_decode(codec.rgb9e5_encode(values))
+    return codec.float_decode(codec.float_encode(values))
+
+
+def table_structure(words, n_entries, previous=None):
+    """(iii): prefix occupancy, unique hash2 per cell, and monotonic growth."""
+    bad = []
+    w = np.asarray(words, dtype=np.uint64).reshape(-1, n_entries)
+    live = w != 0
+    # prefix: once an entry is empty, the rest of the cell is empty
+    after_gap = np.cumsum(~live, axis=1) > 0
+    if np.any(live & after_gap):
+        bad.append(f"{int(np.sum(np.any(live & after_gap, axis=1)))} cells with holes")
+    h = (w >> np.uint64(32)).astype(np.int64)
+    for cell in np.nonzero(live.sum(1) > 1)[0]:
+        hs = h[cell][live[cell]]
+        if len(set(hs.tolist())) != len(hs):
+            bad.append(f"cell {cell}: duplicate hash2")
+            break
+    if previous is not None:
+        p = np.asarray(previous, dtype=np.uint64).reshape(-1, n_entries)
+        changed = (p != 0) & (p != w)
+        if np.any(changed):
+            bad.append(f"{int(changed.sum())} stored words changed")
+    return bad
+
+
+class KeyLog:
+    """All descriptors seen so far: key -> list of (hit id, ordinal), with oracle values."""
+
+    def __init__(self):
+        self.by_key = defaultdict(list)      # (k0, k1) -> [(frame, local hit, c)]
+        self.cellhash = set()                # (cell, hash2) of every keyed sample
+
+    def add(self, frame, mat, c, local_idx, ky):
+        for j, li in enumerate(local_idx):
+            if ky.bypass[j]:
+                continue
+            self.by_key[(int(ky.k0[j]), int(ky.k1[j]))].append((frame, int(li), c))
+            self.cellhash.add((int(ky.cell[j]), int(ky.hash2[j])))
+
+
+def check_frame(materials, textures, hits, frame, state, value, outputs, n_cells,
+                log: KeyLog, values_by_frame, level_bias=0, level_max=K.LEVEL_MAX_DEFAULT,
+                rtol=1e-5, min_subgraph_nodes=2):
+    """Check (i) and (iv) for one frame of GPU results and extend the key log.
+
+    state [n, 8] uint8 (0 miss, 1 hit, 2 bypass, 3 none), value [n, 8, 3]
+    (decoded value on a hit), outputs dict of [n, ...] arrays.  values_by_frame
+    collects, per frame, the oracle's per-(hit, c) values for (i).
+    Returns a list of violations."""
+    bad = []
+    n = len(hits)
+    mat = hits.material.astype(np.int64)
+    frame_vals = {}
+    pending_hits = []                      # (h, c, key, type, gpu value)
+    for m in np.unique(mat):
+        idx = np.nonzero(mat == m)[0]
+        if m >= len(materials):
+            continue
+        material = materials[m]
+        cach = graph.cacheable_outputs(material, min_subgraph_nodes)
+        subst = {}
+        kys = []
+        for c, (node, sock) in enumerate(cach):
+            ky = K.compute_keys(int(m), node, sock, hits.uv[idx], hits.duv[idx], n_cells,
+                                level_bias, level_max)
+            kys.append(ky)
+            otype = graph.output_type(material, node, sock)
+            st = state[idx, c]
+            if np.any((st == 2) != ky.bypass):
+                bad.append(f"material {m} ordinal {c}: bypass decisions differ")
+            hit = st == 1
+            if hit.any():
+                v = value[idx, c, :3] if otype == "COLOR" else value[idx, c, 0]
+                subst[(node, sock)] = (hit, v.astype(np.float64))
+                for j in np.nonzero(hit)[0]:
+                    pending_hits.append((int(idx[j]), c, (int(ky.k0[j]), int(ky.k1[j])), otype,
+                                         v[j]))
+        out, vals = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures, subst)
+        for k in ("base_color", "roughness", "normal"):
+            ref = out[k]
+            got = outputs[k][idx]
+            err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+            if not np.all(err <= rtol):
+                bad.append(f"material {m}: {k} max rel err {float(err.max()):.3g}")
+        for c, (node, sock) in enumerate(cach):
+            otype = graph.output_type(material, node, sock)
+            dv = decoded_candidates(vals[(node, sock)], otype)
+            for j, h in enumerate(idx):
+                frame_vals[(int(h), c)] = dv[j]
+            log.add(frame, int(m), c, idx, kys[c])
+    values_by_frame[frame] = frame_vals
+    # (i): a found value equals the stored value of some sample with the same key
+    for h, c, key, otype, gv in pending_hits:
+        ok = False
+        for (f, li, cc) in log.by_key.get(key, []):
+            cand = values_by_frame[f].get((li, cc))
+            if cand is None:
+                continue
+            cand = np.atleast_1d(cand)
+            g = np.atleast_1d(gv).astype(np.float64)[:cand.shape[0]]
+            if otype == "COLOR":
+                step = codec.rgb9e5_step(codec.rgb9e5_encode(np.reshape(cand, (1, 3))))[0]
+                if np.all(np.abs(g - cand) <= step * 1.0001):
+                    ok = True
+                    break
+            elif np.all(np.abs(g - cand) <= rtol * np.maximum(np.abs(cand), 1.0)):
+                ok = True
+                break
+        if not ok:
+            bad.append(f"hit {h} ordinal {c}: found value matches no sample of its key")
+            if len(bad) > 20:
+                break
+    return bad
+
+
+def check_entries_come_from_keys(words, n_entries, log: KeyLog):
+    """(ii): every live entry's (cell, hash2) belongs to a keyed sample."""
+    w = np.asarray(words, dtype=np.uint64).reshape(-1, n_entries)
+    cells, ents = np.nonzero(w != 0)
+    missing = 0
+    for cell, e in zip(cells, ents):
+        if (int(cell), int(w[cell, e] >> np.uint64(32))) not in log.cellhash:
+            missing += 1
+    return [f"{missing} live entries with no matching descriptor"] if missing else []

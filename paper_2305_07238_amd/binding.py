@@ -1,0 +1,359 @@
+"""ctypes binding of libpmc (include/pmc.h).
+
+Argument marshalling only: every step of shading runs in the library's HIP
+kernels.  The module refuses to import when ``libpmc.so`` has not been built
+(there is no fallback path).  Functions carry the C names; ``Context`` and
+``Cache`` are thin owners of the opaque handles that raise on error codes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(python -c 'import __graft_entry__ as g; g.build()')")
+lib = C.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------------- constants --
+PMC_OK, PMC_ERR_INVALID, PMC_ERR_GRAPH, PMC_ERR_OOM, PMC_ERR_HIP, PMC_ERR_UNSUPPORTED, \
+    PMC_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+OPS = {"UV_INPUT": 0, "IMAGE_TEXTURE": 1, "VALUE_NOISE": 2, "PERLIN_NOISE": 3, "MIX": 4,
+       "MATH": 5, "COLOR_RAMP": 6, "NORMAL_MAP": 7, "BSDF_OUTPUT": 8}
+MATH_OPS = {"ADD": 0, "MUL": 1, "POW": 2}
+PMC_NODE_CLAMP = 1
+PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE = 0, 1
+PMC_MODE_UNCACHED, PMC_MODE_CACHED, PMC_MODE_SNAPSHOT = 0, 1, 2
+PMC_FLAG_SORT, PMC_FLAG_PERSISTENT = 1, 2
+MAX_CACHEABLE = 8
+
+
+# ----------------------------------------------------------------- structs ----
+class pmc_input(C.Structure):
+    _fields_ = [("node", C.c_int32), ("socket", C.c_uint32), ("value", C.c_float * 3)]
+
+
+class pmc_node_desc(C.Structure):
+    _fields_ = [("op", C.c_uint32), ("variant", C.c_uint32), ("flags", C.c_uint32),
+                ("seed", C.c_uint32), ("freq", C.c_float), ("octaves", C.c_uint32),
+                ("inp", pmc_input * 3), ("ramp_pos", C.c_float * 8),
+                ("ramp_rgba", (C.c_float * 4) * 8)]
+
+
+class pmc_texture_desc(C.Structure):
+    _fields_ = [("texels", C.c_void_p), ("width", C.c_uint32), ("height", C.c_uint32)]
+
+
+class pmc_compile_opts(C.Structure):
+    _fields_ = [("min_subgraph_nodes", C.c_uint32), ("no_fold", C.c_uint32),
+                ("reserved", C.c_uint32 * 6)]
+
+
+class pmc_material_info(C.Structure):
+    _fields_ = [("n_nodes", C.c_uint32), ("n_live", C.c_uint32), ("n_folded", C.c_uint32),
+                ("n_instr", C.c_uint32), ("n_regs", C.c_uint32), ("n_cacheable", C.c_uint32),
+                ("cacheable_node", C.c_uint32 * MAX_CACHEABLE),
+                ("cacheable_socket", C.c_uint32 * MAX_CACHEABLE),
+                ("subgraph_nodes", C.c_uint32 * MAX_CACHEABLE),
+                ("cacheable_type", C.c_uint32 * MAX_CACHEABLE)]
+
+
+class pmc_cache_params(C.Structure):
+    _fields_ = [("n_cells", C.c_uint64), ("n_entries", C.c_uint32), ("entry_bytes", C.c_uint32),
+                ("policy", C.c_uint32), ("level_bias", C.c_int32), ("level_max", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class pmc_hits(C.Structure):
+    _fields_ = [("material", C.c_void_p), ("uv", C.c_void_p), ("duv", C.c_void_p),
+                ("normal", C.c_void_p), ("n", C.c_uint64)]
+
+
+class pmc_bsdf_out(C.Structure):
+    _fields_ = [("base_color", C.c_void_p), ("roughness", C.c_void_p), ("normal", C.c_void_p)]
+
+
+class pmc_debug_out(C.Structure):
+    _fields_ = [("state", C.c_void_p), ("value", C.c_void_p)]
+
+
+class pmc_shade_params(C.Structure):
+    _fields_ = [("mode", C.c_uint32), ("flags", C.c_uint32), ("frame", C.c_uint32),
+                ("chunk_waves", C.c_uint32), ("blocks_per_cu", C.c_uint32),
+                ("reserved", C.c_uint32 * 3)]
+
+
+STAT_FIELDS = ("hits_shaded", "probes", "cache_hits", "bypasses", "inserts", "cas_failures",
+               "present", "cell_full", "overwrites", "nonfinite", "candidates",
+               "nodes_executed", "nodes_total", "invalid_material")
+
+
+class pmc_stats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64 * 2)]
+
+
+class pmc_key_record(C.Structure):
+    _fields_ = [("cell", C.c_uint32), ("hash2", C.c_uint32), ("level", C.c_int32),
+                ("tx", C.c_int32), ("ty", C.c_int32), ("bypass", C.c_uint32)]
+
+
+KEY_RECORD_DTYPE = np.dtype([("cell", "<u4"), ("hash2", "<u4"), ("level", "<i4"),
+                             ("tx", "<i4"), ("ty", "<i4"), ("bypass", "<u4")])
+
+# ------------------------------------------------------------- prototypes -----
+_P = C.c_void_p
+_S = C.c_int32
+_proto = {
+    "pmc_abi_version": (C.c_uint32, []),
+    "pmc_abi_sizeof": (C.c_size_t, [C.c_uint32]),
+    "pmc_create": (_S, [C.c_int, C.POINTER(C.c_void_p)]),
+    "pmc_destroy": (None, [_P]),
+    "pmc_last_error": (C.c_char_p, [_P]),
+    "pmc_set_textures": (_S, [_P, C.POINTER(pmc_texture_desc), C.c_uint32]),
+    "pmc_compile_materials": (_S, [_P, C.POINTER(pmc_node_desc), C.POINTER(C.c_uint32),
+                                   C.c_uint32, C.POINTER(pmc_compile_opts)]),
+    "pmc_get_material_info": (_S, [_P, C.c_uint32, C.POINTER(pmc_material_info)]),
+    "pmc_cache_create": (_S, [_P, C.POINTER(pmc_cache_params), _P, C.POINTER(C.c_void_p)]),
+    "pmc_cache_destroy": (None, [_P]),
+    "pmc_cache_clear": (_S, [_P, _P]),
+    "pmc_cache_device_ptr": (_S, [_P, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)]),
+    "pmc_cache_export": (_S, [_P, _P, C.c_size_t, _P]),
+    "pmc_cache_import": (_S, [_P, _P, C.c_size_t, _P]),
+    "pmc_shade": (_S, [_P, _P, C.POINTER(pmc_hits), C.POINTER(pmc_bsdf_out),
+                       C.POINTER(pmc_shade_params), _P, C.POINTER(pmc_debug_out), _P]),
+    "pmc_debug_keys": (_S, [_P, _P, C.POINTER(pmc_hits), _P, _P]),
+    "pmc_cache_insert_raw": (_S, [_P, _P, _P, _P, C.c_uint64, C.c_uint32, _P, _P]),
+    "pmc_cache_lookup_raw": (_S, [_P, _P, _P, C.c_uint64, _P, _P, _P]),
+}
+for _name, (_res, _args) in _proto.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+EXPORTED = tuple(_proto)
+
+
+class PmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pmc error {code}: {msg}")
+        self.code = code
+
+
+# --------------------------------------------------------------- marshalling --
+
+def node_array(materials) -> tuple:
+    """scenes.Material list -> (pmc_node_desc array, uint32 offsets array)."""
+    total = sum(len(m.nodes) for m in materials)
+    arr = (pmc_node_desc * max(total, 1))()
+    offsets = (C.c_uint32 * (len(materials) + 1))()
+    k = 0
+    for mi, m in enumerate(materials):
+        offsets[mi] = k
+        for nd in m.nodes:
+            d = arr[k]
+            d.op = OPS[nd.op]
+            if nd.op == "MATH":
+                d.variant = MATH_OPS[nd.math_op]
+            elif nd.op == "IMAGE_TEXTURE":
+                d.variant = nd.texture
+            d.flags = PMC_NODE_CLAMP if nd.clamp else 0
+            d.seed = nd.seed & 0xFFFFFFFF
+            d.freq = nd.freq
+            d.octaves = nd.octaves
+            for s in range(3):
+                if s < len(nd.inputs):
+                    inp = nd.inputs[s]
+                    d.inp[s].node = inp.node
+                    d.inp[s].socket = inp.socket
+                    for c in range(3):
+                        d.inp[s].value[c] = inp.value[c]
+                else:
+                    d.inp[s].node = -1
+            if nd.op == "COLOR_RAMP":
+                for c in range(8):
+                    d.ramp_pos[c] = nd.ramp_pos[c]
+                    for q in range(4):
+                        d.ramp_rgba[c][q] = nd.ramp_rgba[c][q]
+            k += 1
+    offsets[len(materials)] = k
+    return arr, offsets
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+class Context:
+    """Owner of a pmc_ctx (device >= 0) or a host-only one (device = -1)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = pmc_create(device, C.byref(h))
+        if st != PMC_OK:
+            raise PmcError(st, f"pmc_create({device}) failed")
+        self.h = h
+        self.device = device
+        self.n_mats = 0
+        self._keep: List = []
+
+    def close(self):
+        if self.h:
+            pmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st):
+        if st != PMC_OK:
+            raise PmcError(st, (pmc_last_error(self.h) or b"").decode())
+
+    def set_textures(self, textures: Sequence[np.ndarray]):
+        descs = (pmc_texture_desc * max(len(textures), 1))()
+        keep = []
+        for i, t in enumerate(textures):
+            a = np.ascontiguousarray(t, dtype=np.uint8)
+            keep.append(a)
+            descs[i].texels = a.ctypes.data
+            descs[i].height, descs[i].width = a.shape[0], a.shape[1]
+        self.check(pmc_set_textures(self.h, descs, len(textures)))
+
+    def compile(self, materials, min_subgraph_nodes: int = 0, no_fold: bool = False):
+        arr, offs = node_array(materials)
+        opts = pmc_compile_opts(min_subgraph_nodes, 1 if no_fold else 0)
+        self.check(pmc_compile_materials(self.h, arr, offs, len(materials), C.byref(opts)))
+        self.n_mats = len(materials)
+
+    def material_info(self, m: int) -> pmc_material_info:
+        info = pmc_material_info()
+        self.check(pmc_get_material_info(self.h, m, C.byref(info)))
+        return info
+
+    def cacheables(self, m: int):
+        info = self.material_info(m)
+        return [(info.cacheable_node[c], info.cacheable_socket[c]) for c in range(info.n_cacheable)]
+
+    def cache(self, n_cells: int, n_entries: int = 8, entry_bytes: int = 16,
+              policy: int = PMC_POLICY_FIRST, level_bias: int = 0, level_max: int = 0,
+              device_mem=None) -> "Cache":
+        return Cache(self, n_cells, n_entries, entry_bytes, policy, level_bias, level_max,
+                     device_mem)
+
+    def shade(self, hits: dict, out: dict, cache: Optional["Cache"] = None,
+              mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, frame: int = 0,
+              stats=None, debug: Optional[dict] = None, chunk_waves: int = 0,
+              blocks_per_cu: int = 0, stream=None):
+        """hits: dict of torch CUDA tensors material/uv/duv/normal; out: base_color/roughness/normal."""
+        h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
+                     _ptr(hits["normal"]), int(hits["material"].numel()))
+        o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
+        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu)
+        dbg = None
+        if debug is not None:
+            dbg = C.byref(pmc_debug_out(_ptr(debug.get("state")), _ptr(debug.get("value"))))
+        self.check(pmc_shade(self.h, cache.h if cache else None, C.byref(h), C.byref(o),
+                             C.byref(p), _ptr(stats), dbg, _stream_ptr(stream)))
+
+    def debug_keys(self, cache: "Cache", hits: dict, out, stream=None):
+        h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
+                     _ptr(hits["normal"]), int(hits["material"].numel()))
+        self.check(pmc_debug_keys(self.h, cache.h, C.byref(h), _ptr(out), _stream_ptr(stream)))
+
+
+class Cache:
+    def __init__(self, ctx: Context, n_cells, n_entries, entry_bytes, policy, level_bias,
+                 level_max, device_mem=None):
+        self.ctx = ctx
+        self.params = pmc_cache_params(int(n_cells), n_entries, entry_bytes, policy, level_bias,
+                                       level_max, 0)
+        h = C.c_void_p()
+        ctx.check(pmc_cache_create(ctx.h, C.byref(self.params), _ptr(device_mem), C.byref(h)))
+        self.h = h
+        ptr, nbytes = C.c_void_p(), C.c_size_t()
+        ctx.check(pmc_cache_device_ptr(self.h, C.byref(ptr), C.byref(nbytes)))
+        self.nbytes = nbytes.value
+        self.n_cells, self.n_entries, self.entry_bytes = int(n_cells), n_entries, entry_bytes
+
+    def close(self):
+        if self.h:
+            pmc_cache_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self, stream=None):
+        self.ctx.check(pmc_cache_clear(self.h, _stream_ptr(stream)))
+
+    def export(self, stream=None) -> np.ndarray:
+        buf = np.zeros(self.nbytes, np.uint8)
+        self.ctx.check(pmc_cache_export(self.h, buf.ctypes.data, self.nbytes, _stream_ptr(stream)))
+        return buf
+
+    def import_(self, raw: np.ndarray, stream=None):
+        raw = np.ascontiguousarray(raw, dtype=np.uint8)
+        self.ctx.check(pmc_cache_import(self.h, raw.ctypes.data, raw.nbytes, _stream_ptr(stream)))
+
+    def words(self, stream=None) -> np.ndarray:
+        """Table as (n_cells * n_entries, entry_bytes // 8) uint64 (word first)."""
+        return self.export(stream).view(np.uint64).reshape(-1, self.entry_bytes // 8)
+
+    def insert_raw(self, k0, k1, enc, frame=0, stats=None, stream=None):
+        self.ctx.check(pmc_cache_insert_raw(self.h, _ptr(k0), _ptr(k1), _ptr(enc), int(k0.numel()),
+                                            frame, _ptr(stats), _stream_ptr(stream)))
+
+    def lookup_raw(self, k0, k1, enc_out, hit_out, stream=None):
+        self.ctx.check(pmc_cache_lookup_raw(self.h, _ptr(k0), _ptr(k1), int(k0.numel()),
+                                            _ptr(enc_out), _ptr(hit_out), _stream_ptr(stream)))
+
+
+# ------------------------------------------------------------ torch helpers ---
+
+def hits_to_device(hits, device="cuda"):
+    """scenes.Hits (numpy) -> dict of torch tensors on the device."""
+    import torch
+    return {
+        "material": torch.from_numpy(np.ascontiguousarray(hits.material, np.uint32).view(np.int32)).to(device),
+        "uv": torch.from_numpy(np.ascontiguousarray(hits.uv, np.float32)).to(device),
+        "duv": torch.from_numpy(np.ascontiguousarray(hits.duv, np.float32)).to(device),
+        "normal": torch.from_numpy(np.ascontiguousarray(hits.normal, np.float32)).to(device),
+    }
+
+
+def alloc_outputs(n: int, device="cuda"):
+    import torch
+    return {"base_color": torch.empty((n, 3), dtype=torch.float32, device=device),
+            "roughness": torch.empty((n,), dtype=torch.float32, device=device),
+            "normal": torch.empty((n, 3), dtype=torch.float32, device=device)}
+
+
+def new_stats(device="cuda"):
+    import torch
+    return torch.zeros(16, dtype=torch.int64, device=device)
+
+
+def stats_dict(t) -> dict:
+    v = t.cpu().numpy().astype(np.uint64)
+    return {f: int(v[i]) for i, f in enumerate(STAT_FIELDS)}

@@ -1,0 +1,535 @@
+// abi.cpp - the C entry points of libpmc: context, textures, graph
+// compilation, cache tables, and the per-batch shading pipeline
+// (material sort -> shade -> snapshot apply -> statistics).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pmc.h"
+#include "compiler.h"
+#include "shade.h"
+
+using namespace pmc;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct pmc_ctx {
+  int device = -1;
+  bool host_only = true;
+  int num_cus = 0;
+  std::string err;
+  Program prog;
+  bool compiled = false;
+  // program on the device
+  DevBuf hdr, instr, cach, pool, lpt;
+  // textures
+  DevBuf texels, texdesc;
+  uint32_t n_tex = 0;
+  // workspace
+  DevBuf perm, counts, cursor, misc, cand, stat_slots;
+  pmc_status fail(pmc_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+};
+
+struct pmc_cache {
+  pmc_ctx* ctx = nullptr;
+  pmc_cache_params params{};
+  void* mem = nullptr;
+  bool owned = false;
+  size_t bytes = 0;
+  DevBuf cell_count, cell_start, cell_cursor, block_sums, sorted;
+};
+
+#define HIP_TRY(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return (ctx)->fail(PMC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+namespace {
+
+void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// grow-only device buffer; contents are not preserved
+pmc_status ensure(pmc_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return PMC_OK;
+  free_buf(b);
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return ctx->fail(e == hipErrorOutOfMemory ? PMC_ERR_OOM : PMC_ERR_HIP,
+                     "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return PMC_OK;
+}
+
+template <typename T>
+pmc_status upload(pmc_ctx* ctx, DevBuf& b, const std::vector<T>& v) {
+  size_t bytes = v.size() * sizeof(T);
+  pmc_status st = ensure(ctx, b, bytes ? bytes : 256);
+  if (st) return st;
+  if (bytes) HIP_TRY(ctx, hipMemcpy(b.p, v.data(), bytes, hipMemcpyHostToDevice));
+  return PMC_OK;
+}
+
+pmc_status need_device(pmc_ctx* ctx) {
+  if (ctx->host_only) return ctx->fail(PMC_ERR_STATE, "host-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return PMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t pmc_abi_version(void) { return PMC_ABI_VERSION; }
+
+size_t pmc_abi_sizeof(uint32_t which) {
+  switch (which) {
+    case 0: return sizeof(pmc_node_desc);
+    case 1: return sizeof(pmc_input);
+    case 2: return sizeof(pmc_texture_desc);
+    case 3: return sizeof(pmc_compile_opts);
+    case 4: return sizeof(pmc_material_info);
+    case 5: return sizeof(pmc_cache_params);
+    case 6: return sizeof(pmc_shade_params);
+    case 7: return sizeof(pmc_stats);
+    case 8: return sizeof(pmc_hits);
+    case 9: return sizeof(pmc_bsdf_out);
+    case 10: return sizeof(pmc_debug_out);
+    case 11: return sizeof(pmc_key_record);
+    default: return 0;
+  }
+}
+
+pmc_status pmc_create(int device, pmc_ctx** out) {
+  if (!out) return PMC_ERR_INVALID;
+  *out = nullptr;
+  pmc_ctx* ctx = new (std::nothrow) pmc_ctx();
+  if (!ctx) return PMC_ERR_OOM;
+  if (device >= 0) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+      delete ctx;
+      return PMC_ERR_INVALID;
+    }
+    ctx->device = device;
+    ctx->host_only = false;
+    if (hipSetDevice(device) != hipSuccess) {
+      delete ctx;
+      return PMC_ERR_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+      delete ctx;
+      return PMC_ERR_HIP;
+    }
+    ctx->num_cus = prop.multiProcessorCount;
+    if (ensure(ctx, ctx->stat_slots, sizeof(unsigned long long) * kStatSlots * kStatStride) ||
+        ensure(ctx, ctx->misc, 256) ||
+        hipMemset(ctx->stat_slots.p, 0, ctx->stat_slots.bytes) != hipSuccess ||
+        hipMemset(ctx->misc.p, 0, ctx->misc.bytes) != hipSuccess) {
+      pmc_destroy(ctx);
+      return PMC_ERR_HIP;
+    }
+  } else if (device != -1) {
+    delete ctx;
+    return PMC_ERR_INVALID;
+  }
+  *out = ctx;
+  return PMC_OK;
+}
+
+void pmc_destroy(pmc_ctx* ctx) {
+  if (!ctx) return;
+  if (!ctx->host_only) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->texels,
+                      &ctx->texdesc, &ctx->perm, &ctx->counts, &ctx->cursor, &ctx->misc,
+                      &ctx->cand, &ctx->stat_slots})
+      free_buf(*b);
+  }
+  delete ctx;
+}
+
+const char* pmc_last_error(const pmc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+pmc_status pmc_set_textures(pmc_ctx* ctx, const pmc_texture_desc* tex, uint32_t n_tex) {
+  if (!ctx) return PMC_ERR_INVALID;
+  if (n_tex && !tex) return ctx->fail(PMC_ERR_INVALID, "set_textures: null texture array");
+  if (pmc_status st = need_device(ctx)) return st;
+  std::vector<TexDesc> desc(n_tex);
+  uint64_t total = 0;
+  for (uint32_t t = 0; t < n_tex; ++t) {
+    if (!tex[t].texels || tex[t].width == 0 || tex[t].height == 0 || tex[t].width > 65536 ||
+        tex[t].height > 65536)
+      return ctx->fail(PMC_ERR_INVALID, "texture %u: null texels or bad size", t);
+    desc[t].offset = total;
+    desc[t].w = tex[t].width;
+    desc[t].h = tex[t].height;
+    total += (uint64_t)tex[t].width * tex[t].height;
+  }
+  if (pmc_status st = ensure(ctx, ctx->texels, total * 4 + 256)) return st;
+  for (uint32_t t = 0; t < n_tex; ++t)
+    HIP_TRY(ctx, hipMemcpy((uint32_t*)ctx->texels.p + desc[t].offset, tex[t].texels,
+                           (size_t)tex[t].width * tex[t].height * 4, hipMemcpyHostToDevice));
+  if (pmc_status st = upload(ctx, ctx->texdesc, desc)) return st;
+  ctx->n_tex = n_tex;
+  return PMC_OK;
+}
+
+pmc_status pmc_compile_materials(pmc_ctx* ctx, const pmc_node_desc* nodes,
+                                 const uint32_t* node_offsets, uint32_t n_mats,
+                                 const pmc_compile_opts* opts) {
+  if (!ctx) return PMC_ERR_INVALID;
+  Program prog;
+  std::string err;
+  pmc_status st = compile_program(nodes, node_offsets, n_mats, opts, prog, err);
+  if (st != PMC_OK) return ctx->fail(st, "%s", err.c_str());
+  if (prog.max_regs > 64)
+    return ctx->fail(PMC_ERR_UNSUPPORTED, "a material needs %u registers (limit 64)",
+                     prog.max_regs);
+  if (!ctx->host_only) {
+    if (pmc_status s2 = need_device(ctx)) return s2;
+    HIP_TRY(ctx, hipDeviceSynchronize());   // no batch may still read the old program
+    if ((st = upload(ctx, ctx->hdr, prog.headers)) || (st = upload(ctx, ctx->instr, prog.instrs)) ||
+        (st = upload(ctx, ctx->cach, prog.cach)) || (st = upload(ctx, ctx->pool, prog.pool)) ||
+        (st = upload(ctx, ctx->lpt, prog.lpt_order)))
+      return st;
+  }
+  ctx->prog = std::move(prog);
+  ctx->compiled = true;
+  return PMC_OK;
+}
+
+pmc_status pmc_get_material_info(const pmc_ctx* ctx, uint32_t mat, pmc_material_info* out) {
+  if (!ctx || !out) return PMC_ERR_INVALID;
+  if (!ctx->compiled) return PMC_ERR_STATE;
+  if (mat >= ctx->prog.info.size()) return PMC_ERR_INVALID;
+  *out = ctx->prog.info[mat];
+  return PMC_OK;
+}
+
+// ------------------------------------------------------------------ cache ---
+
+pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* p, void* device_mem,
+                            pmc_cache** out) {
+  if (!ctx || !p || !out) return PMC_ERR_INVALID;
+  *out = nullptr;
+  if (pmc_status st = need_device(ctx)) return st;
+  if (p->n_cells == 0 || p->n_cells >= (1ull << 32))
+    return ctx->fail(PMC_ERR_INVALID, "n_cells must be in [1, 2^32)");
+  if (p->n_entries == 0 || p->n_entries > 64)
+    return ctx->fail(PMC_ERR_INVALID, "n_entries must be in [1, 64]");
+  if (p->entry_bytes != 8 && p->entry_bytes != 16)
+    return ctx->fail(PMC_ERR_INVALID, "entry_bytes must be 8 or 16");
+  if (p->policy > PMC_POLICY_OVERWRITE) return ctx->fail(PMC_ERR_INVALID, "unknown policy");
+  if (p->policy == PMC_POLICY_OVERWRITE && p->entry_bytes != 16)
+    return ctx->fail(PMC_ERR_INVALID, "OVERWRITE needs 16-byte entries (stamps)");
+  if (p->level_max > 30) return ctx->fail(PMC_ERR_INVALID, "level_max must be <= 30");
+  pmc_cache* c = new (std::nothrow) pmc_cache();
+  if (!c) return PMC_ERR_OOM;
+  c->ctx = ctx;
+  c->params = *p;
+  if (c->params.level_max == 0) c->params.level_max = 20;
+  c->bytes = (size_t)p->n_cells * p->n_entries * p->entry_bytes;
+  if (device_mem) {
+    if (((uintptr_t)device_mem & 255u) != 0) {
+      delete c;
+      return ctx->fail(PMC_ERR_INVALID, "device_mem must be 256-byte aligned");
+    }
+    c->mem = device_mem;
+  } else {
+    hipError_t e = hipMalloc(&c->mem, c->bytes);
+    if (e != hipSuccess) {
+      delete c;
+      return ctx->fail(PMC_ERR_OOM, "hipMalloc(%zu) for the table failed", c->bytes);
+    }
+    c->owned = true;
+  }
+  hipError_t e = hipMemset(c->mem, 0, c->bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    pmc_cache_destroy(c);
+    return ctx->fail(PMC_ERR_HIP, "clearing the table failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return PMC_OK;
+}
+
+void pmc_cache_destroy(pmc_cache* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (c->owned && c->mem) (void)hipFree(c->mem);
+  for (DevBuf* b : {&c->cell_count, &c->cell_start, &c->cell_cursor, &c->block_sums, &c->sorted})
+    free_buf(*b);
+  delete c;
+}
+
+pmc_status pmc_cache_clear(pmc_cache* c, void* stream) {
+  if (!c) return PMC_ERR_INVALID;
+  pmc_ctx* ctx = c->ctx;
+  if (pmc_status st = need_device(ctx)) return st;
+  HIP_TRY(ctx, launch_fill_u64((uint64_t*)c->mem, 0ull, c->bytes / 8, (hipStream_t)stream));
+  return PMC_OK;
+}
+
+pmc_status pmc_cache_device_ptr(pmc_cache* c, void** ptr, size_t* bytes) {
+  if (!c || !ptr || !bytes) return PMC_ERR_INVALID;
+  *ptr = c->mem;
+  *bytes = c->bytes;
+  return PMC_OK;
+}
+
+pmc_status pmc_cache_export(pmc_cache* c, void* host_dst, size_t bytes, void* stream) {
+  if (!c || !host_dst) return PMC_ERR_INVALID;
+  pmc_ctx* ctx = c->ctx;
+  if (bytes != c->bytes) return ctx->fail(PMC_ERR_INVALID, "export: size %zu != table %zu", bytes, c->bytes);
+  if (pmc_status st = need_device(ctx)) return st;
+  HIP_TRY(ctx, hipMemcpyAsync(host_dst, c->mem, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+  return PMC_OK;
+}
+
+pmc_status pmc_cache_import(pmc_cache* c, const void* host_src, size_t bytes, void* stream) {
+  if (!c || !host_src) return PMC_ERR_INVALID;
+  pmc_ctx* ctx = c->ctx;
+  if (bytes != c->bytes) return ctx->fail(PMC_ERR_INVALID, "import: size %zu != table %zu", bytes, c->bytes);
+  if (pmc_status st = need_device(ctx)) return st;
+  HIP_TRY(ctx, hipMemcpyAsync(c->mem, host_src, bytes, hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+  return PMC_OK;
+}
+
+// ---------------------------------------------------------------- shading ---
+
+static void fill_program_args(pmc_ctx* ctx, ShadeArgs& a) {
+  std::memset(&a, 0, sizeof a);
+  a.hdr = (const MatHeader*)ctx->hdr.p;
+  a.instr = (const Instr*)ctx->instr.p;
+  a.cach = (const CachDesc*)ctx->cach.p;
+  a.pool = (const float*)ctx->pool.p;
+  a.tex = (const TexDesc*)ctx->texdesc.p;
+  a.texels = (const uint32_t*)ctx->texels.p;
+  a.n_mats = (uint32_t)ctx->prog.headers.size();
+  a.n_regs = ctx->prog.max_regs ? ctx->prog.max_regs : 1;
+}
+
+static void fill_cache_args(pmc_cache* c, ShadeArgs& a) {
+  a.table = (uint64_t*)c->mem;
+  a.n_cells = (uint32_t)c->params.n_cells;
+  a.n_entries = c->params.n_entries;
+  a.entry_words = c->params.entry_bytes / 8;
+  a.policy = c->params.policy;
+  a.level_bias = c->params.level_bias;
+  a.level_max = (int32_t)c->params.level_max;
+}
+
+static pmc_status check_hits(pmc_ctx* ctx, const pmc_hits* h) {
+  if (!h) return ctx->fail(PMC_ERR_INVALID, "null hits");
+  if (h->n >= (1ull << 27)) return ctx->fail(PMC_ERR_INVALID, "at most 2^27 - 1 hits per call");
+  if (h->n && (!h->material || !h->uv || !h->duv || !h->normal))
+    return ctx->fail(PMC_ERR_INVALID, "null hit array");
+  if (((uintptr_t)h->uv & 7u) || ((uintptr_t)h->duv & 15u))
+    return ctx->fail(PMC_ERR_INVALID, "uv must be 8-byte and duv 16-byte aligned");
+  return PMC_OK;
+}
+
+static pmc_status ready(pmc_ctx* ctx) {
+  if (pmc_status st = need_device(ctx)) return st;
+  if (!ctx->compiled) return ctx->fail(PMC_ERR_STATE, "no compiled graph set");
+  if (ctx->prog.max_texture >= (int32_t)ctx->n_tex)
+    return ctx->fail(PMC_ERR_STATE, "graphs use texture %d but %u are set",
+                     ctx->prog.max_texture, ctx->n_tex);
+  return PMC_OK;
+}
+
+pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                     const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
+                     const pmc_debug_out* dbg, void* stream) {
+  if (!ctx) return PMC_ERR_INVALID;
+  if (pmc_status st = ready(ctx)) return st;
+  if (pmc_status st = check_hits(ctx, hits)) return st;
+  if (!params) return ctx->fail(PMC_ERR_INVALID, "null params");
+  if (params->mode > PMC_MODE_SNAPSHOT) return ctx->fail(PMC_ERR_INVALID, "unknown mode");
+  if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT))
+    return ctx->fail(PMC_ERR_INVALID, "unknown flags");
+  if (hits->n && (!out || !out->base_color || !out->roughness || !out->normal))
+    return ctx->fail(PMC_ERR_INVALID, "null output array");
+  if (cache && cache->ctx != ctx) return ctx->fail(PMC_ERR_INVALID, "cache of another context");
+  const uint32_t n = (uint32_t)hits->n;
+  if (n == 0) return PMC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t mode = params->mode;
+  if (!cache) mode = PMC_MODE_UNCACHED;
+  const bool sort = params->flags & PMC_FLAG_SORT;
+  const bool persistent = params->flags & PMC_FLAG_PERSISTENT;
+
+  ShadeArgs a;
+  fill_program_args(ctx, a);
+  a.material = hits->material;
+  a.uv = hits->uv;
+  a.duv = hits->duv;
+  a.normal = hits->normal;
+  a.n = n;
+  a.mode = mode;
+  a.out_base = out->base_color;
+  a.out_rough = out->roughness;
+  a.out_normal = out->normal;
+  a.frame = params->frame;
+  a.chunk_waves = params->chunk_waves ? params->chunk_waves : 1;
+  a.stat_slots = stats ? (unsigned long long*)ctx->stat_slots.p : nullptr;
+  a.dbg_state = dbg ? dbg->state : nullptr;
+  a.dbg_value = dbg ? dbg->value : nullptr;
+  uint32_t* misc = (uint32_t*)ctx->misc.p;
+  a.queue = misc + 0;
+  if (mode != PMC_MODE_UNCACHED) fill_cache_args(cache, a);
+
+  const uint32_t n_mats = a.n_mats;
+  if (sort) {
+    pmc_status st;
+    if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
+        (st = ensure(ctx, ctx->counts, (size_t)(n_mats + 1) * 4)) ||
+        (st = ensure(ctx, ctx->cursor, (size_t)(n_mats + 1) * 4)))
+      return st;
+    HIP_TRY(ctx, launch_material_sort(hits->material, n, n_mats, (const uint32_t*)ctx->lpt.p,
+                                      (uint32_t*)ctx->counts.p, (uint32_t*)ctx->cursor.p,
+                                      (uint32_t*)ctx->perm.p, misc + 0, misc + 1, s));
+    a.perm = (const uint32_t*)ctx->perm.p;
+  } else {
+    HIP_TRY(ctx, launch_fill_u32(misc, 0u, 2, s));
+  }
+  if (mode == PMC_MODE_SNAPSHOT) {
+    size_t cap = (size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1);
+    pmc_status st;
+    if ((st = ensure(ctx, ctx->cand, cap * 16)) || (st = ensure(ctx, cache->sorted, cap * 16)))
+      return st;
+    const uint32_t ncell = (uint32_t)cache->params.n_cells;
+    if (!cache->cell_count.p) {
+      if ((st = ensure(ctx, cache->cell_count, (size_t)ncell * 4))) return st;
+      HIP_TRY(ctx, launch_fill_u32((uint32_t*)cache->cell_count.p, 0u, ncell, s));
+    }
+    if ((st = ensure(ctx, cache->cell_start, (size_t)ncell * 4)) ||
+        (st = ensure(ctx, cache->cell_cursor, (size_t)ncell * 4)) ||
+        (st = ensure(ctx, cache->block_sums, (size_t)snapshot_scan_blocks(ncell) * 4 + 4)))
+      return st;
+    a.cand = (uint4*)ctx->cand.p;
+    a.cand_count = misc + 1;
+    a.cand_cap = (uint32_t)cap;
+  }
+  const uint32_t n_chunks = (n + 63) / 64;
+  uint32_t grid;
+  if (persistent) {
+    uint32_t bpc = params->blocks_per_cu;
+    if (bpc == 0) {
+      size_t lds_per_block = (size_t)4 * a.n_regs * 256;
+      bpc = (uint32_t)((160 * 1024) / (lds_per_block ? lds_per_block : 1));
+      bpc = bpc < 1 ? 1 : (bpc > 8 ? 8 : bpc);
+    }
+    grid = (uint32_t)ctx->num_cus * bpc;
+    uint32_t max_useful = (n_chunks + 3) / 4;
+    if (grid > max_useful) grid = max_useful ? max_useful : 1;
+  } else {
+    grid = (n_chunks + 3) / 4;
+  }
+  HIP_TRY(ctx, launch_shade(a, persistent, grid, s));
+  if (mode == PMC_MODE_SNAPSHOT) {
+    SnapshotArgs sa;
+    sa.table = a.table;
+    sa.n_cells = a.n_cells;
+    sa.n_entries = a.n_entries;
+    sa.entry_words = a.entry_words;
+    sa.policy = a.policy;
+    sa.frame = a.frame;
+    sa.cand = a.cand;
+    sa.sorted = (uint4*)cache->sorted.p;
+    sa.cand_count = a.cand_count;
+    sa.cand_cap = a.cand_cap;
+    sa.cell_count = (uint32_t*)cache->cell_count.p;
+    sa.cell_start = (uint32_t*)cache->cell_start.p;
+    sa.cell_cursor = (uint32_t*)cache->cell_cursor.p;
+    sa.block_sums = (uint32_t*)cache->block_sums.p;
+    sa.stat_slots = a.stat_slots;
+    HIP_TRY(ctx, launch_snapshot_apply(sa, s));
+  }
+  if (stats) HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));
+  return PMC_OK;
+}
+
+pmc_status pmc_debug_keys(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                          pmc_key_record* out, void* stream) {
+  if (!ctx) return PMC_ERR_INVALID;
+  if (pmc_status st = ready(ctx)) return st;
+  if (pmc_status st = check_hits(ctx, hits)) return st;
+  if (!cache || !out) return ctx->fail(PMC_ERR_INVALID, "null cache or output");
+  if (hits->n == 0) return PMC_OK;
+  ShadeArgs a;
+  fill_program_args(ctx, a);
+  fill_cache_args(cache, a);
+  a.material = hits->material;
+  a.uv = hits->uv;
+  a.duv = hits->duv;
+  a.n = (uint32_t)hits->n;
+  HIP_TRY(ctx, launch_debug_keys(a, out, (hipStream_t)stream));
+  return PMC_OK;
+}
+
+pmc_status pmc_cache_insert_raw(pmc_cache* c, const uint64_t* k0, const uint64_t* k1,
+                                const uint32_t* enc, uint64_t n, uint32_t frame,
+                                pmc_stats* stats, void* stream) {
+  if (!c) return PMC_ERR_INVALID;
+  pmc_ctx* ctx = c->ctx;
+  if (pmc_status st = need_device(ctx)) return st;
+  if (n && (!k0 || !k1 || !enc)) return ctx->fail(PMC_ERR_INVALID, "null raw arrays");
+  if (n >= (1ull << 32)) return ctx->fail(PMC_ERR_INVALID, "too many raw inserts");
+  if (n == 0) return PMC_OK;
+  ShadeArgs a;
+  std::memset(&a, 0, sizeof a);
+  fill_cache_args(c, a);
+  a.frame = frame;
+  a.stat_slots = stats ? (unsigned long long*)ctx->stat_slots.p : nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(ctx, launch_insert_raw(a, k0, k1, enc, n, s));
+  if (stats) HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));
+  return PMC_OK;
+}
+
+pmc_status pmc_cache_lookup_raw(pmc_cache* c, const uint64_t* k0, const uint64_t* k1, uint64_t n,
+                                uint32_t* enc_out, uint8_t* hit, void* stream) {
+  if (!c) return PMC_ERR_INVALID;
+  pmc_ctx* ctx = c->ctx;
+  if (pmc_status st = need_device(ctx)) return st;
+  if (n && (!k0 || !k1 || !enc_out || !hit)) return ctx->fail(PMC_ERR_INVALID, "null raw arrays");
+  if (n >= (1ull << 32)) return ctx->fail(PMC_ERR_INVALID, "too many raw lookups");
+  if (n == 0) return PMC_OK;
+  ShadeArgs a;
+  std::memset(&a, 0, sizeof a);
+  fill_cache_args(c, a);
+  HIP_TRY(ctx, launch_lookup_raw(a, k0, k1, n, enc_out, hit, (hipStream_t)stream));
+  return PMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// device_common.h - device-side helpers shared by the HIP kernels of libpmc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "program.h"
+
+namespace pmc {
+
+// Uniform (wave-invariant) program data is read through the constant address
+// space so the compiler emits scalar loads (SMEM, scalar cache) for it.
+#define PMC_CONST __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ const PMC_CONST T* as_const(const T* p) {
+  return (const PMC_CONST T*)(p);
+}
+
+// ---- 64-bit finalizer (SplitMix64 output mix, Steele/Lea/Flood 2014) ------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kSeedCell = 0x9E3779B97F4A7C15ull;    // Hash: cell index
+constexpr uint64_t kSeedVerify = 0xC2B2AE3D27D4EB4Full;  // Hash2: verification key
+
+// ---- descriptor of a cacheable output (Sec. 3.1 Eq. 1, Sec. 3.2) -----------
+struct Key {
+  uint32_t cell, hash2;
+  int32_t level, tx, ty;
+  bool bypass;
+};
+
+// Level: floor(lambda) with lambda = -log2(min |g|) (Eq. 1), from the binary64
+// squared norms; frexp gives m2 = f 2^e, f in [1/2, 1), and then
+// floor(lambda) = floor((-e + [f == 1/2]) / 2).
+__device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float u, float v,
+                                        float4 g, int bias, int lmax, uint32_t n_cells) {
+  Key k;
+  k.cell = 0; k.hash2 = 1; k.level = 0; k.tx = 0; k.ty = 0; k.bypass = true;
+  if (!(isfinite(u) && isfinite(v) && isfinite(g.x) && isfinite(g.y) && isfinite(g.z) &&
+        isfinite(g.w)))
+    return k;
+  double s1 = (double)g.x * (double)g.x + (double)g.y * (double)g.y;  // products exact
+  double s2 = (double)g.z * (double)g.z + (double)g.w * (double)g.w;
+  double m2 = s1 < s2 ? s1 : s2;
+  int L;
+  if (m2 == 0.0) {
+    L = lmax;
+  } else {
+    int e;
+    double f = frexp(m2, &e);
+    int t = -e + (f == 0.5 ? 1 : 0);
+    int F = t >> 1;                        // arithmetic shift = floor division by 2
+    L = F + bias;
+    L = L < 0 ? 0 : (L > lmax ? lmax : L);
+  }
+  double x = ldexp((double)u, L);
+  double y = ldexp((double)v, L);
+  const double lim = 2147483648.0;
+  if (!(x >= -lim && x < lim && y >= -lim && y < lim)) return k;
+  int tx = (int)floor(x), ty = (int)floor(y);
+  uint64_t k0 = ((uint64_t)mat << 32) | (uint64_t)node_sock | (uint64_t)(uint32_t)L;
+  uint64_t k1 = ((uint64_t)(uint32_t)tx << 32) | (uint64_t)(uint32_t)ty;
+  uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
+  uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
+  k.cell = (uint32_t)(hc >> 32) % n_cells;
+  k.hash2 = (uint32_t)hv;
+  if (k.hash2 == 0) k.hash2 = 1;
+  k.level = L; k.tx = tx; k.ty = ty; k.bypass = false;
+  return k;
+}
+
+// Descriptor hashes of raw descriptor words (Algorithm 1 surface).
+__device__ __forceinline__ void raw_hash(uint64_t k0, uint64_t k1, uint32_t n_cells,
+                                         uint32_t* cell, uint32_t* hash2) {
+  uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
+  uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
+  *cell = (uint32_t)(hc >> 32) % n_cells;
+  uint32_t h = (uint32_t)hv;
+  *hash2 = h ? h : 1u;
+}
+
+// ---- 32-bit value codes (Sec. 3.3) -----------------------------------------
+// FLOAT: binary32 bits.  COLOR: RGB9E5 (Khronos EXT_texture_shared_exponent,
+// N = 9, B = 15), computed exactly: only power-of-two scalings and an exact
+// round-half-up.
+__device__ __forceinline__ uint32_t round_half_up(float x) {
+  float t = floorf(x);
+  return (uint32_t)t + ((x - t) >= 0.5f ? 1u : 0u);
+}
+
+__device__ __forceinline__ uint32_t rgb9e5_encode(float r, float g, float b) {
+  const float kMax = 65408.0f;
+  r = fminf(fmaxf(r, 0.0f), kMax);
+  g = fminf(fmaxf(g, 0.0f), kMax);
+  b = fminf(fmaxf(b, 0.0f), kMax);
+  float mx = fmaxf(r, fmaxf(g, b));
+  int exp_p = 0;
+  if (mx > 0.0f) {
+    int e;
+    frexpf(mx, &e);                      // mx = f 2^e, floor(log2 mx) = e - 1
+    int fl = e - 1;
+    exp_p = (fl < -16 ? -16 : fl) + 16;
+  }
+  float scale = ldexpf(1.0f, 24 - exp_p);
+  if (round_half_up(mx * scale) == 512u) {
+    exp_p += 1;
+    scale *= 0.5f;
+  }
+  uint32_t rm = round_half_up(r * scale), gm = round_half_up(g * scale),
+           bm = round_half_up(b * scale);
+  return rm | (gm << 9) | (bm << 18) | ((uint32_t)exp_p << 27);
+}
+
+__device__ __forceinline__ float3 rgb9e5_decode(uint32_t c) {
+  int e = (int)(c >> 27) - 24;
+  return make_float3(ldexpf((float)(c & 0x1FF), e), ldexpf((float)((c >> 9) & 0x1FF), e),
+                     ldexpf((float)((c >> 18) & 0x1FF), e));
+}
+
+// ---- wave helpers -----------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace pmc

@@ -1,0 +1,98 @@
+// shade.h - kernel arguments and host launchers of libpmc's HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pmc.h"
+#include "program.h"
+
+namespace pmc {
+
+// Counter slots, in the order of pmc_stats.
+enum {
+  CNT_HITS = 0, CNT_PROBES, CNT_CACHE_HITS, CNT_BYPASSES, CNT_INSERTS, CNT_CAS_FAIL,
+  CNT_PRESENT, CNT_FULL, CNT_OVERWRITES, CNT_NONFINITE, CNT_CANDIDATES, CNT_NODES_EXEC,
+  CNT_NODES_TOTAL, CNT_INVALID, kNumCounters
+};
+constexpr int kStatSlots = 64;       // counters are spread over slots to limit atomic contention
+constexpr int kStatStride = 16;      // u64 per slot (= sizeof(pmc_stats) / 8)
+
+struct ShadeArgs {
+  // compiled program
+  const MatHeader* hdr;
+  const Instr* instr;
+  const CachDesc* cach;
+  const float* pool;
+  const TexDesc* tex;
+  const uint32_t* texels;
+  uint32_t n_mats;
+  uint32_t n_regs;               // LDS registers per lane (max over materials)
+  // hits
+  const uint32_t* material;
+  const float* uv;
+  const float* duv;
+  const float* normal;
+  const uint32_t* perm;          // processing order (material-sorted), NULL = identity
+  uint32_t n;
+  uint32_t mode;
+  // outputs
+  float* out_base;
+  float* out_rough;
+  float* out_normal;
+  // cache
+  uint64_t* table;
+  uint32_t n_cells;
+  uint32_t n_entries;
+  uint32_t entry_words;          // 64-bit words per entry: 1 (8 B) or 2 (16 B)
+  uint32_t policy;
+  int32_t level_bias;
+  int32_t level_max;
+  uint32_t frame;
+  uint32_t chunk_waves;
+  // snapshot candidates {cell, seq, code, hash2}
+  uint4* cand;
+  uint32_t* cand_count;
+  uint32_t cand_cap;
+  // stats and diagnostics
+  unsigned long long* stat_slots;
+  uint8_t* dbg_state;
+  float* dbg_value;
+  uint32_t* queue;               // persistent work counter
+};
+
+hipError_t launch_shade(const ShadeArgs& a, bool persistent, uint32_t grid, hipStream_t s);
+hipError_t launch_debug_keys(const ShadeArgs& a, pmc_key_record* out, hipStream_t s);
+hipError_t launch_insert_raw(const ShadeArgs& a, const uint64_t* k0, const uint64_t* k1,
+                             const uint32_t* enc, uint64_t n, hipStream_t s);
+hipError_t launch_lookup_raw(const ShadeArgs& a, const uint64_t* k0, const uint64_t* k1,
+                             uint64_t n, uint32_t* enc_out, uint8_t* hit, hipStream_t s);
+
+// util.hip
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t value, uint64_t n, hipStream_t s);
+hipError_t launch_stats_reduce(unsigned long long* slots, pmc_stats* out, hipStream_t s);
+
+// sort.hip: material sort.  counts/cursor: n_mats + 1 entries (last = invalid ids).
+hipError_t launch_material_sort(const uint32_t* material, uint32_t n, uint32_t n_mats,
+                                const uint32_t* lpt_order, uint32_t* counts, uint32_t* cursor,
+                                uint32_t* perm, uint32_t* reset_a, uint32_t* reset_b,
+                                hipStream_t s);
+
+// snapshot.hip: apply the candidates of one batch in (hit, ordinal) order.
+struct SnapshotArgs {
+  uint64_t* table;
+  uint32_t n_cells, n_entries, entry_words, policy, frame;
+  const uint4* cand;
+  uint4* sorted;
+  const uint32_t* cand_count;
+  uint32_t cand_cap;
+  uint32_t* cell_count;          // n_cells
+  uint32_t* cell_start;          // n_cells
+  uint32_t* cell_cursor;         // n_cells
+  uint32_t* block_sums;          // scan scratch
+  unsigned long long* stat_slots;
+};
+hipError_t launch_snapshot_apply(const SnapshotArgs& a, hipStream_t s);
+uint32_t snapshot_scan_blocks(uint32_t n_cells);
+
+}  // namespace pmc

@@ -1,0 +1,668 @@
+// shade.hip - the shading kernel: descriptor keys, cache probes, the node
+// interpreter and cache inserts for one batch of hits.
+//
+// Paper passages: Sec. 2 (networks executed as data in storage order),
+// Sec. 3 (at a cacheable node look up first; on a hit use the value and skip
+// the sub-graph, otherwise evaluate it and store the result), Sec. 3.1 and
+// Eq. 1 (descriptor: material, node, level, texel), Sec. 3.2 (two hashes,
+// N_c cells x N_e entries, keep the first value), Sec. 3.3 and Algorithm 1
+// (lock-free insert with one 64-bit compare-and-swap of hash2 << 32 | code).
+//
+// Execution model (gfx950, wave64): a wave takes 64 hits (a chunk).  Hits are
+// normally sorted by material first, so a chunk holds one material and the
+// program is read with scalar loads; a chunk that straddles materials runs
+// the program once per material with the other lanes masked off.  Per lane:
+//   1. compute the key of every cacheable output and probe its cell
+//      (all K probes are issued before any result is used);
+//   2. miss_mask = outputs not found; run each instruction whose need mask
+//      intersects the wave's needs (EXEC = lanes that need it), so a wave whose
+//      lanes all hit skips the sub-graphs entirely;
+//   3. after a cacheable output is computed on a miss, encode and insert it
+//      (CACHED: Algorithm 1 CAS; SNAPSHOT: append an insert candidate);
+//   4. write the BSDF inputs.
+#include "shade.h"
+
+#include "device_common.h"
+
+namespace pmc {
+
+// ---------------------------------------------------------------- helpers ---
+
+struct LaneRegs {                      // per-wave register file in LDS, [reg][lane]
+  float* base;
+  int lane;
+  __device__ __forceinline__ float get(int r) const { return base[r * 64 + lane]; }
+  __device__ __forceinline__ void set(int r, float v) const { base[r * 64 + lane] = v; }
+};
+
+struct HitData {
+  float u, v;
+  float4 g;
+  float3 n;
+};
+
+__device__ __forceinline__ float read_f(uint32_t op, const PMC_CONST float* k, const LaneRegs& R,
+                                        const HitData& hd) {
+  uint32_t kind = op & 0xFF, kofs = (op >> 8) & 0xFF, r = op >> 16;
+  switch (kind) {
+    case OPK_CONST_F: case OPK_CONST_C: return k[kofs];
+    case OPK_REG_F: case OPK_REG_F2C: return R.get(r);
+    case OPK_REG_C2F: case OPK_REG_C:
+      return (R.get(r) + R.get(r + 1) + R.get(r + 2)) / 3.0f;
+    default: return 0.0f;
+  }
+}
+
+__device__ __forceinline__ float3 read_c(uint32_t op, const PMC_CONST float* k, const LaneRegs& R,
+                                         const HitData& hd) {
+  uint32_t kind = op & 0xFF, kofs = (op >> 8) & 0xFF, r = op >> 16;
+  switch (kind) {
+    case OPK_CONST_C: return make_float3(k[kofs], k[kofs + 1], k[kofs + 2]);
+    case OPK_CONST_F: { float x = k[kofs]; return make_float3(x, x, x); }
+    case OPK_REG_C: case OPK_REG_C2F: return make_float3(R.get(r), R.get(r + 1), R.get(r + 2));
+    case OPK_REG_F: case OPK_REG_F2C: { float x = R.get(r); return make_float3(x, x, x); }
+    case OPK_NORMAL: return hd.n;
+    default: return make_float3(0.f, 0.f, 0.f);
+  }
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return a + t * (b - a); }
+__device__ __forceinline__ float clamp01f(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// Noise corner hash: low 32 bits of mix64(((u32)i << 32 | (u32)j) ^ seed * golden).
+__device__ __forceinline__ uint32_t lattice_hash(int i, int j, uint64_t sgold) {
+  uint64_t z = ((uint64_t)(uint32_t)i << 32) | (uint64_t)(uint32_t)j;
+  return (uint32_t)mix64(z ^ sgold);
+}
+
+__device__ float value_noise(float u, float v, float f0, int octaves, uint32_t seed) {
+  float total = 0.0f, norm = 0.0f, amp = 1.0f, freq = f0;
+  for (int o = 0; o < octaves; ++o) {
+    uint64_t sg = (uint64_t)(seed + (uint32_t)o) * kGolden;
+    float px = u * freq, py = v * freq;
+    float fi = floorf(px), fj = floorf(py);
+    float fx = px - fi, fy = py - fj;
+    int i = (int)fi, j = (int)fj;
+    const float s = 2.3283064365386963e-10f;  // 2^-32
+    float h00 = (float)lattice_hash(i, j, sg) * s;
+    float h10 = (float)lattice_hash(i + 1, j, sg) * s;
+    float h01 = (float)lattice_hash(i, j + 1, sg) * s;
+    float h11 = (float)lattice_hash(i + 1, j + 1, sg) * s;
+    float sx = fx * fx * (3.0f - 2.0f * fx);
+    float sy = fy * fy * (3.0f - 2.0f * fy);
+    float n = lerpf(lerpf(h00, h10, sx), lerpf(h01, h11, sx), sy);
+    total += amp * n;
+    norm += amp;
+    amp *= 0.5f;
+    freq *= 2.0f;
+  }
+  return total / norm;
+}
+
+// gradient g(h & 7) of {(1,0),(-1,0),(0,1),(0,-1),(1,1),(-1,1),(1,-1),(-1,-1)} dotted with (dx, dy)
+__device__ __forceinline__ float grad_dot(uint32_t h, float dx, float dy) {
+  uint32_t id = h & 7u;
+  float gx = (id == 2u || id == 3u) ? 0.0f : ((id & 1u) ? -1.0f : 1.0f);
+  float gy = id < 2u ? 0.0f : (id < 4u ? ((id & 1u) ? -1.0f : 1.0f) : ((id & 2u) ? -1.0f : 1.0f));
+  return gx * dx + gy * dy;
+}
+
+__device__ __forceinline__ float fade5(float t) {
+  return t * t * t * (t * (t * 6.0f - 15.0f) + 10.0f);
+}
+
+__device__ float perlin_noise(float u, float v, float f0, int octaves, uint32_t seed) {
+  float total = 0.0f, norm = 0.0f, amp = 1.0f, freq = f0;
+  for (int o = 0; o < octaves; ++o) {
+    uint64_t sg = (uint64_t)(seed + (uint32_t)o) * kGolden;
+    float px = u * freq, py = v * freq;
+    float fi = floorf(px), fj = floorf(py);
+    float fx = px - fi, fy = py - fj;
+    int i = (int)fi, j = (int)fj;
+    float d00 = grad_dot(lattice_hash(i, j, sg), fx, fy);
+    float d10 = grad_dot(lattice_hash(i + 1, j, sg), fx - 1.0f, fy);
+    float d01 = grad_dot(lattice_hash(i, j + 1, sg), fx, fy - 1.0f);
+    float d11 = grad_dot(lattice_hash(i + 1, j + 1, sg), fx - 1.0f, fy - 1.0f);
+    float qx = fade5(fx), qy = fade5(fy);
+    float n = lerpf(lerpf(d00, d10, qx), lerpf(d01, d11, qx), qy);
+    total += amp * n;
+    norm += amp;
+    amp *= 0.5f;
+    freq *= 2.0f;
+  }
+  return 0.5f + 0.5f * (total / norm);
+}
+
+__device__ __forceinline__ int wrap_index(int i, uint32_t w) {
+  if ((w & (w - 1u)) == 0u) return i & (int)(w - 1u);
+  int r = i % (int)w;
+  return r < 0 ? r + (int)w : r;
+}
+
+__device__ __forceinline__ float4 texel(const uint32_t* pool, uint64_t off, uint32_t w, int i,
+                                        int j) {
+  uint32_t t = pool[off + (uint64_t)j * w + (uint32_t)i];
+  const float s = 1.0f / 255.0f;
+  return make_float4((float)(t & 0xFF) * s, (float)((t >> 8) & 0xFF) * s,
+                     (float)((t >> 16) & 0xFF) * s, (float)(t >> 24) * s);
+}
+
+__device__ __forceinline__ float4 image_texture(const ShadeArgs& a, uint32_t tex, float u,
+                                                float v) {
+  const PMC_CONST TexDesc* td = as_const(a.tex) + tex;
+  uint64_t off = td->offset;
+  uint32_t w = td->w, h = td->h;
+  float x = u * (float)w - 0.5f, y = v * (float)h - 0.5f;
+  float x0 = floorf(x), y0 = floorf(y);
+  float fx = x - x0, fy = y - y0;
+  int i0 = (int)x0, j0 = (int)y0;
+  int ia = wrap_index(i0, w), ib = wrap_index(i0 + 1, w);
+  int ja = wrap_index(j0, h), jb = wrap_index(j0 + 1, h);
+  float4 t00 = texel(a.texels, off, w, ia, ja), t10 = texel(a.texels, off, w, ib, ja);
+  float4 t01 = texel(a.texels, off, w, ia, jb), t11 = texel(a.texels, off, w, ib, jb);
+  float4 r;
+  r.x = lerpf(lerpf(t00.x, t10.x, fx), lerpf(t01.x, t11.x, fx), fy);
+  r.y = lerpf(lerpf(t00.y, t10.y, fx), lerpf(t01.y, t11.y, fx), fy);
+  r.z = lerpf(lerpf(t00.z, t10.z, fx), lerpf(t01.z, t11.z, fx), fy);
+  r.w = lerpf(lerpf(t00.w, t10.w, fx), lerpf(t01.w, t11.w, fx), fy);
+  return r;
+}
+
+__device__ __forceinline__ float4 color_ramp(const PMC_CONST float* p, float fac) {
+  // p: 8 positions then 8 RGBA stops
+  const PMC_CONST float* c = p + 8;
+  if (!(fac > p[0])) return make_float4(c[0], c[1], c[2], c[3]);
+  if (fac >= p[7]) return make_float4(c[28], c[29], c[30], c[31]);
+  int k = 0;
+#pragma unroll
+  for (int q = 1; q < 7; ++q) k += (fac >= p[q]) ? 1 : 0;   // positions ascending
+  float pk = p[k], pk1 = p[k + 1];
+  float t = (fac - pk) / (pk1 - pk);
+  const PMC_CONST float* a = c + 4 * k;
+  const PMC_CONST float* b = c + 4 * (k + 1);
+  return make_float4(lerpf(a[0], b[0], t), lerpf(a[1], b[1], t), lerpf(a[2], b[2], t),
+                     lerpf(a[3], b[3], t));
+}
+
+__device__ __forceinline__ float3 normalize_or(float3 v, float3 fb) {
+  float l = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+  if (!(l >= 1e-12f)) return fb;
+  return make_float3(v.x / l, v.y / l, v.z / l);
+}
+
+// Orthonormal basis after Duff et al. 2017 (JCGT 6(1)); sign = +1 when n.z >= 0.
+__device__ __forceinline__ float3 normal_map(float3 c, float strength, float3 n) {
+  float3 t = make_float3(2.0f * c.x - 1.0f, 2.0f * c.y - 1.0f, 2.0f * c.z - 1.0f);
+  float sign = n.z >= 0.0f ? 1.0f : -1.0f;
+  float a = -1.0f / (sign + n.z);
+  float b = n.x * n.y * a;
+  float3 T = make_float3(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+  float3 B = make_float3(b, sign + n.y * n.y * a, -n.y);
+  float3 v = make_float3(t.x * T.x + t.y * B.x + t.z * n.x, t.x * T.y + t.y * B.y + t.z * n.y,
+                         t.x * T.z + t.y * B.z + t.z * n.z);
+  v = normalize_or(v, n);
+  float3 m = make_float3(n.x + strength * (v.x - n.x), n.y + strength * (v.y - n.y),
+                         n.z + strength * (v.z - n.z));
+  return normalize_or(m, n);
+}
+
+// ----------------------------------------------------------- cache access ---
+
+struct Counters {
+  uint32_t v[kNumCounters];
+};
+
+__device__ __forceinline__ uint64_t* entry_word(const ShadeArgs& a, uint32_t cell, uint32_t i) {
+  return a.table + ((uint64_t)cell * a.n_entries + i) * a.entry_words;
+}
+
+// Lookup: first entry whose hash equals hash2 is a hit; an empty entry or the
+// end of the cell is a miss.  All entries of a chunk of 8 are loaded at once.
+__device__ __forceinline__ bool cache_lookup(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
+                                             uint32_t* code) {
+  for (uint32_t base = 0; base < a.n_entries; base += 8) {
+    uint64_t w[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      w[j] = (base + j < a.n_entries) ? *entry_word(a, cell, base + j) : 0ull;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (base + j >= a.n_entries) return false;
+      if ((uint32_t)(w[j] >> 32) == hash2) {
+        *code = (uint32_t)w[j];
+        return true;
+      }
+      if (w[j] == 0ull) return false;
+    }
+  }
+  return false;
+}
+
+__device__ __forceinline__ uint64_t load_relaxed(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Algorithm 1: find the first entry holding hash2 or empty, then CAS(0 -> new).
+// OVERWRITE: a full cell evicts the entry with the smallest stamp, if older
+// than this frame.  Counter slots: CNT_INSERTS, CNT_CAS_FAIL, CNT_PRESENT,
+// CNT_FULL, CNT_OVERWRITES.
+__device__ __noinline__ void cache_insert(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
+                                          uint32_t code, Counters& cnt) {
+  const uint64_t neu = ((uint64_t)hash2 << 32) | code;
+  int idx = -1;
+  for (uint32_t i = 0; i < a.n_entries; ++i) {
+    uint64_t cur = load_relaxed(entry_word(a, cell, i));
+    uint32_t h = (uint32_t)(cur >> 32);
+    if (h == hash2 || h == 0u) {
+      idx = (int)i;
+      break;
+    }
+  }
+  if (idx >= 0) {
+    uint64_t* p = entry_word(a, cell, (uint32_t)idx);
+    uint64_t expected = 0ull;
+    bool ok = __hip_atomic_compare_exchange_strong(p, &expected, neu, __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ok) {
+      if (a.entry_words == 2) ((uint32_t*)p)[2] = a.frame + 1u;
+      cnt.v[CNT_INSERTS]++;
+    } else if ((uint32_t)(expected >> 32) == hash2) {
+      cnt.v[CNT_PRESENT]++;
+    } else {
+      cnt.v[CNT_CAS_FAIL]++;
+    }
+    return;
+  }
+  if (a.policy == PMC_POLICY_OVERWRITE && a.entry_words == 2) {
+    uint32_t best = 0xFFFFFFFFu;
+    int victim = -1;
+    for (uint32_t i = 0; i < a.n_entries; ++i) {
+      uint32_t* sp = (uint32_t*)entry_word(a, cell, i) + 2;
+      uint32_t st = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (st < best) {
+        best = st;
+        victim = (int)i;
+      }
+    }
+    if (victim >= 0 && best < a.frame + 1u) {
+      uint64_t* p = entry_word(a, cell, (uint32_t)victim);
+      uint64_t observed = load_relaxed(p);
+      if ((uint32_t)(observed >> 32) != hash2 &&
+          __hip_atomic_compare_exchange_strong(p, &observed, neu, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ((uint32_t*)p)[2] = a.frame + 1u;
+        cnt.v[CNT_OVERWRITES]++;
+        return;
+      }
+      cnt.v[CNT_CAS_FAIL]++;
+      return;
+    }
+  }
+  cnt.v[CNT_FULL]++;
+}
+
+// Snapshot mode: the insert becomes a candidate {cell, seq, code, hash2}
+// applied after the batch in seq order.  One atomic per wave reserves slots.
+__device__ __forceinline__ void append_candidate(const ShadeArgs& a, bool want, uint32_t cell,
+                                                 uint32_t hash2, uint32_t code, uint32_t seq,
+                                                 Counters& cnt) {
+  uint64_t m = __ballot(want);
+  if (m == 0ull) return;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(a.cand_count, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (want) {
+    uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
+    if (pos < a.cand_cap) a.cand[pos] = make_uint4(cell, seq, code, hash2);
+    cnt.v[CNT_CANDIDATES]++;
+  }
+}
+
+// ------------------------------------------------------------- the kernel ---
+
+template <int MODE>
+__device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, uint32_t h,
+                                               const HitData& hd, const LaneRegs& R,
+                                               Counters& cnt) {
+  const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
+  const uint32_t n_cach = H->n_cach, cbeg = H->cach_begin;
+  uint32_t miss = 0u, ins = 0u;
+
+  // 1. keys and probes (Sec. 3: look up at the cacheable node first)
+  for (uint32_t c = 0; c < n_cach; ++c) {
+    const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + c;
+    uint8_t st = 0;
+    if (MODE == PMC_MODE_UNCACHED) {
+      miss |= 1u << c;
+      st = 0;
+    } else {
+      Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.n_cells);
+      if (k.bypass) {
+        miss |= 1u << c;
+        cnt.v[CNT_BYPASSES]++;
+        st = 2;
+      } else {
+        cnt.v[CNT_PROBES]++;
+        uint32_t code;
+        if (cache_lookup(a, k.cell, k.hash2, &code)) {
+          cnt.v[CNT_CACHE_HITS]++;
+          st = 1;
+          const int r = cd->reg;
+          if (cd->otype == OT_COLOR) {
+            float3 v = rgb9e5_decode(code);
+            R.set(r, v.x); R.set(r + 1, v.y); R.set(r + 2, v.z);
+            if (a.dbg_value) {
+              float* dv = a.dbg_value + ((uint64_t)h * 8 + c) * 3;
+              dv[0] = v.x; dv[1] = v.y; dv[2] = v.z;
+            }
+          } else {
+            float v = __uint_as_float(code);
+            R.set(r, v);
+            if (a.dbg_value) a.dbg_value[((uint64_t)h * 8 + c) * 3] = v;
+          }
+        } else {
+          miss |= 1u << c;
+          ins |= 1u << c;
+        }
+      }
+    }
+    if (a.dbg_state) a.dbg_state[(uint64_t)h * 8 + c] = st;
+  }
+  if (a.dbg_state)
+    for (uint32_t c = n_cach; c < 8; ++c) a.dbg_state[(uint64_t)h * 8 + c] = 3;
+
+  // 2. interpret (Sec. 2), skipping what the lookups made unnecessary (Sec. 3)
+  const uint32_t n_instr = H->n_instr;
+  const PMC_CONST Instr* I = as_const(a.instr) + H->instr_begin;
+  cnt.v[CNT_NODES_TOTAL] += n_instr;
+  for (uint32_t i = 0; i < n_instr; ++i, ++I) {
+    const uint32_t exec = I->exec;
+    const bool need = (exec & kAlways) != 0u || (exec & miss) != 0u;
+    if (!need) continue;
+    cnt.v[CNT_NODES_EXEC]++;
+    const PMC_CONST float* K = I->k;
+    float3 o0 = make_float3(0.f, 0.f, 0.f);
+    float o1 = 0.0f;
+    switch (I->op) {
+      case PMC_OP_IMAGE_TEXTURE: {
+        float4 t = image_texture(a, I->param, hd.u, hd.v);
+        o0 = make_float3(t.x, t.y, t.z);
+        o1 = t.w;
+        break;
+      }
+      case PMC_OP_VALUE_NOISE:
+        o0.x = value_noise(hd.u, hd.v, K[7], I->variant, I->param);
+        break;
+      case PMC_OP_PERLIN_NOISE:
+        o0.x = perlin_noise(hd.u, hd.v, K[7], I->variant, I->param);
+        break;
+      case PMC_OP_MIX: {
+        float t = clamp01f(read_f(I->src[0], K, R, hd));
+        float3 x = read_c(I->src[1], K, R, hd), y = read_c(I->src[2], K, R, hd);
+        o0 = make_float3(x.x + t * (y.x - x.x), x.y + t * (y.y - x.y), x.z + t * (y.z - x.z));
+        break;
+      }
+      case PMC_OP_MATH: {
+        float x = read_f(I->src[0], K, R, hd), y = read_f(I->src[1], K, R, hd), r;
+        const uint32_t v = I->variant;
+        if (v == PMC_MATH_ADD) r = x + y;
+        else if (v == PMC_MATH_MUL) r = x * y;
+        else r = x > 0.0f ? powf(x, y) : 0.0f;
+        if (I->flags & PMC_NODE_CLAMP) r = clamp01f(r);
+        o0.x = r;
+        break;
+      }
+      case PMC_OP_COLOR_RAMP: {
+        float4 t = color_ramp(as_const(a.pool) + I->param, read_f(I->src[0], K, R, hd));
+        o0 = make_float3(t.x, t.y, t.z);
+        o1 = t.w;
+        break;
+      }
+      case PMC_OP_NORMAL_MAP:
+        o0 = normal_map(read_c(I->src[0], K, R, hd), read_f(I->src[1], K, R, hd), hd.n);
+        break;
+      default:
+        break;
+    }
+    // write the outputs; a socket that was found in the cache keeps the cached value
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const uint32_t dst = I->dst[s];
+      if (dst == kNoReg) continue;
+      const uint32_t ord = I->cord[s];
+      const bool is_c = I->otype[s] != OT_FLOAT;
+      const float3 val = s == 0 ? o0 : make_float3(o1, o1, o1);
+      if (ord == kNoOrd || ((miss >> ord) & 1u)) {
+        R.set(dst, val.x);
+        if (is_c) { R.set(dst + 1, val.y); R.set(dst + 2, val.z); }
+      }
+      if (MODE != PMC_MODE_UNCACHED && ord != kNoOrd) {
+        // 3. store the computed value (Sec. 3; Algorithm 1)
+        bool want = (ins >> ord) & 1u;
+        uint32_t code = 0u, cell = 0u, hash2 = 0u;
+        if (want) {
+          bool finite = isfinite(val.x) && (!is_c || (isfinite(val.y) && isfinite(val.z)));
+          if (!finite) {
+            cnt.v[CNT_NONFINITE]++;
+            want = false;
+          } else {
+            code = is_c ? rgb9e5_encode(val.x, val.y, val.z) : __float_as_uint(val.x);
+            const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + ord;
+            Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max,
+                             a.n_cells);
+            cell = k.cell;
+            hash2 = k.hash2;
+          }
+        }
+        if (MODE == PMC_MODE_SNAPSHOT) {
+          append_candidate(a, want, cell, hash2, code, h * 32u + ord, cnt);
+        } else if (want) {
+          cache_insert(a, cell, hash2, code, cnt);
+        }
+      }
+    }
+  }
+
+  // 4. BSDF inputs
+  const PMC_CONST float* OK = H->out_k;
+  float3 base = read_c(H->out_src[0], OK, R, hd);
+  float rough = read_f(H->out_src[1], OK, R, hd);
+  float3 nrm = read_c(H->out_src[2], OK, R, hd);
+  a.out_base[(uint64_t)h * 3 + 0] = base.x;
+  a.out_base[(uint64_t)h * 3 + 1] = base.y;
+  a.out_base[(uint64_t)h * 3 + 2] = base.z;
+  a.out_rough[h] = rough;
+  a.out_normal[(uint64_t)h * 3 + 0] = nrm.x;
+  a.out_normal[(uint64_t)h * 3 + 1] = nrm.y;
+  a.out_normal[(uint64_t)h * 3 + 2] = nrm.z;
+}
+
+__device__ __forceinline__ void shade_default(const ShadeArgs& a, uint32_t h, const HitData& hd) {
+  a.out_base[(uint64_t)h * 3 + 0] = 0.8f;
+  a.out_base[(uint64_t)h * 3 + 1] = 0.8f;
+  a.out_base[(uint64_t)h * 3 + 2] = 0.8f;
+  a.out_rough[h] = 0.5f;
+  a.out_normal[(uint64_t)h * 3 + 0] = hd.n.x;
+  a.out_normal[(uint64_t)h * 3 + 1] = hd.n.y;
+  a.out_normal[(uint64_t)h * 3 + 2] = hd.n.z;
+  if (a.dbg_state)
+    for (int c = 0; c < 8; ++c) a.dbg_state[(uint64_t)h * 8 + c] = 3;
+}
+
+template <int MODE>
+__device__ __forceinline__ void shade_chunk(const ShadeArgs& a, uint32_t chunk,
+                                            const LaneRegs& R, Counters& cnt) {
+  const uint32_t idx = chunk * 64u + (uint32_t)R.lane;
+  const bool active = idx < a.n;
+  uint32_t h = 0, mat = 0xFFFFFFFFu;
+  HitData hd;
+  hd.u = hd.v = 0.0f;
+  hd.g = make_float4(0.f, 0.f, 0.f, 0.f);
+  hd.n = make_float3(0.f, 0.f, 1.f);
+  if (active) {
+    h = a.perm ? a.perm[idx] : idx;
+    mat = a.material[h];
+    float2 uv = reinterpret_cast<const float2*>(a.uv)[h];
+    hd.u = uv.x;
+    hd.v = uv.y;
+    hd.g = reinterpret_cast<const float4*>(a.duv)[h];
+    hd.n = make_float3(a.normal[(uint64_t)h * 3], a.normal[(uint64_t)h * 3 + 1],
+                       a.normal[(uint64_t)h * 3 + 2]);
+    cnt.v[CNT_HITS]++;
+  }
+  uint64_t pending = __ballot(active);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t m = __builtin_amdgcn_readlane(mat, leader);
+    const bool mine = active && mat == m;
+    pending &= ~__ballot(mine);
+    if (mine) {
+      if (m < a.n_mats) {
+        shade_material<MODE>(a, m, h, hd, R, cnt);
+      } else {
+        cnt.v[CNT_INVALID]++;
+        shade_default(a, h, hd);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt) {
+  if (!a.stat_slots) return;
+  unsigned long long* slot = a.stat_slots + (uint64_t)(blockIdx.x % kStatSlots) * kNumCounters;
+#pragma unroll
+  for (int q = 0; q < kNumCounters; ++q) {
+    uint32_t s = wave_sum(cnt.v[q]);
+    if (lane_id() == 0 && s) atomicAdd(slot + q, (unsigned long long)s);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
+  extern __shared__ float lds[];
+  LaneRegs R{lds + (threadIdx.x >> 6) * a.n_regs * 64, lane_id()};
+  Counters cnt;
+#pragma unroll
+  for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
+  const uint32_t chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (chunk * 64u < a.n) shade_chunk<MODE>(a, chunk, R, cnt);
+  flush_counters(a, cnt);
+}
+
+// Persistent variant: every wave pops `chunk_waves` chunks at a time from a
+// queue counter until the batch is exhausted (the exit test is reached by
+// every wave because the counter only grows).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
+  extern __shared__ float lds[];
+  LaneRegs R{lds + (threadIdx.x >> 6) * a.n_regs * 64, lane_id()};
+  Counters cnt;
+#pragma unroll
+  for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
+  const uint32_t n_chunks = (a.n + 63u) / 64u;
+  for (;;) {
+    uint32_t first = 0;
+    if (lane_id() == 0) first = atomicAdd(a.queue, a.chunk_waves);
+    first = __builtin_amdgcn_readfirstlane(first);
+    if (first >= n_chunks) break;
+    const uint32_t last = min(first + a.chunk_waves, n_chunks);
+    for (uint32_t c = first; c < last; ++c) shade_chunk<MODE>(a, c, R, cnt);
+  }
+  flush_counters(a, cnt);
+}
+
+// ---------------------------------------------------------- host launchers ---
+
+hipError_t launch_shade(const ShadeArgs& a, bool persistent, uint32_t grid, hipStream_t s) {
+  const size_t lds = (size_t)4 * a.n_regs * 64 * sizeof(float);
+  const uint32_t mode = a.mode;
+  if (persistent) {
+    if (mode == PMC_MODE_UNCACHED)
+      hipLaunchKernelGGL(k_shade_persistent<PMC_MODE_UNCACHED>, dim3(grid), dim3(256), lds, s, a);
+    else if (mode == PMC_MODE_CACHED)
+      hipLaunchKernelGGL(k_shade_persistent<PMC_MODE_CACHED>, dim3(grid), dim3(256), lds, s, a);
+    else
+      hipLaunchKernelGGL(k_shade_persistent<PMC_MODE_SNAPSHOT>, dim3(grid), dim3(256), lds, s, a);
+  } else {
+    if (mode == PMC_MODE_UNCACHED)
+      hipLaunchKernelGGL(k_shade_flat<PMC_MODE_UNCACHED>, dim3(grid), dim3(256), lds, s, a);
+    else if (mode == PMC_MODE_CACHED)
+      hipLaunchKernelGGL(k_shade_flat<PMC_MODE_CACHED>, dim3(grid), dim3(256), lds, s, a);
+    else
+      hipLaunchKernelGGL(k_shade_flat<PMC_MODE_SNAPSHOT>, dim3(grid), dim3(256), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- debug key export ---
+
+__global__ void k_debug_keys(ShadeArgs a, pmc_key_record* out) {
+  const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= a.n) return;
+  const uint32_t m = a.material[h];
+  float2 uv = reinterpret_cast<const float2*>(a.uv)[h];
+  float4 g = reinterpret_cast<const float4*>(a.duv)[h];
+  uint32_t n_cach = m < a.n_mats ? a.hdr[m].n_cach : 0u;
+  for (uint32_t c = 0; c < 8; ++c) {
+    pmc_key_record r;
+    r.cell = 0; r.hash2 = 0; r.level = 0; r.tx = 0; r.ty = 0; r.bypass = 2;
+    if (c < n_cach) {
+      const CachDesc cd = a.cach[a.hdr[m].cach_begin + c];
+      Key k = make_key(m, cd.node_sock, uv.x, uv.y, g, a.level_bias, a.level_max, a.n_cells);
+      r.bypass = k.bypass ? 1u : 0u;
+      if (!k.bypass) {
+        r.cell = k.cell; r.hash2 = k.hash2; r.level = k.level; r.tx = k.tx; r.ty = k.ty;
+      }
+    }
+    out[(uint64_t)h * 8 + c] = r;
+  }
+}
+
+hipError_t launch_debug_keys(const ShadeArgs& a, pmc_key_record* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_debug_keys, dim3((a.n + 255) / 256), dim3(256), 0, s, a, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- Algorithm 1, raw surface ---
+
+__global__ void k_insert_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1,
+                             const uint32_t* enc, uint64_t n) {
+  Counters cnt;
+#pragma unroll
+  for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    uint32_t cell, hash2;
+    raw_hash(k0[i], k1[i], a.n_cells, &cell, &hash2);
+    cache_insert(a, cell, hash2, enc[i], cnt);
+  }
+  flush_counters(a, cnt);
+}
+
+__global__ void k_lookup_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1, uint64_t n,
+                             uint32_t* enc_out, uint8_t* hit) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t cell, hash2, code = 0;
+  raw_hash(k0[i], k1[i], a.n_cells, &cell, &hash2);
+  bool f = cache_lookup(a, cell, hash2, &code);
+  hit[i] = f ? 1 : 0;
+  enc_out[i] = f ? code : 0u;
+}
+
+hipError_t launch_insert_raw(const ShadeArgs& a, const uint64_t* k0, const uint64_t* k1,
+                             const uint32_t* enc, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_insert_raw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, k0, k1,
+                     enc, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookup_raw(const ShadeArgs& a, const uint64_t* k0, const uint64_t* k1,
+                             uint64_t n, uint32_t* enc_out, uint8_t* hit, hipStream_t s) {
+  hipLaunchKernelGGL(k_lookup_raw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, k0, k1,
+                     n, enc_out, hit);
+  return hipGetLastError();
+}
+
+}  // namespace pmc

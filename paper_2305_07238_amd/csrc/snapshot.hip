@@ -1,0 +1,192 @@
+// snapshot.hip - deterministic application of a batch's insert candidates.
+//
+// In snapshot mode every lookup of a batch sees the table as it was before the
+// batch; each miss leaves a candidate {cell, seq = hit * 32 + ordinal, code,
+// hash2}.  Applying the candidates one after another in ascending seq with
+// Algorithm 1 gives a unique table.  Cells are independent, so the candidates
+// are grouped by cell (count -> scan -> scatter) and one thread per cell
+// applies its own candidates in seq order.
+#include "device_common.h"
+#include "shade.h"
+
+namespace pmc {
+
+constexpr uint32_t kScanThreads = 256;
+constexpr uint32_t kScanItems = 16;
+constexpr uint32_t kScanTile = kScanThreads * kScanItems;   // cells per scan block
+
+uint32_t snapshot_scan_blocks(uint32_t n_cells) { return (n_cells + kScanTile - 1) / kScanTile; }
+
+__global__ __launch_bounds__(256) void k_cand_count(SnapshotArgs a) {
+  const uint32_t n = min(*a.cand_count, a.cand_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    atomicAdd(&a.cell_count[a.cand[i].x], 1u);
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  // 256 threads = 4 waves
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  uint32_t wbase = 0, all = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (k < w) wbase += sh[k];
+    all += sh[k];
+  }
+  __syncthreads();
+  *total = all;
+  return wbase + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_up(const uint32_t* cnt, uint32_t n,
+                                                 uint32_t* block_sums) {
+  __shared__ uint32_t sh[4];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t s = 0;
+  for (uint32_t k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += cnt[base + k];
+  uint32_t total;
+  block_excl_scan(s, sh, &total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* block_sums, uint32_t nb) {
+  __shared__ uint32_t sh[4];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < nb; b0 += 256) {
+    uint32_t i = b0 + threadIdx.x;
+    uint32_t v = i < nb ? block_sums[i] : 0u;
+    uint32_t total;
+    uint32_t ex = block_excl_scan(v, sh, &total);
+    if (i < nb) block_sums[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += total;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* cnt, uint32_t n,
+                                                   const uint32_t* block_sums, uint32_t* start,
+                                                   uint32_t* cursor) {
+  __shared__ uint32_t sh[4];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? cnt[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_sums[blockIdx.x] + block_excl_scan(s, sh, &total);
+#pragma unroll
+  for (uint32_t k = 0; k < kScanItems; ++k) {
+    if (base + k < n) {
+      start[base + k] = run;
+      cursor[base + k] = run;
+    }
+    run += v[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cand_scatter(SnapshotArgs a) {
+  const uint32_t n = min(*a.cand_count, a.cand_cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint4 c = a.cand[i];
+    uint32_t pos = atomicAdd(&a.cell_cursor[c.x], 1u);
+    a.sorted[pos] = c;
+  }
+}
+
+// One thread per cell: Algorithm 1 applied sequentially to the cell's candidates
+// in ascending seq; stamps = frame + 1.  Clears the cell's count for the next batch.
+__global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
+  uint32_t c_ins = 0, c_present = 0, c_full = 0, c_over = 0;
+  const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell < a.n_cells) {
+    const uint32_t n = a.cell_count[cell];
+    if (n) {
+      a.cell_count[cell] = 0u;
+      const uint32_t base = a.cell_start[cell];
+      uint64_t* w0 = a.table + (uint64_t)cell * a.n_entries * a.entry_words;
+      const uint32_t stamp = a.frame + 1u;
+      int64_t last = -1;
+      for (uint32_t step = 0; step < n; ++step) {
+        // next candidate in seq order (seqs are distinct)
+        uint32_t best = 0xFFFFFFFFu, bi = 0;
+        for (uint32_t j = 0; j < n; ++j) {
+          uint32_t sq = a.sorted[base + j].y;
+          if ((int64_t)sq > last && sq <= best) { best = sq; bi = j; }
+        }
+        last = best;
+        const uint4 c = a.sorted[base + bi];
+        const uint32_t hash2 = c.w;
+        const uint64_t neu = ((uint64_t)hash2 << 32) | c.z;
+        int idx = -1;
+        for (uint32_t i = 0; i < a.n_entries; ++i) {
+          uint32_t h = (uint32_t)(w0[(uint64_t)i * a.entry_words] >> 32);
+          if (h == hash2 || h == 0u) { idx = (int)i; break; }
+        }
+        if (idx >= 0) {
+          uint64_t* p = w0 + (uint64_t)idx * a.entry_words;
+          if (*p == 0ull) {
+            *p = neu;
+            if (a.entry_words == 2) ((uint32_t*)p)[2] = stamp;
+            c_ins++;
+          } else {
+            c_present++;
+          }
+        } else if (a.policy == PMC_POLICY_OVERWRITE && a.entry_words == 2) {
+          uint32_t bs = 0xFFFFFFFFu;
+          int victim = -1;
+          for (uint32_t i = 0; i < a.n_entries; ++i) {
+            uint32_t st = ((uint32_t*)(w0 + (uint64_t)i * 2))[2];
+            if (st < bs) { bs = st; victim = (int)i; }
+          }
+          if (victim >= 0 && bs < stamp) {
+            uint64_t* p = w0 + (uint64_t)victim * 2;
+            *p = neu;
+            ((uint32_t*)p)[2] = stamp;
+            c_over++;
+          } else {
+            c_full++;
+          }
+        } else {
+          c_full++;
+        }
+      }
+    }
+  }
+  if (a.stat_slots) {
+    unsigned long long* slot = a.stat_slots + (uint64_t)(blockIdx.x % kStatSlots) * kStatStride;
+    uint32_t v[4] = {wave_sum(c_ins), wave_sum(c_present), wave_sum(c_full), wave_sum(c_over)};
+    const int q[4] = {CNT_INSERTS, CNT_PRESENT, CNT_FULL, CNT_OVERWRITES};
+    if (lane_id() == 0)
+      for (int k = 0; k < 4; ++k)
+        if (v[k]) atomicAdd(slot + q[k], (unsigned long long)v[k]);
+  }
+}
+
+hipError_t launch_snapshot_apply(const SnapshotArgs& a, hipStream_t s) {
+  const unsigned cgrid = 2048;
+  hipLaunchKernelGGL(k_cand_count, dim3(cgrid), dim3(256), 0, s, a);
+  const uint32_t nb = snapshot_scan_blocks(a.n_cells);
+  hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(kScanThreads), 0, s, a.cell_count, a.n_cells,
+                     a.block_sums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, a.block_sums, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, a.cell_count, a.n_cells,
+                     a.block_sums, a.cell_start, a.cell_cursor);
+  hipLaunchKernelGGL(k_cand_scatter, dim3(cgrid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_cell_apply, dim3((a.n_cells + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace pmc

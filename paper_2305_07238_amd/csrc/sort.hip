@@ -1,0 +1,105 @@
+// sort.hip - group the hits of a batch by material so that every wave runs a
+// single program (histogram -> scan in longest-program-first order -> scatter).
+// Within a material the original order is kept inside each 64-hit wave; the
+// order of waves is the order their atomics land.  Hits whose material id is
+// out of range go to the last bucket.
+#include "device_common.h"
+#include "shade.h"
+
+namespace pmc {
+
+constexpr uint32_t kLdsHistMax = 16384;   // buckets histogrammed in LDS (64 KiB)
+
+__global__ __launch_bounds__(256) void k_hist(const uint32_t* material, uint32_t n,
+                                              uint32_t n_mats, uint32_t* counts) {
+  extern __shared__ uint32_t hist[];
+  const uint32_t nb = n_mats + 1;
+  const bool use_lds = nb <= kLdsHistMax;
+  if (use_lds)
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint32_t m = material[i];
+    uint32_t b = m < n_mats ? m : n_mats;
+    if (use_lds) atomicAdd(&hist[b], 1u);
+    else atomicAdd(&counts[b], 1u);
+  }
+  __syncthreads();
+  if (use_lds)
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
+      if (hist[b]) atomicAdd(&counts[b], hist[b]);
+}
+
+// One block: exclusive scan of the bucket counts in rank order (materials by
+// decreasing program length, invalid bucket last) -> cursor[bucket].
+__global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* counts, uint32_t n_mats,
+                                                      const uint32_t* lpt, uint32_t* cursor,
+                                                      uint32_t* reset_a, uint32_t* reset_b) {
+  __shared__ uint32_t part[1024];
+  const uint32_t nb = n_mats + 1;
+  const uint32_t per = (nb + blockDim.x - 1) / blockDim.x;
+  const uint32_t r0 = threadIdx.x * per;
+  uint32_t local = 0;
+  for (uint32_t r = r0; r < r0 + per && r < nb; ++r) local += counts[r < n_mats ? lpt[r] : n_mats];
+  part[threadIdx.x] = local;
+  __syncthreads();
+  for (uint32_t off = 1; off < blockDim.x; off <<= 1) {     // Hillis-Steele inclusive scan
+    uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - local;
+  for (uint32_t r = r0; r < r0 + per && r < nb; ++r) {
+    uint32_t b = r < n_mats ? lpt[r] : n_mats;
+    cursor[b] = run;
+    run += counts[b];
+  }
+  if (threadIdx.x == 0) {
+    if (reset_a) *reset_a = 0u;
+    if (reset_b) *reset_b = 0u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const uint32_t* material, uint32_t n,
+                                                 uint32_t n_mats, uint32_t* cursor,
+                                                 uint32_t* perm) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  uint32_t b = 0;
+  if (valid) {
+    uint32_t m = material[i];
+    b = m < n_mats ? m : n_mats;
+  }
+  uint64_t act = __ballot(valid);
+  while (act) {
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const uint32_t bl = __builtin_amdgcn_readlane(b, leader);
+    const uint64_t match = __ballot(valid && b == bl);
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&cursor[bl], (uint32_t)__popcll(match));
+    base = __shfl(base, leader, 64);
+    if (valid && b == bl) perm[base + (uint32_t)__popcll(match & lanemask_lt())] = i;
+    act &= ~match;
+  }
+}
+
+hipError_t launch_material_sort(const uint32_t* material, uint32_t n, uint32_t n_mats,
+                                const uint32_t* lpt_order, uint32_t* counts, uint32_t* cursor,
+                                uint32_t* perm, uint32_t* reset_a, uint32_t* reset_b,
+                                hipStream_t s) {
+  const uint32_t nb = n_mats + 1;
+  hipError_t e = launch_fill_u32(counts, 0u, nb, s);
+  if (e != hipSuccess) return e;
+  uint32_t blocks = (n + 4095) / 4096;
+  blocks = blocks < 1024 ? (blocks ? blocks : 1) : 1024;
+  size_t lds = nb <= kLdsHistMax ? nb * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL(k_hist, dim3(blocks), dim3(256), lds, s, material, n, n_mats, counts);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, counts, n_mats, lpt_order, cursor,
+                     reset_a, reset_b);
+  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, material, n, n_mats,
+                     cursor, perm);
+  return hipGetLastError();
+}
+
+}  // namespace pmc

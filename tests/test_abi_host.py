@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI: exports, struct layouts, and the graph
+compiler (host-only context, no GPU) against the oracle's independent
+cacheable marking."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import graph
+from paper_2305_07238_amd import binding as B
+from paper_2305_07238_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pmc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmc_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(B.lib, n), n
+        assert n in B.EXPORTED, f"binding lacks {n}"
+
+
+def test_struct_layouts_match_the_header():
+    assert B.pmc_abi_version() == 1
+    for i, st in enumerate([B.pmc_node_desc, B.pmc_input, B.pmc_texture_desc, B.pmc_compile_opts,
+                            B.pmc_material_info, B.pmc_cache_params, B.pmc_shade_params,
+                            B.pmc_stats, B.pmc_hits, B.pmc_bsdf_out, B.pmc_debug_out,
+                            B.pmc_key_record]):
+        assert B.pmc_abi_sizeof(i) == C.sizeof(st), st.__name__
+    assert B.pmc_abi_sizeof(99) == 0
+    assert C.sizeof(B.pmc_node_desc) == 244
+    assert C.sizeof(B.pmc_stats) == 128
+
+
+def test_host_only_context_refuses_device_work():
+    ctx = B.Context(-1)
+    with pytest.raises(B.PmcError) as e:
+        ctx.set_textures([np.zeros((4, 4, 4), np.uint8)])
+    assert e.value.code == B.PMC_ERR_STATE
+    ctx.close()
+
+
+def _compile(mats, **kw):
+    ctx = B.Context(-1)
+    ctx.compile(mats, **kw)
+    return ctx
+
+
+def test_compiler_marking_matches_oracle_tiny():
+    m = scenes.tiny_material()
+    ctx = _compile([m])
+    assert ctx.cacheables(0) == graph.cacheable_outputs(m) == [(4, 0), (6, 0)]
+    info = ctx.material_info(0)
+    assert info.n_nodes == 8 and info.n_live == 8 and info.n_folded == 0
+    assert info.n_instr == 6                       # UV input and sink are not instructions
+    assert list(info.cacheable_type)[:2] == [1, 0]  # ramp colour (RGB9E5), roughness (float)
+    assert list(info.subgraph_nodes)[:2] == [4, 6]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_compiler_marking_matches_oracle_random(seed):
+    sc = scenes.mid_scene(seed=seed, width=120, height=120, frames=1, tex_size=8)
+    ctx = _compile(sc.materials)
+    for mi, m in enumerate(sc.materials):
+        assert ctx.cacheables(mi) == graph.cacheable_outputs(m), mi
+        info = ctx.material_info(mi)
+        assert info.n_regs <= 64
+        assert info.n_live == sum(graph.reachable(m))
+
+
+def test_large_networks_fit_the_register_file():
+    sc_rng = np.random.default_rng(5)
+    mats = [scenes.random_material(sc_rng, 400, 4) for _ in range(20)]
+    ctx = _compile(mats)
+    for mi in range(len(mats)):
+        assert ctx.cacheables(mi) == graph.cacheable_outputs(mats[mi])
+        assert ctx.material_info(mi).n_regs <= 64
+
+
+def test_constant_folding_and_min_subgraph_option():
+    N, L, Cn = scenes.Node, scenes.Input.link, scenes.Input.const
+    m = scenes.Material([
+        N("UV_INPUT"),
+        N("MATH", [Cn(0.25), Cn(0.5)], math_op="ADD"),                  # folds to 0.75
+        N("MATH", [L(1), Cn(2.0)], math_op="MUL", clamp=True),          # folds to 1.0
+        N("PERLIN_NOISE", [L(0)], freq=4, octaves=2, seed=3),
+        N("MIX", [L(2), L(3, 0), Cn(0.1, 0.2, 0.3)]),
+        N("BSDF_OUTPUT", [L(4), L(3), Cn()]),
+    ])
+    ctx = _compile([m])
+    info = ctx.material_info(0)
+    assert info.n_folded == 2 and info.n_instr == 2
+    assert ctx.cacheables(0) == graph.cacheable_outputs(m) == [(4, 0)]
+    ctx2 = _compile([m], no_fold=True)
+    assert ctx2.material_info(0).n_instr == 4
+    ctx3 = _compile([m], min_subgraph_nodes=1)
+    assert ctx3.cacheables(0) == graph.cacheable_outputs(m, 1) == [(3, 0), (4, 0)]
+
+
+@pytest.mark.parametrize("bad", ["cycle", "type", "no_sink", "link", "ramp"])
+def test_compiler_rejects_bad_graphs(bad):
+    N, L, Cn = scenes.Node, scenes.Input.link, scenes.Input.const
+    pos = tuple(np.linspace(0, 1, 8))
+    rgba = tuple((0.5, 0.5, 0.5, 1.0) for _ in range(8))
+    if bad == "cycle":
+        nodes = [N("MATH", [L(1), Cn(1)]), N("MATH", [L(0), Cn(1)]), N("BSDF_OUTPUT", [Cn(), L(0), Cn()])]
+    elif bad == "type":
+        nodes = [N("UV_INPUT"), N("MATH", [L(0), Cn(1)]), N("BSDF_OUTPUT", [Cn(), L(1), Cn()])]
+    elif bad == "no_sink":
+        nodes = [N("UV_INPUT")]
+    elif bad == "link":
+        nodes = [N("UV_INPUT"), N("BSDF_OUTPUT", [L(7), Cn(), Cn()])]
+    else:
+        nodes = [N("COLOR_RAMP", [Cn(0.5)], ramp_pos=pos[::-1], ramp_rgba=rgba),
+                 N("BSDF_OUTPUT", [L(0), Cn(), Cn()])]
+    ctx = B.Context(-1)
+    with pytest.raises(B.PmcError) as e:
+        ctx.compile([scenes.Material(nodes)])
+    assert e.value.code == B.PMC_ERR_GRAPH
+    assert "material 0" in str(e.value)

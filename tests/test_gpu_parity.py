@@ -1,0 +1,342 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: descriptor fields (cell, hash2, level, texel) bit-exact; node outputs
+within RTOL of the oracle; snapshot-mode tables bit-exact in hash halves,
+positions and stamps, values within one encoding step; nondeterministic
+(CAS) runs accepted by the oracle's invariant checker.
+"""
+import numpy as np
+import pytest
+
+from oracle import check, codec, graph, keys as K, render, table
+from paper_2305_07238_amd import scenes
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2305_07238_amd import binding as B  # noqa: E402
+
+
+def _oracle_keys(scene, hits, n_cells, bias=0, lmax=20):
+    """Per-(hit, ordinal) oracle key records, same layout as pmc_key_record."""
+    n = len(hits)
+    rec = np.zeros((n, 8), dtype=B.KEY_RECORD_DTYPE)
+    rec["bypass"] = 2
+    mat = hits.material.astype(np.int64)
+    for m in np.unique(mat):
+        if m >= len(scene.materials):
+            continue
+        idx = np.nonzero(mat == m)[0]
+        for c, (node, sock) in enumerate(graph.cacheable_outputs(scene.materials[m])):
+            ky = K.compute_keys(int(m), node, sock, hits.uv[idx], hits.duv[idx], n_cells, bias, lmax)
+            r = rec[idx, c]
+            r["bypass"] = ky.bypass.astype(np.uint32)
+            ok = ~ky.bypass
+            r["cell"] = np.where(ok, ky.cell, 0)
+            r["hash2"] = np.where(ok, ky.hash2, 0)
+            r["level"] = np.where(ok, ky.level, 0)
+            r["tx"] = np.where(ok, ky.tx, 0)
+            r["ty"] = np.where(ok, ky.ty, 0)
+            rec[idx, c] = r
+    return rec
+
+
+def _gpu_keys(ctx, cache, hits_np):
+    n = len(hits_np)
+    out = torch.zeros(n * 8 * 6, dtype=torch.int32, device="cuda")
+    ctx.debug_keys(cache, B.hits_to_device(hits_np), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(B.KEY_RECORD_DTYPE).reshape(n, 8)
+
+
+# ------------------------------------------------------------------ keys ------
+
+def test_keys_bit_exact_tiny_all_hits():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    cache = ctx.cache(sc.cache.n_cells)
+    h = sc.all_hits()
+    got = _gpu_keys(ctx, cache, h)
+    want = _oracle_keys(sc, h, sc.cache.n_cells)
+    assert np.array_equal(got, want)
+    assert np.all(got["level"][:, :2] == 6)
+
+
+@pytest.mark.parametrize("bias,lmax,n_cells", [(0, 20, 524288), (1, 20, 99991), (-2, 5, 1000003)])
+def test_keys_bit_exact_mid(bias, lmax, n_cells):
+    sc = G.small_mid_scene(frames=1)
+    ctx = G.setup(sc)
+    cache = ctx.cache(n_cells, 8, 16, level_bias=bias, level_max=lmax)
+    h = sc.frame(0)
+    got = _gpu_keys(ctx, cache, h)
+    want = _oracle_keys(sc, h, n_cells, bias, lmax)
+    assert np.array_equal(got, want)
+
+
+def test_keys_edge_cases():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    cache = ctx.cache(777)
+    rng = np.random.default_rng(4)
+    n = 4096 + 37
+    uv = rng.uniform(-3, 3, (n, 2)).astype(np.float32)
+    g = (rng.uniform(0, 1, (n, 4)) * np.exp2(rng.integers(-30, 6, (n, 4)))).astype(np.float32)
+    uv[:5] = [[np.nan, 0], [0, np.inf], [1e20, 0], [0.5, 0.5], [0.25, -0.75]]
+    g[3] = [0, 0, 1, 1]                     # zero footprint -> level_max
+    g[4] = [np.nan, 0, 0, 0]
+    g[5:9] = [[2 ** -6, 0, 0, 2 ** -6], [2 ** -7, 0, 0, 1], [0, 0.25, 0.25, 0], [4, 4, 4, 4]]
+    hits = scenes.Hits(np.zeros(n, np.uint32), uv, g, np.tile([0, 0, 1.0], (n, 1)).astype(np.float32))
+    got = _gpu_keys(ctx, cache, hits)
+    want = _oracle_keys(sc, hits, 777)
+    assert np.array_equal(got, want)
+    assert list(got["bypass"][:5, 0]) == [1, 1, 1, 0, 1]
+    assert got["level"][3, 0] == 20
+
+
+# ------------------------------------------------------- uncached values ------
+
+def test_uncached_tiny_matches_oracle():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    h = sc.frame(0)
+    out, _, _, st = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED)
+    ref = render.shade_uncached(sc.materials, sc.textures, h)
+    for k in ref:
+        assert G.max_rel(out[k], ref[k]) <= G.RTOL, (k, G.max_rel(out[k], ref[k]))
+    assert st["hits_shaded"] == len(h) and st["probes"] == 0
+    assert st["nodes_executed"] == st["nodes_total"] == 6 * len(h)
+
+
+@pytest.mark.parametrize("flags", [0, B.PMC_FLAG_SORT, B.PMC_FLAG_SORT | B.PMC_FLAG_PERSISTENT])
+def test_uncached_mid_matches_oracle(flags):
+    sc = G.small_mid_scene(frames=1)
+    ctx = G.setup(sc)
+    h = sc.frame(0)
+    out, _, _, st = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED, flags=flags)
+    ref = render.shade_uncached(sc.materials, sc.textures, h)
+    errs = {k: G.max_rel(out[k], ref[k]) for k in ref}
+    print("uncached mid max rel err", errs)
+    for k in ref:
+        assert errs[k] <= G.RTOL, errs
+    assert st["hits_shaded"] == len(h)
+
+
+def test_uncached_orders_are_bit_identical():
+    sc = G.small_mid_scene(frames=1)
+    ctx = G.setup(sc)
+    h = sc.frame(0)
+    a, *_ = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED, flags=0)
+    b, *_ = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED, flags=B.PMC_FLAG_SORT)
+    c, *_ = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED,
+                    flags=B.PMC_FLAG_SORT | B.PMC_FLAG_PERSISTENT, chunk_waves=3)
+    for k in a:
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
+
+
+def test_invalid_material_and_ragged_batch():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    h = sc.frame(0).take(np.arange(1000))             # not a multiple of 64
+    h.material = h.material.copy()
+    h.material[::7] = 5                                # out of range
+    out, state, _, st = G.shade(ctx, h, ctx.cache(1024), mode=B.PMC_MODE_CACHED, debug=True)
+    bad = h.material == 5
+    assert st["invalid_material"] == bad.sum()
+    assert np.all(out["base_color"][bad] == np.float32(0.8))
+    assert np.all(out["roughness"][bad] == 0.5)
+    assert np.array_equal(out["normal"][bad], h.normal[bad])
+    assert np.all(state[bad] == 3)
+    ref = render.shade_uncached(sc.materials, sc.textures, h)
+    assert G.max_rel(out["base_color"], ref["base_color"]) <= 2e-3   # cached: RGB9E5 quantised
+
+
+def test_empty_batch_is_a_no_op():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    h = sc.frame(0).take(np.arange(0))
+    out = B.alloc_outputs(0)
+    ctx.shade(B.hits_to_device(h), out, None, mode=B.PMC_MODE_UNCACHED)
+
+
+# ------------------------------------------------------------ snapshot --------
+
+def _table_parity(gpu_words, ref: table.Table, types_by_cellhash=None):
+    """Hash halves, positions and stamps bit-exact; value codes equal or within one step."""
+    gw = gpu_words[:, 0]
+    rw = ref.words()
+    assert np.array_equal(gw >> np.uint64(32), rw >> np.uint64(32))
+    if gpu_words.shape[1] == 2:
+        stamps = (gpu_words[:, 1] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        assert np.array_equal(stamps, ref.stamps())
+        assert np.all(gpu_words[:, 1] >> np.uint64(32) == 0)
+    return int(np.sum(gw != rw))
+
+
+def test_snapshot_tiny_matches_oracle_exactly():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    cache = ctx.cache(sc.cache.n_cells, 8, 16)
+    ref_t = table.Table(sc.cache.n_cells, 8, 16)
+    total_hits = 0
+    for f in range(4):
+        h = sc.frame(f)
+        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                        debug=True)
+        assert np.array_equal(state[:, :2] == 1, ref.found[:, :2])
+        assert st["cache_hits"] == ref.stats["hits"]
+        assert st["inserts"] == ref.stats.get("inserted", 0)
+        total_hits += st["cache_hits"]
+        diff = _table_parity(cache.words(), ref_t)
+        # found values: equal to the oracle's table values up to one RGB9E5 step / RTOL
+        hit = state[:, 0] == 1
+        if hit.any():
+            step = codec.rgb9e5_step(codec.rgb9e5_encode(ref.found_value[hit, 0, :]))
+            assert np.all(np.abs(value[hit, 0, :] - ref.found_value[hit, 0, :]) <= step[:, None])
+            assert G.max_rel(value[hit, 1, 0], ref.found_value[hit, 1, 0]) <= G.RTOL
+        # outputs: oracle evaluation with the GPU's found values substituted
+        subst = {}
+        for c, (node, sock) in enumerate(graph.cacheable_outputs(sc.materials[0])):
+            m = state[:, c] == 1
+            if m.any():
+                v = value[:, c, :3] if c == 0 else value[:, c, 0]
+                subst[(node, sock)] = (m, v.astype(np.float64))
+        o, _ = graph.evaluate(sc.materials[0], h.uv, h.normal, sc.textures, subst)
+        for k in o:
+            assert G.max_rel(out[k], o[k]) <= G.RTOL, k
+    assert total_hits == 24576                        # exactly 3/4 of 32768 probes
+
+
+def test_snapshot_mid_two_frames_matches_oracle():
+    sc = G.small_mid_scene(frames=2)
+    ctx = G.setup(sc)
+    n_cells = 1 << 13                                  # small table: cells overflow
+    cache = ctx.cache(n_cells, 8, 16)
+    ref_t = table.Table(n_cells, 8, 16)
+    for f in range(2):
+        h = sc.frame(f)
+        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        assert np.array_equal(state == 1, ref.found)
+        assert st["cache_hits"] == ref.stats["hits"]
+        assert st["cell_full"] == ref.stats.get("full", 0)
+        _table_parity(cache.words(), ref_t)
+    print("mid snapshot stats", st)
+
+
+# -------------------------------------------------- nondeterministic (CAS) ----
+
+@pytest.mark.parametrize("flags", [B.PMC_FLAG_SORT, B.PMC_FLAG_SORT | B.PMC_FLAG_PERSISTENT])
+def test_cached_tiny_single_launch_invariants(flags):
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    cache = ctx.cache(sc.cache.n_cells, 8, 16)
+    h = sc.all_hits()                                  # 16384 hits in one launch
+    out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, flags=flags,
+                                    debug=True)
+    log, vals = check.KeyLog(), {}
+    bad = check.check_frame(sc.materials, sc.textures, h, 0, state, value, out,
+                            sc.cache.n_cells, log, vals)
+    words = cache.words()[:, 0]
+    bad += check.table_structure(words, 8)
+    bad += check.check_entries_come_from_keys(words, 8, log)
+    assert not bad, bad[:5]
+    assert 0 <= st["cache_hits"] <= 24576
+    assert st["inserts"] == np.count_nonzero(words) <= 8192
+    print("single launch:", st)
+
+
+def test_cached_mid_frames_invariants():
+    sc = G.small_mid_scene(frames=3)
+    ctx = G.setup(sc)
+    n_cells = 1 << 14
+    cache = ctx.cache(n_cells, 8, 16)
+    log, vals = check.KeyLog(), {}
+    prev = None
+    for f in range(3):
+        h = sc.frame(f)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        bad = check.check_frame(sc.materials, sc.textures, h, f, state, value, out, n_cells,
+                                log, vals)
+        words = cache.words()[:, 0]
+        bad += check.table_structure(words, 8, prev)
+        bad += check.check_entries_come_from_keys(words, 8, log)
+        assert not bad, (f, bad[:5])
+        prev = words
+    print("mid cached frame stats", st)
+
+
+# -------------------------------------------------- Algorithm 1 surface -------
+
+def test_raw_insert_same_key_contention():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    cache = ctx.cache(64, 8, 16)
+    n = 1 << 16
+    k0 = torch.full((n,), 12345, dtype=torch.int64, device="cuda")
+    k1 = torch.full((n,), 678, dtype=torch.int64, device="cuda")
+    enc = torch.arange(n, dtype=torch.int32, device="cuda")
+    stats = B.new_stats()
+    cache.insert_raw(k0, k1, enc, frame=3, stats=stats)
+    torch.cuda.synchronize()
+    st = B.stats_dict(stats)
+    assert st["inserts"] == 1
+    assert st["present"] + st["cas_failures"] == n - 1
+    w = cache.words()
+    live = w[:, 0] != 0
+    assert live.sum() == 1
+    assert int(w[live, 1][0] & np.uint64(0xFFFFFFFF)) == 4          # stamp = frame + 1
+
+
+def test_raw_insert_and_lookup_distinct_keys():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    n_cells, ne = 4096, 8
+    cache = ctx.cache(n_cells, ne, 8)
+    n = 6000                                           # ~1.5 keys per cell: no cell overflows
+    rng = np.random.default_rng(9)
+    k0 = rng.integers(0, 2 ** 62, n, dtype=np.int64)
+    k1 = rng.integers(0, 2 ** 62, n, dtype=np.int64)
+    enc = rng.integers(0, 2 ** 31, n, dtype=np.int64).astype(np.int32)
+    t = lambda a: torch.from_numpy(a).cuda()
+    cache.insert_raw(t(k0), t(k1), t(enc))
+    enc_out = torch.zeros(n, dtype=torch.int32, device="cuda")
+    hit = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    cache.lookup_raw(t(k0), t(k1), enc_out, hit)
+    torch.cuda.synchronize()
+    assert hit.cpu().numpy().all()
+    assert np.array_equal(enc_out.cpu().numpy(), enc)
+    # the same set of words, cell by cell, as the oracle (positions depend on race order)
+    from oracle import hashing
+    hc = hashing.descriptor_hash(k0.astype(np.uint64), k1.astype(np.uint64), hashing.SEED_CELL)
+    hv = hashing.descriptor_hash(k0.astype(np.uint64), k1.astype(np.uint64), hashing.SEED_VERIFY)
+    cell = ((hc >> np.uint64(32)) % np.uint64(n_cells)).astype(np.int64)
+    h2 = (hv & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    h2[h2 == 0] = 1
+    ref = table.Table(n_cells, ne, 8)
+    for i in range(n):
+        ref.insert(int(cell[i]), int(h2[i]), int(enc[i]) & 0xFFFFFFFF)
+    gw = cache.words()[:, 0].reshape(n_cells, ne)
+    rw = ref.words().reshape(n_cells, ne)
+    assert np.array_equal(np.sort(gw, axis=1), np.sort(rw, axis=1))
+    assert not check.table_structure(gw.ravel(), ne)
+
+
+def test_cache_clear_export_import_round_trip():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    cache = ctx.cache(sc.cache.n_cells, 8, 16)
+    G.shade(ctx, sc.frame(0), cache, mode=B.PMC_MODE_SNAPSHOT, frame=0)
+    raw = cache.export()
+    assert np.count_nonzero(raw) > 0
+    cache.clear()
+    torch.cuda.synchronize()
+    assert np.count_nonzero(cache.export()) == 0
+    cache.import_(raw)
+    assert np.array_equal(cache.export(), raw)
