@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Shading samples/s and cache hit rate of progressive material caching on one MI355X.
+
+One step = one progressive render of the workload from an empty table: every
+frame (one batch of hits, one sample per pixel) goes through material sort,
+key computation, probes, the node interpreter on misses and lock-free inserts
+(the paper's GPU update, Sec. 3.3).  Inputs are generated on the host, seeded,
+and resident in HBM before timing starts.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shading samples/s + cache hit rate, cached/surrogate vs uncached, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes of the shade kernel (per unit of work)
+B_HIT_IN = 40          # material 4, uv 8, duv 16, normal 12
+B_HIT_OUT = 28         # base colour 12, roughness 4, normal 12
+B_PERM = 4             # sorted index read
+B_PROBE = 128          # one N_e x 16 B cell scanned per lookup
+B_INSERT = 16          # one entry written per miss that inserts
+B_TEXEL = 16           # four RGBA8 texels per evaluated image-texture node
+
+
+def workload(name, frames=None):
+    from paper_2305_07238_amd import scenes
+    if name == "mid":
+        sc = scenes.mid_scene(frames=frames or 16)
+        desc = ("mid: 64 materials (8-64 nodes: image texture 1024^2 RGBA8, Perlin 4 oct, mix, "
+                "math, ramp, normal map), 1920x1080 x %d progressive frames, Zipf(1.1) materials, "
+                "table 2^22 slots x 16 B (N_c=524288, N_e=8), keep-first" % sc.frames)
+    elif name == "tiny":
+        sc = scenes.tiny_scene()
+        desc = "tiny: 1 material, 8 nodes, 64x64 px x 4 spp, table 2^16 slots x 16 B"
+    elif name == "batching":
+        sc = scenes.batching_scene(frames=frames or 64)
+        desc = ("batching: 1000 materials (lognormal sizes 4-400 nodes), 1920x1080 x %d frames, "
+                "table 2^24 slots x 16 B" % sc.frames)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return sc, desc
+
+
+def cpu_baseline(sc, sample_hits=262144, frames=3):
+    """The FP64 oracle (snapshot-mode progressive shading) on a bounded sample."""
+    from oracle import render, table
+    t = table.Table(sc.cache.n_cells, sc.cache.n_entries, sc.cache.entry_bytes)
+    batches = [sc.frame(f).take(np.arange(min(sample_hits, sc.hits_per_frame)))
+               for f in range(min(frames, sc.frames))]
+    t0 = time.perf_counter()
+    render.shade_snapshot(sc.materials, sc.textures, batches, t)
+    dt = time.perf_counter() - t0
+    n = sum(len(b) for b in batches)
+    return {"value": n / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {len(batches[0])} hits (screen order) of frames 0-{len(batches)-1}, "
+                      f"snapshot-mode shading in FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--frames", type=int, default=0)
+    ap.add_argument("--mode", default="cached", choices=["cached", "snapshot", "uncached"])
+    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--uncached-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        raise SystemExit(2)
+
+    import torch
+    from paper_2305_07238_amd import binding as B
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    sc, desc = workload(args.workload, args.frames or None)
+    log(f"workload {args.workload}: {sc.frames} frames x {sc.hits_per_frame} hits")
+    frames = [sc.frame(f) for f in range(sc.frames)]
+    dev = [B.hits_to_device(h) for h in frames]
+    n_frame = sc.hits_per_frame
+    n_step = n_frame * sc.frames
+    out = B.alloc_outputs(n_frame)
+
+    ctx = B.Context(0)
+    ctx.set_textures(sc.textures)
+    ctx.compile(sc.materials)
+    cc = sc.cache
+    policy = B.PMC_POLICY_OVERWRITE if cc.policy == "OVERWRITE" else B.PMC_POLICY_FIRST
+    cache = ctx.cache(cc.n_cells, cc.n_entries, cc.entry_bytes, policy)
+    mode = {"cached": B.PMC_MODE_CACHED, "snapshot": B.PMC_MODE_SNAPSHOT,
+            "uncached": B.PMC_MODE_UNCACHED}[args.mode]
+    flags = B.PMC_FLAG_SORT | (B.PMC_FLAG_PERSISTENT if args.persistent else 0)
+    log("inputs resident; warming up")
+
+    def step(m=mode, stats=None):
+        cache.clear()
+        for f in range(sc.frames):
+            ctx.shade(dev[f], out, cache, mode=m, flags=flags, frame=f, stats=stats)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region
+    ctx.profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    prof = ctx.profile_read(reset=True)
+    ctx.profile_enable(False)
+    log(f"{ms_step:.3f} ms/step; phases {prof}")
+
+    # one more step with counters (same work) for hit rate and algorithmic bytes
+    stats = B.new_stats()
+    step(stats=stats)
+    torch.cuda.synchronize()
+    st = B.stats_dict(stats)
+    misses = st["probes"] - st["cache_hits"]
+    shade_bytes = (n_step * (B_HIT_IN + B_HIT_OUT + B_PERM) + st["probes"] * B_PROBE +
+                   misses * B_INSERT + st["texture_evals"] * B_TEXEL)
+    shade_ms, shade_launches = prof["shade"]
+    shade_ms_step = shade_ms / args.steps
+    achieved = shade_bytes / (shade_ms_step * 1e-3) / 1e9
+
+    # uncached reference on the same inputs
+    unc = None
+    if mode != B.PMC_MODE_UNCACHED and args.uncached_steps > 0:
+        step(m=B.PMC_MODE_UNCACHED)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(args.uncached_steps):
+            step(m=B.PMC_MODE_UNCACHED)
+        ev1.record()
+        torch.cuda.synchronize()
+        unc = ev0.elapsed_time(ev1) / args.uncached_steps
+        log(f"uncached {unc:.3f} ms/step")
+
+    value = n_step / (ms_step * 1e-3)
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "hits_per_step": n_step, "frames": sc.frames,
+                   "mode": args.mode + (" persistent" if args.persistent else ""),
+                   "sort": True},
+        "cache_hit_rate": st["cache_hits"] / max(st["probes"], 1),
+        "found_per_sample": st["cache_hits"] / max(st["hits_shaded"], 1),
+        "nodes_executed_fraction": st["nodes_executed"] / max(st["nodes_total"], 1),
+        "uncached_samples_per_s": (n_step / (unc * 1e-3)) if unc else None,
+        "speedup_vs_uncached": (unc / ms_step) if unc else None,
+        "stats": st,
+        "phase_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_shade_flat" if not args.persistent else "k_shade_persistent",
+                     "bytes_per_step": shade_bytes,
+                     "avg_launch_ms": shade_ms / max(shade_launches, 1)},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        res["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -242,7 +242,8 @@ typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade
     uint64_t nodes_executed;   /* lane-instructions executed by the interpreter */
     uint64_t nodes_total;      /* lane-instructions of full (uncached) evaluation */
     uint64_t invalid_material; /* hits with a material id out of range */
-    uint64_t reserved[2];
+    uint64_t texture_evals;    /* lane evaluations of image-texture nodes (4 texel loads each) */
+    uint64_t reserved;
 } pmc_stats;
 
 /* Shade one batch (one progressive pass).  cache NULL or mode UNCACHED:
@@ -274,6 +275,21 @@ pmc_status pmc_cache_insert_raw(pmc_cache* cache, const uint64_t* k0, const uint
 /* Lookup of raw descriptors: hit[i] = 1 and enc_out[i] = code when found. */
 pmc_status pmc_cache_lookup_raw(pmc_cache* cache, const uint64_t* k0, const uint64_t* k1,
                                 uint64_t n, uint32_t* enc_out, uint8_t* hit, void* stream);
+
+/* ------------------------------------------------------------- profiling */
+
+/* Phase timing with HIP events recorded on the stream of each pmc_shade call,
+ * around the launches of each phase.  Phases: 0 material sort, 1 shade
+ * kernel, 2 snapshot apply, 3 statistics reduction. */
+typedef struct pmc_profile {
+    double ms[4];              /* accumulated milliseconds per phase */
+    uint64_t launches[4];      /* calls that recorded the phase */
+} pmc_profile;
+/* Start (on != 0) or stop recording.  Starting discards earlier records. */
+pmc_status pmc_profile_enable(pmc_ctx* ctx, int on);
+/* Wait for every recorded event, sum the phase times into *out, and, when
+ * reset != 0, discard the records. */
+pmc_status pmc_profile_read(pmc_ctx* ctx, pmc_profile* out, int reset);
 
 #ifdef __cplusplus
 }

@@ -91,11 +91,18 @@ class pmc_shade_params(C.Structure):
 
 STAT_FIELDS = ("hits_shaded", "probes", "cache_hits", "bypasses", "inserts", "cas_failures",
                "present", "cell_full", "overwrites", "nonfinite", "candidates",
-               "nodes_executed", "nodes_total", "invalid_material")
+               "nodes_executed", "nodes_total", "invalid_material", "texture_evals")
 
 
 class pmc_stats(C.Structure):
-    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64 * 2)]
+    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64)]
+
+
+class pmc_profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_uint64 * 4)]
+
+
+PROFILE_PHASES = ("sort", "shade", "snapshot", "stats")
 
 
 class pmc_key_record(C.Structure):
@@ -130,6 +137,8 @@ _proto = {
     "pmc_debug_keys": (_S, [_P, _P, C.POINTER(pmc_hits), _P, _P]),
     "pmc_cache_insert_raw": (_S, [_P, _P, _P, _P, C.c_uint64, C.c_uint32, _P, _P]),
     "pmc_cache_lookup_raw": (_S, [_P, _P, _P, C.c_uint64, _P, _P, _P]),
+    "pmc_profile_enable": (_S, [_P, C.c_int]),
+    "pmc_profile_read": (_S, [_P, C.POINTER(pmc_profile), C.c_int]),
 }
 for _name, (_res, _args) in _proto.items():
     _fn = getattr(lib, _name)
@@ -272,6 +281,14 @@ class Context:
             dbg = C.byref(pmc_debug_out(_ptr(debug.get("state")), _ptr(debug.get("value"))))
         self.check(pmc_shade(self.h, cache.h if cache else None, C.byref(h), C.byref(o),
                              C.byref(p), _ptr(stats), dbg, _stream_ptr(stream)))
+
+    def profile_enable(self, on: bool = True):
+        self.check(pmc_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        p = pmc_profile()
+        self.check(pmc_profile_read(self.h, C.byref(p), 1 if reset else 0))
+        return {ph: (p.ms[i], int(p.launches[i])) for i, ph in enumerate(PROFILE_PHASES)}
 
     def debug_keys(self, cache: "Cache", hits: dict, out, stream=None):
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),

@@ -34,6 +34,11 @@ struct pmc_ctx {
   uint32_t n_tex = 0;
   // workspace
   DevBuf perm, counts, cursor, misc, cand, stat_slots;
+  // phase timing: events recorded in pairs per phase
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_records;
   pmc_status fail(pmc_status code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -62,6 +67,34 @@ struct pmc_cache {
   } while (0)
 
 namespace {
+
+hipEvent_t next_event(pmc_ctx* ctx) {
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  return ctx->ev_pool[ctx->ev_used++];
+}
+
+// Records a start event on construction and an end event on finish().
+struct PhaseTimer {
+  pmc_ctx* ctx;
+  int phase;
+  hipStream_t s;
+  hipEvent_t start = nullptr;
+  PhaseTimer(pmc_ctx* c, int ph, hipStream_t st) : ctx(c), phase(ph), s(st) {
+    if (ctx->profiling && (start = next_event(ctx))) (void)hipEventRecord(start, s);
+  }
+  void finish() {
+    if (!start) return;
+    hipEvent_t end = next_event(ctx);
+    if (!end) return;
+    (void)hipEventRecord(end, s);
+    ctx->ev_records.push_back({phase, {start, end}});
+    start = nullptr;
+  }
+};
 
 void free_buf(DevBuf& b) {
   if (b.p) (void)hipFree(b.p);
@@ -170,8 +203,37 @@ void pmc_destroy(pmc_ctx* ctx) {
                       &ctx->texdesc, &ctx->perm, &ctx->counts, &ctx->cursor, &ctx->misc,
                       &ctx->cand, &ctx->stat_slots})
       free_buf(*b);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   }
   delete ctx;
+}
+
+pmc_status pmc_profile_enable(pmc_ctx* ctx, int on) {
+  if (!ctx) return PMC_ERR_INVALID;
+  if (pmc_status st = need_device(ctx)) return st;
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  ctx->profiling = on != 0;
+  ctx->ev_records.clear();
+  ctx->ev_used = 0;
+  return PMC_OK;
+}
+
+pmc_status pmc_profile_read(pmc_ctx* ctx, pmc_profile* out, int reset) {
+  if (!ctx || !out) return PMC_ERR_INVALID;
+  if (pmc_status st = need_device(ctx)) return st;
+  std::memset(out, 0, sizeof *out);
+  for (auto& r : ctx->ev_records) {
+    HIP_TRY(ctx, hipEventSynchronize(r.second.second));
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, r.second.first, r.second.second));
+    out->ms[r.first] += ms;
+    out->launches[r.first] += 1;
+  }
+  if (reset) {
+    ctx->ev_records.clear();
+    ctx->ev_used = 0;
+  }
+  return PMC_OK;
 }
 
 const char* pmc_last_error(const pmc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
@@ -415,9 +477,11 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
         (st = ensure(ctx, ctx->counts, (size_t)(n_mats + 1) * 4)) ||
         (st = ensure(ctx, ctx->cursor, (size_t)(n_mats + 1) * 4)))
       return st;
+    PhaseTimer t0(ctx, 0, s);
     HIP_TRY(ctx, launch_material_sort(hits->material, n, n_mats, (const uint32_t*)ctx->lpt.p,
                                       (uint32_t*)ctx->counts.p, (uint32_t*)ctx->cursor.p,
                                       (uint32_t*)ctx->perm.p, misc + 0, misc + 1, s));
+    t0.finish();
     a.perm = (const uint32_t*)ctx->perm.p;
   } else {
     HIP_TRY(ctx, launch_fill_u32(misc, 0u, 2, s));
@@ -455,7 +519,9 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   } else {
     grid = (n_chunks + 3) / 4;
   }
+  PhaseTimer t1(ctx, 1, s);
   HIP_TRY(ctx, launch_shade(a, persistent, grid, s));
+  t1.finish();
   if (mode == PMC_MODE_SNAPSHOT) {
     SnapshotArgs sa;
     sa.table = a.table;
@@ -473,9 +539,15 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     sa.cell_cursor = (uint32_t*)cache->cell_cursor.p;
     sa.block_sums = (uint32_t*)cache->block_sums.p;
     sa.stat_slots = a.stat_slots;
+    PhaseTimer t2(ctx, 2, s);
     HIP_TRY(ctx, launch_snapshot_apply(sa, s));
+    t2.finish();
   }
-  if (stats) HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));
+  if (stats) {
+    PhaseTimer t3(ctx, 3, s);
+    HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));
+    t3.finish();
+  }
   return PMC_OK;
 }
 

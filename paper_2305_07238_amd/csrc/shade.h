@@ -12,7 +12,7 @@ namespace pmc {
 enum {
   CNT_HITS = 0, CNT_PROBES, CNT_CACHE_HITS, CNT_BYPASSES, CNT_INSERTS, CNT_CAS_FAIL,
   CNT_PRESENT, CNT_FULL, CNT_OVERWRITES, CNT_NONFINITE, CNT_CANDIDATES, CNT_NODES_EXEC,
-  CNT_NODES_TOTAL, CNT_INVALID, kNumCounters
+  CNT_NODES_TOTAL, CNT_INVALID, CNT_TEX_EVALS, kNumCounters
 };
 constexpr int kStatSlots = 64;       // counters are spread over slots to limit atomic contention
 constexpr int kStatStride = 16;      // u64 per slot (= sizeof(pmc_stats) / 8)

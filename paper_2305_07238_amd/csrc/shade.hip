@@ -386,6 +386,7 @@ __device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, u
     float o1 = 0.0f;
     switch (I->op) {
       case PMC_OP_IMAGE_TEXTURE: {
+        cnt.v[CNT_TEX_EVALS]++;
         float4 t = image_texture(a, I->param, hd.u, hd.v);
         o0 = make_float3(t.x, t.y, t.z);
         o1 = t.w;
@@ -530,7 +531,7 @@ __device__ __forceinline__ void shade_chunk(const ShadeArgs& a, uint32_t chunk,
 
 __device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt) {
   if (!a.stat_slots) return;
-  unsigned long long* slot = a.stat_slots + (uint64_t)(blockIdx.x % kStatSlots) * kNumCounters;
+  unsigned long long* slot = a.stat_slots + (uint64_t)(blockIdx.x % kStatSlots) * kStatStride;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) {
     uint32_t s = wave_sum(cnt.v[q]);
