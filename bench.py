@@ -30,6 +30,18 @@ B_INSERT = 16          # one entry written per miss that inserts
 B_TEXEL = 16           # four RGBA8 texels per evaluated image-texture node
 
 
+def kernel_bytes(st, n_hits):
+    """Algorithmic bytes of the probe kernel and of the deferred-miss kernel (one step)."""
+    deferred = st["deferred"]
+    probe = (n_hits * (B_HIT_IN + B_PERM) + st["probes"] * B_PROBE +
+             (n_hits - deferred) * B_HIT_OUT + deferred * 4 +
+             (st["insert_attempts"] - st["insert_attempts_deferred"]) * B_INSERT +
+             (st["texture_evals"] - st["texture_evals_deferred"]) * B_TEXEL)
+    miss = (deferred * (B_HIT_IN + 4 + B_HIT_OUT) + st["probes_deferred"] * B_PROBE +
+            st["insert_attempts_deferred"] * B_INSERT + st["texture_evals_deferred"] * B_TEXEL)
+    return {"probe": probe, "miss": miss}
+
+
 def workload(name, frames=None):
     from paper_2305_07238_amd import scenes
     if name == "mid":
@@ -75,6 +87,8 @@ def main():
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uncached-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 3 times (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -83,6 +97,16 @@ def main():
 
     import torch
     from paper_2305_07238_amd import binding as B
+
+    if args.calibrate_copy:
+        n = 1 << 28                                    # 2^28 int32 = 1 GiB each way
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -134,12 +158,11 @@ def main():
     step(stats=stats)
     torch.cuda.synchronize()
     st = B.stats_dict(stats)
-    misses = st["probes"] - st["cache_hits"]
-    shade_bytes = (n_step * (B_HIT_IN + B_HIT_OUT + B_PERM) + st["probes"] * B_PROBE +
-                   misses * B_INSERT + st["texture_evals"] * B_TEXEL)
-    shade_ms, shade_launches = prof["shade"]
-    shade_ms_step = shade_ms / args.steps
-    achieved = shade_bytes / (shade_ms_step * 1e-3) / 1e9
+    kb = kernel_bytes(st, n_step)
+    probe_ms, probe_launches = prof["probe"]
+    miss_ms, miss_launches = prof["miss"]
+    achieved = kb["probe"] / (probe_ms / args.steps * 1e-3) / 1e9
+    miss_gbs = kb["miss"] / (miss_ms / args.steps * 1e-3) / 1e9 if miss_ms > 0 else None
 
     # uncached reference on the same inputs
     unc = None
@@ -173,6 +196,7 @@ def main():
                    "sort": True},
         "cache_hit_rate": st["cache_hits"] / max(st["probes"], 1),
         "found_per_sample": st["cache_hits"] / max(st["hits_shaded"], 1),
+        "deferred_fraction": st["deferred"] / max(st["hits_shaded"], 1),
         "nodes_executed_fraction": st["nodes_executed"] / max(st["nodes_total"], 1),
         "uncached_samples_per_s": (n_step / (unc * 1e-3)) if unc else None,
         "speedup_vs_uncached": (unc / ms_step) if unc else None,
@@ -180,9 +204,12 @@ def main():
         "phase_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_shade_flat" if not args.persistent else "k_shade_persistent",
-                     "bytes_per_step": shade_bytes,
-                     "avg_launch_ms": shade_ms / max(shade_launches, 1)},
+                     "kernel": ("k_shade_persistent" if args.persistent else "k_shade_flat") +
+                               "<mode, KIND_PROBE> (probe + hit program + in-place waves)",
+                     "bytes_per_launch": kb["probe"] / sc.frames,
+                     "avg_launch_ms": probe_ms / max(probe_launches, 1)},
+        "miss_kernel": {"achieved_gbs": miss_gbs, "bytes_per_launch": kb["miss"] / sc.frames,
+                        "avg_launch_ms": miss_ms / max(miss_launches, 1)},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

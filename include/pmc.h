@@ -215,7 +215,8 @@ enum pmc_mode {
 };
 enum pmc_flags {
     PMC_FLAG_SORT = 1u,        /* sort hits by material first so each wave runs one program */
-    PMC_FLAG_PERSISTENT = 2u   /* persistent waves pull work from a queue */
+    PMC_FLAG_PERSISTENT = 2u,  /* persistent waves pull work from a queue */
+    PMC_FLAG_NO_DEFER = 4u     /* evaluate misses in the wave that probed them (no compaction) */
 };
 
 typedef struct pmc_shade_params {
@@ -224,7 +225,11 @@ typedef struct pmc_shade_params {
     uint32_t frame;            /* progressive pass index (stamps = frame + 1) */
     uint32_t chunk_waves;      /* persistent: 64-hit chunks taken per queue pop; 0 = 1 */
     uint32_t blocks_per_cu;    /* persistent: resident blocks per CU; 0 = library choice */
-    uint32_t reserved[3];
+    uint32_t defer_max;        /* cached modes: when at most this many lanes of a 64-hit wave
+                                  missed, those lanes are set aside and evaluated later in
+                                  dense waves; more misses are evaluated in place.
+                                  0 = library default (48); >= 64 = always set aside */
+    uint32_t reserved[2];
 } pmc_shade_params;
 
 typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade */
@@ -243,8 +248,13 @@ typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade
     uint64_t nodes_total;      /* lane-instructions of full (uncached) evaluation */
     uint64_t invalid_material; /* hits with a material id out of range */
     uint64_t texture_evals;    /* lane evaluations of image-texture nodes (4 texel loads each) */
-    uint64_t reserved;
-} pmc_stats;
+    uint64_t deferred;         /* hits set aside by the probe kernel for dense evaluation */
+    uint64_t insert_attempts;  /* finite values offered to the table (CAS or candidate) */
+    uint64_t texture_evals_deferred;    /* texture_evals done while evaluating deferred hits */
+    uint64_t insert_attempts_deferred;  /* insert_attempts made for deferred hits */
+    uint64_t probes_deferred;  /* lookups repeated when a deferred hit is evaluated */
+    uint64_t reserved[12];
+} pmc_stats;                   /* 256 bytes */
 
 /* Shade one batch (one progressive pass).  cache NULL or mode UNCACHED:
  * plain evaluation.  stats: device pmc_stats to accumulate into (NULL ok).
@@ -279,11 +289,13 @@ pmc_status pmc_cache_lookup_raw(pmc_cache* cache, const uint64_t* k0, const uint
 /* ------------------------------------------------------------- profiling */
 
 /* Phase timing with HIP events recorded on the stream of each pmc_shade call,
- * around the launches of each phase.  Phases: 0 material sort, 1 shade
- * kernel, 2 snapshot apply, 3 statistics reduction. */
+ * around the launches of each phase.  Phases: 0 material sort, 1 probe (or
+ * full shade) kernel, 2 miss compaction (scan + gather), 3 miss evaluation
+ * kernel, 4 snapshot apply, 5 statistics reduction. */
+#define PMC_PROFILE_PHASES 6
 typedef struct pmc_profile {
-    double ms[4];              /* accumulated milliseconds per phase */
-    uint64_t launches[4];      /* calls that recorded the phase */
+    double ms[PMC_PROFILE_PHASES];          /* accumulated milliseconds per phase */
+    uint64_t launches[PMC_PROFILE_PHASES];  /* calls that recorded the phase */
 } pmc_profile;
 /* Start (on != 0) or stop recording.  Starting discards earlier records. */
 pmc_status pmc_profile_enable(pmc_ctx* ctx, int on);

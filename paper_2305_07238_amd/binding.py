@@ -30,7 +30,7 @@ MATH_OPS = {"ADD": 0, "MUL": 1, "POW": 2}
 PMC_NODE_CLAMP = 1
 PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE = 0, 1
 PMC_MODE_UNCACHED, PMC_MODE_CACHED, PMC_MODE_SNAPSHOT = 0, 1, 2
-PMC_FLAG_SORT, PMC_FLAG_PERSISTENT = 1, 2
+PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_NO_DEFER = 1, 2, 4
 MAX_CACHEABLE = 8
 
 
@@ -86,23 +86,25 @@ class pmc_debug_out(C.Structure):
 class pmc_shade_params(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("flags", C.c_uint32), ("frame", C.c_uint32),
                 ("chunk_waves", C.c_uint32), ("blocks_per_cu", C.c_uint32),
-                ("reserved", C.c_uint32 * 3)]
+                ("defer_max", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 STAT_FIELDS = ("hits_shaded", "probes", "cache_hits", "bypasses", "inserts", "cas_failures",
                "present", "cell_full", "overwrites", "nonfinite", "candidates",
-               "nodes_executed", "nodes_total", "invalid_material", "texture_evals")
+               "nodes_executed", "nodes_total", "invalid_material", "texture_evals",
+               "deferred", "insert_attempts", "texture_evals_deferred",
+               "insert_attempts_deferred", "probes_deferred")
 
 
 class pmc_stats(C.Structure):
-    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64)]
+    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64 * 12)]
+
+
+PROFILE_PHASES = ("sort", "probe", "compact", "miss", "snapshot", "stats")
 
 
 class pmc_profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_uint64 * 4)]
-
-
-PROFILE_PHASES = ("sort", "shade", "snapshot", "stats")
+    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_uint64 * 6)]
 
 
 class pmc_key_record(C.Structure):
@@ -270,12 +272,12 @@ class Context:
     def shade(self, hits: dict, out: dict, cache: Optional["Cache"] = None,
               mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, frame: int = 0,
               stats=None, debug: Optional[dict] = None, chunk_waves: int = 0,
-              blocks_per_cu: int = 0, stream=None):
+              blocks_per_cu: int = 0, defer_max: int = 0, stream=None):
         """hits: dict of torch CUDA tensors material/uv/duv/normal; out: base_color/roughness/normal."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), int(hits["material"].numel()))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
-        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu)
+        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max)
         dbg = None
         if debug is not None:
             dbg = C.byref(pmc_debug_out(_ptr(debug.get("state")), _ptr(debug.get("value"))))
@@ -368,7 +370,7 @@ def alloc_outputs(n: int, device="cuda"):
 
 def new_stats(device="cuda"):
     import torch
-    return torch.zeros(16, dtype=torch.int64, device=device)
+    return torch.zeros(32, dtype=torch.int64, device=device)
 
 
 def stats_dict(t) -> dict:

@@ -34,6 +34,8 @@ struct pmc_ctx {
   uint32_t n_tex = 0;
   // workspace
   DevBuf perm, counts, cursor, misc, cand, stat_slots;
+  DevBuf chunk_miss, chunk_off, local, list, scan_sums;
+  size_t counts_cleared = 0;   // bytes of `counts` known to be zero
   // phase timing: events recorded in pairs per phase
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -201,7 +203,8 @@ void pmc_destroy(pmc_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->texels,
                       &ctx->texdesc, &ctx->perm, &ctx->counts, &ctx->cursor, &ctx->misc,
-                      &ctx->cand, &ctx->stat_slots})
+                      &ctx->cand, &ctx->stat_slots, &ctx->chunk_miss, &ctx->chunk_off,
+                      &ctx->local, &ctx->list, &ctx->scan_sums})
       free_buf(*b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   }
@@ -437,7 +440,7 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   if (pmc_status st = check_hits(ctx, hits)) return st;
   if (!params) return ctx->fail(PMC_ERR_INVALID, "null params");
   if (params->mode > PMC_MODE_SNAPSHOT) return ctx->fail(PMC_ERR_INVALID, "unknown mode");
-  if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT))
+  if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT | PMC_FLAG_NO_DEFER))
     return ctx->fail(PMC_ERR_INVALID, "unknown flags");
   if (hits->n && (!out || !out->base_color || !out->roughness || !out->normal))
     return ctx->fail(PMC_ERR_INVALID, "null output array");
@@ -471,20 +474,29 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   if (mode != PMC_MODE_UNCACHED) fill_cache_args(cache, a);
 
   const uint32_t n_mats = a.n_mats;
+  // misc[0] probe/full queue, misc[1] candidate count, misc[2] miss queue, misc[3] miss count
   if (sort) {
     pmc_status st;
     if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
-        (st = ensure(ctx, ctx->counts, (size_t)(n_mats + 1) * 4)) ||
         (st = ensure(ctx, ctx->cursor, (size_t)(n_mats + 1) * 4)))
       return st;
+    const size_t cbytes = (size_t)(n_mats + 1) * 4;
+    if (ctx->counts.bytes < cbytes || !ctx->counts.p) {
+      if ((st = ensure(ctx, ctx->counts, cbytes))) return st;
+      ctx->counts_cleared = 0;
+    }
+    if (ctx->counts_cleared < ctx->counts.bytes) {
+      HIP_TRY(ctx, launch_fill_u32((uint32_t*)ctx->counts.p, 0u, ctx->counts.bytes / 4, s));
+      ctx->counts_cleared = ctx->counts.bytes;
+    }
     PhaseTimer t0(ctx, 0, s);
     HIP_TRY(ctx, launch_material_sort(hits->material, n, n_mats, (const uint32_t*)ctx->lpt.p,
                                       (uint32_t*)ctx->counts.p, (uint32_t*)ctx->cursor.p,
-                                      (uint32_t*)ctx->perm.p, misc + 0, misc + 1, s));
+                                      (uint32_t*)ctx->perm.p, misc, 4, s));
     t0.finish();
     a.perm = (const uint32_t*)ctx->perm.p;
   } else {
-    HIP_TRY(ctx, launch_fill_u32(misc, 0u, 2, s));
+    HIP_TRY(ctx, launch_fill_u32(misc, 0u, 4, s));
   }
   if (mode == PMC_MODE_SNAPSHOT) {
     size_t cap = (size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1);
@@ -498,30 +510,61 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     }
     if ((st = ensure(ctx, cache->cell_start, (size_t)ncell * 4)) ||
         (st = ensure(ctx, cache->cell_cursor, (size_t)ncell * 4)) ||
-        (st = ensure(ctx, cache->block_sums, (size_t)snapshot_scan_blocks(ncell) * 4 + 4)))
+        (st = ensure(ctx, cache->block_sums, (size_t)scan_blocks(ncell) * 4 + 4)))
       return st;
     a.cand = (uint4*)ctx->cand.p;
     a.cand_count = misc + 1;
     a.cand_cap = (uint32_t)cap;
   }
   const uint32_t n_chunks = (n + 63) / 64;
+  uint32_t bpc = params->blocks_per_cu;
+  if (bpc == 0) {
+    size_t lds_per_block = (size_t)4 * a.n_regs * 256;
+    bpc = (uint32_t)((160 * 1024) / (lds_per_block ? lds_per_block : 1));
+    bpc = bpc < 1 ? 1 : (bpc > 8 ? 8 : bpc);
+  }
+  const uint32_t grid_p = (uint32_t)ctx->num_cus * bpc;
   uint32_t grid;
   if (persistent) {
-    uint32_t bpc = params->blocks_per_cu;
-    if (bpc == 0) {
-      size_t lds_per_block = (size_t)4 * a.n_regs * 256;
-      bpc = (uint32_t)((160 * 1024) / (lds_per_block ? lds_per_block : 1));
-      bpc = bpc < 1 ? 1 : (bpc > 8 ? 8 : bpc);
-    }
-    grid = (uint32_t)ctx->num_cus * bpc;
     uint32_t max_useful = (n_chunks + 3) / 4;
-    if (grid > max_useful) grid = max_useful ? max_useful : 1;
+    grid = grid_p < max_useful ? grid_p : (max_useful ? max_useful : 1);
   } else {
     grid = (n_chunks + 3) / 4;
   }
-  PhaseTimer t1(ctx, 1, s);
-  HIP_TRY(ctx, launch_shade(a, persistent, grid, s));
-  t1.finish();
+  const bool defer = mode != PMC_MODE_UNCACHED && !(params->flags & PMC_FLAG_NO_DEFER);
+  if (!defer) {
+    PhaseTimer t1(ctx, 1, s);
+    HIP_TRY(ctx, launch_shade(a, KIND_FULL, persistent, grid, s));
+    t1.finish();
+  } else {
+    pmc_status st;
+    const uint32_t nsb = scan_blocks(n_chunks) + 1;
+    if ((st = ensure(ctx, ctx->chunk_miss, (size_t)n_chunks * 4)) ||
+        (st = ensure(ctx, ctx->chunk_off, (size_t)n_chunks * 4)) ||
+        (st = ensure(ctx, ctx->local, (size_t)n_chunks * 64 * 4)) ||
+        (st = ensure(ctx, ctx->list, (size_t)n * 4)) ||
+        (st = ensure(ctx, ctx->scan_sums, (size_t)nsb * 4)))
+      return st;
+    a.chunk_miss = (uint32_t*)ctx->chunk_miss.p;
+    a.local = (uint32_t*)ctx->local.p;
+    a.defer_max = params->defer_max ? params->defer_max : 48u;
+    PhaseTimer t1(ctx, 1, s);
+    HIP_TRY(ctx, launch_shade(a, KIND_PROBE, persistent, grid, s));
+    t1.finish();
+    PhaseTimer t2(ctx, 2, s);
+    HIP_TRY(ctx, launch_exclusive_scan(a.chunk_miss, n_chunks, (uint32_t*)ctx->chunk_off.p, nullptr,
+                                       (uint32_t*)ctx->scan_sums.p, misc + 3, s));
+    HIP_TRY(ctx, launch_compact(a.chunk_miss, (const uint32_t*)ctx->chunk_off.p, a.local,
+                                (uint32_t*)ctx->list.p, n_chunks, s));
+    t2.finish();
+    ShadeArgs b = a;
+    b.list = (const uint32_t*)ctx->list.p;
+    b.list_count = misc + 3;
+    b.queue = misc + 2;
+    PhaseTimer t3(ctx, 3, s);
+    HIP_TRY(ctx, launch_shade(b, KIND_MISS, true, grid_p, s));
+    t3.finish();
+  }
   if (mode == PMC_MODE_SNAPSHOT) {
     SnapshotArgs sa;
     sa.table = a.table;
@@ -539,14 +582,14 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     sa.cell_cursor = (uint32_t*)cache->cell_cursor.p;
     sa.block_sums = (uint32_t*)cache->block_sums.p;
     sa.stat_slots = a.stat_slots;
-    PhaseTimer t2(ctx, 2, s);
+    PhaseTimer t4(ctx, 4, s);
     HIP_TRY(ctx, launch_snapshot_apply(sa, s));
-    t2.finish();
+    t4.finish();
   }
   if (stats) {
-    PhaseTimer t3(ctx, 3, s);
+    PhaseTimer t5(ctx, 5, s);
     HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));
-    t3.finish();
+    t5.finish();
   }
   return PMC_OK;
 }

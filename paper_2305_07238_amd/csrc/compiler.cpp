@@ -516,6 +516,13 @@ struct MatCompiler {
       }
       P.instrs.push_back(I);
     }
+    // hit program: a lane whose lookups all hit runs only the always-needed nodes
+    h.hit_begin = uint32_t(P.instrs.size());
+    for (uint32_t q = h.instr_begin; q < h.instr_begin + h.n_instr; ++q) {
+      Instr copy = P.instrs[q];
+      if (copy.exec & kAlways) P.instrs.push_back(copy);
+    }
+    h.n_hit = uint32_t(P.instrs.size()) - h.hit_begin;
     int kofs = 0;
     for (int k = 0; k < 3; ++k) h.out_src[k] = operand(sink, k, h.out_k, &kofs);
     for (size_t c = 0; c < cach.size(); ++c) {

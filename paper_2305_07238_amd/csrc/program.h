@@ -54,16 +54,19 @@ struct Instr {              // 64 bytes, one per emitted node
 };
 static_assert(sizeof(Instr) == 64, "Instr layout");
 
-struct MatHeader {          // 64 bytes
-  uint32_t instr_begin;
+struct MatHeader {          // 128 bytes
+  uint32_t instr_begin;     // full program: every live node
   uint32_t n_instr;
   uint32_t n_regs;
   uint32_t n_cach;
   uint32_t cach_begin;
   uint32_t out_src[3];      // operands of base colour, roughness, normal
   float out_k[8];           // their constants: base k[0..2], roughness k[3]
+  uint32_t hit_begin;       // hit program: only the nodes needed when every lookup hit
+  uint32_t n_hit;           // (the instructions whose need mask has kAlways)
+  uint32_t pad[14];
 };
-static_assert(sizeof(MatHeader) == 64, "MatHeader layout");
+static_assert(sizeof(MatHeader) == 128, "MatHeader layout");
 
 struct CachDesc {           // 16 bytes, one per cacheable output
   uint32_t node_sock;       // node << 16 | socket << 8 (low byte: level)

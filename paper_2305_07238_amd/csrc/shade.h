@@ -12,10 +12,12 @@ namespace pmc {
 enum {
   CNT_HITS = 0, CNT_PROBES, CNT_CACHE_HITS, CNT_BYPASSES, CNT_INSERTS, CNT_CAS_FAIL,
   CNT_PRESENT, CNT_FULL, CNT_OVERWRITES, CNT_NONFINITE, CNT_CANDIDATES, CNT_NODES_EXEC,
-  CNT_NODES_TOTAL, CNT_INVALID, CNT_TEX_EVALS, kNumCounters
+  CNT_NODES_TOTAL, CNT_INVALID, CNT_TEX_EVALS, CNT_DEFERRED, CNT_INS_TRIED, CNT_TEX_DEFERRED,
+  CNT_INS_TRIED_DEFERRED, CNT_PROBES_DEFERRED, kNumCounters
 };
+enum { KIND_FULL = 0, KIND_PROBE = 1, KIND_MISS = 2 };   // shade kernel variants
 constexpr int kStatSlots = 64;       // counters are spread over slots to limit atomic contention
-constexpr int kStatStride = 16;      // u64 per slot (= sizeof(pmc_stats) / 8)
+constexpr int kStatStride = 32;      // u64 per slot (= sizeof(pmc_stats) / 8)
 
 struct ShadeArgs {
   // compiled program
@@ -58,9 +60,18 @@ struct ShadeArgs {
   uint8_t* dbg_state;
   float* dbg_value;
   uint32_t* queue;               // persistent work counter
+  // deferred misses (probe kernel -> compaction -> miss kernel)
+  const uint32_t* list;          // compacted deferred hits (miss kernel)
+  const uint32_t* list_count;    // their number (device)
+  uint32_t* chunk_miss;          // deferred lanes per 64-hit chunk (probe kernel)
+  uint32_t* local;               // deferred hit ids, chunk-local slices (probe kernel)
+  uint32_t defer_max;            // defer a wave's misses when at most this many lanes missed
 };
 
-hipError_t launch_shade(const ShadeArgs& a, bool persistent, uint32_t grid, hipStream_t s);
+hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,
+                        hipStream_t s);
+hipError_t launch_compact(const uint32_t* chunk_miss, const uint32_t* off, const uint32_t* local,
+                          uint32_t* list, uint32_t n_chunks, hipStream_t s);
 hipError_t launch_debug_keys(const ShadeArgs& a, pmc_key_record* out, hipStream_t s);
 hipError_t launch_insert_raw(const ShadeArgs& a, const uint64_t* k0, const uint64_t* k1,
                              const uint32_t* enc, uint64_t n, hipStream_t s);
@@ -71,11 +82,18 @@ hipError_t launch_lookup_raw(const ShadeArgs& a, const uint64_t* k0, const uint6
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t value, uint64_t n, hipStream_t s);
 hipError_t launch_stats_reduce(unsigned long long* slots, pmc_stats* out, hipStream_t s);
+// exclusive scan of n u32 -> out (and out_copy if not null); *total = sum (if not null).
+// block_sums needs scan_blocks(n) + 1 entries.
+uint32_t scan_blocks(uint32_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* out_copy,
+                                 uint32_t* block_sums, uint32_t* total, hipStream_t s);
 
 // sort.hip: material sort.  counts/cursor: n_mats + 1 entries (last = invalid ids).
+// counts must be all-zero on entry (the scan clears it again); reset[0..n_reset) is
+// zeroed after the scan (n_reset <= 1024).
 hipError_t launch_material_sort(const uint32_t* material, uint32_t n, uint32_t n_mats,
                                 const uint32_t* lpt_order, uint32_t* counts, uint32_t* cursor,
-                                uint32_t* perm, uint32_t* reset_a, uint32_t* reset_b,
+                                uint32_t* perm, uint32_t* reset, uint32_t n_reset,
                                 hipStream_t s);
 
 // snapshot.hip: apply the candidates of one batch in (hit, ordinal) order.
@@ -93,6 +111,5 @@ struct SnapshotArgs {
   unsigned long long* stat_slots;
 };
 hipError_t launch_snapshot_apply(const SnapshotArgs& a, hipStream_t s);
-uint32_t snapshot_scan_blocks(uint32_t n_cells);
 
 }  // namespace pmc

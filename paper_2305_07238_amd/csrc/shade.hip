@@ -321,32 +321,33 @@ __device__ __forceinline__ void append_candidate(const ShadeArgs& a, bool want, 
 
 // ------------------------------------------------------------- the kernel ---
 
-template <int MODE>
-__device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, uint32_t h,
-                                               const HitData& hd, const LaneRegs& R,
-                                               Counters& cnt) {
+// Probe every cacheable output of material m for this lane (Sec. 3: look up at
+// the cacheable node first).  Found values go to their registers.  Returns the
+// miss mask (bypassed outputs count as misses); *ins gets the misses that may
+// be inserted.
+template <int MODE, bool COUNT>
+__device__ __forceinline__ uint32_t probe_all(const ShadeArgs& a, uint32_t m, uint32_t h,
+                                              const HitData& hd, const LaneRegs& R,
+                                              Counters& cnt, uint32_t* ins) {
   const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
   const uint32_t n_cach = H->n_cach, cbeg = H->cach_begin;
-  uint32_t miss = 0u, ins = 0u;
-
-  // 1. keys and probes (Sec. 3: look up at the cacheable node first)
+  uint32_t miss = 0u, insm = 0u;
   for (uint32_t c = 0; c < n_cach; ++c) {
     const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + c;
     uint8_t st = 0;
     if (MODE == PMC_MODE_UNCACHED) {
       miss |= 1u << c;
-      st = 0;
     } else {
       Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.n_cells);
       if (k.bypass) {
         miss |= 1u << c;
-        cnt.v[CNT_BYPASSES]++;
+        if (COUNT) cnt.v[CNT_BYPASSES]++;
         st = 2;
       } else {
-        cnt.v[CNT_PROBES]++;
+        cnt.v[COUNT ? CNT_PROBES : CNT_PROBES_DEFERRED]++;
         uint32_t code;
         if (cache_lookup(a, k.cell, k.hash2, &code)) {
-          cnt.v[CNT_CACHE_HITS]++;
+          if (COUNT) cnt.v[CNT_CACHE_HITS]++;
           st = 1;
           const int r = cd->reg;
           if (cd->otype == OT_COLOR) {
@@ -363,7 +364,7 @@ __device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, u
           }
         } else {
           miss |= 1u << c;
-          ins |= 1u << c;
+          insm |= 1u << c;
         }
       }
     }
@@ -371,12 +372,23 @@ __device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, u
   }
   if (a.dbg_state)
     for (uint32_t c = n_cach; c < 8; ++c) a.dbg_state[(uint64_t)h * 8 + c] = 3;
+  *ins = insm;
+  return miss;
+}
 
-  // 2. interpret (Sec. 2), skipping what the lookups made unnecessary (Sec. 3)
-  const uint32_t n_instr = H->n_instr;
-  const PMC_CONST Instr* I = as_const(a.instr) + H->instr_begin;
-  cnt.v[CNT_NODES_TOTAL] += n_instr;
-  for (uint32_t i = 0; i < n_instr; ++i, ++I) {
+// Interpret instructions [first, first + count) of material m (Sec. 2).  An
+// instruction runs for a lane iff its need mask has kAlways or meets the
+// lane's misses (Sec. 3: a found value makes its sub-graph unnecessary).  A
+// cacheable output computed on a miss is encoded and stored (Algorithm 1), or
+// becomes a snapshot candidate.
+template <int MODE, bool DEF>
+__device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint32_t h,
+                                            const HitData& hd, const LaneRegs& R, Counters& cnt,
+                                            uint32_t first, uint32_t count, uint32_t miss,
+                                            uint32_t ins) {
+  const PMC_CONST Instr* I = as_const(a.instr) + first;
+  const uint32_t cbeg = (as_const(a.hdr) + m)->cach_begin;
+  for (uint32_t i = 0; i < count; ++i, ++I) {
     const uint32_t exec = I->exec;
     const bool need = (exec & kAlways) != 0u || (exec & miss) != 0u;
     if (!need) continue;
@@ -387,6 +399,7 @@ __device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, u
     switch (I->op) {
       case PMC_OP_IMAGE_TEXTURE: {
         cnt.v[CNT_TEX_EVALS]++;
+        if (DEF) cnt.v[CNT_TEX_DEFERRED]++;
         float4 t = image_texture(a, I->param, hd.u, hd.v);
         o0 = make_float3(t.x, t.y, t.z);
         o1 = t.w;
@@ -439,7 +452,6 @@ __device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, u
         if (is_c) { R.set(dst + 1, val.y); R.set(dst + 2, val.z); }
       }
       if (MODE != PMC_MODE_UNCACHED && ord != kNoOrd) {
-        // 3. store the computed value (Sec. 3; Algorithm 1)
         bool want = (ins >> ord) & 1u;
         uint32_t code = 0u, cell = 0u, hash2 = 0u;
         if (want) {
@@ -448,6 +460,8 @@ __device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, u
             cnt.v[CNT_NONFINITE]++;
             want = false;
           } else {
+            cnt.v[CNT_INS_TRIED]++;
+            if (DEF) cnt.v[CNT_INS_TRIED_DEFERRED]++;
             code = is_c ? rgb9e5_encode(val.x, val.y, val.z) : __float_as_uint(val.x);
             const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + ord;
             Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max,
@@ -464,8 +478,11 @@ __device__ __forceinline__ void shade_material(const ShadeArgs& a, uint32_t m, u
       }
     }
   }
+}
 
-  // 4. BSDF inputs
+__device__ __forceinline__ void write_outputs(const ShadeArgs& a, uint32_t m, uint32_t h,
+                                              const HitData& hd, const LaneRegs& R) {
+  const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
   const PMC_CONST float* OK = H->out_k;
   float3 base = read_c(H->out_src[0], OK, R, hd);
   float rough = read_f(H->out_src[1], OK, R, hd);
@@ -491,42 +508,121 @@ __device__ __forceinline__ void shade_default(const ShadeArgs& a, uint32_t h, co
     for (int c = 0; c < 8; ++c) a.dbg_state[(uint64_t)h * 8 + c] = 3;
 }
 
-template <int MODE>
-__device__ __forceinline__ void shade_chunk(const ShadeArgs& a, uint32_t chunk,
-                                            const LaneRegs& R, Counters& cnt) {
-  const uint32_t idx = chunk * 64u + (uint32_t)R.lane;
-  const bool active = idx < a.n;
-  uint32_t h = 0, mat = 0xFFFFFFFFu;
+// Full evaluation of this lane: probes, the whole program, outputs.  COUNT =
+// false for deferred lanes, whose lookups the probe kernel already counted.
+template <int MODE, bool COUNT>
+__device__ __forceinline__ void shade_full(const ShadeArgs& a, uint32_t m, uint32_t h,
+                                           const HitData& hd, const LaneRegs& R, Counters& cnt) {
+  const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
+  uint32_t ins = 0u;
+  uint32_t miss = probe_all<MODE, COUNT>(a, m, h, hd, R, cnt, &ins);
+  cnt.v[CNT_NODES_TOTAL] += H->n_instr;
+  run_program<MODE, !COUNT>(a, m, h, hd, R, cnt, H->instr_begin, H->n_instr, miss, ins);
+  write_outputs(a, m, h, hd, R);
+}
+
+struct LaneHit {
+  bool active;
+  uint32_t h, mat;
   HitData hd;
-  hd.u = hd.v = 0.0f;
-  hd.g = make_float4(0.f, 0.f, 0.f, 0.f);
-  hd.n = make_float3(0.f, 0.f, 1.f);
-  if (active) {
-    h = a.perm ? a.perm[idx] : idx;
-    mat = a.material[h];
+};
+
+__device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t* list,
+                                             uint32_t list_n, uint32_t chunk, Counters& cnt) {
+  LaneHit L;
+  const uint32_t idx = chunk * 64u + (uint32_t)lane_id();
+  L.active = idx < list_n;
+  L.h = 0;
+  L.mat = 0xFFFFFFFFu;
+  L.hd.u = L.hd.v = 0.0f;
+  L.hd.g = make_float4(0.f, 0.f, 0.f, 0.f);
+  L.hd.n = make_float3(0.f, 0.f, 1.f);
+  if (L.active) {
+    const uint32_t h = list ? list[idx] : idx;
+    L.h = h;
+    L.mat = a.material[h];
     float2 uv = reinterpret_cast<const float2*>(a.uv)[h];
-    hd.u = uv.x;
-    hd.v = uv.y;
-    hd.g = reinterpret_cast<const float4*>(a.duv)[h];
-    hd.n = make_float3(a.normal[(uint64_t)h * 3], a.normal[(uint64_t)h * 3 + 1],
-                       a.normal[(uint64_t)h * 3 + 2]);
-    cnt.v[CNT_HITS]++;
+    L.hd.u = uv.x;
+    L.hd.v = uv.y;
+    L.hd.g = reinterpret_cast<const float4*>(a.duv)[h];
+    L.hd.n = make_float3(a.normal[(uint64_t)h * 3], a.normal[(uint64_t)h * 3 + 1],
+                         a.normal[(uint64_t)h * 3 + 2]);
   }
-  uint64_t pending = __ballot(active);
+  return L;
+}
+
+// KIND_FULL / KIND_MISS: every lane of the chunk is evaluated completely.
+template <int MODE>
+__device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* list,
+                                           uint32_t list_n, uint32_t chunk, const LaneRegs& R,
+                                           Counters& cnt, bool count_hits) {
+  LaneHit L = load_lane(a, list, list_n, chunk, cnt);
+  if (L.active && count_hits) cnt.v[CNT_HITS]++;
+  uint64_t pending = __ballot(L.active);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
-    const uint32_t m = __builtin_amdgcn_readlane(mat, leader);
-    const bool mine = active && mat == m;
+    const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
+    const bool mine = L.active && L.mat == m;
     pending &= ~__ballot(mine);
     if (mine) {
       if (m < a.n_mats) {
-        shade_material<MODE>(a, m, h, hd, R, cnt);
+        if (count_hits) shade_full<MODE, true>(a, m, L.h, L.hd, R, cnt);
+        else shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt);
       } else {
         cnt.v[CNT_INVALID]++;
-        shade_default(a, h, hd);
+        shade_default(a, L.h, L.hd);
       }
     }
   }
+}
+
+// KIND_PROBE: probe first.  Lanes whose lookups all hit run only the hit
+// program.  When few lanes of a wave missed (<= defer_max), those lanes are
+// deferred: their hit index is written to the chunk's slice of `local` and
+// evaluated later, compacted into dense waves, by the miss kernel.  When many
+// missed, the whole wave is evaluated here.
+template <int MODE>
+__device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
+                                            Counters& cnt) {
+  LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
+  if (L.active) cnt.v[CNT_HITS]++;
+  bool deferred = false;
+  uint64_t pending = __ballot(L.active);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
+    const bool mine = L.active && L.mat == m;
+    pending &= ~__ballot(mine);
+    if (mine) {
+      if (m < a.n_mats) {
+        const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
+        uint32_t ins = 0u;
+        const uint32_t miss = probe_all<MODE, true>(a, m, L.h, L.hd, R, cnt, &ins);
+        const uint32_t d = (uint32_t)__popcll(__ballot(miss != 0u));
+        if (d > a.defer_max) {
+          cnt.v[CNT_NODES_TOTAL] += H->n_instr;
+          run_program<MODE, false>(a, m, L.h, L.hd, R, cnt, H->instr_begin, H->n_instr, miss,
+                                   ins);
+          write_outputs(a, m, L.h, L.hd, R);
+        } else if (miss != 0u) {
+          deferred = true;
+        } else {
+          cnt.v[CNT_NODES_TOTAL] += H->n_instr;
+          run_program<MODE, false>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u, 0u);
+          write_outputs(a, m, L.h, L.hd, R);
+        }
+      } else {
+        cnt.v[CNT_INVALID]++;
+        shade_default(a, L.h, L.hd);
+      }
+    }
+  }
+  const uint64_t dm = __ballot(deferred);
+  if (deferred) {
+    cnt.v[CNT_DEFERRED]++;
+    a.local[chunk * 64u + (uint32_t)__popcll(dm & lanemask_lt())] = L.h;
+  }
+  if (lane_id() == 0) a.chunk_miss[chunk] = (uint32_t)__popcll(dm);
 }
 
 __device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt) {
@@ -539,60 +635,107 @@ __device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt
   }
 }
 
-template <int MODE>
+template <int MODE, int KIND>
+__device__ __forceinline__ void do_chunk(const ShadeArgs& a, uint32_t chunk, uint32_t list_n,
+                                         const LaneRegs& R, Counters& cnt) {
+  if (KIND == KIND_PROBE) chunk_probe<MODE>(a, chunk, R, cnt);
+  else if (KIND == KIND_MISS) chunk_full<MODE>(a, a.list, list_n, chunk, R, cnt, false);
+  else chunk_full<MODE>(a, a.perm, list_n, chunk, R, cnt, true);
+}
+
+template <int KIND>
+__device__ __forceinline__ uint32_t list_length(const ShadeArgs& a) {
+  return KIND == KIND_MISS ? *a.list_count : a.n;
+}
+
+template <int MODE, int KIND>
 __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   extern __shared__ float lds[];
   LaneRegs R{lds + (threadIdx.x >> 6) * a.n_regs * 64, lane_id()};
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
+  const uint32_t list_n = list_length<KIND>(a);
   const uint32_t chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (chunk * 64u < a.n) shade_chunk<MODE>(a, chunk, R, cnt);
+  if (chunk * 64u < list_n) do_chunk<MODE, KIND>(a, chunk, list_n, R, cnt);
   flush_counters(a, cnt);
 }
 
 // Persistent variant: every wave pops `chunk_waves` chunks at a time from a
-// queue counter until the batch is exhausted (the exit test is reached by
+// queue counter until the list is exhausted (the exit test is reached by
 // every wave because the counter only grows).
-template <int MODE>
+template <int MODE, int KIND>
 __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   extern __shared__ float lds[];
   LaneRegs R{lds + (threadIdx.x >> 6) * a.n_regs * 64, lane_id()};
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
-  const uint32_t n_chunks = (a.n + 63u) / 64u;
+  const uint32_t list_n = list_length<KIND>(a);
+  const uint32_t n_chunks = (list_n + 63u) / 64u;
   for (;;) {
     uint32_t first = 0;
     if (lane_id() == 0) first = atomicAdd(a.queue, a.chunk_waves);
     first = __builtin_amdgcn_readfirstlane(first);
     if (first >= n_chunks) break;
     const uint32_t last = min(first + a.chunk_waves, n_chunks);
-    for (uint32_t c = first; c < last; ++c) shade_chunk<MODE>(a, c, R, cnt);
+    for (uint32_t c = first; c < last; ++c) do_chunk<MODE, KIND>(a, c, list_n, R, cnt);
   }
   flush_counters(a, cnt);
 }
 
+// Compaction of the deferred lanes: chunk c's deferred hits go to
+// list[off[c] ..), keeping the material-sorted order.
+__global__ __launch_bounds__(256) void k_compact(const uint32_t* chunk_miss, const uint32_t* off,
+                                                 const uint32_t* local, uint32_t* list,
+                                                 uint32_t n_chunks) {
+  const uint32_t chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (chunk >= n_chunks) return;
+  const uint32_t r = (uint32_t)lane_id();
+  if (r < chunk_miss[chunk]) list[off[chunk] + r] = local[chunk * 64u + r];
+}
+
 // ---------------------------------------------------------- host launchers ---
 
-hipError_t launch_shade(const ShadeArgs& a, bool persistent, uint32_t grid, hipStream_t s) {
-  const size_t lds = (size_t)4 * a.n_regs * 64 * sizeof(float);
+template <int KIND>
+static void launch_kind(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
+                        hipStream_t s) {
   const uint32_t mode = a.mode;
   if (persistent) {
     if (mode == PMC_MODE_UNCACHED)
-      hipLaunchKernelGGL(k_shade_persistent<PMC_MODE_UNCACHED>, dim3(grid), dim3(256), lds, s, a);
+      hipLaunchKernelGGL((k_shade_persistent<PMC_MODE_UNCACHED, KIND>), dim3(grid), dim3(256),
+                         lds, s, a);
     else if (mode == PMC_MODE_CACHED)
-      hipLaunchKernelGGL(k_shade_persistent<PMC_MODE_CACHED>, dim3(grid), dim3(256), lds, s, a);
+      hipLaunchKernelGGL((k_shade_persistent<PMC_MODE_CACHED, KIND>), dim3(grid), dim3(256), lds,
+                         s, a);
     else
-      hipLaunchKernelGGL(k_shade_persistent<PMC_MODE_SNAPSHOT>, dim3(grid), dim3(256), lds, s, a);
+      hipLaunchKernelGGL((k_shade_persistent<PMC_MODE_SNAPSHOT, KIND>), dim3(grid), dim3(256),
+                         lds, s, a);
   } else {
     if (mode == PMC_MODE_UNCACHED)
-      hipLaunchKernelGGL(k_shade_flat<PMC_MODE_UNCACHED>, dim3(grid), dim3(256), lds, s, a);
+      hipLaunchKernelGGL((k_shade_flat<PMC_MODE_UNCACHED, KIND>), dim3(grid), dim3(256), lds, s,
+                         a);
     else if (mode == PMC_MODE_CACHED)
-      hipLaunchKernelGGL(k_shade_flat<PMC_MODE_CACHED>, dim3(grid), dim3(256), lds, s, a);
+      hipLaunchKernelGGL((k_shade_flat<PMC_MODE_CACHED, KIND>), dim3(grid), dim3(256), lds, s, a);
     else
-      hipLaunchKernelGGL(k_shade_flat<PMC_MODE_SNAPSHOT>, dim3(grid), dim3(256), lds, s, a);
+      hipLaunchKernelGGL((k_shade_flat<PMC_MODE_SNAPSHOT, KIND>), dim3(grid), dim3(256), lds, s,
+                         a);
   }
+}
+
+hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,
+                        hipStream_t s) {
+  const size_t lds = (size_t)4 * a.n_regs * 64 * sizeof(float);
+  if (kind == KIND_PROBE) launch_kind<KIND_PROBE>(a, persistent, grid, lds, s);
+  else if (kind == KIND_MISS) launch_kind<KIND_MISS>(a, persistent, grid, lds, s);
+  else launch_kind<KIND_FULL>(a, persistent, grid, lds, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const uint32_t* chunk_miss, const uint32_t* off, const uint32_t* local,
+                          uint32_t* list, uint32_t n_chunks, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3((n_chunks + 3) / 4), dim3(256), 0, s, chunk_miss, off, local,
+                     list, n_chunks);
   return hipGetLastError();
 }
 

@@ -11,90 +11,10 @@
 
 namespace pmc {
 
-constexpr uint32_t kScanThreads = 256;
-constexpr uint32_t kScanItems = 16;
-constexpr uint32_t kScanTile = kScanThreads * kScanItems;   // cells per scan block
-
-uint32_t snapshot_scan_blocks(uint32_t n_cells) { return (n_cells + kScanTile - 1) / kScanTile; }
-
 __global__ __launch_bounds__(256) void k_cand_count(SnapshotArgs a) {
   const uint32_t n = min(*a.cand_count, a.cand_cap);
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     atomicAdd(&a.cell_count[a.cand[i].x], 1u);
-}
-
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  // 256 threads = 4 waves
-  const int lane = lane_id(), w = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) sh[w] = x;
-  __syncthreads();
-  uint32_t wbase = 0, all = 0;
-  for (int k = 0; k < 4; ++k) {
-    if (k < w) wbase += sh[k];
-    all += sh[k];
-  }
-  __syncthreads();
-  *total = all;
-  return wbase + x - v;
-}
-
-__global__ __launch_bounds__(256) void k_scan_up(const uint32_t* cnt, uint32_t n,
-                                                 uint32_t* block_sums) {
-  __shared__ uint32_t sh[4];
-  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  uint32_t s = 0;
-  for (uint32_t k = 0; k < kScanItems; ++k)
-    if (base + k < n) s += cnt[base + k];
-  uint32_t total;
-  block_excl_scan(s, sh, &total);
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t* block_sums, uint32_t nb) {
-  __shared__ uint32_t sh[4];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t b0 = 0; b0 < nb; b0 += 256) {
-    uint32_t i = b0 + threadIdx.x;
-    uint32_t v = i < nb ? block_sums[i] : 0u;
-    uint32_t total;
-    uint32_t ex = block_excl_scan(v, sh, &total);
-    if (i < nb) block_sums[i] = carry + ex;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += total;
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* cnt, uint32_t n,
-                                                   const uint32_t* block_sums, uint32_t* start,
-                                                   uint32_t* cursor) {
-  __shared__ uint32_t sh[4];
-  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? cnt[base + k] : 0u;
-    s += v[k];
-  }
-  uint32_t total;
-  uint32_t run = block_sums[blockIdx.x] + block_excl_scan(s, sh, &total);
-#pragma unroll
-  for (uint32_t k = 0; k < kScanItems; ++k) {
-    if (base + k < n) {
-      start[base + k] = run;
-      cursor[base + k] = run;
-    }
-    run += v[k];
-  }
 }
 
 __global__ __launch_bounds__(256) void k_cand_scatter(SnapshotArgs a) {
@@ -178,12 +98,9 @@ __global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
 hipError_t launch_snapshot_apply(const SnapshotArgs& a, hipStream_t s) {
   const unsigned cgrid = 2048;
   hipLaunchKernelGGL(k_cand_count, dim3(cgrid), dim3(256), 0, s, a);
-  const uint32_t nb = snapshot_scan_blocks(a.n_cells);
-  hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(kScanThreads), 0, s, a.cell_count, a.n_cells,
-                     a.block_sums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, a.block_sums, nb);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, a.cell_count, a.n_cells,
-                     a.block_sums, a.cell_start, a.cell_cursor);
+  hipError_t e = launch_exclusive_scan(a.cell_count, a.n_cells, a.cell_start, a.cell_cursor,
+                                       a.block_sums, nullptr, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cand_scatter, dim3(cgrid), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_cell_apply, dim3((a.n_cells + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -31,10 +31,11 @@ __global__ __launch_bounds__(256) void k_hist(const uint32_t* material, uint32_t
 }
 
 // One block: exclusive scan of the bucket counts in rank order (materials by
-// decreasing program length, invalid bucket last) -> cursor[bucket].
-__global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* counts, uint32_t n_mats,
+// decreasing program length, invalid bucket last) -> cursor[bucket].  The
+// counts are cleared for the next batch, and `reset[0 .. n_reset)` is zeroed.
+__global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* counts, uint32_t n_mats,
                                                       const uint32_t* lpt, uint32_t* cursor,
-                                                      uint32_t* reset_a, uint32_t* reset_b) {
+                                                      uint32_t* reset, uint32_t n_reset) {
   __shared__ uint32_t part[1024];
   const uint32_t nb = n_mats + 1;
   const uint32_t per = (nb + blockDim.x - 1) / blockDim.x;
@@ -54,10 +55,60 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t* counts, ui
     uint32_t b = r < n_mats ? lpt[r] : n_mats;
     cursor[b] = run;
     run += counts[b];
+    counts[b] = 0u;
   }
-  if (threadIdx.x == 0) {
-    if (reset_a) *reset_a = 0u;
-    if (reset_b) *reset_b = 0u;
+  if (threadIdx.x < n_reset) reset[threadIdx.x] = 0u;
+}
+
+// Block-aggregated scatter: a block takes kScatterTile consecutive hits, ranks
+// them per bucket in LDS (one LDS atomic per wave and bucket), reserves one
+// global range per bucket present in the tile, then writes the permutation.
+constexpr uint32_t kScatterPer = 32;
+constexpr uint32_t kScatterTile = 256 * kScatterPer;
+
+__global__ __launch_bounds__(256) void k_scatter_block(const uint32_t* material, uint32_t n,
+                                                       uint32_t n_mats, uint32_t* cursor,
+                                                       uint32_t* perm) {
+  extern __shared__ uint32_t sh[];
+  const uint32_t nb = n_mats + 1;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) sh[b] = 0u;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kScatterTile;
+  uint32_t pos[kScatterPer], bk[kScatterPer];
+#pragma unroll
+  for (uint32_t r = 0; r < kScatterPer; ++r) {
+    const uint32_t i = base + r * 256u + threadIdx.x;
+    const bool valid = i < n;
+    uint32_t b = 0;
+    if (valid) {
+      uint32_t m = material[i];
+      b = m < n_mats ? m : n_mats;
+    }
+    uint32_t p = 0;
+    uint64_t act = __ballot(valid);
+    while (act) {
+      const int leader = __ffsll((unsigned long long)act) - 1;
+      const uint32_t bl = __builtin_amdgcn_readlane(b, leader);
+      const uint64_t match = __ballot(valid && b == bl);
+      uint32_t old = 0;
+      if (lane_id() == leader) old = atomicAdd(&sh[bl], (uint32_t)__popcll(match));
+      old = __shfl(old, leader, 64);
+      if (valid && b == bl) p = old + (uint32_t)__popcll(match & lanemask_lt());
+      act &= ~match;
+    }
+    pos[r] = p;
+    bk[r] = b;
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    const uint32_t c = sh[b];
+    if (c) sh[b] = atomicAdd(&cursor[b], c);
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r = 0; r < kScatterPer; ++r) {
+    const uint32_t i = base + r * 256u + threadIdx.x;
+    if (i < n) perm[sh[bk[r]] + pos[r]] = i;
   }
 }
 
@@ -86,19 +137,23 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t* material, uint3
 
 hipError_t launch_material_sort(const uint32_t* material, uint32_t n, uint32_t n_mats,
                                 const uint32_t* lpt_order, uint32_t* counts, uint32_t* cursor,
-                                uint32_t* perm, uint32_t* reset_a, uint32_t* reset_b,
+                                uint32_t* perm, uint32_t* reset, uint32_t n_reset,
                                 hipStream_t s) {
+  // counts[] is all-zero on entry (cleared at allocation and by each scan)
   const uint32_t nb = n_mats + 1;
-  hipError_t e = launch_fill_u32(counts, 0u, nb, s);
-  if (e != hipSuccess) return e;
   uint32_t blocks = (n + 4095) / 4096;
   blocks = blocks < 1024 ? (blocks ? blocks : 1) : 1024;
-  size_t lds = nb <= kLdsHistMax ? nb * sizeof(uint32_t) : 0;
-  hipLaunchKernelGGL(k_hist, dim3(blocks), dim3(256), lds, s, material, n, n_mats, counts);
+  const bool lds_ok = nb <= kLdsHistMax;
+  hipLaunchKernelGGL(k_hist, dim3(blocks), dim3(256), lds_ok ? nb * sizeof(uint32_t) : 0, s,
+                     material, n, n_mats, counts);
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, counts, n_mats, lpt_order, cursor,
-                     reset_a, reset_b);
-  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, material, n, n_mats,
-                     cursor, perm);
+                     reset, n_reset);
+  if (lds_ok)
+    hipLaunchKernelGGL(k_scatter_block, dim3((n + kScatterTile - 1) / kScatterTile), dim3(256),
+                       nb * sizeof(uint32_t), s, material, n, n_mats, cursor, perm);
+  else
+    hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, material, n, n_mats,
+                       cursor, perm);
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ def test_struct_layouts_match_the_header():
         assert B.pmc_abi_sizeof(i) == C.sizeof(st), st.__name__
     assert B.pmc_abi_sizeof(99) == 0
     assert C.sizeof(B.pmc_node_desc) == 244
-    assert C.sizeof(B.pmc_stats) == 128
+    assert C.sizeof(B.pmc_stats) == 256
 
 
 def test_host_only_context_refuses_device_work():
