@@ -238,16 +238,56 @@ __device__ __forceinline__ bool cache_lookup(const ShadeArgs& a, uint32_t cell, 
   return false;
 }
 
+// Cooperative lookup for 128-byte cells (8 entries of 16 bytes): every lane
+// owns one cell (hash2 == 0: no lookup).  In round t the 8 lanes of group
+// g = lane / 8 read the 8 words of the cell owned by lane 8t + g, so each load
+// instruction fetches 8 whole cells and every cell line is fetched once.  The
+// first entry holding hash2 or empty decides, as in the per-lane scan.
+// Requires all 64 lanes of the wave to be active.
+__device__ __forceinline__ bool coop_lookup128(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
+                                               uint32_t* code) {
+  const int lane = lane_id();
+  const int g = lane >> 3, j = lane & 7;
+  const char* base = reinterpret_cast<const char*>(a.table);
+  bool found = false;
+  uint32_t cd = 0u;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int src = 8 * t + g;
+    const uint32_t c_src = __shfl(cell, src, 64);
+    const uint32_t h_src = __shfl(hash2, src, 64);
+    uint64_t w = 0ull;
+    if (h_src != 0u) w = *reinterpret_cast<const uint64_t*>(base + (uint64_t)c_src * 128u + j * 16);
+    const uint64_t hb = __ballot(h_src != 0u && (uint32_t)(w >> 32) == h_src);
+    const uint64_t eb = __ballot(h_src != 0u && w == 0ull);
+    // owners of round t are lanes 8t .. 8t+7; owner 8t + gg reads group gg's bits
+    const int gg = lane & 7;
+    const uint32_t hm = (uint32_t)(hb >> (8 * gg)) & 0xFFu;
+    const uint32_t em = (uint32_t)(eb >> (8 * gg)) & 0xFFu;
+    const uint32_t any = hm | em;
+    const int first = any ? __ffs(any) - 1 : 0;
+    const uint32_t v = __shfl((uint32_t)w, 8 * gg + first, 64);
+    if ((lane >> 3) == t && any && ((hm >> first) & 1u)) {
+      found = true;
+      cd = v;
+    }
+  }
+  *code = cd;
+  return found;
+}
+
 __device__ __forceinline__ uint64_t load_relaxed(uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Algorithm 1: find the first entry holding hash2 or empty, then CAS(0 -> new).
 // OVERWRITE: a full cell evicts the entry with the smallest stamp, if older
-// than this frame.  Counter slots: CNT_INSERTS, CNT_CAS_FAIL, CNT_PRESENT,
-// CNT_FULL, CNT_OVERWRITES.
-__device__ __noinline__ void cache_insert(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
-                                          uint32_t code, Counters& cnt) {
+// than this frame.  Returns the outcome (counted by the caller without
+// branches, which keeps the counters in registers).
+enum { INS_DONE = 0, INS_PRESENT = 1, INS_CAS_FAIL = 2, INS_FULL = 3, INS_OVERWRITE = 4 };
+
+__device__ __forceinline__ int cache_insert(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
+                                            uint32_t code) {
   const uint64_t neu = ((uint64_t)hash2 << 32) | code;
   int idx = -1;
   for (uint32_t i = 0; i < a.n_entries; ++i) {
@@ -263,15 +303,8 @@ __device__ __noinline__ void cache_insert(const ShadeArgs& a, uint32_t cell, uin
     uint64_t expected = 0ull;
     bool ok = __hip_atomic_compare_exchange_strong(p, &expected, neu, __ATOMIC_RELAXED,
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ok) {
-      if (a.entry_words == 2) ((uint32_t*)p)[2] = a.frame + 1u;
-      cnt.v[CNT_INSERTS]++;
-    } else if ((uint32_t)(expected >> 32) == hash2) {
-      cnt.v[CNT_PRESENT]++;
-    } else {
-      cnt.v[CNT_CAS_FAIL]++;
-    }
-    return;
+    if (ok && a.entry_words == 2) ((uint32_t*)p)[2] = a.frame + 1u;
+    return ok ? INS_DONE : ((uint32_t)(expected >> 32) == hash2 ? INS_PRESENT : INS_CAS_FAIL);
   }
   if (a.policy == PMC_POLICY_OVERWRITE && a.entry_words == 2) {
     uint32_t best = 0xFFFFFFFFu;
@@ -287,18 +320,22 @@ __device__ __noinline__ void cache_insert(const ShadeArgs& a, uint32_t cell, uin
     if (victim >= 0 && best < a.frame + 1u) {
       uint64_t* p = entry_word(a, cell, (uint32_t)victim);
       uint64_t observed = load_relaxed(p);
-      if ((uint32_t)(observed >> 32) != hash2 &&
-          __hip_atomic_compare_exchange_strong(p, &observed, neu, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        ((uint32_t*)p)[2] = a.frame + 1u;
-        cnt.v[CNT_OVERWRITES]++;
-        return;
-      }
-      cnt.v[CNT_CAS_FAIL]++;
-      return;
+      bool ok = (uint32_t)(observed >> 32) != hash2 &&
+                __hip_atomic_compare_exchange_strong(p, &observed, neu, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ok) ((uint32_t*)p)[2] = a.frame + 1u;
+      return ok ? INS_OVERWRITE : INS_CAS_FAIL;
     }
   }
-  cnt.v[CNT_FULL]++;
+  return INS_FULL;
+}
+
+__device__ __forceinline__ void count_insert(Counters& cnt, bool did, int o) {
+  cnt.v[CNT_INSERTS] += (uint32_t)(did && o == INS_DONE);
+  cnt.v[CNT_PRESENT] += (uint32_t)(did && o == INS_PRESENT);
+  cnt.v[CNT_CAS_FAIL] += (uint32_t)(did && o == INS_CAS_FAIL);
+  cnt.v[CNT_FULL] += (uint32_t)(did && o == INS_FULL);
+  cnt.v[CNT_OVERWRITES] += (uint32_t)(did && o == INS_OVERWRITE);
 }
 
 // Snapshot mode: the insert becomes a candidate {cell, seq, code, hash2}
@@ -312,65 +349,90 @@ __device__ __forceinline__ void append_candidate(const ShadeArgs& a, bool want, 
   uint32_t base = 0;
   if (lane_id() == leader) base = atomicAdd(a.cand_count, (uint32_t)__popcll(m));
   base = __shfl(base, leader, 64);
+  cnt.v[CNT_CANDIDATES] += (uint32_t)want;
   if (want) {
     uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
     if (pos < a.cand_cap) a.cand[pos] = make_uint4(cell, seq, code, hash2);
-    cnt.v[CNT_CANDIDATES]++;
   }
 }
 
 // ------------------------------------------------------------- the kernel ---
 
-// Probe every cacheable output of material m for this lane (Sec. 3: look up at
-// the cacheable node first).  Found values go to their registers.  Returns the
-// miss mask (bypassed outputs count as misses); *ins gets the misses that may
-// be inserted.
+// Probe every cacheable output of the lane's material (Sec. 3: look up at the
+// cacheable node first).  Runs with the whole wave active, before the
+// per-material split.  Found values go to their registers.  Returns the miss
+// mask (bypassed outputs count as misses); *ins gets the misses that may be
+// inserted.  COUNT = false when the lookups were already counted (deferred hits).
 template <int MODE, bool COUNT>
-__device__ __forceinline__ uint32_t probe_all(const ShadeArgs& a, uint32_t m, uint32_t h,
-                                              const HitData& hd, const LaneRegs& R,
-                                              Counters& cnt, uint32_t* ins) {
-  const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
-  const uint32_t n_cach = H->n_cach, cbeg = H->cach_begin;
+__device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active, uint32_t m,
+                                                uint32_t h, const HitData& hd, const LaneRegs& R,
+                                                Counters& cnt, uint32_t* ins) {
+  uint32_t n_cach = 0u, cbeg = 0u;
+  if (active && m < a.n_mats) {
+    const MatHeader* H = a.hdr + m;
+    n_cach = H->n_cach;
+    cbeg = H->cach_begin;
+  }
   uint32_t miss = 0u, insm = 0u;
-  for (uint32_t c = 0; c < n_cach; ++c) {
-    const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + c;
-    uint8_t st = 0;
+  const bool coop = a.n_entries == 8u && a.entry_words == 2u;
+  for (uint32_t c = 0; __ballot(c < n_cach) != 0ull; ++c) {
+    const bool has = c < n_cach;
     if (MODE == PMC_MODE_UNCACHED) {
-      miss |= 1u << c;
-    } else {
-      Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.n_cells);
-      if (k.bypass) {
+      if (has) {
         miss |= 1u << c;
-        if (COUNT) cnt.v[CNT_BYPASSES]++;
-        st = 2;
-      } else {
-        cnt.v[COUNT ? CNT_PROBES : CNT_PROBES_DEFERRED]++;
-        uint32_t code;
-        if (cache_lookup(a, k.cell, k.hash2, &code)) {
-          if (COUNT) cnt.v[CNT_CACHE_HITS]++;
-          st = 1;
-          const int r = cd->reg;
-          if (cd->otype == OT_COLOR) {
-            float3 v = rgb9e5_decode(code);
-            R.set(r, v.x); R.set(r + 1, v.y); R.set(r + 2, v.z);
-            if (a.dbg_value) {
-              float* dv = a.dbg_value + ((uint64_t)h * 8 + c) * 3;
-              dv[0] = v.x; dv[1] = v.y; dv[2] = v.z;
-            }
-          } else {
-            float v = __uint_as_float(code);
-            R.set(r, v);
-            if (a.dbg_value) a.dbg_value[((uint64_t)h * 8 + c) * 3] = v;
+        if (a.dbg_state) a.dbg_state[(uint64_t)h * 8 + c] = 0;
+      }
+      continue;
+    }
+    CachDesc cd;
+    cd.node_sock = 0u; cd.reg = 0; cd.otype = 0;
+    Key k;
+    k.bypass = true; k.cell = 0u; k.hash2 = 0u;
+    if (has) {
+      cd = a.cach[cbeg + c];
+      k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.n_cells);
+    }
+    const uint32_t h2 = (has && !k.bypass) ? k.hash2 : 0u;
+    uint32_t code = 0u;
+    bool found;
+    if (coop) {
+      found = coop_lookup128(a, k.cell, h2, &code);
+    } else {
+      found = false;
+      if (h2) found = cache_lookup(a, k.cell, h2, &code);
+    }
+    if (!has) continue;
+    if (COUNT) cnt.v[CNT_BYPASSES] += (uint32_t)k.bypass;
+    cnt.v[COUNT ? CNT_PROBES : CNT_PROBES_DEFERRED] += (uint32_t)!k.bypass;
+    if (COUNT) cnt.v[CNT_CACHE_HITS] += (uint32_t)(!k.bypass && found);
+    uint8_t st = 0;
+    if (k.bypass) {
+      miss |= 1u << c;
+      st = 2;
+    } else {
+      if (found) {
+        st = 1;
+        const int r = cd.reg;
+        if (cd.otype == OT_COLOR) {
+          float3 v = rgb9e5_decode(code);
+          R.set(r, v.x); R.set(r + 1, v.y); R.set(r + 2, v.z);
+          if (a.dbg_value) {
+            float* dv = a.dbg_value + ((uint64_t)h * 8 + c) * 3;
+            dv[0] = v.x; dv[1] = v.y; dv[2] = v.z;
           }
         } else {
-          miss |= 1u << c;
-          insm |= 1u << c;
+          float v = __uint_as_float(code);
+          R.set(r, v);
+          if (a.dbg_value) a.dbg_value[((uint64_t)h * 8 + c) * 3] = v;
         }
+      } else {
+        miss |= 1u << c;
+        insm |= 1u << c;
       }
     }
     if (a.dbg_state) a.dbg_state[(uint64_t)h * 8 + c] = st;
   }
-  if (a.dbg_state)
+  if (a.dbg_state && active && m < a.n_mats)
     for (uint32_t c = n_cach; c < 8; ++c) a.dbg_state[(uint64_t)h * 8 + c] = 3;
   *ins = insm;
   return miss;
@@ -454,14 +516,13 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
       if (MODE != PMC_MODE_UNCACHED && ord != kNoOrd) {
         bool want = (ins >> ord) & 1u;
         uint32_t code = 0u, cell = 0u, hash2 = 0u;
+        const bool finite = isfinite(val.x) && (!is_c || (isfinite(val.y) && isfinite(val.z)));
+        cnt.v[CNT_NONFINITE] += (uint32_t)(want && !finite);
+        want = want && finite;
+        cnt.v[CNT_INS_TRIED] += (uint32_t)want;
+        if (DEF) cnt.v[CNT_INS_TRIED_DEFERRED] += (uint32_t)want;
         if (want) {
-          bool finite = isfinite(val.x) && (!is_c || (isfinite(val.y) && isfinite(val.z)));
-          if (!finite) {
-            cnt.v[CNT_NONFINITE]++;
-            want = false;
-          } else {
-            cnt.v[CNT_INS_TRIED]++;
-            if (DEF) cnt.v[CNT_INS_TRIED_DEFERRED]++;
+          {
             code = is_c ? rgb9e5_encode(val.x, val.y, val.z) : __float_as_uint(val.x);
             const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + ord;
             Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max,
@@ -472,8 +533,10 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
         }
         if (MODE == PMC_MODE_SNAPSHOT) {
           append_candidate(a, want, cell, hash2, code, h * 32u + ord, cnt);
-        } else if (want) {
-          cache_insert(a, cell, hash2, code, cnt);
+        } else {
+          int o = INS_FULL;
+          if (want) o = cache_insert(a, cell, hash2, code);
+          count_insert(cnt, want, o);
         }
       }
     }
@@ -508,16 +571,15 @@ __device__ __forceinline__ void shade_default(const ShadeArgs& a, uint32_t h, co
     for (int c = 0; c < 8; ++c) a.dbg_state[(uint64_t)h * 8 + c] = 3;
 }
 
-// Full evaluation of this lane: probes, the whole program, outputs.  COUNT =
-// false for deferred lanes, whose lookups the probe kernel already counted.
-template <int MODE, bool COUNT>
+// Full evaluation of this lane after its probes: the whole program, outputs.
+// DEF: the lane is a deferred hit (counted apart).
+template <int MODE, bool DEF>
 __device__ __forceinline__ void shade_full(const ShadeArgs& a, uint32_t m, uint32_t h,
-                                           const HitData& hd, const LaneRegs& R, Counters& cnt) {
+                                           const HitData& hd, const LaneRegs& R, Counters& cnt,
+                                           uint32_t miss, uint32_t ins) {
   const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
-  uint32_t ins = 0u;
-  uint32_t miss = probe_all<MODE, COUNT>(a, m, h, hd, R, cnt, &ins);
   cnt.v[CNT_NODES_TOTAL] += H->n_instr;
-  run_program<MODE, !COUNT>(a, m, h, hd, R, cnt, H->instr_begin, H->n_instr, miss, ins);
+  run_program<MODE, DEF>(a, m, h, hd, R, cnt, H->instr_begin, H->n_instr, miss, ins);
   write_outputs(a, m, h, hd, R);
 }
 
@@ -552,12 +614,14 @@ __device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t*
 }
 
 // KIND_FULL / KIND_MISS: every lane of the chunk is evaluated completely.
-template <int MODE>
+template <int MODE, bool DEF>
 __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* list,
                                            uint32_t list_n, uint32_t chunk, const LaneRegs& R,
-                                           Counters& cnt, bool count_hits) {
+                                           Counters& cnt) {
   LaneHit L = load_lane(a, list, list_n, chunk, cnt);
-  if (L.active && count_hits) cnt.v[CNT_HITS]++;
+  if (L.active && !DEF) cnt.v[CNT_HITS]++;
+  uint32_t ins = 0u;
+  const uint32_t miss = probe_chunk<MODE, !DEF>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins);
   uint64_t pending = __ballot(L.active);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -566,8 +630,7 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* l
     pending &= ~__ballot(mine);
     if (mine) {
       if (m < a.n_mats) {
-        if (count_hits) shade_full<MODE, true>(a, m, L.h, L.hd, R, cnt);
-        else shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt);
+        shade_full<MODE, DEF>(a, m, L.h, L.hd, R, cnt, miss, ins);
       } else {
         cnt.v[CNT_INVALID]++;
         shade_default(a, L.h, L.hd);
@@ -586,6 +649,8 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
                                             Counters& cnt) {
   LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
   if (L.active) cnt.v[CNT_HITS]++;
+  uint32_t ins = 0u;
+  const uint32_t miss = probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins);
   bool deferred = false;
   uint64_t pending = __ballot(L.active);
   while (pending) {
@@ -596,14 +661,9 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
     if (mine) {
       if (m < a.n_mats) {
         const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
-        uint32_t ins = 0u;
-        const uint32_t miss = probe_all<MODE, true>(a, m, L.h, L.hd, R, cnt, &ins);
         const uint32_t d = (uint32_t)__popcll(__ballot(miss != 0u));
         if (d > a.defer_max) {
-          cnt.v[CNT_NODES_TOTAL] += H->n_instr;
-          run_program<MODE, false>(a, m, L.h, L.hd, R, cnt, H->instr_begin, H->n_instr, miss,
-                                   ins);
-          write_outputs(a, m, L.h, L.hd, R);
+          shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt, miss, ins);
         } else if (miss != 0u) {
           deferred = true;
         } else {
@@ -639,8 +699,8 @@ template <int MODE, int KIND>
 __device__ __forceinline__ void do_chunk(const ShadeArgs& a, uint32_t chunk, uint32_t list_n,
                                          const LaneRegs& R, Counters& cnt) {
   if (KIND == KIND_PROBE) chunk_probe<MODE>(a, chunk, R, cnt);
-  else if (KIND == KIND_MISS) chunk_full<MODE>(a, a.list, list_n, chunk, R, cnt, false);
-  else chunk_full<MODE>(a, a.perm, list_n, chunk, R, cnt, true);
+  else if (KIND == KIND_MISS) chunk_full<MODE, true>(a, a.list, list_n, chunk, R, cnt);
+  else chunk_full<MODE, false>(a, a.perm, list_n, chunk, R, cnt);
 }
 
 template <int KIND>
@@ -661,9 +721,11 @@ __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   flush_counters(a, cnt);
 }
 
-// Persistent variant: every wave pops `chunk_waves` chunks at a time from a
-// queue counter until the list is exhausted (the exit test is reached by
-// every wave because the counter only grows).
+// Persistent variant: a fixed grid of waves walks the chunk list with a static
+// stride (wave w takes runs of `chunk_waves` chunks starting at w * chunk_waves,
+// then every total_waves * chunk_waves).  No shared work counter: same-address
+// atomics serialise across the XCDs.  The material sort orders chunks by
+// decreasing program length, so the stride deals long work out first.
 template <int MODE, int KIND>
 __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   extern __shared__ float lds[];
@@ -673,12 +735,11 @@ __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
   const uint32_t list_n = list_length<KIND>(a);
   const uint32_t n_chunks = (list_n + 63u) / 64u;
-  for (;;) {
-    uint32_t first = 0;
-    if (lane_id() == 0) first = atomicAdd(a.queue, a.chunk_waves);
-    first = __builtin_amdgcn_readfirstlane(first);
-    if (first >= n_chunks) break;
-    const uint32_t last = min(first + a.chunk_waves, n_chunks);
+  const uint32_t cw = a.chunk_waves;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  for (uint32_t first = w * cw; first < n_chunks; first += waves * cw) {
+    const uint32_t last = min(first + cw, n_chunks);
     for (uint32_t c = first; c < last; ++c) do_chunk<MODE, KIND>(a, c, list_n, R, cnt);
   }
   flush_counters(a, cnt);
@@ -776,11 +837,13 @@ __global__ void k_insert_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int o = INS_FULL;
   if (i < n) {
     uint32_t cell, hash2;
     raw_hash(k0[i], k1[i], a.n_cells, &cell, &hash2);
-    cache_insert(a, cell, hash2, enc[i], cnt);
+    o = cache_insert(a, cell, hash2, enc[i]);
   }
+  count_insert(cnt, i < n, o);
   flush_counters(a, cnt);
 }
 

@@ -18,11 +18,28 @@ __global__ __launch_bounds__(256) void k_hist(const uint32_t* material, uint32_t
   if (use_lds)
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
   __syncthreads();
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    uint32_t m = material[i];
-    uint32_t b = m < n_mats ? m : n_mats;
-    if (use_lds) atomicAdd(&hist[b], 1u);
-    else atomicAdd(&counts[b], 1u);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t end = ((n + stride - 1) / stride) * stride;   // uniform trip count
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < end; i += stride) {
+    const bool valid = i < n;
+    uint32_t b = 0;
+    if (valid) {
+      uint32_t m = material[i];
+      b = m < n_mats ? m : n_mats;
+    }
+    // one atomic per (wave, bucket): hits arrive in screen order, so a wave
+    // usually holds one or two materials
+    uint64_t act = __ballot(valid);
+    while (act) {
+      const int leader = __ffsll((unsigned long long)act) - 1;
+      const uint32_t bl = __builtin_amdgcn_readlane(b, leader);
+      const uint64_t match = __ballot(valid && b == bl);
+      if (lane_id() == leader) {
+        if (use_lds) atomicAdd(&hist[bl], (uint32_t)__popcll(match));
+        else atomicAdd(&counts[bl], (uint32_t)__popcll(match));
+      }
+      act &= ~match;
+    }
   }
   __syncthreads();
   if (use_lds)
