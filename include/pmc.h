@@ -174,7 +174,8 @@ typedef struct pmc_cache_params {
  * 0 = empty (Sec. 3.3). */
 pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* params, void* device_mem,
                             pmc_cache** out);
-/* Destroy the handle (and the table if library-allocated).  NULL accepted. */
+/* Destroy the handle (and the table if library-allocated).  NULL accepted.
+ * Destroy every cache of a context before the context itself. */
 void pmc_cache_destroy(pmc_cache* cache);
 /* Empty every entry (asynchronous on stream; a fill kernel, no memset node). */
 pmc_status pmc_cache_clear(pmc_cache* cache, void* stream);

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -221,9 +222,13 @@ class Context:
         self.h = h
         self.device = device
         self.n_mats = 0
-        self._keep: List = []
+        self._caches = weakref.WeakSet()
 
     def close(self):
+        # caches first: a context must outlive its tables (the cyclic garbage
+        # collector may finalise a context before the caches that refer to it)
+        for c in list(self._caches):
+            c.close()
         if self.h:
             pmc_destroy(self.h)
             self.h = None
@@ -307,6 +312,7 @@ class Cache:
         h = C.c_void_p()
         ctx.check(pmc_cache_create(ctx.h, C.byref(self.params), _ptr(device_mem), C.byref(h)))
         self.h = h
+        ctx._caches.add(self)
         ptr, nbytes = C.c_void_p(), C.c_size_t()
         ctx.check(pmc_cache_device_ptr(self.h, C.byref(ptr), C.byref(nbytes)))
         self.nbytes = nbytes.value

@@ -54,6 +54,7 @@ struct pmc_ctx {
 
 struct pmc_cache {
   pmc_ctx* ctx = nullptr;
+  int device = 0;                // kept here so destruction never reads the context
   pmc_cache_params params{};
   void* mem = nullptr;
   bool owned = false;
@@ -317,6 +318,7 @@ pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* p, void* devic
   pmc_cache* c = new (std::nothrow) pmc_cache();
   if (!c) return PMC_ERR_OOM;
   c->ctx = ctx;
+  c->device = ctx->device;
   c->params = *p;
   if (c->params.level_max == 0) c->params.level_max = 20;
   c->bytes = (size_t)p->n_cells * p->n_entries * p->entry_bytes;
@@ -346,7 +348,7 @@ pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* p, void* devic
 
 void pmc_cache_destroy(pmc_cache* c) {
   if (!c) return;
-  (void)hipSetDevice(c->ctx->device);
+  (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->owned && c->mem) (void)hipFree(c->mem);
   for (DevBuf* b : {&c->cell_count, &c->cell_start, &c->cell_cursor, &c->block_sums, &c->sorted})
