@@ -226,11 +226,12 @@ typedef struct pmc_shade_params {
     uint32_t frame;            /* progressive pass index (stamps = frame + 1) */
     uint32_t chunk_waves;      /* persistent: 64-hit chunks taken per queue pop; 0 = 1 */
     uint32_t blocks_per_cu;    /* persistent: resident blocks per CU; 0 = library choice */
-    uint32_t defer_max;        /* cached modes: when at most this many lanes of a 64-hit wave
-                                  missed, those lanes are set aside and evaluated later in
-                                  dense waves; more misses are evaluated in place.
-                                  0 = library default (48); >= 64 = always set aside */
-    uint32_t reserved[2];
+    uint32_t defer_max;        /* cached modes: when d lanes of a 64-hit wave missed and
+                                  defer_min <= d <= defer_max, those lanes are set aside and
+                                  evaluated later in dense waves; otherwise the wave evaluates
+                                  its misses in place.  0 = library default (48) */
+    uint32_t defer_min;        /* 0 = library default (4); 1 = defer every eligible miss */
+    uint32_t reserved;
 } pmc_shade_params;
 
 typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade */

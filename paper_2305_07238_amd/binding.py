@@ -87,7 +87,7 @@ class pmc_debug_out(C.Structure):
 class pmc_shade_params(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("flags", C.c_uint32), ("frame", C.c_uint32),
                 ("chunk_waves", C.c_uint32), ("blocks_per_cu", C.c_uint32),
-                ("defer_max", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+                ("defer_max", C.c_uint32), ("defer_min", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 STAT_FIELDS = ("hits_shaded", "probes", "cache_hits", "bypasses", "inserts", "cas_failures",
@@ -277,12 +277,12 @@ class Context:
     def shade(self, hits: dict, out: dict, cache: Optional["Cache"] = None,
               mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, frame: int = 0,
               stats=None, debug: Optional[dict] = None, chunk_waves: int = 0,
-              blocks_per_cu: int = 0, defer_max: int = 0, stream=None):
+              blocks_per_cu: int = 0, defer_max: int = 0, defer_min: int = 0, stream=None):
         """hits: dict of torch CUDA tensors material/uv/duv/normal; out: base_color/roughness/normal."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), int(hits["material"].numel()))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
-        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max)
+        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max, defer_min)
         dbg = None
         if debug is not None:
             dbg = C.byref(pmc_debug_out(_ptr(debug.get("state")), _ptr(debug.get("value"))))

@@ -550,6 +550,7 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.chunk_miss = (uint32_t*)ctx->chunk_miss.p;
     a.local = (uint32_t*)ctx->local.p;
     a.defer_max = params->defer_max ? params->defer_max : 48u;
+    a.defer_min = params->defer_min ? params->defer_min : 4u;
     PhaseTimer t1(ctx, 1, s);
     HIP_TRY(ctx, launch_shade(a, KIND_PROBE, persistent, grid, s));
     t1.finish();

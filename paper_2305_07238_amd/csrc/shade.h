@@ -65,7 +65,8 @@ struct ShadeArgs {
   const uint32_t* list_count;    // their number (device)
   uint32_t* chunk_miss;          // deferred lanes per 64-hit chunk (probe kernel)
   uint32_t* local;               // deferred hit ids, chunk-local slices (probe kernel)
-  uint32_t defer_max;            // defer a wave's misses when at most this many lanes missed
+  uint32_t defer_max;            // defer a wave's misses when defer_min <= missed lanes <= defer_max
+  uint32_t defer_min;
 };
 
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,

@@ -219,7 +219,8 @@ __device__ __forceinline__ uint64_t* entry_word(const ShadeArgs& a, uint32_t cel
 // Lookup: first entry whose hash equals hash2 is a hit; an empty entry or the
 // end of the cell is a miss.  All entries of a chunk of 8 are loaded at once.
 __device__ __forceinline__ bool cache_lookup(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
-                                             uint32_t* code) {
+                                             uint32_t* code, uint32_t* slot) {
+  *slot = 0xFFu;
   for (uint32_t base = 0; base < a.n_entries; base += 8) {
     uint64_t w[8];
 #pragma unroll
@@ -232,7 +233,10 @@ __device__ __forceinline__ bool cache_lookup(const ShadeArgs& a, uint32_t cell, 
         *code = (uint32_t)w[j];
         return true;
       }
-      if (w[j] == 0ull) return false;
+      if (w[j] == 0ull) {
+        *slot = base + j;
+        return false;
+      }
     }
   }
   return false;
@@ -242,37 +246,47 @@ __device__ __forceinline__ bool cache_lookup(const ShadeArgs& a, uint32_t cell, 
 // owns one cell (hash2 == 0: no lookup).  In round t the 8 lanes of group
 // g = lane / 8 read the 8 words of the cell owned by lane 8t + g, so each load
 // instruction fetches 8 whole cells and every cell line is fetched once.  The
-// first entry holding hash2 or empty decides, as in the per-lane scan.
-// Requires all 64 lanes of the wave to be active.
+// loads are unconditional (a lane without a lookup reads cell 0) so all eight
+// rounds can be in flight together.  The first entry holding hash2 or empty
+// decides, as in the per-lane scan; *slot gets the first empty entry (8 = none)
+// for the insert that may follow a miss.  All 64 lanes must be active.
 __device__ __forceinline__ bool coop_lookup128(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
-                                               uint32_t* code) {
+                                               uint32_t* code, uint32_t* slot) {
   const int lane = lane_id();
   const int g = lane >> 3, j = lane & 7;
   const char* base = reinterpret_cast<const char*>(a.table);
-  bool found = false;
-  uint32_t cd = 0u;
+  uint64_t w[8];
+  uint32_t hs[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
     const int src = 8 * t + g;
     const uint32_t c_src = __shfl(cell, src, 64);
-    const uint32_t h_src = __shfl(hash2, src, 64);
-    uint64_t w = 0ull;
-    if (h_src != 0u) w = *reinterpret_cast<const uint64_t*>(base + (uint64_t)c_src * 128u + j * 16);
-    const uint64_t hb = __ballot(h_src != 0u && (uint32_t)(w >> 32) == h_src);
-    const uint64_t eb = __ballot(h_src != 0u && w == 0ull);
+    hs[t] = __shfl(hash2, src, 64);
+    const uint32_t c_use = hs[t] != 0u ? c_src : 0u;
+    w[t] = *reinterpret_cast<const uint64_t*>(base + (uint64_t)c_use * 128u + j * 16);
+  }
+  bool found = false;
+  uint32_t cd = 0u, empty = 8u;
+  const int gg = lane & 7;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const uint64_t hb = __ballot(hs[t] != 0u && (uint32_t)(w[t] >> 32) == hs[t]);
+    const uint64_t eb = __ballot(hs[t] != 0u && w[t] == 0ull);
     // owners of round t are lanes 8t .. 8t+7; owner 8t + gg reads group gg's bits
-    const int gg = lane & 7;
     const uint32_t hm = (uint32_t)(hb >> (8 * gg)) & 0xFFu;
     const uint32_t em = (uint32_t)(eb >> (8 * gg)) & 0xFFu;
     const uint32_t any = hm | em;
     const int first = any ? __ffs(any) - 1 : 0;
-    const uint32_t v = __shfl((uint32_t)w, 8 * gg + first, 64);
-    if ((lane >> 3) == t && any && ((hm >> first) & 1u)) {
-      found = true;
+    const uint32_t v = __shfl((uint32_t)w[t], 8 * gg + first, 64);
+    if ((lane >> 3) == t) {
+      const bool hit = any && ((hm >> first) & 1u);
+      found = hit;
       cd = v;
+      empty = (any && !hit) ? (uint32_t)first : 8u;
     }
   }
   *code = cd;
+  *slot = empty;
   return found;
 }
 
@@ -330,6 +344,22 @@ __device__ __forceinline__ int cache_insert(const ShadeArgs& a, uint32_t cell, u
   return INS_FULL;
 }
 
+// FIRST policy with the probe's scan reused: the lookup found entries
+// 0 .. slot-1 holding other keys and entry `slot` empty (slot >= n_entries: the
+// cell was full).  Entries never change once written under FIRST, so a CAS at
+// `slot` is Algorithm 1 with its scan taken at lookup time.
+__device__ __forceinline__ int cache_insert_at(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
+                                               uint32_t code, uint32_t slot) {
+  if (slot >= a.n_entries) return INS_FULL;
+  uint64_t* p = entry_word(a, cell, slot);
+  uint64_t expected = 0ull;
+  const uint64_t neu = ((uint64_t)hash2 << 32) | code;
+  bool ok = __hip_atomic_compare_exchange_strong(p, &expected, neu, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ok && a.entry_words == 2) ((uint32_t*)p)[2] = a.frame + 1u;
+  return ok ? INS_DONE : ((uint32_t)(expected >> 32) == hash2 ? INS_PRESENT : INS_CAS_FAIL);
+}
+
 __device__ __forceinline__ void count_insert(Counters& cnt, bool did, int o) {
   cnt.v[CNT_INSERTS] += (uint32_t)(did && o == INS_DONE);
   cnt.v[CNT_PRESENT] += (uint32_t)(did && o == INS_PRESENT);
@@ -366,14 +396,14 @@ __device__ __forceinline__ void append_candidate(const ShadeArgs& a, bool want, 
 template <int MODE, bool COUNT>
 __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active, uint32_t m,
                                                 uint32_t h, const HitData& hd, const LaneRegs& R,
-                                                Counters& cnt, uint32_t* ins) {
+                                                Counters& cnt, uint32_t* ins, uint32_t* slots) {
   uint32_t n_cach = 0u, cbeg = 0u;
   if (active && m < a.n_mats) {
     const MatHeader* H = a.hdr + m;
     n_cach = H->n_cach;
     cbeg = H->cach_begin;
   }
-  uint32_t miss = 0u, insm = 0u;
+  uint32_t miss = 0u, insm = 0u, slot_bits = 0xFFFFFFFFu;
   const bool coop = a.n_entries == 8u && a.entry_words == 2u;
   for (uint32_t c = 0; __ballot(c < n_cach) != 0ull; ++c) {
     const bool has = c < n_cach;
@@ -393,15 +423,17 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
       k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.n_cells);
     }
     const uint32_t h2 = (has && !k.bypass) ? k.hash2 : 0u;
-    uint32_t code = 0u;
+    uint32_t code = 0u, slot = 0xFFu;
     bool found;
     if (coop) {
-      found = coop_lookup128(a, k.cell, h2, &code);
+      found = coop_lookup128(a, k.cell, h2, &code, &slot);
     } else {
       found = false;
-      if (h2) found = cache_lookup(a, k.cell, h2, &code);
+      if (h2) found = cache_lookup(a, k.cell, h2, &code, &slot);
     }
     if (!has) continue;
+    // 4 bits per ordinal: first empty entry (15 = none or beyond 15)
+    slot_bits = (slot_bits & ~(0xFu << (4 * c))) | ((slot < 15u ? slot : 15u) << (4 * c));
     if (COUNT) cnt.v[CNT_BYPASSES] += (uint32_t)k.bypass;
     cnt.v[COUNT ? CNT_PROBES : CNT_PROBES_DEFERRED] += (uint32_t)!k.bypass;
     if (COUNT) cnt.v[CNT_CACHE_HITS] += (uint32_t)(!k.bypass && found);
@@ -435,6 +467,7 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
   if (a.dbg_state && active && m < a.n_mats)
     for (uint32_t c = n_cach; c < 8; ++c) a.dbg_state[(uint64_t)h * 8 + c] = 3;
   *ins = insm;
+  *slots = slot_bits;
   return miss;
 }
 
@@ -447,7 +480,7 @@ template <int MODE, bool DEF>
 __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint32_t h,
                                             const HitData& hd, const LaneRegs& R, Counters& cnt,
                                             uint32_t first, uint32_t count, uint32_t miss,
-                                            uint32_t ins) {
+                                            uint32_t ins, uint32_t slots) {
   const PMC_CONST Instr* I = as_const(a.instr) + first;
   const uint32_t cbeg = (as_const(a.hdr) + m)->cach_begin;
   for (uint32_t i = 0; i < count; ++i, ++I) {
@@ -535,7 +568,12 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
           append_candidate(a, want, cell, hash2, code, h * 32u + ord, cnt);
         } else {
           int o = INS_FULL;
-          if (want) o = cache_insert(a, cell, hash2, code);
+          if (want) {
+            const uint32_t slot = (slots >> (4 * ord)) & 0xFu;
+            o = (a.policy == PMC_POLICY_FIRST && slot != 0xFu)
+                    ? cache_insert_at(a, cell, hash2, code, slot)
+                    : cache_insert(a, cell, hash2, code);
+          }
           count_insert(cnt, want, o);
         }
       }
@@ -576,10 +614,10 @@ __device__ __forceinline__ void shade_default(const ShadeArgs& a, uint32_t h, co
 template <int MODE, bool DEF>
 __device__ __forceinline__ void shade_full(const ShadeArgs& a, uint32_t m, uint32_t h,
                                            const HitData& hd, const LaneRegs& R, Counters& cnt,
-                                           uint32_t miss, uint32_t ins) {
+                                           uint32_t miss, uint32_t ins, uint32_t slots) {
   const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
   cnt.v[CNT_NODES_TOTAL] += H->n_instr;
-  run_program<MODE, DEF>(a, m, h, hd, R, cnt, H->instr_begin, H->n_instr, miss, ins);
+  run_program<MODE, DEF>(a, m, h, hd, R, cnt, H->instr_begin, H->n_instr, miss, ins, slots);
   write_outputs(a, m, h, hd, R);
 }
 
@@ -620,8 +658,9 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* l
                                            Counters& cnt) {
   LaneHit L = load_lane(a, list, list_n, chunk, cnt);
   if (L.active && !DEF) cnt.v[CNT_HITS]++;
-  uint32_t ins = 0u;
-  const uint32_t miss = probe_chunk<MODE, !DEF>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins);
+  uint32_t ins = 0u, slots = 0u;
+  const uint32_t miss =
+      probe_chunk<MODE, !DEF>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
   uint64_t pending = __ballot(L.active);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -630,7 +669,7 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* l
     pending &= ~__ballot(mine);
     if (mine) {
       if (m < a.n_mats) {
-        shade_full<MODE, DEF>(a, m, L.h, L.hd, R, cnt, miss, ins);
+        shade_full<MODE, DEF>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
       } else {
         cnt.v[CNT_INVALID]++;
         shade_default(a, L.h, L.hd);
@@ -640,17 +679,20 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* l
 }
 
 // KIND_PROBE: probe first.  Lanes whose lookups all hit run only the hit
-// program.  When few lanes of a wave missed (<= defer_max), those lanes are
-// deferred: their hit index is written to the chunk's slice of `local` and
-// evaluated later, compacted into dense waves, by the miss kernel.  When many
-// missed, the whole wave is evaluated here.
+// program.  When the number d of lanes that missed satisfies
+// defer_min <= d <= defer_max, those lanes are deferred: their hit index is
+// written to the chunk's slice of `local` and evaluated later, compacted into
+// dense waves, by the miss kernel.  Otherwise the wave is evaluated here: many
+// misses fill the wave anyway, and a few isolated misses cost less in place
+// (they overlap with other waves' probes) than a latency-bound extra pass.
 template <int MODE>
 __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
                                             Counters& cnt) {
   LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
   if (L.active) cnt.v[CNT_HITS]++;
-  uint32_t ins = 0u;
-  const uint32_t miss = probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins);
+  uint32_t ins = 0u, slots = 0u;
+  const uint32_t miss =
+      probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
   bool deferred = false;
   uint64_t pending = __ballot(L.active);
   while (pending) {
@@ -662,13 +704,13 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
       if (m < a.n_mats) {
         const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
         const uint32_t d = (uint32_t)__popcll(__ballot(miss != 0u));
-        if (d > a.defer_max) {
-          shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt, miss, ins);
+        if (d > a.defer_max || (d != 0u && d < a.defer_min)) {
+          shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
         } else if (miss != 0u) {
           deferred = true;
         } else {
           cnt.v[CNT_NODES_TOTAL] += H->n_instr;
-          run_program<MODE, false>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u, 0u);
+          run_program<MODE, false>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u, 0u, 0u);
           write_outputs(a, m, L.h, L.hd, R);
         }
       } else {
@@ -853,7 +895,8 @@ __global__ void k_lookup_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1
   if (i >= n) return;
   uint32_t cell, hash2, code = 0;
   raw_hash(k0[i], k1[i], a.n_cells, &cell, &hash2);
-  bool f = cache_lookup(a, cell, hash2, &code);
+  uint32_t slot;
+  bool f = cache_lookup(a, cell, hash2, &code, &slot);
   hit[i] = f ? 1 : 0;
   enc_out[i] = f ? code : 0u;
 }
