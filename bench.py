@@ -31,15 +31,11 @@ B_TEXEL = 16           # four RGBA8 texels per evaluated image-texture node
 
 
 def kernel_bytes(st, n_hits):
-    """Algorithmic bytes of the probe kernel and of the deferred-miss kernel (one step)."""
-    deferred = st["deferred"]
-    probe = (n_hits * (B_HIT_IN + B_PERM) + st["probes"] * B_PROBE +
-             (n_hits - deferred) * B_HIT_OUT + deferred * 4 +
-             (st["insert_attempts"] - st["insert_attempts_deferred"]) * B_INSERT +
-             (st["texture_evals"] - st["texture_evals_deferred"]) * B_TEXEL)
-    miss = (deferred * (B_HIT_IN + 4 + B_HIT_OUT) + st["probes_deferred"] * B_PROBE +
-            st["insert_attempts_deferred"] * B_INSERT + st["texture_evals_deferred"] * B_TEXEL)
-    return {"probe": probe, "miss": miss}
+    """Algorithmic bytes of one step of the shade kernel (all its launches)."""
+    return (n_hits * (B_HIT_IN + B_PERM + B_HIT_OUT) +
+            (st["probes"] + st["probes_deferred"]) * B_PROBE +
+            st["deferred"] * (B_HIT_IN + 4) +
+            st["insert_attempts"] * B_INSERT + st["texture_evals"] * B_TEXEL)
 
 
 def workload(name, frames=None):
@@ -159,10 +155,8 @@ def main():
     torch.cuda.synchronize()
     st = B.stats_dict(stats)
     kb = kernel_bytes(st, n_step)
-    probe_ms, probe_launches = prof["probe"]
-    miss_ms, miss_launches = prof["miss"]
-    achieved = kb["probe"] / (probe_ms / args.steps * 1e-3) / 1e9
-    miss_gbs = kb["miss"] / (miss_ms / args.steps * 1e-3) / 1e9 if miss_ms > 0 else None
+    shade_ms, shade_launches = prof["shade"]
+    achieved = kb / (shade_ms / args.steps * 1e-3) / 1e9
 
     # uncached reference on the same inputs
     unc = None
@@ -205,11 +199,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": ("k_shade_persistent" if args.persistent else "k_shade_flat") +
-                               "<mode, KIND_PROBE> (probe + hit program + in-place waves)",
-                     "bytes_per_launch": kb["probe"] / sc.frames,
-                     "avg_launch_ms": probe_ms / max(probe_launches, 1)},
-        "miss_kernel": {"achieved_gbs": miss_gbs, "bytes_per_launch": kb["miss"] / sc.frames,
-                        "avg_launch_ms": miss_ms / max(miss_launches, 1)},
+                               "<mode, KIND_PROBE>",
+                     "bytes_per_launch": kb / sc.frames,
+                     "avg_launch_ms": shade_ms / max(shade_launches, 1)},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

@@ -216,22 +216,22 @@ enum pmc_mode {
 };
 enum pmc_flags {
     PMC_FLAG_SORT = 1u,        /* sort hits by material first so each wave runs one program */
-    PMC_FLAG_PERSISTENT = 2u,  /* persistent waves pull work from a queue */
-    PMC_FLAG_NO_DEFER = 4u     /* evaluate misses in the wave that probed them (no compaction) */
+    PMC_FLAG_PERSISTENT = 2u,  /* a fixed grid of waves walks the work with a static stride */
+    PMC_FLAG_NO_DEFER = 4u     /* cached modes: evaluate misses in the wave that probed them */
 };
 
 typedef struct pmc_shade_params {
     uint32_t mode;             /* enum pmc_mode */
     uint32_t flags;            /* enum pmc_flags */
     uint32_t frame;            /* progressive pass index (stamps = frame + 1) */
-    uint32_t chunk_waves;      /* persistent: 64-hit chunks taken per queue pop; 0 = 1 */
+    uint32_t chunk_waves;      /* run length: consecutive 64-hit chunks taken by one wave;
+                                  0 = 8 in cached modes, 1 otherwise */
     uint32_t blocks_per_cu;    /* persistent: resident blocks per CU; 0 = library choice */
-    uint32_t defer_max;        /* cached modes: when d lanes of a 64-hit wave missed and
-                                  defer_min <= d <= defer_max, those lanes are set aside and
-                                  evaluated later in dense waves; otherwise the wave evaluates
-                                  its misses in place.  0 = library default (48) */
-    uint32_t defer_min;        /* 0 = library default (4); 1 = defer every eligible miss */
-    uint32_t reserved;
+    uint32_t defer_max;        /* cached modes: a 64-hit chunk with more than defer_max missing
+                                  lanes is evaluated where it was probed; sparser misses are
+                                  staged per wave (in LDS) and evaluated together in dense
+                                  passes over the wave's run.  0 = library default (48) */
+    uint32_t reserved[2];
 } pmc_shade_params;
 
 typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade */
@@ -250,11 +250,11 @@ typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade
     uint64_t nodes_total;      /* lane-instructions of full (uncached) evaluation */
     uint64_t invalid_material; /* hits with a material id out of range */
     uint64_t texture_evals;    /* lane evaluations of image-texture nodes (4 texel loads each) */
-    uint64_t deferred;         /* hits set aside by the probe kernel for dense evaluation */
+    uint64_t deferred;         /* hits staged for a dense evaluation after their probes */
     uint64_t insert_attempts;  /* finite values offered to the table (CAS or candidate) */
     uint64_t texture_evals_deferred;    /* texture_evals done while evaluating deferred hits */
     uint64_t insert_attempts_deferred;  /* insert_attempts made for deferred hits */
-    uint64_t probes_deferred;  /* lookups repeated when a deferred hit is evaluated */
+    uint64_t probes_deferred;  /* lookups repeated when a staged hit is evaluated */
     uint64_t reserved[12];
 } pmc_stats;                   /* 256 bytes */
 
@@ -291,10 +291,9 @@ pmc_status pmc_cache_lookup_raw(pmc_cache* cache, const uint64_t* k0, const uint
 /* ------------------------------------------------------------- profiling */
 
 /* Phase timing with HIP events recorded on the stream of each pmc_shade call,
- * around the launches of each phase.  Phases: 0 material sort, 1 probe (or
- * full shade) kernel, 2 miss compaction (scan + gather), 3 miss evaluation
- * kernel, 4 snapshot apply, 5 statistics reduction. */
-#define PMC_PROFILE_PHASES 6
+ * around the launches of each phase.  Phases: 0 material sort, 1 shade
+ * kernel, 2 snapshot apply, 3 statistics reduction. */
+#define PMC_PROFILE_PHASES 4
 typedef struct pmc_profile {
     double ms[PMC_PROFILE_PHASES];          /* accumulated milliseconds per phase */
     uint64_t launches[PMC_PROFILE_PHASES];  /* calls that recorded the phase */

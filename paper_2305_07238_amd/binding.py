@@ -87,7 +87,7 @@ class pmc_debug_out(C.Structure):
 class pmc_shade_params(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("flags", C.c_uint32), ("frame", C.c_uint32),
                 ("chunk_waves", C.c_uint32), ("blocks_per_cu", C.c_uint32),
-                ("defer_max", C.c_uint32), ("defer_min", C.c_uint32), ("reserved", C.c_uint32)]
+                ("defer_max", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 STAT_FIELDS = ("hits_shaded", "probes", "cache_hits", "bypasses", "inserts", "cas_failures",
@@ -101,11 +101,11 @@ class pmc_stats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64 * 12)]
 
 
-PROFILE_PHASES = ("sort", "probe", "compact", "miss", "snapshot", "stats")
+PROFILE_PHASES = ("sort", "shade", "snapshot", "stats")
 
 
 class pmc_profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_uint64 * 6)]
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_uint64 * 4)]
 
 
 class pmc_key_record(C.Structure):
@@ -277,12 +277,12 @@ class Context:
     def shade(self, hits: dict, out: dict, cache: Optional["Cache"] = None,
               mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, frame: int = 0,
               stats=None, debug: Optional[dict] = None, chunk_waves: int = 0,
-              blocks_per_cu: int = 0, defer_max: int = 0, defer_min: int = 0, stream=None):
+              blocks_per_cu: int = 0, defer_max: int = 0, stream=None):
         """hits: dict of torch CUDA tensors material/uv/duv/normal; out: base_color/roughness/normal."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), int(hits["material"].numel()))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
-        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max, defer_min)
+        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max)
         dbg = None
         if debug is not None:
             dbg = C.byref(pmc_debug_out(_ptr(debug.get("state")), _ptr(debug.get("value"))))

@@ -34,7 +34,6 @@ struct pmc_ctx {
   uint32_t n_tex = 0;
   // workspace
   DevBuf perm, counts, cursor, misc, cand, stat_slots;
-  DevBuf chunk_miss, chunk_off, local, list, scan_sums;
   size_t counts_cleared = 0;   // bytes of `counts` known to be zero
   // phase timing: events recorded in pairs per phase
   bool profiling = false;
@@ -204,8 +203,7 @@ void pmc_destroy(pmc_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->texels,
                       &ctx->texdesc, &ctx->perm, &ctx->counts, &ctx->cursor, &ctx->misc,
-                      &ctx->cand, &ctx->stat_slots, &ctx->chunk_miss, &ctx->chunk_off,
-                      &ctx->local, &ctx->list, &ctx->scan_sums})
+                      &ctx->cand, &ctx->stat_slots})
       free_buf(*b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   }
@@ -467,16 +465,14 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.out_rough = out->roughness;
   a.out_normal = out->normal;
   a.frame = params->frame;
-  a.chunk_waves = params->chunk_waves ? params->chunk_waves : 1;
   a.stat_slots = stats ? (unsigned long long*)ctx->stat_slots.p : nullptr;
   a.dbg_state = dbg ? dbg->state : nullptr;
   a.dbg_value = dbg ? dbg->value : nullptr;
   uint32_t* misc = (uint32_t*)ctx->misc.p;
-  a.queue = misc + 0;
   if (mode != PMC_MODE_UNCACHED) fill_cache_args(cache, a);
 
   const uint32_t n_mats = a.n_mats;
-  // misc[0] probe/full queue, misc[1] candidate count, misc[2] miss queue, misc[3] miss count
+  // misc[1]: snapshot candidate count (reset by the sort's scan, or filled here)
   if (sort) {
     pmc_status st;
     if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
@@ -519,55 +515,27 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.cand_cap = (uint32_t)cap;
   }
   const uint32_t n_chunks = (n + 63) / 64;
-  uint32_t bpc = params->blocks_per_cu;
-  if (bpc == 0) {
-    size_t lds_per_block = (size_t)4 * a.n_regs * 256;
-    bpc = (uint32_t)((160 * 1024) / (lds_per_block ? lds_per_block : 1));
-    bpc = bpc < 1 ? 1 : (bpc > 8 ? 8 : bpc);
-  }
-  const uint32_t grid_p = (uint32_t)ctx->num_cus * bpc;
+  const bool probe_first = mode != PMC_MODE_UNCACHED && !(params->flags & PMC_FLAG_NO_DEFER);
+  a.chunk_waves = params->chunk_waves ? params->chunk_waves : (probe_first ? 8u : 1u);
+  a.defer_max = params->defer_max ? params->defer_max : 48u;
+  const uint32_t runs = (n_chunks + a.chunk_waves - 1) / a.chunk_waves;
   uint32_t grid;
   if (persistent) {
-    uint32_t max_useful = (n_chunks + 3) / 4;
-    grid = grid_p < max_useful ? grid_p : (max_useful ? max_useful : 1);
+    uint32_t bpc = params->blocks_per_cu;
+    if (bpc == 0) {
+      size_t lds_per_block = shade_lds_bytes(a.n_regs);
+      bpc = (uint32_t)((160 * 1024) / (lds_per_block ? lds_per_block : 1));
+      bpc = bpc < 1 ? 1 : (bpc > 8 ? 8 : bpc);
+    }
+    grid = (uint32_t)ctx->num_cus * bpc;
+    const uint32_t max_useful = (runs + 3) / 4;
+    if (grid > max_useful) grid = max_useful ? max_useful : 1;
   } else {
-    grid = (n_chunks + 3) / 4;
+    grid = (runs + 3) / 4;
   }
-  const bool defer = mode != PMC_MODE_UNCACHED && !(params->flags & PMC_FLAG_NO_DEFER);
-  if (!defer) {
-    PhaseTimer t1(ctx, 1, s);
-    HIP_TRY(ctx, launch_shade(a, KIND_FULL, persistent, grid, s));
-    t1.finish();
-  } else {
-    pmc_status st;
-    const uint32_t nsb = scan_blocks(n_chunks) + 1;
-    if ((st = ensure(ctx, ctx->chunk_miss, (size_t)n_chunks * 4)) ||
-        (st = ensure(ctx, ctx->chunk_off, (size_t)n_chunks * 4)) ||
-        (st = ensure(ctx, ctx->local, (size_t)n_chunks * 64 * 4)) ||
-        (st = ensure(ctx, ctx->list, (size_t)n * 4)) ||
-        (st = ensure(ctx, ctx->scan_sums, (size_t)nsb * 4)))
-      return st;
-    a.chunk_miss = (uint32_t*)ctx->chunk_miss.p;
-    a.local = (uint32_t*)ctx->local.p;
-    a.defer_max = params->defer_max ? params->defer_max : 48u;
-    a.defer_min = params->defer_min ? params->defer_min : 4u;
-    PhaseTimer t1(ctx, 1, s);
-    HIP_TRY(ctx, launch_shade(a, KIND_PROBE, persistent, grid, s));
-    t1.finish();
-    PhaseTimer t2(ctx, 2, s);
-    HIP_TRY(ctx, launch_exclusive_scan(a.chunk_miss, n_chunks, (uint32_t*)ctx->chunk_off.p, nullptr,
-                                       (uint32_t*)ctx->scan_sums.p, misc + 3, s));
-    HIP_TRY(ctx, launch_compact(a.chunk_miss, (const uint32_t*)ctx->chunk_off.p, a.local,
-                                (uint32_t*)ctx->list.p, n_chunks, s));
-    t2.finish();
-    ShadeArgs b = a;
-    b.list = (const uint32_t*)ctx->list.p;
-    b.list_count = misc + 3;
-    b.queue = misc + 2;
-    PhaseTimer t3(ctx, 3, s);
-    HIP_TRY(ctx, launch_shade(b, KIND_MISS, true, grid_p, s));
-    t3.finish();
-  }
+  PhaseTimer t1(ctx, 1, s);
+  HIP_TRY(ctx, launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, grid, s));
+  t1.finish();
   if (mode == PMC_MODE_SNAPSHOT) {
     SnapshotArgs sa;
     sa.table = a.table;
@@ -585,14 +553,14 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     sa.cell_cursor = (uint32_t*)cache->cell_cursor.p;
     sa.block_sums = (uint32_t*)cache->block_sums.p;
     sa.stat_slots = a.stat_slots;
-    PhaseTimer t4(ctx, 4, s);
+    PhaseTimer t2(ctx, 2, s);
     HIP_TRY(ctx, launch_snapshot_apply(sa, s));
-    t4.finish();
+    t2.finish();
   }
   if (stats) {
-    PhaseTimer t5(ctx, 5, s);
+    PhaseTimer t3(ctx, 3, s);
     HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));
-    t5.finish();
+    t3.finish();
   }
   return PMC_OK;
 }

@@ -15,7 +15,7 @@ enum {
   CNT_NODES_TOTAL, CNT_INVALID, CNT_TEX_EVALS, CNT_DEFERRED, CNT_INS_TRIED, CNT_TEX_DEFERRED,
   CNT_INS_TRIED_DEFERRED, CNT_PROBES_DEFERRED, kNumCounters
 };
-enum { KIND_FULL = 0, KIND_PROBE = 1, KIND_MISS = 2 };   // shade kernel variants
+enum { KIND_FULL = 0, KIND_PROBE = 1 };   // shade kernel variants
 constexpr int kStatSlots = 64;       // counters are spread over slots to limit atomic contention
 constexpr int kStatStride = 32;      // u64 per slot (= sizeof(pmc_stats) / 8)
 
@@ -50,7 +50,7 @@ struct ShadeArgs {
   int32_t level_bias;
   int32_t level_max;
   uint32_t frame;
-  uint32_t chunk_waves;
+  uint32_t chunk_waves;          // consecutive 64-hit chunks per wave run
   // snapshot candidates {cell, seq, code, hash2}
   uint4* cand;
   uint32_t* cand_count;
@@ -59,20 +59,12 @@ struct ShadeArgs {
   unsigned long long* stat_slots;
   uint8_t* dbg_state;
   float* dbg_value;
-  uint32_t* queue;               // persistent work counter
-  // deferred misses (probe kernel -> compaction -> miss kernel)
-  const uint32_t* list;          // compacted deferred hits (miss kernel)
-  const uint32_t* list_count;    // their number (device)
-  uint32_t* chunk_miss;          // deferred lanes per 64-hit chunk (probe kernel)
-  uint32_t* local;               // deferred hit ids, chunk-local slices (probe kernel)
-  uint32_t defer_max;            // defer a wave's misses when defer_min <= missed lanes <= defer_max
-  uint32_t defer_min;
+  uint32_t defer_max;            // a chunk with more missing lanes is evaluated in place
 };
 
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,
                         hipStream_t s);
-hipError_t launch_compact(const uint32_t* chunk_miss, const uint32_t* off, const uint32_t* local,
-                          uint32_t* list, uint32_t n_chunks, hipStream_t s);
+size_t shade_lds_bytes(uint32_t n_regs);
 hipError_t launch_debug_keys(const ShadeArgs& a, pmc_key_record* out, hipStream_t s);
 hipError_t launch_insert_raw(const ShadeArgs& a, const uint64_t* k0, const uint64_t* k1,
                              const uint32_t* enc, uint64_t n, hipStream_t s);

@@ -570,9 +570,13 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
           int o = INS_FULL;
           if (want) {
             const uint32_t slot = (slots >> (4 * ord)) & 0xFu;
-            o = (a.policy == PMC_POLICY_FIRST && slot != 0xFu)
-                    ? cache_insert_at(a, cell, hash2, code, slot)
-                    : cache_insert(a, cell, hash2, code);
+            if (a.policy == PMC_POLICY_FIRST && slot != 0xFu) {
+              o = cache_insert_at(a, cell, hash2, code, slot);
+              // another key took that entry since the lookup: run Algorithm 1 afresh
+              if (o == INS_CAS_FAIL) o = cache_insert(a, cell, hash2, code);
+            } else {
+              o = cache_insert(a, cell, hash2, code);
+            }
           }
           count_insert(cnt, want, o);
         }
@@ -651,16 +655,15 @@ __device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t*
   return L;
 }
 
-// KIND_FULL / KIND_MISS: every lane of the chunk is evaluated completely.
-template <int MODE, bool DEF>
-__device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* list,
-                                           uint32_t list_n, uint32_t chunk, const LaneRegs& R,
+// KIND_FULL: every lane of the chunk is evaluated completely.
+template <int MODE>
+__device__ __forceinline__ void chunk_full(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
                                            Counters& cnt) {
-  LaneHit L = load_lane(a, list, list_n, chunk, cnt);
-  if (L.active && !DEF) cnt.v[CNT_HITS]++;
+  LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
+  cnt.v[CNT_HITS] += (uint32_t)L.active;
   uint32_t ins = 0u, slots = 0u;
   const uint32_t miss =
-      probe_chunk<MODE, !DEF>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
+      probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
   uint64_t pending = __ballot(L.active);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -669,7 +672,7 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* l
     pending &= ~__ballot(mine);
     if (mine) {
       if (m < a.n_mats) {
-        shade_full<MODE, DEF>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
+        shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
       } else {
         cnt.v[CNT_INVALID]++;
         shade_default(a, L.h, L.hd);
@@ -678,18 +681,40 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const uint32_t* l
   }
 }
 
+// Per-wave staging buffer of deferred hits (LDS): ids of hits of one material
+// whose lookups missed.  A wave walks a run of consecutive, material-sorted
+// chunks; sparse misses are collected here and evaluated together in one
+// dense pass (Sec. 3: evaluate the sub-graph on a miss) when the buffer is
+// full, when the material changes, or at the end of the run.
+struct DeferBuf {
+  uint32_t* ids;      // 64 entries
+  uint32_t count;     // wave-uniform
+  uint32_t mat;       // wave-uniform
+};
+
+// Evaluate the staged hits (all 64 lanes active on entry).  The lookups are
+// repeated: in CACHED mode they may now find values inserted since.
+template <int MODE>
+__device__ __forceinline__ void flush_deferred(const ShadeArgs& a, DeferBuf& B, const LaneRegs& R,
+                                            Counters& cnt) {
+  const uint32_t m = B.mat;
+  const bool act = (uint32_t)lane_id() < B.count;
+  LaneHit L = load_lane(a, B.ids, B.count, 0u, cnt);
+  uint32_t ins = 0u, slots = 0u;
+  const uint32_t miss = probe_chunk<MODE, false>(a, act, m, L.h, L.hd, R, cnt, &ins, &slots);
+  if (act) shade_full<MODE, true>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
+  B.count = 0u;
+}
+
 // KIND_PROBE: probe first.  Lanes whose lookups all hit run only the hit
-// program.  When the number d of lanes that missed satisfies
-// defer_min <= d <= defer_max, those lanes are deferred: their hit index is
-// written to the chunk's slice of `local` and evaluated later, compacted into
-// dense waves, by the miss kernel.  Otherwise the wave is evaluated here: many
-// misses fill the wave anyway, and a few isolated misses cost less in place
-// (they overlap with other waves' probes) than a latency-bound extra pass.
+// program.  If more than defer_max lanes of the chunk missed, the chunk is
+// dense enough to be evaluated in place; otherwise its missing lanes go to the
+// wave's staging buffer.
 template <int MODE>
 __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
-                                            Counters& cnt) {
+                                            Counters& cnt, DeferBuf& B) {
   LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
-  if (L.active) cnt.v[CNT_HITS]++;
+  cnt.v[CNT_HITS] += (uint32_t)L.active;
   uint32_t ins = 0u, slots = 0u;
   const uint32_t miss =
       probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
@@ -704,7 +729,7 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
       if (m < a.n_mats) {
         const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
         const uint32_t d = (uint32_t)__popcll(__ballot(miss != 0u));
-        if (d > a.defer_max || (d != 0u && d < a.defer_min)) {
+        if (d > a.defer_max) {
           shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
         } else if (miss != 0u) {
           deferred = true;
@@ -719,12 +744,31 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
       }
     }
   }
-  const uint64_t dm = __ballot(deferred);
-  if (deferred) {
-    cnt.v[CNT_DEFERRED]++;
-    a.local[chunk * 64u + (uint32_t)__popcll(dm & lanemask_lt())] = L.h;
+  // stage the deferred lanes, one material at a time (the chunk's own work is done,
+  // so a flush may reuse the register file)
+  cnt.v[CNT_DEFERRED] += (uint32_t)deferred;
+  uint64_t dm = __ballot(deferred);
+  while (dm) {
+    const int leader = __ffsll((unsigned long long)dm) - 1;
+    const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
+    const bool member = deferred && L.mat == m;
+    const uint64_t mm = __ballot(member);
+    dm &= ~mm;
+    if (B.count != 0u && B.mat != m) flush_deferred<MODE>(a, B, R, cnt);
+    B.mat = m;
+    const uint32_t n_new = (uint32_t)__popcll(mm);
+    const uint32_t room = 64u - B.count;
+    const uint32_t r = (uint32_t)__popcll(mm & lanemask_lt());
+    if (member && r < room) B.ids[B.count + r] = L.h;
+    if (n_new >= room) {
+      B.count = 64u;
+      flush_deferred<MODE>(a, B, R, cnt);
+      if (member && r >= room) B.ids[r - room] = L.h;
+      B.count = n_new - room;
+    } else {
+      B.count += n_new;
+    }
   }
-  if (lane_id() == 0) a.chunk_miss[chunk] = (uint32_t)__popcll(dm);
 }
 
 __device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt) {
@@ -737,68 +781,63 @@ __device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt
   }
 }
 
+// One run = `chunk_waves` consecutive chunks handled by one wave.
 template <int MODE, int KIND>
-__device__ __forceinline__ void do_chunk(const ShadeArgs& a, uint32_t chunk, uint32_t list_n,
-                                         const LaneRegs& R, Counters& cnt) {
-  if (KIND == KIND_PROBE) chunk_probe<MODE>(a, chunk, R, cnt);
-  else if (KIND == KIND_MISS) chunk_full<MODE, true>(a, a.list, list_n, chunk, R, cnt);
-  else chunk_full<MODE, false>(a, a.perm, list_n, chunk, R, cnt);
+__device__ __forceinline__ void do_run(const ShadeArgs& a, uint32_t first, uint32_t n_chunks,
+                                       const LaneRegs& R, Counters& cnt, DeferBuf& B) {
+  const uint32_t last = min(first + a.chunk_waves, n_chunks);
+  for (uint32_t c = first; c < last; ++c) {
+    if (KIND == KIND_PROBE) chunk_probe<MODE>(a, c, R, cnt, B);
+    else chunk_full<MODE>(a, c, R, cnt);
+  }
+  if (KIND == KIND_PROBE && B.count != 0u) flush_deferred<MODE>(a, B, R, cnt);
 }
 
-template <int KIND>
-__device__ __forceinline__ uint32_t list_length(const ShadeArgs& a) {
-  return KIND == KIND_MISS ? *a.list_count : a.n;
+// LDS per wave: the register file [n_regs][64] floats, then 64 staging ids.
+__device__ __forceinline__ float* wave_lds(float* lds, const ShadeArgs& a) {
+  return lds + (threadIdx.x >> 6) * (a.n_regs * 64 + 64);
 }
 
 template <int MODE, int KIND>
 __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   extern __shared__ float lds[];
-  LaneRegs R{lds + (threadIdx.x >> 6) * a.n_regs * 64, lane_id()};
+  float* wl = wave_lds(lds, a);
+  LaneRegs R{wl, lane_id()};
+  DeferBuf B{reinterpret_cast<uint32_t*>(wl + a.n_regs * 64), 0u, 0u};
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
-  const uint32_t list_n = list_length<KIND>(a);
-  const uint32_t chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (chunk * 64u < list_n) do_chunk<MODE, KIND>(a, chunk, list_n, R, cnt);
+  const uint32_t n_chunks = (a.n + 63u) / 64u;
+  const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t first = w * a.chunk_waves;
+  if (first < n_chunks) do_run<MODE, KIND>(a, first, n_chunks, R, cnt, B);
   flush_counters(a, cnt);
 }
 
-// Persistent variant: a fixed grid of waves walks the chunk list with a static
-// stride (wave w takes runs of `chunk_waves` chunks starting at w * chunk_waves,
-// then every total_waves * chunk_waves).  No shared work counter: same-address
-// atomics serialise across the XCDs.  The material sort orders chunks by
-// decreasing program length, so the stride deals long work out first.
+// Persistent variant: a fixed grid of waves walks the runs with a static stride
+// (no shared work counter: same-address atomics serialise across the XCDs).
+// The material sort orders hits by decreasing program length, so the stride
+// deals the long programs out first.
 template <int MODE, int KIND>
 __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   extern __shared__ float lds[];
-  LaneRegs R{lds + (threadIdx.x >> 6) * a.n_regs * 64, lane_id()};
+  float* wl = wave_lds(lds, a);
+  LaneRegs R{wl, lane_id()};
+  DeferBuf B{reinterpret_cast<uint32_t*>(wl + a.n_regs * 64), 0u, 0u};
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
-  const uint32_t list_n = list_length<KIND>(a);
-  const uint32_t n_chunks = (list_n + 63u) / 64u;
-  const uint32_t cw = a.chunk_waves;
+  const uint32_t n_chunks = (a.n + 63u) / 64u;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  for (uint32_t first = w * cw; first < n_chunks; first += waves * cw) {
-    const uint32_t last = min(first + cw, n_chunks);
-    for (uint32_t c = first; c < last; ++c) do_chunk<MODE, KIND>(a, c, list_n, R, cnt);
-  }
+  for (uint32_t first = w * a.chunk_waves; first < n_chunks; first += waves * a.chunk_waves)
+    do_run<MODE, KIND>(a, first, n_chunks, R, cnt, B);
   flush_counters(a, cnt);
 }
 
-// Compaction of the deferred lanes: chunk c's deferred hits go to
-// list[off[c] ..), keeping the material-sorted order.
-__global__ __launch_bounds__(256) void k_compact(const uint32_t* chunk_miss, const uint32_t* off,
-                                                 const uint32_t* local, uint32_t* list,
-                                                 uint32_t n_chunks) {
-  const uint32_t chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (chunk >= n_chunks) return;
-  const uint32_t r = (uint32_t)lane_id();
-  if (r < chunk_miss[chunk]) list[off[chunk] + r] = local[chunk * 64u + r];
-}
-
 // ---------------------------------------------------------- host launchers ---
+
+size_t shade_lds_bytes(uint32_t n_regs) { return (size_t)4 * (n_regs * 64 + 64) * sizeof(float); }
 
 template <int KIND>
 static void launch_kind(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
@@ -828,17 +867,9 @@ static void launch_kind(const ShadeArgs& a, bool persistent, uint32_t grid, size
 
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,
                         hipStream_t s) {
-  const size_t lds = (size_t)4 * a.n_regs * 64 * sizeof(float);
+  const size_t lds = shade_lds_bytes(a.n_regs);
   if (kind == KIND_PROBE) launch_kind<KIND_PROBE>(a, persistent, grid, lds, s);
-  else if (kind == KIND_MISS) launch_kind<KIND_MISS>(a, persistent, grid, lds, s);
   else launch_kind<KIND_FULL>(a, persistent, grid, lds, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_compact(const uint32_t* chunk_miss, const uint32_t* off, const uint32_t* local,
-                          uint32_t* list, uint32_t n_chunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact, dim3((n_chunks + 3) / 4), dim3(256), 0, s, chunk_miss, off, local,
-                     list, n_chunks);
   return hipGetLastError();
 }
 

@@ -348,7 +348,7 @@ def test_snapshot_deferral_settings_are_bit_identical(setting):
     n_cells = 1 << 14
     ref_cache, cache = ctx.cache(n_cells), ctx.cache(n_cells)
     kw = {"no_defer": dict(flags=B.PMC_FLAG_SORT | B.PMC_FLAG_NO_DEFER),
-          "always_defer": dict(flags=B.PMC_FLAG_SORT, defer_max=64, defer_min=1),
+          "always_defer": dict(flags=B.PMC_FLAG_SORT, defer_max=64, chunk_waves=16),
           "persistent": dict(flags=B.PMC_FLAG_SORT | B.PMC_FLAG_PERSISTENT, chunk_waves=2)}[setting]
     for f in range(3):
         h = sc.frame(f)
