@@ -229,6 +229,46 @@ def test_snapshot_mid_two_frames_matches_oracle():
     print("mid snapshot stats", st)
 
 
+@pytest.mark.parametrize("n_cells,n_entries", [(512, 8), (1000, 5)])
+def test_snapshot_overwrite_matches_oracle(n_cells, n_entries):
+    """OVERWRITE: a full cell evicts its oldest-stamped entry; the deterministic
+    snapshot order makes the table unique, so it must match the oracle."""
+    sc = G.small_mid_scene(frames=3)
+    ctx = G.setup(sc)
+    cache = ctx.cache(n_cells, n_entries, 16, policy=B.PMC_POLICY_OVERWRITE)
+    ref_t = table.Table(n_cells, n_entries, 16)
+    for f in range(3):
+        h = sc.frame(f).take(np.arange(0, 115200, 3))      # 38,400 hits, many materials
+        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f,
+                                          policy=table.OVERWRITE)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                        debug=True)
+        assert np.array_equal(state == 1, ref.found)
+        assert st["overwrites"] == ref.stats.get("overwritten", 0)
+        assert st["inserts"] == ref.stats.get("inserted", 0)
+        _table_parity(cache.words(), ref_t)
+    assert st["overwrites"] > 0
+
+
+def test_cached_overwrite_invariants():
+    """Nondeterministic OVERWRITE: every found value still belongs to its key."""
+    sc = G.small_mid_scene(frames=2)
+    ctx = G.setup(sc)
+    n_cells = 256
+    cache = ctx.cache(n_cells, 8, 16, policy=B.PMC_POLICY_OVERWRITE)
+    log, vals = check.KeyLog(), {}
+    for f in range(2):
+        h = sc.frame(f).take(np.arange(0, 115200, 4))
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                                        debug=True)
+        bad = check.check_frame(sc.materials, sc.textures, h, f, state, value, out, n_cells,
+                                log, vals)
+        words = cache.words()[:, 0]
+        bad += check.check_entries_come_from_keys(words, 8, log)
+        assert not bad, (f, bad[:5])
+    assert st["overwrites"] > 0
+
+
 # -------------------------------------------------- nondeterministic (CAS) ----
 
 @pytest.mark.parametrize("flags", [B.PMC_FLAG_SORT, B.PMC_FLAG_SORT | B.PMC_FLAG_PERSISTENT])
