@@ -38,6 +38,11 @@ def kernel_bytes(st, n_hits):
             st["insert_attempts"] * B_INSERT + st["texture_evals"] * B_TEXEL)
 
 
+def scenes_concat(sc):
+    from paper_2305_07238_amd import scenes
+    return scenes.Hits.concat([sc.frame(f) for f in range(sc.frames)])
+
+
 def workload(name, frames=None):
     from paper_2305_07238_amd import scenes
     if name == "mid":
@@ -80,7 +85,6 @@ def main():
     ap.add_argument("--workload", default="mid")
     ap.add_argument("--frames", type=int, default=0)
     ap.add_argument("--mode", default="cached", choices=["cached", "snapshot", "uncached"])
-    ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uncached-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -109,11 +113,12 @@ def main():
 
     sc, desc = workload(args.workload, args.frames or None)
     log(f"workload {args.workload}: {sc.frames} frames x {sc.hits_per_frame} hits")
-    frames = [sc.frame(f) for f in range(sc.frames)]
-    dev = [B.hits_to_device(h) for h in frames]
     n_frame = sc.hits_per_frame
     n_step = n_frame * sc.frames
-    out = B.alloc_outputs(n_frame)
+    hits = B.hits_to_device(scenes_concat(sc))
+    frame_views = [{k: v[f * n_frame:(f + 1) * n_frame] for k, v in hits.items()}
+                   for f in range(sc.frames)]
+    out = B.alloc_outputs(n_frame)          # the renderer consumes each frame's BSDF inputs
 
     ctx = B.Context(0)
     ctx.set_textures(sc.textures)
@@ -123,31 +128,48 @@ def main():
     cache = ctx.cache(cc.n_cells, cc.n_entries, cc.entry_bytes, policy)
     mode = {"cached": B.PMC_MODE_CACHED, "snapshot": B.PMC_MODE_SNAPSHOT,
             "uncached": B.PMC_MODE_UNCACHED}[args.mode]
-    flags = B.PMC_FLAG_SORT | (B.PMC_FLAG_PERSISTENT if args.persistent else 0)
-    log("inputs resident; warming up")
+    use_cache = cache if mode != B.PMC_MODE_UNCACHED else None
+    log("inputs resident; autotuning launch parameters on the first frames")
 
-    def step(m=mode, stats=None):
-        cache.clear()
-        for f in range(sc.frames):
-            ctx.shade(dev[f], out, cache, mode=m, flags=flags, frame=f, stats=stats)
-
+    tune_frames = min(4, sc.frames)
+    tune = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, tune_frames, out, mode=mode))
+    b = tune.best
+    best = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
+                blocks_per_cu=b.blocks_per_cu)
+    log(f"autotune: {best} {tune.best_ms:.3f} ms vs defaults {tune.default_ms:.3f} ms "
+        f"({tune.n_tried} settings, {tune_frames} frames)")
+    graph = ctx.frame_graph(use_cache, ctx.frame_plan(hits, n_frame, sc.frames, out, mode=mode,
+                                                      clear_cache=True, **best))
     for _ in range(args.warmup):
-        step()
+        graph.launch()
     torch.cuda.synchronize()
 
-    # timed region
-    ctx.profile_enable(True)
+    # timed region: whole progressive renders, each from an empty table
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     ev0.record()
     for _ in range(args.steps):
-        step()
+        graph.launch()
     ev1.record()
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"{ms_step:.3f} ms/step (graph replay)")
+
+    # the same work launched per frame with HIP-event phase timing on the stream
+    def step(m=mode, stats=None, kw=best):
+        if m != B.PMC_MODE_UNCACHED:
+            cache.clear()
+        for f in range(sc.frames):
+            ctx.shade(frame_views[f], out, use_cache if m != B.PMC_MODE_UNCACHED else None,
+                      mode=m, frame=f, stats=stats, **kw)
+
+    prof_steps = 3
+    ctx.profile_enable(True)
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
     prof = ctx.profile_read(reset=True)
     ctx.profile_enable(False)
-    log(f"{ms_step:.3f} ms/step; phases {prof}")
+    log(f"phases over {prof_steps} steps: {prof}")
 
     # one more step with counters (same work) for hit rate and algorithmic bytes
     stats = B.new_stats()
@@ -156,16 +178,18 @@ def main():
     st = B.stats_dict(stats)
     kb = kernel_bytes(st, n_step)
     shade_ms, shade_launches = prof["shade"]
-    achieved = kb / (shade_ms / args.steps * 1e-3) / 1e9
+    achieved = kb / (shade_ms / prof_steps * 1e-3) / 1e9
 
-    # uncached reference on the same inputs
+    # uncached reference on the same inputs, also replayed as a graph
     unc = None
     if mode != B.PMC_MODE_UNCACHED and args.uncached_steps > 0:
-        step(m=B.PMC_MODE_UNCACHED)
+        g_u = ctx.frame_graph(None, ctx.frame_plan(hits, n_frame, sc.frames, out,
+                                                   mode=B.PMC_MODE_UNCACHED))
+        g_u.launch()
         torch.cuda.synchronize()
         ev0.record()
         for _ in range(args.uncached_steps):
-            step(m=B.PMC_MODE_UNCACHED)
+            g_u.launch()
         ev1.record()
         torch.cuda.synchronize()
         unc = ev0.elapsed_time(ev1) / args.uncached_steps
@@ -186,8 +210,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "hits_per_step": n_step, "frames": sc.frames,
-                   "mode": args.mode + (" persistent" if args.persistent else ""),
-                   "sort": True},
+                   "mode": args.mode, "launch": "one HIP graph per step (table clear + frames)",
+                   "autotuned": best},
         "cache_hit_rate": st["cache_hits"] / max(st["probes"], 1),
         "found_per_sample": st["cache_hits"] / max(st["hits_shaded"], 1),
         "deferred_fraction": st["deferred"] / max(st["hits_shaded"], 1),
@@ -195,11 +219,11 @@ def main():
         "uncached_samples_per_s": (n_step / (unc * 1e-3)) if unc else None,
         "speedup_vs_uncached": (unc / ms_step) if unc else None,
         "stats": st,
-        "phase_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "phase_ms_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("k_shade_persistent" if args.persistent else "k_shade_flat") +
-                               "<mode, KIND_PROBE>",
+                     "kernel": ("k_shade_persistent" if b.flags & B.PMC_FLAG_PERSISTENT
+                                else "k_shade_flat") + "<mode>",
                      "bytes_per_launch": kb / sc.frames,
                      "avg_launch_ms": shade_ms / max(shade_launches, 1)},
     }

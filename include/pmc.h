@@ -127,8 +127,9 @@ void pmc_destroy(pmc_ctx* ctx);
 /* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
 const char* pmc_last_error(const pmc_ctx* ctx);
 /* ABI version (PMC_ABI_VERSION) and sizeof of the public structs, by index
- * 0..7 (node_desc, input, texture_desc, compile_opts, material_info,
- * cache_params, shade_params, stats); 0 for an unknown index. */
+ * 0..14 (node_desc, input, texture_desc, compile_opts, material_info,
+ * cache_params, shade_params, stats, hits, bsdf_out, debug_out, key_record,
+ * frame_plan, tune_result, profile); 0 for an unknown index. */
 uint32_t pmc_abi_version(void);
 size_t pmc_abi_sizeof(uint32_t which);
 
@@ -217,7 +218,8 @@ enum pmc_mode {
 enum pmc_flags {
     PMC_FLAG_SORT = 1u,        /* sort hits by material first so each wave runs one program */
     PMC_FLAG_PERSISTENT = 2u,  /* a fixed grid of waves walks the work with a static stride */
-    PMC_FLAG_NO_DEFER = 4u     /* cached modes: evaluate misses in the wave that probed them */
+    PMC_FLAG_DEFER = 4u        /* cached modes: stage sparse misses per wave and evaluate them
+                                  in dense passes (see defer_max) instead of in place */
 };
 
 typedef struct pmc_shade_params {
@@ -225,11 +227,11 @@ typedef struct pmc_shade_params {
     uint32_t flags;            /* enum pmc_flags */
     uint32_t frame;            /* progressive pass index (stamps = frame + 1) */
     uint32_t chunk_waves;      /* run length: consecutive 64-hit chunks taken by one wave;
-                                  0 = 8 in cached modes, 1 otherwise */
+                                  0 = 4 with PMC_FLAG_DEFER, 1 otherwise */
     uint32_t blocks_per_cu;    /* persistent: resident blocks per CU; 0 = library choice */
-    uint32_t defer_max;        /* cached modes: a 64-hit chunk with more than defer_max missing
-                                  lanes is evaluated where it was probed; sparser misses are
-                                  staged per wave (in LDS) and evaluated together in dense
+    uint32_t defer_max;        /* PMC_FLAG_DEFER: a 64-hit chunk with more than defer_max
+                                  missing lanes is evaluated where it was probed; sparser misses
+                                  are staged per wave (in LDS) and evaluated together in dense
                                   passes over the wave's run.  0 = library default (48) */
     uint32_t reserved[2];
 } pmc_shade_params;
@@ -287,6 +289,55 @@ pmc_status pmc_cache_insert_raw(pmc_cache* cache, const uint64_t* k0, const uint
 /* Lookup of raw descriptors: hit[i] = 1 and enc_out[i] = code when found. */
 pmc_status pmc_cache_lookup_raw(pmc_cache* cache, const uint64_t* k0, const uint64_t* k1,
                                 uint64_t n, uint32_t* enc_out, uint8_t* hit, void* stream);
+
+/* ------------------------------------------------------- progressive frames */
+
+/* A progressive render: n_frames batches of hits_per_frame hits each, shaded
+ * in order against one table (Sec. 1 and 3: values are inserted while frames
+ * are rendered and reused by later frames). */
+typedef struct pmc_frame_plan {
+    pmc_hits hits;             /* device arrays of n_frames * hits_per_frame hits, frame-major
+                                  (hits.n is ignored) */
+    uint64_t hits_per_frame;   /* < 2^27 */
+    uint32_t n_frames;
+    uint32_t first_frame;      /* frame index of the first batch (stamps = frame + 1) */
+    pmc_bsdf_out out;          /* device outputs */
+    uint32_t out_per_frame;    /* 1: frame f writes entries [f * hits_per_frame, ...);
+                                  0: every frame writes entries [0, hits_per_frame) */
+    uint32_t clear_cache;      /* 1: empty the table before the first frame */
+    pmc_shade_params params;   /* for every frame; params.frame is ignored */
+    pmc_stats* stats;          /* device counters accumulated by every frame, or NULL */
+} pmc_frame_plan;
+
+typedef struct pmc_frame_graph pmc_frame_graph;   /* opaque */
+
+/* Capture the whole plan (table clear, then per frame: material sort, shade,
+ * snapshot apply, statistics) into one HIP graph.  All device workspace is
+ * reserved before capture; launches allocate nothing.  The plan's pointers are
+ * baked into the graph and must stay valid while it is used.  Synchronous. */
+pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* plan,
+                                  pmc_frame_graph** out);
+/* Replay the captured frames on `stream` (asynchronous). */
+pmc_status pmc_frame_graph_launch(pmc_frame_graph* graph, void* stream);
+/* Release the graph.  NULL accepted. */
+void pmc_frame_graph_destroy(pmc_frame_graph* graph);
+
+/* Launch-parameter search.  Shades the plan's frames (without capture) under
+ * each candidate setting of flags (persistence, deferral), chunk_waves,
+ * defer_max and blocks_per_cu, timing each with HIP events (best of two
+ * runs, the table cleared before each), and writes the fastest setting to
+ * *best (mode taken from plan->params).  The table is left cleared.  If
+ * json_path is not NULL, every candidate and its time are written there as
+ * JSON.  Synchronous. */
+typedef struct pmc_tune_result {
+    pmc_shade_params best;     /* fastest setting found */
+    double best_ms;            /* its time for the plan's frames */
+    double default_ms;         /* time with the library defaults (flags = SORT) */
+    uint32_t n_tried;
+    uint32_t reserved;
+} pmc_tune_result;
+pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* plan,
+                        pmc_tune_result* out, const char* json_path);
 
 /* ------------------------------------------------------------- profiling */
 

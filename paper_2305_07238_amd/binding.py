@@ -31,7 +31,7 @@ MATH_OPS = {"ADD": 0, "MUL": 1, "POW": 2}
 PMC_NODE_CLAMP = 1
 PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE = 0, 1
 PMC_MODE_UNCACHED, PMC_MODE_CACHED, PMC_MODE_SNAPSHOT = 0, 1, 2
-PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_NO_DEFER = 1, 2, 4
+PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_DEFER = 1, 2, 4
 MAX_CACHEABLE = 8
 
 
@@ -90,6 +90,17 @@ class pmc_shade_params(C.Structure):
                 ("defer_max", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
+class pmc_frame_plan(C.Structure):
+    _fields_ = [("hits", pmc_hits), ("hits_per_frame", C.c_uint64), ("n_frames", C.c_uint32),
+                ("first_frame", C.c_uint32), ("out", pmc_bsdf_out), ("out_per_frame", C.c_uint32),
+                ("clear_cache", C.c_uint32), ("params", pmc_shade_params), ("stats", C.c_void_p)]
+
+
+class pmc_tune_result(C.Structure):
+    _fields_ = [("best", pmc_shade_params), ("best_ms", C.c_double), ("default_ms", C.c_double),
+                ("n_tried", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 STAT_FIELDS = ("hits_shaded", "probes", "cache_hits", "bypasses", "inserts", "cas_failures",
                "present", "cell_full", "overwrites", "nonfinite", "candidates",
                "nodes_executed", "nodes_total", "invalid_material", "texture_evals",
@@ -140,6 +151,11 @@ _proto = {
     "pmc_debug_keys": (_S, [_P, _P, C.POINTER(pmc_hits), _P, _P]),
     "pmc_cache_insert_raw": (_S, [_P, _P, _P, _P, C.c_uint64, C.c_uint32, _P, _P]),
     "pmc_cache_lookup_raw": (_S, [_P, _P, _P, C.c_uint64, _P, _P, _P]),
+    "pmc_frame_graph_create": (_S, [_P, _P, C.POINTER(pmc_frame_plan), C.POINTER(C.c_void_p)]),
+    "pmc_frame_graph_launch": (_S, [_P, _P]),
+    "pmc_frame_graph_destroy": (None, [_P]),
+    "pmc_autotune": (_S, [_P, _P, C.POINTER(pmc_frame_plan), C.POINTER(pmc_tune_result),
+                          C.c_char_p]),
     "pmc_profile_enable": (_S, [_P, C.c_int]),
     "pmc_profile_read": (_S, [_P, C.POINTER(pmc_profile), C.c_int]),
 }
@@ -225,8 +241,8 @@ class Context:
         self._caches = weakref.WeakSet()
 
     def close(self):
-        # caches first: a context must outlive its tables (the cyclic garbage
-        # collector may finalise a context before the caches that refer to it)
+        # caches and graphs first: a context must outlive them (the cyclic garbage
+        # collector may finalise a context before the objects that refer to it)
         for c in list(self._caches):
             c.close()
         if self.h:
@@ -297,10 +313,61 @@ class Context:
         self.check(pmc_profile_read(self.h, C.byref(p), 1 if reset else 0))
         return {ph: (p.ms[i], int(p.launches[i])) for i, ph in enumerate(PROFILE_PHASES)}
 
+    def frame_plan(self, hits: dict, hits_per_frame: int, n_frames: int, out: dict,
+                   mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, first_frame: int = 0,
+                   out_per_frame: bool = False, clear_cache: bool = True, stats=None,
+                   chunk_waves: int = 0, blocks_per_cu: int = 0,
+                   defer_max: int = 0) -> pmc_frame_plan:
+        """hits: torch tensors holding n_frames * hits_per_frame hits, frame-major."""
+        h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
+                     _ptr(hits["normal"]), 0)
+        o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
+        prm = pmc_shade_params(mode, flags, 0, chunk_waves, blocks_per_cu, defer_max)
+        plan = pmc_frame_plan(h, hits_per_frame, n_frames, first_frame, o, int(out_per_frame),
+                              int(clear_cache), prm, _ptr(stats))
+        plan._keep = (hits, out, stats)
+        return plan
+
+    def frame_graph(self, cache: Optional["Cache"], plan: pmc_frame_plan) -> "FrameGraph":
+        return FrameGraph(self, cache, plan)
+
+    def autotune(self, cache: Optional["Cache"], plan: pmc_frame_plan,
+                 json_path: Optional[str] = None) -> pmc_tune_result:
+        res = pmc_tune_result()
+        self.check(pmc_autotune(self.h, cache.h if cache else None, C.byref(plan), C.byref(res),
+                                json_path.encode() if json_path else None))
+        return res
+
     def debug_keys(self, cache: "Cache", hits: dict, out, stream=None):
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), int(hits["material"].numel()))
         self.check(pmc_debug_keys(self.h, cache.h, C.byref(h), _ptr(out), _stream_ptr(stream)))
+
+
+class FrameGraph:
+    """A progressive render captured into one HIP graph (pmc_frame_graph_*)."""
+
+    def __init__(self, ctx: Context, cache: Optional["Cache"], plan: pmc_frame_plan):
+        self.ctx, self.cache, self.plan = ctx, cache, plan
+        h = C.c_void_p()
+        ctx.check(pmc_frame_graph_create(ctx.h, cache.h if cache else None, C.byref(plan),
+                                         C.byref(h)))
+        self.h = h
+        ctx._caches.add(self)           # released before the context
+
+    def launch(self, stream=None):
+        self.ctx.check(pmc_frame_graph_launch(self.h, _stream_ptr(stream)))
+
+    def close(self):
+        if self.h:
+            pmc_frame_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Cache:

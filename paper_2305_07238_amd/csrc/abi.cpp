@@ -1,74 +1,13 @@
 // abi.cpp - the C entry points of libpmc: context, textures, graph
 // compilation, cache tables, and the per-batch shading pipeline
 // (material sort -> shade -> snapshot apply -> statistics).
-#include <hip/hip_runtime.h>
-
-#include <cstdarg>
-#include <cstdio>
 #include <cstring>
-#include <string>
-#include <vector>
 
-#include "../../include/pmc.h"
-#include "compiler.h"
-#include "shade.h"
+#include "context.h"
 
 using namespace pmc;
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
-struct pmc_ctx {
-  int device = -1;
-  bool host_only = true;
-  int num_cus = 0;
-  std::string err;
-  Program prog;
-  bool compiled = false;
-  // program on the device
-  DevBuf hdr, instr, cach, pool, lpt;
-  // textures
-  DevBuf texels, texdesc;
-  uint32_t n_tex = 0;
-  // workspace
-  DevBuf perm, counts, cursor, misc, cand, stat_slots;
-  size_t counts_cleared = 0;   // bytes of `counts` known to be zero
-  // phase timing: events recorded in pairs per phase
-  bool profiling = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_records;
-  pmc_status fail(pmc_status code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    err = buf;
-    return code;
-  }
-};
-
-struct pmc_cache {
-  pmc_ctx* ctx = nullptr;
-  int device = 0;                // kept here so destruction never reads the context
-  pmc_cache_params params{};
-  void* mem = nullptr;
-  bool owned = false;
-  size_t bytes = 0;
-  DevBuf cell_count, cell_start, cell_cursor, block_sums, sorted;
-};
-
-#define HIP_TRY(ctx, call)                                                              \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return (ctx)->fail(PMC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
-  } while (0)
-
-namespace {
+namespace pmc {
 
 hipEvent_t next_event(pmc_ctx* ctx) {
   if (ctx->ev_used == ctx->ev_pool.size()) {
@@ -79,24 +18,18 @@ hipEvent_t next_event(pmc_ctx* ctx) {
   return ctx->ev_pool[ctx->ev_used++];
 }
 
-// Records a start event on construction and an end event on finish().
-struct PhaseTimer {
-  pmc_ctx* ctx;
-  int phase;
-  hipStream_t s;
-  hipEvent_t start = nullptr;
-  PhaseTimer(pmc_ctx* c, int ph, hipStream_t st) : ctx(c), phase(ph), s(st) {
-    if (ctx->profiling && (start = next_event(ctx))) (void)hipEventRecord(start, s);
-  }
-  void finish() {
-    if (!start) return;
-    hipEvent_t end = next_event(ctx);
-    if (!end) return;
-    (void)hipEventRecord(end, s);
-    ctx->ev_records.push_back({phase, {start, end}});
-    start = nullptr;
-  }
-};
+PhaseTimer::PhaseTimer(pmc_ctx* c, int ph, hipStream_t st) : ctx(c), phase(ph), s(st) {
+  if (ctx->profiling && (start = next_event(ctx))) (void)hipEventRecord(start, s);
+}
+
+void PhaseTimer::finish() {
+  if (!start) return;
+  hipEvent_t end = next_event(ctx);
+  if (!end) return;
+  (void)hipEventRecord(end, s);
+  ctx->ev_records.push_back({phase, {start, end}});
+  start = nullptr;
+}
 
 void free_buf(DevBuf& b) {
   if (b.p) (void)hipFree(b.p);
@@ -104,9 +37,10 @@ void free_buf(DevBuf& b) {
   b.bytes = 0;
 }
 
-// grow-only device buffer; contents are not preserved
 pmc_status ensure(pmc_ctx* ctx, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return PMC_OK;
+  if (ctx->no_alloc)
+    return ctx->fail(PMC_ERR_STATE, "workspace of %zu bytes not reserved before capture", bytes);
   free_buf(b);
   if (bytes == 0) bytes = 256;
   hipError_t e = hipMalloc(&b.p, bytes);
@@ -119,18 +53,22 @@ pmc_status ensure(pmc_ctx* ctx, DevBuf& b, size_t bytes) {
   return PMC_OK;
 }
 
+pmc_status need_device(pmc_ctx* ctx) {
+  if (ctx->host_only) return ctx->fail(PMC_ERR_STATE, "host-only context has no device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return PMC_OK;
+}
+
+}  // namespace pmc
+
+namespace {
+
 template <typename T>
 pmc_status upload(pmc_ctx* ctx, DevBuf& b, const std::vector<T>& v) {
   size_t bytes = v.size() * sizeof(T);
   pmc_status st = ensure(ctx, b, bytes ? bytes : 256);
   if (st) return st;
   if (bytes) HIP_TRY(ctx, hipMemcpy(b.p, v.data(), bytes, hipMemcpyHostToDevice));
-  return PMC_OK;
-}
-
-pmc_status need_device(pmc_ctx* ctx) {
-  if (ctx->host_only) return ctx->fail(PMC_ERR_STATE, "host-only context has no device");
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
   return PMC_OK;
 }
 
@@ -154,6 +92,9 @@ size_t pmc_abi_sizeof(uint32_t which) {
     case 9: return sizeof(pmc_bsdf_out);
     case 10: return sizeof(pmc_debug_out);
     case 11: return sizeof(pmc_key_record);
+    case 12: return sizeof(pmc_frame_plan);
+    case 13: return sizeof(pmc_tune_result);
+    case 14: return sizeof(pmc_profile);
     default: return 0;
   }
 }
@@ -432,26 +373,69 @@ static pmc_status ready(pmc_ctx* ctx) {
   return PMC_OK;
 }
 
-pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
-                     const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
-                     const pmc_debug_out* dbg, void* stream) {
-  if (!ctx) return PMC_ERR_INVALID;
+}  // extern "C"
+
+namespace pmc {
+
+pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                            const pmc_bsdf_out* out, const pmc_shade_params* params) {
   if (pmc_status st = ready(ctx)) return st;
   if (pmc_status st = check_hits(ctx, hits)) return st;
   if (!params) return ctx->fail(PMC_ERR_INVALID, "null params");
   if (params->mode > PMC_MODE_SNAPSHOT) return ctx->fail(PMC_ERR_INVALID, "unknown mode");
-  if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT | PMC_FLAG_NO_DEFER))
+  if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT | PMC_FLAG_DEFER))
     return ctx->fail(PMC_ERR_INVALID, "unknown flags");
   if (hits->n && (!out || !out->base_color || !out->roughness || !out->normal))
     return ctx->fail(PMC_ERR_INVALID, "null output array");
   if (cache && cache->ctx != ctx) return ctx->fail(PMC_ERR_INVALID, "cache of another context");
+  return PMC_OK;
+}
+
+pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mode,
+                         uint32_t flags, hipStream_t s) {
+  const uint32_t n_mats = (uint32_t)ctx->prog.headers.size();
+  pmc_status st;
+  if (flags & PMC_FLAG_SORT) {
+    if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
+        (st = ensure(ctx, ctx->cursor, (size_t)(n_mats + 1) * 4)))
+      return st;
+    const size_t cbytes = (size_t)(n_mats + 1) * 4;
+    if (ctx->counts.bytes < cbytes || !ctx->counts.p) {
+      if ((st = ensure(ctx, ctx->counts, cbytes))) return st;
+      ctx->counts_cleared = 0;
+    }
+    if (ctx->counts_cleared < ctx->counts.bytes) {
+      HIP_TRY(ctx, launch_fill_u32((uint32_t*)ctx->counts.p, 0u, ctx->counts.bytes / 4, s));
+      ctx->counts_cleared = ctx->counts.bytes;
+    }
+  }
+  if (mode == PMC_MODE_SNAPSHOT && cache) {
+    const size_t cap = (size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1);
+    if ((st = ensure(ctx, ctx->cand, cap * 16)) || (st = ensure(ctx, cache->sorted, cap * 16)))
+      return st;
+    const uint32_t ncell = (uint32_t)cache->params.n_cells;
+    if (!cache->cell_count.p) {
+      if ((st = ensure(ctx, cache->cell_count, (size_t)ncell * 4))) return st;
+      HIP_TRY(ctx, launch_fill_u32((uint32_t*)cache->cell_count.p, 0u, ncell, s));
+    }
+    if ((st = ensure(ctx, cache->cell_start, (size_t)ncell * 4)) ||
+        (st = ensure(ctx, cache->cell_cursor, (size_t)ncell * 4)) ||
+        (st = ensure(ctx, cache->block_sums, (size_t)scan_blocks(ncell) * 4 + 4)))
+      return st;
+  }
+  return PMC_OK;
+}
+
+pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                       const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
+                       const pmc_debug_out* dbg, hipStream_t s) {
   const uint32_t n = (uint32_t)hits->n;
   if (n == 0) return PMC_OK;
-  hipStream_t s = (hipStream_t)stream;
   uint32_t mode = params->mode;
   if (!cache) mode = PMC_MODE_UNCACHED;
   const bool sort = params->flags & PMC_FLAG_SORT;
   const bool persistent = params->flags & PMC_FLAG_PERSISTENT;
+  if (pmc_status st = reserve_batch(ctx, cache, n, mode, params->flags, s)) return st;
 
   ShadeArgs a;
   fill_program_args(ctx, a);
@@ -471,24 +455,10 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   uint32_t* misc = (uint32_t*)ctx->misc.p;
   if (mode != PMC_MODE_UNCACHED) fill_cache_args(cache, a);
 
-  const uint32_t n_mats = a.n_mats;
   // misc[1]: snapshot candidate count (reset by the sort's scan, or filled here)
   if (sort) {
-    pmc_status st;
-    if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
-        (st = ensure(ctx, ctx->cursor, (size_t)(n_mats + 1) * 4)))
-      return st;
-    const size_t cbytes = (size_t)(n_mats + 1) * 4;
-    if (ctx->counts.bytes < cbytes || !ctx->counts.p) {
-      if ((st = ensure(ctx, ctx->counts, cbytes))) return st;
-      ctx->counts_cleared = 0;
-    }
-    if (ctx->counts_cleared < ctx->counts.bytes) {
-      HIP_TRY(ctx, launch_fill_u32((uint32_t*)ctx->counts.p, 0u, ctx->counts.bytes / 4, s));
-      ctx->counts_cleared = ctx->counts.bytes;
-    }
     PhaseTimer t0(ctx, 0, s);
-    HIP_TRY(ctx, launch_material_sort(hits->material, n, n_mats, (const uint32_t*)ctx->lpt.p,
+    HIP_TRY(ctx, launch_material_sort(hits->material, n, a.n_mats, (const uint32_t*)ctx->lpt.p,
                                       (uint32_t*)ctx->counts.p, (uint32_t*)ctx->cursor.p,
                                       (uint32_t*)ctx->perm.p, misc, 4, s));
     t0.finish();
@@ -497,26 +467,13 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     HIP_TRY(ctx, launch_fill_u32(misc, 0u, 4, s));
   }
   if (mode == PMC_MODE_SNAPSHOT) {
-    size_t cap = (size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1);
-    pmc_status st;
-    if ((st = ensure(ctx, ctx->cand, cap * 16)) || (st = ensure(ctx, cache->sorted, cap * 16)))
-      return st;
-    const uint32_t ncell = (uint32_t)cache->params.n_cells;
-    if (!cache->cell_count.p) {
-      if ((st = ensure(ctx, cache->cell_count, (size_t)ncell * 4))) return st;
-      HIP_TRY(ctx, launch_fill_u32((uint32_t*)cache->cell_count.p, 0u, ncell, s));
-    }
-    if ((st = ensure(ctx, cache->cell_start, (size_t)ncell * 4)) ||
-        (st = ensure(ctx, cache->cell_cursor, (size_t)ncell * 4)) ||
-        (st = ensure(ctx, cache->block_sums, (size_t)scan_blocks(ncell) * 4 + 4)))
-      return st;
     a.cand = (uint4*)ctx->cand.p;
     a.cand_count = misc + 1;
-    a.cand_cap = (uint32_t)cap;
+    a.cand_cap = (uint32_t)((size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1));
   }
   const uint32_t n_chunks = (n + 63) / 64;
-  const bool probe_first = mode != PMC_MODE_UNCACHED && !(params->flags & PMC_FLAG_NO_DEFER);
-  a.chunk_waves = params->chunk_waves ? params->chunk_waves : (probe_first ? 8u : 1u);
+  const bool probe_first = mode != PMC_MODE_UNCACHED && (params->flags & PMC_FLAG_DEFER);
+  a.chunk_waves = params->chunk_waves ? params->chunk_waves : (probe_first ? 4u : 1u);
   a.defer_max = params->defer_max ? params->defer_max : 48u;
   const uint32_t runs = (n_chunks + a.chunk_waves - 1) / a.chunk_waves;
   uint32_t grid;
@@ -563,6 +520,18 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     t3.finish();
   }
   return PMC_OK;
+}
+
+}  // namespace pmc
+
+extern "C" {
+
+pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                     const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
+                     const pmc_debug_out* dbg, void* stream) {
+  if (!ctx) return PMC_ERR_INVALID;
+  if (pmc_status st = check_shade_args(ctx, cache, hits, out, params)) return st;
+  return shade_batch(ctx, cache, hits, out, params, stats, dbg, (hipStream_t)stream);
 }
 
 pmc_status pmc_debug_keys(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,

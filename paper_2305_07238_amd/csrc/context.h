@@ -1,0 +1,101 @@
+// context.h - library-internal state of a pmc context and its caches, and the
+// helpers shared by the C entry points (abi.cpp) and the frame graphs (frame.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/pmc.h"
+#include "compiler.h"
+#include "shade.h"
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct pmc_ctx {
+  int device = -1;
+  bool host_only = true;
+  int num_cus = 0;
+  std::string err;
+  pmc::Program prog;
+  bool compiled = false;
+  // program on the device
+  DevBuf hdr, instr, cach, pool, lpt;
+  // textures
+  DevBuf texels, texdesc;
+  uint32_t n_tex = 0;
+  // workspace
+  DevBuf perm, counts, cursor, misc, cand, stat_slots;
+  size_t counts_cleared = 0;   // bytes of `counts` known to be zero
+  bool no_alloc = false;       // set while a frame graph is captured
+  // phase timing: events recorded in pairs per phase
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_records;
+  pmc_status fail(pmc_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+};
+
+struct pmc_cache {
+  pmc_ctx* ctx = nullptr;
+  int device = 0;                // kept here so destruction never reads the context
+  pmc_cache_params params{};
+  void* mem = nullptr;
+  bool owned = false;
+  size_t bytes = 0;
+  DevBuf cell_count, cell_start, cell_cursor, block_sums, sorted;
+};
+
+#define HIP_TRY(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return (ctx)->fail(PMC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+namespace pmc {
+
+void free_buf(DevBuf& b);
+// grow-only device buffer; contents are not preserved.  Fails with
+// PMC_ERR_STATE when it would allocate while ctx->no_alloc is set.
+pmc_status ensure(pmc_ctx* ctx, DevBuf& b, size_t bytes);
+pmc_status need_device(pmc_ctx* ctx);
+hipEvent_t next_event(pmc_ctx* ctx);
+
+// Records a start event on construction and an end event on finish().
+struct PhaseTimer {
+  pmc_ctx* ctx;
+  int phase;
+  hipStream_t s;
+  hipEvent_t start = nullptr;
+  PhaseTimer(pmc_ctx* c, int ph, hipStream_t st);
+  void finish();
+};
+
+// Argument checks of pmc_shade (host side, nothing enqueued).
+pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                            const pmc_bsdf_out* out, const pmc_shade_params* params);
+// Device workspace for batches of up to n hits (all allocations and first-use
+// clears, enqueued on s).  After this, shade_batch for such batches allocates nothing.
+pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mode,
+                         uint32_t flags, hipStream_t s);
+// The per-batch pipeline: material sort -> shade -> snapshot apply -> stats.
+pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                       const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
+                       const pmc_debug_out* dbg, hipStream_t s);
+
+}  // namespace pmc

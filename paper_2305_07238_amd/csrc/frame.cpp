@@ -1,0 +1,238 @@
+// frame.cpp - progressive frames as one HIP graph, and the launch-parameter
+// autotuner.
+//
+// A progressive render shades frame after frame against one table (Sec. 1,
+// Sec. 3: values inserted while rendering are reused by later frames).  The
+// whole sequence is captured once into a HIP graph and replayed: every
+// per-frame parameter (frame index, hit and output offsets) is baked into
+// the captured kernel arguments, and all workspace is reserved before
+// capture so that replays allocate nothing.
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "context.h"
+
+using namespace pmc;
+
+struct pmc_frame_graph {
+  pmc_ctx* ctx = nullptr;
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+pmc_hits frame_hits(const pmc_frame_plan* p, uint32_t f) {
+  pmc_hits h = p->hits;
+  const uint64_t o = (uint64_t)f * p->hits_per_frame;
+  h.material = p->hits.material + o;
+  h.uv = p->hits.uv + 2 * o;
+  h.duv = p->hits.duv + 4 * o;
+  h.normal = p->hits.normal + 3 * o;
+  h.n = p->hits_per_frame;
+  return h;
+}
+
+pmc_bsdf_out frame_out(const pmc_frame_plan* p, uint32_t f) {
+  pmc_bsdf_out o = p->out;
+  const uint64_t k = p->out_per_frame ? (uint64_t)f * p->hits_per_frame : 0;
+  o.base_color = p->out.base_color + 3 * k;
+  o.roughness = p->out.roughness + k;
+  o.normal = p->out.normal + 3 * k;
+  return o;
+}
+
+pmc_status check_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p) {
+  if (!p) return ctx->fail(PMC_ERR_INVALID, "null plan");
+  if (p->n_frames == 0 || p->hits_per_frame == 0)
+    return ctx->fail(PMC_ERR_INVALID, "plan needs frames and hits");
+  pmc_hits h0 = frame_hits(p, 0);
+  pmc_bsdf_out o0 = frame_out(p, 0);
+  if (pmc_status st = check_shade_args(ctx, cache, &h0, &o0, &p->params)) return st;
+  if (p->params.mode != PMC_MODE_UNCACHED && !cache)
+    return ctx->fail(PMC_ERR_INVALID, "cached plan without a cache");
+  return PMC_OK;
+}
+
+// enqueue the plan's work on s (no validation)
+pmc_status enqueue_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p,
+                        const pmc_shade_params& prm, hipStream_t s) {
+  if (p->clear_cache && cache)
+    HIP_TRY(ctx, launch_fill_u64((uint64_t*)cache->mem, 0ull, cache->bytes / 8, s));
+  for (uint32_t f = 0; f < p->n_frames; ++f) {
+    pmc_hits h = frame_hits(p, f);
+    pmc_bsdf_out o = frame_out(p, f);
+    pmc_shade_params q = prm;
+    q.frame = p->first_frame + f;
+    if (pmc_status st = shade_batch(ctx, cache, &h, &o, &q, p->stats, nullptr, s)) return st;
+  }
+  return PMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* plan,
+                                  pmc_frame_graph** out) {
+  if (!ctx || !out) return PMC_ERR_INVALID;
+  *out = nullptr;
+  if (pmc_status st = check_plan(ctx, cache, plan)) return st;
+  hipStream_t cs = nullptr;
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const uint32_t mode = cache ? plan->params.mode : PMC_MODE_UNCACHED;
+  pmc_status st = reserve_batch(ctx, cache, (uint32_t)plan->hits_per_frame, mode,
+                                plan->params.flags, cs);
+  if (st == PMC_OK && hipStreamSynchronize(cs) != hipSuccess)
+    st = ctx->fail(PMC_ERR_HIP, "workspace reservation failed");
+  pmc_frame_graph* g = nullptr;
+  if (st == PMC_OK) {
+    g = new (std::nothrow) pmc_frame_graph();
+    if (!g) st = PMC_ERR_OOM;
+  }
+  if (st == PMC_OK) {
+    g->ctx = ctx;
+    g->device = ctx->device;
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    ctx->no_alloc = true;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      st = ctx->fail(PMC_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    } else {
+      st = enqueue_plan(ctx, cache, plan, plan->params, cs);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(cs, &graph);
+      if (st == PMC_OK && e != hipSuccess)
+        st = ctx->fail(PMC_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      g->graph = graph;
+    }
+    ctx->no_alloc = false;
+    ctx->profiling = prof;
+    if (st == PMC_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess)
+        st = ctx->fail(PMC_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (st != PMC_OK) {
+    pmc_frame_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return PMC_OK;
+}
+
+pmc_status pmc_frame_graph_launch(pmc_frame_graph* g, void* stream) {
+  if (!g || !g->exec) return PMC_ERR_INVALID;
+  pmc_ctx* ctx = g->ctx;
+  HIP_TRY(ctx, hipSetDevice(g->device));
+  HIP_TRY(ctx, hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return PMC_OK;
+}
+
+void pmc_frame_graph_destroy(pmc_frame_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* plan,
+                        pmc_tune_result* out, const char* json_path) {
+  if (!ctx || !out) return PMC_ERR_INVALID;
+  if (pmc_status st = check_plan(ctx, cache, plan)) return st;
+  std::memset(out, 0, sizeof *out);
+  hipStream_t s = nullptr;
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const bool cached = cache && plan->params.mode != PMC_MODE_UNCACHED;
+  pmc_frame_plan p = *plan;
+  p.clear_cache = cached ? 1u : 0u;
+  p.stats = nullptr;
+
+  struct Cand { uint32_t flags, chunk_waves, defer_max, bpc; double ms; };
+  std::vector<Cand> cands;
+  const uint32_t base = PMC_FLAG_SORT;
+  for (uint32_t pers = 0; pers < 2; ++pers) {
+    const uint32_t pf = pers ? PMC_FLAG_PERSISTENT : 0u;
+    for (uint32_t cw : {1u, 2u, 4u}) cands.push_back({base | pf, cw, 0u, 0u, 0.0});
+    if (cached)
+      for (uint32_t cw : {2u, 4u, 8u})
+        for (uint32_t dm : {32u, 48u}) cands.push_back({base | pf | PMC_FLAG_DEFER, cw, dm, 0u, 0.0});
+  }
+  for (uint32_t bpc : {2u, 4u}) cands.push_back({base | PMC_FLAG_PERSISTENT, 1u, 0u, bpc, 0.0});
+
+  pmc_status st = PMC_OK;
+  auto time_one = [&](const pmc_shade_params& prm, double* ms) -> pmc_status {
+    double best = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {           // first run warms up
+      HIP_TRY(ctx, hipEventRecord(e0, s));
+      if (pmc_status r = enqueue_plan(ctx, cache, &p, prm, s)) return r;
+      HIP_TRY(ctx, hipEventRecord(e1, s));
+      HIP_TRY(ctx, hipEventSynchronize(e1));
+      float t = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&t, e0, e1));
+      if (rep > 0 && t < best) best = t;
+    }
+    *ms = best;
+    return PMC_OK;
+  };
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  pmc_shade_params def = plan->params;
+  def.flags = PMC_FLAG_SORT;
+  def.chunk_waves = def.defer_max = def.blocks_per_cu = 0;
+  st = time_one(def, &out->default_ms);
+  double best_ms = 1e30;
+  size_t best_i = 0;
+  for (size_t i = 0; st == PMC_OK && i < cands.size(); ++i) {
+    pmc_shade_params prm = plan->params;
+    prm.flags = cands[i].flags;
+    prm.chunk_waves = cands[i].chunk_waves;
+    prm.defer_max = cands[i].defer_max;
+    prm.blocks_per_cu = cands[i].bpc;
+    st = time_one(prm, &cands[i].ms);
+    if (st == PMC_OK && cands[i].ms < best_ms) {
+      best_ms = cands[i].ms;
+      best_i = i;
+    }
+  }
+  ctx->profiling = prof;
+  if (st == PMC_OK && cached) {
+    (void)launch_fill_u64((uint64_t*)cache->mem, 0ull, cache->bytes / 8, s);
+    (void)hipStreamSynchronize(s);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (st != PMC_OK) return st;
+  out->best = plan->params;
+  out->best.flags = cands[best_i].flags;
+  out->best.chunk_waves = cands[best_i].chunk_waves;
+  out->best.defer_max = cands[best_i].defer_max;
+  out->best.blocks_per_cu = cands[best_i].bpc;
+  out->best_ms = best_ms;
+  out->n_tried = (uint32_t)cands.size();
+  if (json_path) {
+    FILE* fp = std::fopen(json_path, "w");
+    if (!fp) return ctx->fail(PMC_ERR_INVALID, "cannot write %s", json_path);
+    std::fprintf(fp, "{\"default_ms\": %.6f, \"best\": %zu, \"candidates\": [", out->default_ms,
+                 best_i);
+    for (size_t i = 0; i < cands.size(); ++i)
+      std::fprintf(fp, "%s{\"flags\": %u, \"chunk_waves\": %u, \"defer_max\": %u, "
+                   "\"blocks_per_cu\": %u, \"ms\": %.6f}", i ? ", " : "", cands[i].flags,
+                   cands[i].chunk_waves, cands[i].defer_max, cands[i].bpc, cands[i].ms);
+    std::fprintf(fp, "]}\n");
+    std::fclose(fp);
+  }
+  return PMC_OK;
+}
+
+}  // extern "C"

@@ -80,10 +80,11 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* counts, uint32_t
 // Block-aggregated scatter: a block takes kScatterTile consecutive hits, ranks
 // them per bucket in LDS (one LDS atomic per wave and bucket), reserves one
 // global range per bucket present in the tile, then writes the permutation.
+constexpr uint32_t kScatterThreads = 512;
 constexpr uint32_t kScatterPer = 32;
-constexpr uint32_t kScatterTile = 256 * kScatterPer;
+constexpr uint32_t kScatterTile = kScatterThreads * kScatterPer;
 
-__global__ __launch_bounds__(256) void k_scatter_block(const uint32_t* material, uint32_t n,
+__global__ __launch_bounds__(512) void k_scatter_block(const uint32_t* material, uint32_t n,
                                                        uint32_t n_mats, uint32_t* cursor,
                                                        uint32_t* perm) {
   extern __shared__ uint32_t sh[];
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void k_scatter_block(const uint32_t* material,
   uint32_t pos[kScatterPer], bk[kScatterPer];
 #pragma unroll
   for (uint32_t r = 0; r < kScatterPer; ++r) {
-    const uint32_t i = base + r * 256u + threadIdx.x;
+    const uint32_t i = base + r * kScatterThreads + threadIdx.x;
     const bool valid = i < n;
     uint32_t b = 0;
     if (valid) {
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(256) void k_scatter_block(const uint32_t* material,
   __syncthreads();
 #pragma unroll
   for (uint32_t r = 0; r < kScatterPer; ++r) {
-    const uint32_t i = base + r * 256u + threadIdx.x;
+    const uint32_t i = base + r * kScatterThreads + threadIdx.x;
     if (i < n) perm[sh[bk[r]] + pos[r]] = i;
   }
 }
@@ -158,16 +159,19 @@ hipError_t launch_material_sort(const uint32_t* material, uint32_t n, uint32_t n
                                 hipStream_t s) {
   // counts[] is all-zero on entry (cleared at allocation and by each scan)
   const uint32_t nb = n_mats + 1;
-  uint32_t blocks = (n + 4095) / 4096;
-  blocks = blocks < 1024 ? (blocks ? blocks : 1) : 1024;
+  // few, large blocks: every block adds its bucket counts with one global atomic
+  // per bucket, and same-address atomics serialise across the XCDs
+  uint32_t blocks = (n + 16383) / 16384;
+  blocks = blocks < 128 ? (blocks ? blocks : 1) : 128;
   const bool lds_ok = nb <= kLdsHistMax;
   hipLaunchKernelGGL(k_hist, dim3(blocks), dim3(256), lds_ok ? nb * sizeof(uint32_t) : 0, s,
                      material, n, n_mats, counts);
   hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, counts, n_mats, lpt_order, cursor,
                      reset, n_reset);
   if (lds_ok)
-    hipLaunchKernelGGL(k_scatter_block, dim3((n + kScatterTile - 1) / kScatterTile), dim3(256),
-                       nb * sizeof(uint32_t), s, material, n, n_mats, cursor, perm);
+    hipLaunchKernelGGL(k_scatter_block, dim3((n + kScatterTile - 1) / kScatterTile),
+                       dim3(kScatterThreads), nb * sizeof(uint32_t), s, material, n, n_mats,
+                       cursor, perm);
   else
     hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, material, n, n_mats,
                        cursor, perm);

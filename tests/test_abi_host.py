@@ -34,7 +34,8 @@ def test_struct_layouts_match_the_header():
     for i, st in enumerate([B.pmc_node_desc, B.pmc_input, B.pmc_texture_desc, B.pmc_compile_opts,
                             B.pmc_material_info, B.pmc_cache_params, B.pmc_shade_params,
                             B.pmc_stats, B.pmc_hits, B.pmc_bsdf_out, B.pmc_debug_out,
-                            B.pmc_key_record]):
+                            B.pmc_key_record, B.pmc_frame_plan, B.pmc_tune_result,
+                            B.pmc_profile]):
         assert B.pmc_abi_sizeof(i) == C.sizeof(st), st.__name__
     assert B.pmc_abi_sizeof(99) == 0
     assert C.sizeof(B.pmc_node_desc) == 244

@@ -1,0 +1,118 @@
+"""Progressive frames captured in a HIP graph, and the autotuner, against
+stream launches and the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import render, table
+from paper_2305_07238_amd import scenes
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2305_07238_amd import binding as B  # noqa: E402
+
+
+def _frames_on_device(sc, n_frames):
+    return B.hits_to_device(scenes.Hits.concat([sc.frame(f) for f in range(n_frames)]))
+
+
+def _slice(d, f, n):
+    return {k: v[f * n:(f + 1) * n] for k, v in d.items()}
+
+
+@pytest.mark.parametrize("mode", [B.PMC_MODE_SNAPSHOT, B.PMC_MODE_UNCACHED])
+def test_frame_graph_replays_match_stream_launches(mode):
+    sc = G.small_mid_scene(frames=3)
+    ctx = G.setup(sc)
+    n, F = sc.hits_per_frame, 3
+    hits = _frames_on_device(sc, F)
+    out_g = B.alloc_outputs(n * F)
+    out_s = B.alloc_outputs(n * F)
+    cache_g, cache_s = ctx.cache(1 << 13), ctx.cache(1 << 13)
+    stats_g = B.new_stats()
+    plan = ctx.frame_plan(hits, n, F, out_g, mode=mode, out_per_frame=True, clear_cache=True,
+                          stats=stats_g)
+    graph = ctx.frame_graph(cache_g if mode != B.PMC_MODE_UNCACHED else None, plan)
+    # eager reference
+    stats_s = B.new_stats()
+    for f in range(F):
+        ctx.shade(_slice(hits, f, n), _slice(out_s, f, n), cache_s if mode else None, mode=mode,
+                  frame=f, stats=stats_s)
+    torch.cuda.synchronize()
+    ref = G.to_numpy(out_s)
+    ref_table = cache_s.export()
+    st_ref = B.stats_dict(stats_s)
+    for rep in range(3):
+        stats_g.zero_()
+        for v in out_g.values():
+            v.fill_(-1.0)
+        graph.launch()
+        torch.cuda.synchronize()
+        got = G.to_numpy(out_g)
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (rep, k)
+        if mode != B.PMC_MODE_UNCACHED:
+            assert np.array_equal(cache_g.export(), ref_table), rep
+        st = B.stats_dict(stats_g)
+        for k in ("hits_shaded", "probes", "cache_hits", "inserts", "present", "cell_full",
+                  "nodes_total"):
+            assert st[k] == st_ref[k], (rep, k)
+        # eager work between replays
+        ctx.shade(_slice(hits, 0, n), _slice(out_s, 0, n), None, mode=B.PMC_MODE_UNCACHED)
+        torch.cuda.synchronize()
+
+
+def test_frame_graph_tiny_snapshot_matches_oracle():
+    sc = scenes.tiny_scene()
+    ctx = G.setup(sc)
+    n, F = sc.hits_per_frame, 4
+    hits = _frames_on_device(sc, F)
+    out = B.alloc_outputs(n)                            # every frame writes the same buffer
+    cache = ctx.cache(sc.cache.n_cells)
+    stats = B.new_stats()
+    graph = ctx.frame_graph(cache, ctx.frame_plan(hits, n, F, out, mode=B.PMC_MODE_SNAPSHOT,
+                                                  stats=stats))
+    graph.launch()
+    torch.cuda.synchronize()
+    ref_t = table.Table(sc.cache.n_cells, 8, 16)
+    res = render.shade_snapshot(sc.materials, sc.textures, [sc.frame(f) for f in range(F)], ref_t)
+    assert B.stats_dict(stats)["cache_hits"] == sum(r.stats["hits"] for r in res) == 24576
+    w = cache.words()
+    assert np.array_equal(w[:, 0] >> np.uint64(32), ref_t.words() >> np.uint64(32))
+    assert np.array_equal((w[:, 1] & np.uint64(0xFFFFFFFF)).astype(np.uint32), ref_t.stamps())
+
+
+def test_autotune_picks_a_valid_setting(tmp_path):
+    sc = G.small_mid_scene(frames=2)
+    ctx = G.setup(sc)
+    n, F = sc.hits_per_frame, 2
+    hits = _frames_on_device(sc, F)
+    out = B.alloc_outputs(n)
+    cache = ctx.cache(1 << 13)
+    plan = ctx.frame_plan(hits, n, F, out, mode=B.PMC_MODE_SNAPSHOT)
+    path = str(tmp_path / "tune.json")
+    res = ctx.autotune(cache, plan, path)
+    assert res.n_tried >= 10 and res.best_ms > 0 and res.best_ms <= res.default_ms * 1.5
+    rec = json.load(open(path))
+    assert len(rec["candidates"]) == res.n_tried
+    assert np.count_nonzero(cache.export()) == 0          # left cleared
+    # the chosen setting gives the same snapshot results as the defaults
+    b = res.best
+    out2 = B.alloc_outputs(n)
+    cache2 = ctx.cache(1 << 13)
+    for f in range(F):
+        h = _slice(hits, f, n)
+        ctx.shade(h, out, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f)
+        ctx.shade(h, out2, cache2, mode=B.PMC_MODE_SNAPSHOT, frame=f, flags=b.flags,
+                  chunk_waves=b.chunk_waves, defer_max=b.defer_max, blocks_per_cu=b.blocks_per_cu)
+    torch.cuda.synchronize()
+    assert np.array_equal(cache.export(), cache2.export())
+    for k in out:
+        assert torch.equal(out[k], out2[k])
