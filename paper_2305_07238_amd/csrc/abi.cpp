@@ -142,8 +142,9 @@ void pmc_destroy(pmc_ctx* ctx) {
   if (!ctx->host_only) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->texels,
-                      &ctx->texdesc, &ctx->perm, &ctx->counts, &ctx->cursor, &ctx->misc,
+    for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->lpt_rank,
+                      &ctx->sort_counts, &ctx->sort_offsets, &ctx->sort_sums, &ctx->texels,
+                      &ctx->texdesc, &ctx->perm, &ctx->misc,
                       &ctx->cand, &ctx->stat_slots})
       free_buf(*b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -221,7 +222,8 @@ pmc_status pmc_compile_materials(pmc_ctx* ctx, const pmc_node_desc* nodes,
     HIP_TRY(ctx, hipDeviceSynchronize());   // no batch may still read the old program
     if ((st = upload(ctx, ctx->hdr, prog.headers)) || (st = upload(ctx, ctx->instr, prog.instrs)) ||
         (st = upload(ctx, ctx->cach, prog.cach)) || (st = upload(ctx, ctx->pool, prog.pool)) ||
-        (st = upload(ctx, ctx->lpt, prog.lpt_order)))
+        (st = upload(ctx, ctx->lpt, prog.lpt_order)) ||
+        (st = upload(ctx, ctx->lpt_rank, prog.lpt_rank)))
       return st;
   }
   ctx->prog = std::move(prog);
@@ -396,18 +398,14 @@ pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mo
   const uint32_t n_mats = (uint32_t)ctx->prog.headers.size();
   pmc_status st;
   if (flags & PMC_FLAG_SORT) {
+    if (n_mats + 1 > 16384)
+      return ctx->fail(PMC_ERR_UNSUPPORTED, "material sort handles at most 16383 materials");
+    const size_t cells = (size_t)(n_mats + 1) * sort_tiles(n);
     if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
-        (st = ensure(ctx, ctx->cursor, (size_t)(n_mats + 1) * 4)))
+        (st = ensure(ctx, ctx->sort_counts, cells * 4)) ||
+        (st = ensure(ctx, ctx->sort_offsets, cells * 4)) ||
+        (st = ensure(ctx, ctx->sort_sums, ((size_t)scan_blocks((uint32_t)cells) + 1) * 4)))
       return st;
-    const size_t cbytes = (size_t)(n_mats + 1) * 4;
-    if (ctx->counts.bytes < cbytes || !ctx->counts.p) {
-      if ((st = ensure(ctx, ctx->counts, cbytes))) return st;
-      ctx->counts_cleared = 0;
-    }
-    if (ctx->counts_cleared < ctx->counts.bytes) {
-      HIP_TRY(ctx, launch_fill_u32((uint32_t*)ctx->counts.p, 0u, ctx->counts.bytes / 4, s));
-      ctx->counts_cleared = ctx->counts.bytes;
-    }
   }
   if (mode == PMC_MODE_SNAPSHOT && cache) {
     const size_t cap = (size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1);
@@ -458,9 +456,10 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   // misc[1]: snapshot candidate count (reset by the sort's scan, or filled here)
   if (sort) {
     PhaseTimer t0(ctx, 0, s);
-    HIP_TRY(ctx, launch_material_sort(hits->material, n, a.n_mats, (const uint32_t*)ctx->lpt.p,
-                                      (uint32_t*)ctx->counts.p, (uint32_t*)ctx->cursor.p,
-                                      (uint32_t*)ctx->perm.p, misc, 4, s));
+    HIP_TRY(ctx, launch_material_sort_tiled(
+                     hits->material, n, a.n_mats, (const uint32_t*)ctx->lpt_rank.p,
+                     (uint32_t*)ctx->sort_counts.p, (uint32_t*)ctx->sort_offsets.p,
+                     (uint32_t*)ctx->sort_sums.p, (uint32_t*)ctx->perm.p, misc, 4, s));
     t0.finish();
     a.perm = (const uint32_t*)ctx->perm.p;
   } else {

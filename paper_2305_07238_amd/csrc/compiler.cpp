@@ -586,6 +586,8 @@ pmc_status compile_program(const pmc_node_desc* nodes, const uint32_t* node_offs
   std::stable_sort(out.lpt_order.begin(), out.lpt_order.end(), [&](uint32_t a, uint32_t b) {
     return out.headers[a].n_instr > out.headers[b].n_instr;
   });
+  out.lpt_rank.resize(n_mats);
+  for (uint32_t r = 0; r < n_mats; ++r) out.lpt_rank[out.lpt_order[r]] = r;
   return PMC_OK;
 }
 

@@ -14,6 +14,7 @@ struct Program {
   std::vector<CachDesc> cach;
   std::vector<float> pool;              // COLOR_RAMP stops (8 positions + 8 RGBA each)
   std::vector<uint32_t> lpt_order;      // materials by decreasing program length
+  std::vector<uint32_t> lpt_rank;       // inverse: rank of each material in lpt_order
   std::vector<pmc_material_info> info;
   uint32_t max_regs = 0;
   uint32_t max_cach = 0;

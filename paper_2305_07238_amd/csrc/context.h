@@ -26,13 +26,13 @@ struct pmc_ctx {
   pmc::Program prog;
   bool compiled = false;
   // program on the device
-  DevBuf hdr, instr, cach, pool, lpt;
+  DevBuf hdr, instr, cach, pool, lpt, lpt_rank;
   // textures
   DevBuf texels, texdesc;
   uint32_t n_tex = 0;
   // workspace
-  DevBuf perm, counts, cursor, misc, cand, stat_slots;
-  size_t counts_cleared = 0;   // bytes of `counts` known to be zero
+  DevBuf perm, misc, cand, stat_slots;
+  DevBuf sort_counts, sort_offsets, sort_sums;   // tiled material sort
   bool no_alloc = false;       // set while a frame graph is captured
   // phase timing: events recorded in pairs per phase
   bool profiling = false;

@@ -81,13 +81,15 @@ uint32_t scan_blocks(uint32_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* out_copy,
                                  uint32_t* block_sums, uint32_t* total, hipStream_t s);
 
-// sort.hip: material sort.  counts/cursor: n_mats + 1 entries (last = invalid ids).
-// counts must be all-zero on entry (the scan clears it again); reset[0..n_reset) is
-// zeroed after the scan (n_reset <= 1024).
-hipError_t launch_material_sort(const uint32_t* material, uint32_t n, uint32_t n_mats,
-                                const uint32_t* lpt_order, uint32_t* counts, uint32_t* cursor,
-                                uint32_t* perm, uint32_t* reset, uint32_t n_reset,
-                                hipStream_t s);
+// Tiled counting sort (no global atomics): buckets in rank order (rank[m] =
+// position of material m by decreasing program length; invalid ids last).
+// mat_counts / offsets need (n_mats + 1) * sort_tiles(n) entries; scan_sums
+// scan_blocks(that) + 1.  reset[0..n_reset) is zeroed.
+uint32_t sort_tiles(uint32_t n);
+hipError_t launch_material_sort_tiled(const uint32_t* material, uint32_t n, uint32_t n_mats,
+                                      const uint32_t* rank, uint32_t* mat_counts,
+                                      uint32_t* offsets, uint32_t* scan_sums, uint32_t* perm,
+                                      uint32_t* reset, uint32_t n_reset, hipStream_t s);
 
 // snapshot.hip: apply the candidates of one batch in (hit, ordinal) order.
 struct SnapshotArgs {

@@ -798,7 +798,8 @@ __device__ __forceinline__ float* wave_lds(float* lds, const ShadeArgs& a) {
   return lds + (threadIdx.x >> 6) * (a.n_regs * 64 + 64);
 }
 
-template <int MODE, int KIND>
+// STATS = false: the counters are dead code and take no registers.
+template <int MODE, int KIND, bool STATS>
 __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
@@ -811,14 +812,14 @@ __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint32_t first = w * a.chunk_waves;
   if (first < n_chunks) do_run<MODE, KIND>(a, first, n_chunks, R, cnt, B);
-  flush_counters(a, cnt);
+  if (STATS) flush_counters(a, cnt);
 }
 
 // Persistent variant: a fixed grid of waves walks the runs with a static stride
 // (no shared work counter: same-address atomics serialise across the XCDs).
 // The material sort orders hits by decreasing program length, so the stride
 // deals the long programs out first.
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool STATS>
 __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
@@ -832,44 +833,44 @@ __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   for (uint32_t first = w * a.chunk_waves; first < n_chunks; first += waves * a.chunk_waves)
     do_run<MODE, KIND>(a, first, n_chunks, R, cnt, B);
-  flush_counters(a, cnt);
+  if (STATS) flush_counters(a, cnt);
 }
 
 // ---------------------------------------------------------- host launchers ---
 
 size_t shade_lds_bytes(uint32_t n_regs) { return (size_t)4 * (n_regs * 64 + 64) * sizeof(float); }
 
-template <int KIND>
+template <int MODE, int KIND, bool STATS>
+static void launch_one(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
+                       hipStream_t s) {
+  if (persistent)
+    hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_shade_flat<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s, a);
+}
+
+template <int KIND, bool STATS>
 static void launch_kind(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
                         hipStream_t s) {
-  const uint32_t mode = a.mode;
-  if (persistent) {
-    if (mode == PMC_MODE_UNCACHED)
-      hipLaunchKernelGGL((k_shade_persistent<PMC_MODE_UNCACHED, KIND>), dim3(grid), dim3(256),
-                         lds, s, a);
-    else if (mode == PMC_MODE_CACHED)
-      hipLaunchKernelGGL((k_shade_persistent<PMC_MODE_CACHED, KIND>), dim3(grid), dim3(256), lds,
-                         s, a);
-    else
-      hipLaunchKernelGGL((k_shade_persistent<PMC_MODE_SNAPSHOT, KIND>), dim3(grid), dim3(256),
-                         lds, s, a);
-  } else {
-    if (mode == PMC_MODE_UNCACHED)
-      hipLaunchKernelGGL((k_shade_flat<PMC_MODE_UNCACHED, KIND>), dim3(grid), dim3(256), lds, s,
-                         a);
-    else if (mode == PMC_MODE_CACHED)
-      hipLaunchKernelGGL((k_shade_flat<PMC_MODE_CACHED, KIND>), dim3(grid), dim3(256), lds, s, a);
-    else
-      hipLaunchKernelGGL((k_shade_flat<PMC_MODE_SNAPSHOT, KIND>), dim3(grid), dim3(256), lds, s,
-                         a);
-  }
+  if (a.mode == PMC_MODE_UNCACHED)
+    launch_one<PMC_MODE_UNCACHED, KIND, STATS>(a, persistent, grid, lds, s);
+  else if (a.mode == PMC_MODE_CACHED)
+    launch_one<PMC_MODE_CACHED, KIND, STATS>(a, persistent, grid, lds, s);
+  else
+    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS>(a, persistent, grid, lds, s);
 }
 
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,
                         hipStream_t s) {
   const size_t lds = shade_lds_bytes(a.n_regs);
-  if (kind == KIND_PROBE) launch_kind<KIND_PROBE>(a, persistent, grid, lds, s);
-  else launch_kind<KIND_FULL>(a, persistent, grid, lds, s);
+  const bool stats = a.stat_slots != nullptr;
+  if (kind == KIND_PROBE) {
+    if (stats) launch_kind<KIND_PROBE, true>(a, persistent, grid, lds, s);
+    else launch_kind<KIND_PROBE, false>(a, persistent, grid, lds, s);
+  } else {
+    if (stats) launch_kind<KIND_FULL, true>(a, persistent, grid, lds, s);
+    else launch_kind<KIND_FULL, false>(a, persistent, grid, lds, s);
+  }
   return hipGetLastError();
 }
 
