@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--mode", default="cached", choices=["cached", "snapshot", "uncached"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uncached-steps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the launch-parameter search (use sort + deferral, 4-chunk runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (for HBM counter scaling)")
     args = ap.parse_args()
@@ -132,12 +134,16 @@ def main():
     log("inputs resident; autotuning launch parameters on the first frames")
 
     tune_frames = min(4, sc.frames)
-    tune = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, tune_frames, out, mode=mode))
-    b = tune.best
-    best = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
-                blocks_per_cu=b.blocks_per_cu)
-    log(f"autotune: {best} {tune.best_ms:.3f} ms vs defaults {tune.default_ms:.3f} ms "
-        f"({tune.n_tried} settings, {tune_frames} frames)")
+    if args.no_autotune:
+        best = dict(flags=B.PMC_FLAG_SORT | (B.PMC_FLAG_DEFER if use_cache else 0),
+                    chunk_waves=4 if use_cache else 1, defer_max=48, blocks_per_cu=0)
+    else:
+        tune = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, tune_frames, out, mode=mode))
+        b = tune.best
+        best = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
+                    blocks_per_cu=b.blocks_per_cu)
+        log(f"autotune: {best} {tune.best_ms:.3f} ms vs defaults {tune.default_ms:.3f} ms "
+            f"({tune.n_tried} settings, {tune_frames} frames)")
     graph = ctx.frame_graph(use_cache, ctx.frame_plan(hits, n_frame, sc.frames, out, mode=mode,
                                                       clear_cache=True, **best))
     for _ in range(args.warmup):
@@ -222,7 +228,7 @@ def main():
         "phase_ms_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("k_shade_persistent" if b.flags & B.PMC_FLAG_PERSISTENT
+                     "kernel": ("k_shade_persistent" if best["flags"] & B.PMC_FLAG_PERSISTENT
                                 else "k_shade_flat") + "<mode>",
                      "bytes_per_launch": kb / sc.frames,
                      "avg_launch_ms": shade_ms / max(shade_launches, 1)},
