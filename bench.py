@@ -38,6 +38,30 @@ def kernel_bytes(st, n_hits):
             st["insert_attempts"] * B_INSERT + st["texture_evals"] * B_TEXEL)
 
 
+KERNEL_SOURCES = ("shade.hip", "shade.h", "device_common.h", "program.h")
+
+
+def measured_traffic(workload_name, best):
+    """HBM bytes per launch of the shade kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration), or None
+    when the kernel sources or the launch settings differ from the profiled ones."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "shade_%s_traffic.json" % workload_name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_07238_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    if any(rec[k] != best[k] for k in ("flags", "chunk_waves", "defer_max")):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def scenes_concat(sc):
     from paper_2305_07238_amd import scenes
     return scenes.Hits.concat([sc.frame(f) for f in range(sc.frames)])
@@ -227,7 +251,8 @@ def main():
         "stats": st,
         "phase_ms_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, best),
                      "kernel": ("k_shade_persistent" if best["flags"] & B.PMC_FLAG_PERSISTENT
                                 else "k_shade_flat") + "<mode>",
                      "bytes_per_launch": kb / sc.frames,
