@@ -127,9 +127,10 @@ void pmc_destroy(pmc_ctx* ctx);
 /* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
 const char* pmc_last_error(const pmc_ctx* ctx);
 /* ABI version (PMC_ABI_VERSION) and sizeof of the public structs, by index
- * 0..14 (node_desc, input, texture_desc, compile_opts, material_info,
+ * 0..19 (node_desc, input, texture_desc, compile_opts, material_info,
  * cache_params, shade_params, stats, hits, bsdf_out, debug_out, key_record,
- * frame_plan, tune_result, profile); 0 for an unknown index. */
+ * frame_plan, tune_result, profile, surrogate_opts, surrogate_slot,
+ * log_record, train_params, surrogate_stat); 0 for an unknown index. */
 uint32_t pmc_abi_version(void);
 size_t pmc_abi_sizeof(uint32_t which);
 
@@ -205,7 +206,8 @@ typedef struct pmc_bsdf_out {  /* device pointers, caller-owned */
 
 /* Optional per-(hit, ordinal) diagnostics, device pointers (may be NULL). */
 typedef struct pmc_debug_out {
-    uint8_t* state;            /* [n][8]: 0 miss, 1 cache hit, 2 bypass, 3 no such ordinal */
+    uint8_t* state;            /* [n][8]: 0 miss, 1 cache hit, 2 bypass, 3 no such ordinal,
+                                  4 value from the surrogate network */
     float* value;              /* [n][8][3]: decoded value on a cache hit (unspecified otherwise) */
 } pmc_debug_out;
 
@@ -218,8 +220,14 @@ enum pmc_mode {
 enum pmc_flags {
     PMC_FLAG_SORT = 1u,        /* sort hits by material first so each wave runs one program */
     PMC_FLAG_PERSISTENT = 2u,  /* a fixed grid of waves walks the work with a static stride */
-    PMC_FLAG_DEFER = 4u        /* cached modes: stage sparse misses per wave and evaluate them
+    PMC_FLAG_DEFER = 4u,       /* cached modes: stage sparse misses per wave and evaluate them
                                   in dense passes (see defer_max) instead of in place */
+    PMC_FLAG_LOG = 8u,         /* cached modes: append a pmc_log_record for each value of a
+                                  surrogated output that is inserted (CACHED: the CAS or eviction
+                                  succeeded; SNAPSHOT: a candidate was emitted) */
+    PMC_FLAG_SURROGATE = 16u   /* cached modes: a missed surrogated output of a trusted material
+                                  takes its value from the material's network (not inserted);
+                                  see the surrogate section below */
 };
 
 typedef struct pmc_shade_params {
@@ -257,7 +265,11 @@ typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade
     uint64_t texture_evals_deferred;    /* texture_evals done while evaluating deferred hits */
     uint64_t insert_attempts_deferred;  /* insert_attempts made for deferred hits */
     uint64_t probes_deferred;  /* lookups repeated when a staged hit is evaluated */
-    uint64_t reserved[12];
+    uint64_t surrogate_used;   /* missed outputs whose value came from a surrogate network */
+    uint64_t logged;           /* records appended to the insert log */
+    uint64_t audited;          /* surrogate-eligible misses evaluated by the graph instead, to
+                                  measure the network's live error */
+    uint64_t reserved[9];
 } pmc_stats;                   /* 256 bytes */
 
 /* Shade one batch (one progressive pass).  cache NULL or mode UNCACHED:
@@ -338,6 +350,131 @@ typedef struct pmc_tune_result {
 } pmc_tune_result;
 pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* plan,
                         pmc_tune_result* out, const char* json_path);
+
+/* ------------------------------------------------------ learned surrogate */
+
+/* Beyond the paper, which caches exact sub-graph values only (Sec. 3): a small
+ * per-material network may stand in for the deepest cacheable sub-graphs on a
+ * cache miss.  The graph stays both the fallback and the judge of the
+ * network's error.
+ *
+ *   surrogated outputs  cacheable outputs whose sub-graph has more than
+ *                       min_subgraph_nodes nodes, packed in ordinal order into
+ *                       4 channels (COLOR 3, FLOAT 1) while they fit; one
+ *                       network ("slot") per material that has any
+ *   features            x[4k..4k+3] = sin(w_k u), cos(w_k u), sin(w_k v), cos(w_k v),
+ *                       w_k = 2 pi 2^(k-3), k = 0..7
+ *   network             h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3
+ *                       with W1 64x32, W2 64x64, W3 4x64: 6532 parameters, stored
+ *                       flat as W1 (row-major [out][in]), b1, W2, b2, W3, b3
+ *   arithmetic          x, weights and activations in binary16 (round to nearest
+ *                       even), products accumulated in FP32 on the matrix cores;
+ *                       biases and the master weights in FP32
+ *   training            mean squared error over the used channels of each sample,
+ *                       Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the master
+ *                       weights; batch sample i of step t is record
+ *                       mix64(seed ^ (t << 32 | i)) mod n_train (SplitMix64 finalizer)
+ *   trust               after training, the maximum absolute error over the
+ *                       held-out records (used channels) must be <= max_err.
+ *                       While shading with PMC_FLAG_SURROGATE, a hit h of frame f
+ *                       with mix64(((f << 32) | h) ^ 0xD6E8FEB86659FD93) >> 58 == 0
+ *                       (1 in 64) is evaluated by the graph instead, and the error of
+ *                       the network there is recorded; a slot whose live error
+ *                       exceeds max_err loses its trust after that call. */
+typedef struct pmc_surrogate_opts {
+    uint32_t min_subgraph_nodes;   /* surrogate outputs with larger sub-graphs; 0 = 32 */
+    uint32_t log_capacity;         /* insert-log records, multiple of 64; 0 = 2^20 */
+    uint64_t seed;                 /* He-uniform initialisation of every slot */
+    float max_err;                 /* trust threshold (max abs error); 0 = 1e-2 */
+    uint32_t reserved[3];
+} pmc_surrogate_opts;
+
+/* Choose the surrogated outputs of the compiled materials, create one slot per
+ * material that has any, initialise their weights, and allocate the insert
+ * log (device contexts).  Replaces an earlier setup.  Host-only contexts get
+ * the slot table only.  *n_slots receives the slot count.  Synchronous. */
+pmc_status pmc_surrogate_setup(pmc_ctx* ctx, const pmc_surrogate_opts* opts, uint32_t* n_slots);
+
+typedef struct pmc_surrogate_slot {
+    uint32_t material;
+    uint32_t ordinal_mask;         /* bit c: cacheable ordinal c is surrogated */
+    uint32_t n_channels;           /* channels used, 1..4 */
+    uint32_t channel[8];           /* first channel of each surrogated ordinal */
+    uint32_t reserved;
+} pmc_surrogate_slot;
+pmc_status pmc_surrogate_get_slot(const pmc_ctx* ctx, uint32_t slot, pmc_surrogate_slot* out);
+
+/* Insert-log record (32 bytes): the exact UV of the hit and the FP32 value
+ * the graph produced there (COLOR: value[0..2]; FLOAT: value[0]; rest 0). */
+typedef struct pmc_log_record {
+    uint32_t material;
+    uint32_t ordinal;
+    float u, v;
+    float value[4];
+} pmc_log_record;
+/* Empty the log (asynchronous). */
+pmc_status pmc_log_clear(pmc_ctx* ctx, void* stream);
+/* Copy up to max records to host memory; *n gets the number held.  The log is
+ * split into 64 regions filled independently; records come region by region.
+ * Synchronous. */
+pmc_status pmc_log_read(pmc_ctx* ctx, pmc_log_record* host_out, uint64_t max, uint64_t* n,
+                        void* stream);
+
+/* Master weights of a slot (6532 FP32 in the flat order above), host memory.
+ * Setting them also resets the slot's Adam state and step count and clears
+ * its trust.  Synchronous. */
+pmc_status pmc_surrogate_set_params(pmc_ctx* ctx, uint32_t slot, const float* host_params);
+pmc_status pmc_surrogate_get_params(pmc_ctx* ctx, uint32_t slot, float* host_params);
+/* Force (trusted != 0) or clear a slot's trust.  Asynchronous. */
+pmc_status pmc_surrogate_set_trust(pmc_ctx* ctx, uint32_t slot, int trusted, void* stream);
+
+typedef struct pmc_train_params {
+    uint32_t steps;                /* Adam steps per slot; 0 = 2000 */
+    uint32_t batch;                /* samples per step, multiple of 128; 0 = 4096 */
+    float lr;                      /* 0 = 1e-3 */
+    uint32_t holdout;              /* held-out records per slot (at most a quarter of them);
+                                      0 = 4096 */
+    uint32_t min_records;          /* slots with fewer log records are skipped; 0 = 1024 */
+    uint32_t reserved;
+    uint64_t seed;                 /* batch sampling */
+} pmc_train_params;
+/* Train every slot on its records of the insert log, all slots at once (one
+ * workgroup each): the log is grouped by slot, the last `holdout` records of
+ * each group are held out, `steps` Adam steps are taken on the rest, and the
+ * held-out error decides the trust.  Asynchronous; read the outcome with
+ * pmc_surrogate_report. */
+pmc_status pmc_surrogate_train(pmc_ctx* ctx, const pmc_train_params* params, void* stream);
+
+/* The same training on caller records (device, n of them, all of the slot's
+ * material), without hold-out or trust change.  Asynchronous. */
+pmc_status pmc_surrogate_train_records(pmc_ctx* ctx, uint32_t slot, const pmc_log_record* records,
+                                       uint32_t n, const pmc_train_params* params, void* stream);
+/* Loss and gradient of the slot's current weights over exactly the n caller
+ * records (device): grads (device, 6532 FP32, flat order) = dL/dparams with
+ * L = sum over used channels (y - target)^2 / (number of used channels);
+ * loss (device, 1 FP32).  Asynchronous. */
+pmc_status pmc_surrogate_grad(pmc_ctx* ctx, uint32_t slot, const pmc_log_record* records,
+                              uint32_t n, float* grads, float* loss, void* stream);
+/* Network outputs y (device [n][4]) at uv (device [n][2]).  Asynchronous. */
+pmc_status pmc_surrogate_infer(pmc_ctx* ctx, uint32_t slot, const float* uv, uint32_t n,
+                               float* y, void* stream);
+
+typedef struct pmc_surrogate_stat {
+    uint32_t material;
+    uint32_t trusted;
+    uint32_t n_train;              /* records trained on by the last pmc_surrogate_train */
+    uint32_t n_heldout;
+    float max_err;                 /* held-out maximum / mean absolute error (used channels) */
+    float mean_err;
+    float loss;                    /* training loss of the last step */
+    float live_max_err;            /* largest error seen on audited hits since the last training */
+    uint32_t steps;                /* Adam steps taken since the weights were set */
+    uint32_t live_checked;         /* audited outputs since the last training */
+    uint32_t reserved[2];
+} pmc_surrogate_stat;              /* 48 bytes */
+/* Copy the per-slot statistics of slots [0, n) to host memory.  Synchronous. */
+pmc_status pmc_surrogate_report(pmc_ctx* ctx, pmc_surrogate_stat* host_out, uint32_t n,
+                                void* stream);
 
 /* ------------------------------------------------------------- profiling */
 

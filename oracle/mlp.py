@@ -23,12 +23,20 @@ binary16 before their products.
 Batch sampling uses a counter-based generator so both sides draw the same
 indices: index(step, i) = mix64(seed ^ (step << 32 | i)) mod n_train, with the
 SplitMix64 finalizer (see hashing.py).
+
+Shading with the network: a missed (not bypassed) surrogated output of a
+trusted material takes the network's value, unless the hit is audited:
+hit h of frame f is audited when mix64(((f << 32) | h) ^ SEED_AUDIT) >> 58 is 0
+(one in 64); audited hits are evaluated by the graph as usual.
 """
 import numpy as np
 
 from .hashing import mix64
 
 N_FEAT, N_HID, N_OUT = 32, 64, 4
+N_PARAMS = 6532
+SEED_AUDIT = 0xD6E8FEB86659FD93
+_SHAPES = ((64, 32), (64,), (64, 64), (64,), (4, 64), (4,))
 OMEGA = 2.0 * np.pi * 2.0 ** (np.arange(8) - 3.0)
 
 
@@ -91,6 +99,47 @@ def adam_update(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         out_m.append(mm)
         out_v.append(vv)
     return out_p, out_m, out_v
+
+
+def unflatten(flat):
+    """Flat parameter vector (W1, b1, W2, b2, W3, b3; W row-major [out][in]) -> list."""
+    flat = np.asarray(flat, dtype=np.float64).ravel()
+    out, k = [], 0
+    for shp in _SHAPES:
+        n = int(np.prod(shp))
+        out.append(flat[k:k + n].reshape(shp))
+        k += n
+    assert k == N_PARAMS
+    return out
+
+
+def flatten(params):
+    return np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in params])
+
+
+def audited(frame, h):
+    h = np.asarray(h, dtype=np.uint64)
+    z = mix64(((np.uint64(frame) << np.uint64(32)) | h) ^ np.uint64(SEED_AUDIT))
+    return (z >> np.uint64(58)) == 0
+
+
+def targets(records, ordmap):
+    """Training targets and channel masks of log records.
+
+    records: structured array with fields ordinal and value[4]; ordmap: dict
+    ordinal -> (first channel, width).  Returns (target [n, 4], mask [n, 4]).
+    """
+    n = len(records)
+    t = np.zeros((n, N_OUT))
+    m = np.zeros((n, N_OUT))
+    for i in range(n):
+        o = int(records["ordinal"][i])
+        if o not in ordmap:
+            continue
+        base, width = ordmap[o]
+        t[i, base:base + width] = records["value"][i][:width]
+        m[i, base:base + width] = 1.0
+    return t, m
 
 
 def batch_indices(seed, step, batch, n_train):

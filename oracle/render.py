@@ -17,7 +17,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from . import codec, graph, keys as K
+from . import codec, graph, keys as K, mlp
 from .table import FIRST, Table
 
 
@@ -57,14 +57,31 @@ class FrameResult:
         self.bypass = np.zeros((n, kmax), dtype=bool)
         self.valid = np.zeros((n, kmax), dtype=bool)        # ordinal exists for the hit's material
         self.found_value = np.full((n, kmax, 3), np.nan)    # decoded value on a cache hit
+        self.surrogate = np.zeros((n, kmax), dtype=bool)    # value taken from the network
+        self.surrogate_value = np.full((n, kmax, 3), np.nan)
+        self.audited = np.zeros((n, kmax), dtype=bool)      # eligible, evaluated by the graph
+        self.live_err = {}                                  # material -> max audited error
+        self.log = []                                       # (material, ordinal, u, v, value)
         self.stats = Counter()
 
 
 def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
                          policy: str = FIRST, level_bias: int = 0,
                          level_max: int = K.LEVEL_MAX_DEFAULT, min_subgraph_nodes: int = 2,
-                         kmax: int = 8, cacheables: Optional[list] = None) -> FrameResult:
-    """One snapshot-mode frame; mutates ``table`` into T_f and returns the frame's results."""
+                         kmax: int = 8, cacheables: Optional[list] = None,
+                         surrogate: Optional[dict] = None,
+                         surrogate_values: Optional[np.ndarray] = None) -> FrameResult:
+    """One snapshot-mode frame; mutates ``table`` into T_f and returns the frame's results.
+
+    surrogate: optional {material: dict(params=[W1, b1, W2, b2, W3, b3],
+    ordmap={ordinal: (first channel, width)}, trusted=bool)} of the materials
+    that have a network.  For a trusted one, a missed surrogated output that
+    is not audited takes the network's value (FP16 rounding points of
+    mlp.forward) and is not inserted; for every one, the inserts of its
+    surrogated outputs are logged.  surrogate_values [n, kmax, 3], if given,
+    replaces the network's values at the substituted entries (to check what
+    follows them against another implementation's network outputs).
+    """
     n = len(hits)
     res = FrameResult(n, kmax)
     mat = hits.material.astype(np.int64)
@@ -112,6 +129,35 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
                                        else np.zeros(len(idx)))
                 full = subst[(node, sock)][1]
                 full[found] = dv
+        sinfo = surrogate.get(int(m)) if surrogate else None
+        y_net = None
+        if sinfo is not None and sinfo["trusted"]:
+            y_net, _ = mlp.forward(sinfo["params"], mlp.features(hits.uv[idx]), round16=True)
+            aud = mlp.audited(frame, idx)
+            for c, (base, width) in sinfo["ordmap"].items():
+                node, sock = cach[c]
+                otype = graph.output_type(material, node, sock)
+                eligible = ~res.found[idx, c] & ~res.bypass[idx, c]
+                sm = eligible & ~aud
+                res.audited[idx, c] = eligible & aud
+                if not sm.any():
+                    continue
+                vals = y_net[:, base:base + width].copy()
+                if surrogate_values is not None:
+                    vals[sm] = surrogate_values[idx[sm], c, :width]
+                res.surrogate[idx, c] = sm
+                res.surrogate_value[idx[sm], c, :width] = vals[sm]
+                res.stats["surrogate_used"] += int(sm.sum())
+                prev = subst.get((node, sock))
+                if prev is None:
+                    prev = (np.zeros(len(idx), dtype=bool),
+                            np.zeros((len(idx), 3)) if otype == "COLOR" else np.zeros(len(idx)))
+                mask, full = prev
+                if otype == "COLOR":
+                    full[sm] = vals[sm]
+                else:
+                    full[sm] = vals[sm, 0]
+                subst[(node, sock)] = (mask | sm, full)
         out, values = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures, subst)
         for k in res.outputs:
             res.outputs[k][idx] = out[k]
@@ -119,7 +165,7 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
             ky = key_list[c]
             otype = graph.output_type(material, node, sock)
             v = values[(node, sock)]
-            miss = np.nonzero(~res.found[idx, c] & ~ky.bypass)[0]
+            miss = np.nonzero(~res.found[idx, c] & ~ky.bypass & ~res.surrogate[idx, c])[0]
             vals = v[miss]
             fin = np.isfinite(vals) if vals.ndim == 1 else np.all(np.isfinite(vals), axis=1)
             res.stats["nonfinite"] += int((~fin).sum())
@@ -127,6 +173,19 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
             encs = encode(vals, otype)
             for j, enc in zip(miss, encs):
                 candidates.append((int(idx[j]), c, int(ky.cell[j]), int(ky.hash2[j]), int(enc)))
+            if sinfo is not None and c in sinfo["ordmap"]:
+                base, width = sinfo["ordmap"][c]
+                for j, val in zip(miss, vals):
+                    vv = np.zeros(4)
+                    vv[:width] = np.atleast_1d(val)[:width]
+                    res.log.append((int(m), c, float(hits.uv[idx[j], 0]),
+                                    float(hits.uv[idx[j], 1]), vv))
+                if y_net is not None:
+                    au = np.nonzero(res.audited[idx, c])[0]
+                    if len(au):
+                        g = np.asarray(v[au], dtype=np.float64).reshape(len(au), -1)[:, :width]
+                        e = np.abs(g - y_net[au, base:base + width]).max()
+                        res.live_err[int(m)] = max(res.live_err.get(int(m), 0.0), float(e))
     res.stats["misses"] = res.stats["probes"] - res.stats["hits"]
     res.stats["candidates"] = len(candidates)
     candidates.sort(key=lambda t: (t[0], t[1]))
@@ -137,9 +196,10 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
 
 def shade_snapshot(materials, textures, frames: List, table: Table, policy: str = FIRST,
                    level_bias: int = 0, level_max: int = K.LEVEL_MAX_DEFAULT,
-                   min_subgraph_nodes: int = 2, kmax: int = 8, first_frame: int = 0):
+                   min_subgraph_nodes: int = 2, kmax: int = 8, first_frame: int = 0,
+                   surrogate: Optional[dict] = None):
     """Progressive snapshot render of a list of hit batches; returns one FrameResult each."""
     cach = [graph.cacheable_outputs(m, min_subgraph_nodes) for m in materials]
     return [shade_snapshot_frame(materials, textures, h, table, first_frame + f, policy,
-                                 level_bias, level_max, min_subgraph_nodes, kmax, cach)
+                                 level_bias, level_max, min_subgraph_nodes, kmax, cach, surrogate)
             for f, h in enumerate(frames)]

@@ -31,7 +31,8 @@ MATH_OPS = {"ADD": 0, "MUL": 1, "POW": 2}
 PMC_NODE_CLAMP = 1
 PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE = 0, 1
 PMC_MODE_UNCACHED, PMC_MODE_CACHED, PMC_MODE_SNAPSHOT = 0, 1, 2
-PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_DEFER = 1, 2, 4
+PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_DEFER, PMC_FLAG_LOG, PMC_FLAG_SURROGATE = 1, 2, 4, 8, 16
+N_PARAMS = 6532
 MAX_CACHEABLE = 8
 
 
@@ -105,11 +106,44 @@ STAT_FIELDS = ("hits_shaded", "probes", "cache_hits", "bypasses", "inserts", "ca
                "present", "cell_full", "overwrites", "nonfinite", "candidates",
                "nodes_executed", "nodes_total", "invalid_material", "texture_evals",
                "deferred", "insert_attempts", "texture_evals_deferred",
-               "insert_attempts_deferred", "probes_deferred")
+               "insert_attempts_deferred", "probes_deferred", "surrogate_used", "logged",
+               "audited")
 
 
 class pmc_stats(C.Structure):
-    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64 * 12)]
+    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [("reserved", C.c_uint64 * 9)]
+
+
+class pmc_surrogate_opts(C.Structure):
+    _fields_ = [("min_subgraph_nodes", C.c_uint32), ("log_capacity", C.c_uint32),
+                ("seed", C.c_uint64), ("max_err", C.c_float), ("reserved", C.c_uint32 * 3)]
+
+
+class pmc_surrogate_slot(C.Structure):
+    _fields_ = [("material", C.c_uint32), ("ordinal_mask", C.c_uint32),
+                ("n_channels", C.c_uint32), ("channel", C.c_uint32 * 8),
+                ("reserved", C.c_uint32)]
+
+
+class pmc_train_params(C.Structure):
+    _fields_ = [("steps", C.c_uint32), ("batch", C.c_uint32), ("lr", C.c_float),
+                ("holdout", C.c_uint32), ("min_records", C.c_uint32), ("reserved", C.c_uint32),
+                ("seed", C.c_uint64)]
+
+
+SURROGATE_STAT_FIELDS = ("material", "trusted", "n_train", "n_heldout", "max_err", "mean_err",
+                         "loss", "live_max_err", "steps", "live_checked")
+
+
+class pmc_surrogate_stat(C.Structure):
+    _fields_ = [("material", C.c_uint32), ("trusted", C.c_uint32), ("n_train", C.c_uint32),
+                ("n_heldout", C.c_uint32), ("max_err", C.c_float), ("mean_err", C.c_float),
+                ("loss", C.c_float), ("live_max_err", C.c_float), ("steps", C.c_uint32),
+                ("live_checked", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+
+
+LOG_RECORD_DTYPE = np.dtype([("material", "<u4"), ("ordinal", "<u4"), ("u", "<f4"),
+                             ("v", "<f4"), ("value", "<f4", (4,))])
 
 
 PROFILE_PHASES = ("sort", "shade", "snapshot", "stats")
@@ -158,6 +192,19 @@ _proto = {
                           C.c_char_p]),
     "pmc_profile_enable": (_S, [_P, C.c_int]),
     "pmc_profile_read": (_S, [_P, C.POINTER(pmc_profile), C.c_int]),
+    "pmc_surrogate_setup": (_S, [_P, C.POINTER(pmc_surrogate_opts), C.POINTER(C.c_uint32)]),
+    "pmc_surrogate_get_slot": (_S, [_P, C.c_uint32, C.POINTER(pmc_surrogate_slot)]),
+    "pmc_log_clear": (_S, [_P, _P]),
+    "pmc_log_read": (_S, [_P, _P, C.c_uint64, C.POINTER(C.c_uint64), _P]),
+    "pmc_surrogate_set_params": (_S, [_P, C.c_uint32, _P]),
+    "pmc_surrogate_get_params": (_S, [_P, C.c_uint32, _P]),
+    "pmc_surrogate_set_trust": (_S, [_P, C.c_uint32, C.c_int, _P]),
+    "pmc_surrogate_train": (_S, [_P, C.POINTER(pmc_train_params), _P]),
+    "pmc_surrogate_train_records": (_S, [_P, C.c_uint32, _P, C.c_uint32,
+                                         C.POINTER(pmc_train_params), _P]),
+    "pmc_surrogate_grad": (_S, [_P, C.c_uint32, _P, C.c_uint32, _P, _P, _P]),
+    "pmc_surrogate_infer": (_S, [_P, C.c_uint32, _P, C.c_uint32, _P, _P]),
+    "pmc_surrogate_report": (_S, [_P, C.POINTER(pmc_surrogate_stat), C.c_uint32, _P]),
 }
 for _name, (_res, _args) in _proto.items():
     _fn = getattr(lib, _name)
@@ -338,6 +385,76 @@ class Context:
                                 json_path.encode() if json_path else None))
         return res
 
+    # ---------------------------------------------------------- surrogate --
+    def surrogate_setup(self, min_subgraph_nodes: int = 0, log_capacity: int = 0, seed: int = 0,
+                        max_err: float = 0.0) -> int:
+        o = pmc_surrogate_opts(min_subgraph_nodes, log_capacity, seed, max_err)
+        n = C.c_uint32()
+        self.check(pmc_surrogate_setup(self.h, C.byref(o), C.byref(n)))
+        self.n_slots = n.value
+        return n.value
+
+    def surrogate_slot(self, slot: int) -> dict:
+        s = pmc_surrogate_slot()
+        self.check(pmc_surrogate_get_slot(self.h, slot, C.byref(s)))
+        return {"material": s.material, "ordinal_mask": s.ordinal_mask,
+                "n_channels": s.n_channels, "channel": list(s.channel)}
+
+    def log_clear(self, stream=None):
+        self.check(pmc_log_clear(self.h, _stream_ptr(stream)))
+
+    def log_read(self, max_records: int = 1 << 26, stream=None) -> np.ndarray:
+        n = C.c_uint64()
+        self.check(pmc_log_read(self.h, None, 0, C.byref(n), _stream_ptr(stream)))
+        k = min(n.value, max_records)
+        buf = np.zeros(k, LOG_RECORD_DTYPE)
+        if k:
+            self.check(pmc_log_read(self.h, buf.ctypes.data, k, C.byref(n),
+                                    _stream_ptr(stream)))
+        return buf
+
+    def surrogate_set_params(self, slot: int, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == N_PARAMS
+        self.check(pmc_surrogate_set_params(self.h, slot, p.ctypes.data))
+
+    def surrogate_get_params(self, slot: int) -> np.ndarray:
+        p = np.zeros(N_PARAMS, np.float32)
+        self.check(pmc_surrogate_get_params(self.h, slot, p.ctypes.data))
+        return p
+
+    def surrogate_set_trust(self, slot: int, trusted: bool, stream=None):
+        self.check(pmc_surrogate_set_trust(self.h, slot, 1 if trusted else 0,
+                                           _stream_ptr(stream)))
+
+    def surrogate_train(self, steps: int = 0, batch: int = 0, lr: float = 0.0, holdout: int = 0,
+                        min_records: int = 0, seed: int = 0, stream=None):
+        p = pmc_train_params(steps, batch, lr, holdout, min_records, 0, seed)
+        self.check(pmc_surrogate_train(self.h, C.byref(p), _stream_ptr(stream)))
+
+    def surrogate_train_records(self, slot: int, records, steps: int = 0, batch: int = 0,
+                                lr: float = 0.0, seed: int = 0, stream=None):
+        """records: torch uint8/int32 CUDA tensor holding n packed pmc_log_record."""
+        n = records.numel() * records.element_size() // 32
+        p = pmc_train_params(steps, batch, lr, 0, 0, 0, seed)
+        self.check(pmc_surrogate_train_records(self.h, slot, _ptr(records), n, C.byref(p),
+                                               _stream_ptr(stream)))
+
+    def surrogate_grad(self, slot: int, records, grads, loss, stream=None):
+        n = records.numel() * records.element_size() // 32
+        self.check(pmc_surrogate_grad(self.h, slot, _ptr(records), n, _ptr(grads), _ptr(loss),
+                                      _stream_ptr(stream)))
+
+    def surrogate_infer(self, slot: int, uv, y, stream=None):
+        self.check(pmc_surrogate_infer(self.h, slot, _ptr(uv), int(uv.shape[0]), _ptr(y),
+                                       _stream_ptr(stream)))
+
+    def surrogate_report(self, stream=None) -> List[dict]:
+        n = getattr(self, "n_slots", 0)
+        arr = (pmc_surrogate_stat * max(n, 1))()
+        self.check(pmc_surrogate_report(self.h, arr, n, _stream_ptr(stream)))
+        return [{f: getattr(arr[k], f) for f in SURROGATE_STAT_FIELDS} for k in range(n)]
+
     def debug_keys(self, cache: "Cache", hits: dict, out, stream=None):
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), int(hits["material"].numel()))
@@ -439,6 +556,13 @@ def alloc_outputs(n: int, device="cuda"):
     return {"base_color": torch.empty((n, 3), dtype=torch.float32, device=device),
             "roughness": torch.empty((n,), dtype=torch.float32, device=device),
             "normal": torch.empty((n, 3), dtype=torch.float32, device=device)}
+
+
+def records_to_device(records: np.ndarray, device="cuda"):
+    """LOG_RECORD_DTYPE array -> torch int32 tensor of the packed 32-byte records."""
+    import torch
+    raw = np.ascontiguousarray(records, LOG_RECORD_DTYPE).view(np.int32).reshape(-1, 8)
+    return torch.from_numpy(raw.copy()).to(device)
 
 
 def new_stats(device="cuda"):

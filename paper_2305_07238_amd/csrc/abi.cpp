@@ -95,6 +95,11 @@ size_t pmc_abi_sizeof(uint32_t which) {
     case 12: return sizeof(pmc_frame_plan);
     case 13: return sizeof(pmc_tune_result);
     case 14: return sizeof(pmc_profile);
+    case 15: return sizeof(pmc_surrogate_opts);
+    case 16: return sizeof(pmc_surrogate_slot);
+    case 17: return sizeof(pmc_log_record);
+    case 18: return sizeof(pmc_train_params);
+    case 19: return sizeof(pmc_surrogate_stat);
     default: return 0;
   }
 }
@@ -145,7 +150,10 @@ void pmc_destroy(pmc_ctx* ctx) {
     for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->lpt_rank,
                       &ctx->sort_counts, &ctx->sort_offsets, &ctx->sort_sums, &ctx->texels,
                       &ctx->texdesc, &ctx->perm, &ctx->misc,
-                      &ctx->cand, &ctx->stat_slots})
+                      &ctx->cand, &ctx->stat_slots, &ctx->surr.w, &ctx->surr.master,
+                      &ctx->surr.state, &ctx->surr.mat_slot_dev, &ctx->surr.log,
+                      &ctx->surr.log_count, &ctx->surr.slot_count, &ctx->surr.slot_begin,
+                      &ctx->surr.slot_cursor, &ctx->surr.scan_sums, &ctx->surr.grouped})
       free_buf(*b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   }
@@ -228,6 +236,9 @@ pmc_status pmc_compile_materials(pmc_ctx* ctx, const pmc_node_desc* nodes,
   }
   ctx->prog = std::move(prog);
   ctx->compiled = true;
+  ctx->surr.ready = false;     // slots refer to the old graph set: set up again
+  ctx->surr.n_slots = 0;
+  ctx->surr.slots.clear();
   return PMC_OK;
 }
 
@@ -385,8 +396,11 @@ pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits
   if (pmc_status st = check_hits(ctx, hits)) return st;
   if (!params) return ctx->fail(PMC_ERR_INVALID, "null params");
   if (params->mode > PMC_MODE_SNAPSHOT) return ctx->fail(PMC_ERR_INVALID, "unknown mode");
-  if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT | PMC_FLAG_DEFER))
+  if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT | PMC_FLAG_DEFER |
+                                  PMC_FLAG_LOG | PMC_FLAG_SURROGATE))
     return ctx->fail(PMC_ERR_INVALID, "unknown flags");
+  if ((params->flags & (PMC_FLAG_LOG | PMC_FLAG_SURROGATE)) && !ctx->surr.ready)
+    return ctx->fail(PMC_ERR_STATE, "PMC_FLAG_LOG / PMC_FLAG_SURROGATE need pmc_surrogate_setup");
   if (hits->n && (!out || !out->base_color || !out->roughness || !out->normal))
     return ctx->fail(PMC_ERR_INVALID, "null output array");
   if (cache && cache->ctx != ctx) return ctx->fail(PMC_ERR_INVALID, "cache of another context");
@@ -452,6 +466,17 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.dbg_value = dbg ? dbg->value : nullptr;
   uint32_t* misc = (uint32_t*)ctx->misc.p;
   if (mode != PMC_MODE_UNCACHED) fill_cache_args(cache, a);
+  const bool surr = (params->flags & PMC_FLAG_SURROGATE) && mode != PMC_MODE_UNCACHED;
+  const bool logged = (params->flags & PMC_FLAG_LOG) && mode != PMC_MODE_UNCACHED;
+  if (surr || logged) {
+    a.surr_w = (const SurrW*)ctx->surr.w.p;
+    a.surr_state = (SurrState*)ctx->surr.state.p;
+  }
+  if (logged) {
+    a.log = (pmc_log_record*)ctx->surr.log.p;
+    a.log_count = (uint32_t*)ctx->surr.log_count.p;
+    a.log_region_cap = ctx->surr.log_cap / 64u;
+  }
 
   // misc[1]: snapshot candidate count (reset by the sort's scan, or filled here)
   if (sort) {
@@ -490,7 +515,8 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     grid = (runs + 3) / 4;
   }
   PhaseTimer t1(ctx, 1, s);
-  HIP_TRY(ctx, launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, grid, s));
+  HIP_TRY(ctx,
+          launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, surr, grid, s));
   t1.finish();
   if (mode == PMC_MODE_SNAPSHOT) {
     SnapshotArgs sa;
@@ -513,6 +539,8 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     HIP_TRY(ctx, launch_snapshot_apply(sa, s));
     t2.finish();
   }
+  if (surr) HIP_TRY(ctx, launch_surr_live_update((SurrState*)ctx->surr.state.p,
+                                                 ctx->surr.n_slots, s));
   if (stats) {
     PhaseTimer t3(ctx, 3, s);
     HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));

@@ -18,6 +18,18 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Surrogate networks and the insert log (pmc_surrogate_setup).
+struct SurrHost {
+  bool ready = false;
+  uint32_t n_slots = 0;
+  uint32_t log_cap = 0;                     // records, 64 regions of log_cap / 64
+  float max_err = 1e-2f;
+  std::vector<pmc_surrogate_slot> slots;
+  std::vector<uint32_t> mat_slot;           // per material, 0xFFFFFFFF = none
+  DevBuf w, master, state, mat_slot_dev, log, log_count;
+  DevBuf slot_count, slot_begin, slot_cursor, scan_sums, grouped;
+};
+
 struct pmc_ctx {
   int device = -1;
   bool host_only = true;
@@ -33,6 +45,7 @@ struct pmc_ctx {
   // workspace
   DevBuf perm, misc, cand, stat_slots;
   DevBuf sort_counts, sort_offsets, sort_sums;   // tiled material sort
+  SurrHost surr;
   bool no_alloc = false;       // set while a frame graph is captured
   // phase timing: events recorded in pairs per phase
   bool profiling = false;

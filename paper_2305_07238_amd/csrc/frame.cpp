@@ -159,7 +159,9 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
 
   struct Cand { uint32_t flags, chunk_waves, defer_max, bpc; double ms; };
   std::vector<Cand> cands;
-  const uint32_t base = PMC_FLAG_SORT;
+  // the surrogate choice is the caller's (it changes results); logging is not
+  // wanted while tuning
+  const uint32_t base = PMC_FLAG_SORT | (plan->params.flags & PMC_FLAG_SURROGATE);
   for (uint32_t pers = 0; pers < 2; ++pers) {
     const uint32_t pf = pers ? PMC_FLAG_PERSISTENT : 0u;
     for (uint32_t cw : {1u, 2u, 4u}) cands.push_back({base | pf, cw, 0u, 0u, 0.0});
@@ -187,7 +189,7 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
   const bool prof = ctx->profiling;
   ctx->profiling = false;
   pmc_shade_params def = plan->params;
-  def.flags = PMC_FLAG_SORT;
+  def.flags = base;
   def.chunk_waves = def.defer_max = def.blocks_per_cu = 0;
   st = time_one(def, &out->default_ms);
   double best_ms = 1e30;

@@ -64,7 +64,10 @@ struct MatHeader {          // 128 bytes
   float out_k[8];           // their constants: base k[0..2], roughness k[3]
   uint32_t hit_begin;       // hit program: only the nodes needed when every lookup hit
   uint32_t n_hit;           // (the instructions whose need mask has kAlways)
-  uint32_t pad[14];
+  uint32_t surr_slot;       // surrogate network of the material (valid when surr_mask != 0)
+  uint32_t surr_mask;       // cacheable ordinals the network can stand in for
+  uint32_t surr_chan;       // first network channel of each ordinal, 4 bits per ordinal
+  uint32_t pad[11];
 };
 static_assert(sizeof(MatHeader) == 128, "MatHeader layout");
 

@@ -5,6 +5,7 @@
 
 #include "../../include/pmc.h"
 #include "program.h"
+#include "surrogate.h"
 
 namespace pmc {
 
@@ -13,7 +14,8 @@ enum {
   CNT_HITS = 0, CNT_PROBES, CNT_CACHE_HITS, CNT_BYPASSES, CNT_INSERTS, CNT_CAS_FAIL,
   CNT_PRESENT, CNT_FULL, CNT_OVERWRITES, CNT_NONFINITE, CNT_CANDIDATES, CNT_NODES_EXEC,
   CNT_NODES_TOTAL, CNT_INVALID, CNT_TEX_EVALS, CNT_DEFERRED, CNT_INS_TRIED, CNT_TEX_DEFERRED,
-  CNT_INS_TRIED_DEFERRED, CNT_PROBES_DEFERRED, kNumCounters
+  CNT_INS_TRIED_DEFERRED, CNT_PROBES_DEFERRED, CNT_SURR_USED, CNT_LOGGED, CNT_AUDITED,
+  kNumCounters
 };
 enum { KIND_FULL = 0, KIND_PROBE = 1 };   // shade kernel variants
 constexpr int kStatSlots = 64;       // counters are spread over slots to limit atomic contention
@@ -60,9 +62,16 @@ struct ShadeArgs {
   uint8_t* dbg_state;
   float* dbg_value;
   uint32_t defer_max;            // a chunk with more missing lanes is evaluated in place
+  // surrogate networks (PMC_FLAG_SURROGATE) and the insert log (PMC_FLAG_LOG)
+  const SurrW* surr_w;
+  SurrState* surr_state;
+  pmc_log_record* log;           // NULL: no logging
+  uint32_t* log_count;           // 64 region counters
+  uint32_t log_region_cap;       // records per region
 };
 
-hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,
+// surr: the variant that consults the surrogate networks (cached modes only).
+hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, bool surr, uint32_t grid,
                         hipStream_t s);
 size_t shade_lds_bytes(uint32_t n_regs);
 hipError_t launch_debug_keys(const ShadeArgs& a, pmc_key_record* out, hipStream_t s);

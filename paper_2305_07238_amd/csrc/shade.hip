@@ -386,6 +386,106 @@ __device__ __forceinline__ void append_candidate(const ShadeArgs& a, bool want, 
   }
 }
 
+// Insert log (training data of the surrogate networks): one 32-byte record
+// {material, ordinal, u, v, value} per logged insert.  The log has 64 regions,
+// each with its own counter (a wave appends to region wave_id % 64 with one
+// atomic); a full region drops further records.
+__device__ __forceinline__ void log_append(const ShadeArgs& a, bool want, uint32_t m, uint32_t ord,
+                                           float u, float v, float3 val, bool is_c,
+                                           Counters& cnt) {
+  const uint64_t mk = __ballot(want);
+  if (mk == 0ull) return;
+  const uint32_t region = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & 63u;
+  const int leader = __ffsll((unsigned long long)mk) - 1;
+  uint32_t base = a.log_region_cap;
+  if (lane_id() == leader) {
+    uint32_t* ctr = a.log_count + region;
+    if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.log_region_cap)
+      base = atomicAdd(ctr, (uint32_t)__popcll(mk));
+  }
+  base = __shfl(base, leader, 64);
+  if (want) {
+    const uint32_t pos = base + (uint32_t)__popcll(mk & lanemask_lt());
+    if (pos < a.log_region_cap) {
+      uint4* d = reinterpret_cast<uint4*>(a.log + (uint64_t)region * a.log_region_cap + pos);
+      d[0] = make_uint4(m, ord, __float_as_uint(u), __float_as_uint(v));
+      d[1] = make_uint4(__float_as_uint(val.x), is_c ? __float_as_uint(val.y) : 0u,
+                        is_c ? __float_as_uint(val.z) : 0u, 0u);
+      cnt.v[CNT_LOGGED]++;
+    }
+  }
+}
+
+// Surrogate output kept on an audited lane, to be compared with the graph's.
+struct Audit {
+  uint32_t mask;     // surrogated ordinals that the graph evaluates instead (0: none)
+  uint32_t slot;
+  float y[4];
+};
+
+__device__ __forceinline__ Audit no_audit() {
+  Audit au;
+  au.mask = 0u;
+  au.slot = 0u;
+  au.y[0] = au.y[1] = au.y[2] = au.y[3] = 0.0f;
+  return au;
+}
+
+// The material's network stands in for its missed surrogated outputs (whole
+// wave active; m wave-uniform; `mine` marks the lanes of material m).  The
+// values go to the outputs' registers, which removes them from the misses (no
+// sub-graph evaluation, no insert).  One eligible hit in 64 is audited
+// instead: evaluated by the graph, with the network's output kept in *au.
+template <int MODE>
+__device__ __forceinline__ void surrogate_fill(const ShadeArgs& a, uint32_t m, bool mine,
+                                               uint32_t h, const HitData& hd, const LaneRegs& R,
+                                               Counters& cnt, uint32_t& miss, uint32_t& ins,
+                                               Audit& au) {
+  if (m >= a.n_mats) return;
+  const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
+  const uint32_t smask = H->surr_mask;
+  if (smask == 0u) return;
+  const uint32_t slot = H->surr_slot;
+  if (as_const(a.surr_state)[slot].trusted == 0u) return;
+  const uint32_t sm = mine ? (ins & smask) : 0u;
+  if (__ballot(sm != 0u) == 0ull) return;
+  float y[4];
+  mlp_wave(a.surr_w + slot, hd.u, hd.v, y);
+  if (sm == 0u) return;
+  if (surrogate_audited(a.frame, h)) {
+    au.mask = sm;
+    au.slot = slot;
+    au.y[0] = y[0]; au.y[1] = y[1]; au.y[2] = y[2]; au.y[3] = y[3];
+    cnt.v[CNT_AUDITED] += (uint32_t)__popc(sm);
+    return;
+  }
+  const uint32_t cbeg = H->cach_begin;
+  for (uint32_t c = 0; c < 8u; ++c) {
+    if (!((smask >> c) & 1u)) continue;
+    if (!((sm >> c) & 1u)) continue;
+    const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + c;
+    const uint32_t ch = (H->surr_chan >> (4u * c)) & 0xFu;
+    const int r = cd->reg;
+    const float v0 = pick4(y, ch);
+    R.set(r, v0);
+    float v1 = v0, v2 = v0;
+    if (cd->otype == OT_COLOR) {
+      v1 = pick4(y, ch + 1u);
+      v2 = pick4(y, ch + 2u);
+      R.set(r + 1, v1);
+      R.set(r + 2, v2);
+    }
+    if (a.dbg_state) a.dbg_state[(uint64_t)h * 8 + c] = 4;
+    if (a.dbg_value) {
+      float* dv = a.dbg_value + ((uint64_t)h * 8 + c) * 3;
+      dv[0] = v0; dv[1] = v1; dv[2] = v2;
+    }
+  }
+  cnt.v[CNT_SURR_USED] += (uint32_t)__popc(sm);
+  miss &= ~sm;
+  ins &= ~sm;
+}
+
 // ------------------------------------------------------------- the kernel ---
 
 // Probe every cacheable output of the lane's material (Sec. 3: look up at the
@@ -476,13 +576,14 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
 // lane's misses (Sec. 3: a found value makes its sub-graph unnecessary).  A
 // cacheable output computed on a miss is encoded and stored (Algorithm 1), or
 // becomes a snapshot candidate.
-template <int MODE, bool DEF>
+template <int MODE, bool DEF, bool SURR>
 __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint32_t h,
                                             const HitData& hd, const LaneRegs& R, Counters& cnt,
                                             uint32_t first, uint32_t count, uint32_t miss,
-                                            uint32_t ins, uint32_t slots) {
+                                            uint32_t ins, uint32_t slots, const Audit& au) {
   const PMC_CONST Instr* I = as_const(a.instr) + first;
-  const uint32_t cbeg = (as_const(a.hdr) + m)->cach_begin;
+  const PMC_CONST MatHeader* MH = as_const(a.hdr) + m;
+  const uint32_t cbeg = MH->cach_begin;
   for (uint32_t i = 0; i < count; ++i, ++I) {
     const uint32_t exec = I->exec;
     const bool need = (exec & kAlways) != 0u || (exec & miss) != 0u;
@@ -564,6 +665,7 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
             hash2 = k.hash2;
           }
         }
+        bool logged = want;
         if (MODE == PMC_MODE_SNAPSHOT) {
           append_candidate(a, want, cell, hash2, code, h * 32u + ord, cnt);
         } else {
@@ -579,6 +681,23 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
             }
           }
           count_insert(cnt, want, o);
+          logged = want && (o == INS_DONE || o == INS_OVERWRITE);
+        }
+        if (a.log && ((MH->surr_mask >> ord) & 1u))
+          log_append(a, logged, m, ord, hd.u, hd.v, val, is_c, cnt);
+        if (SURR && ((au.mask >> ord) & 1u)) {
+          // audited lane: the graph's value against the network's
+          const uint32_t ch = (MH->surr_chan >> (4u * ord)) & 0xFu;
+          float e = fabsf(val.x - pick4(au.y, ch));
+          if (is_c) {
+            const float e1 = fabsf(val.y - pick4(au.y, ch + 1u));
+            const float e2 = fabsf(val.z - pick4(au.y, ch + 2u));
+            e = (e1 > e || e1 != e1) ? e1 : e;
+            e = (e2 > e || e2 != e2) ? e2 : e;
+          }
+          SurrState* ss = a.surr_state + au.slot;
+          atomicMax(&ss->live_err_bits, e != e ? 0x7FC00000u : __float_as_uint(e));
+          atomicAdd(&ss->live_n, 1u);
         }
       }
     }
@@ -615,13 +734,15 @@ __device__ __forceinline__ void shade_default(const ShadeArgs& a, uint32_t h, co
 
 // Full evaluation of this lane after its probes: the whole program, outputs.
 // DEF: the lane is a deferred hit (counted apart).
-template <int MODE, bool DEF>
+template <int MODE, bool DEF, bool SURR>
 __device__ __forceinline__ void shade_full(const ShadeArgs& a, uint32_t m, uint32_t h,
                                            const HitData& hd, const LaneRegs& R, Counters& cnt,
-                                           uint32_t miss, uint32_t ins, uint32_t slots) {
+                                           uint32_t miss, uint32_t ins, uint32_t slots,
+                                           const Audit& au) {
   const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
   cnt.v[CNT_NODES_TOTAL] += H->n_instr;
-  run_program<MODE, DEF>(a, m, h, hd, R, cnt, H->instr_begin, H->n_instr, miss, ins, slots);
+  run_program<MODE, DEF, SURR>(a, m, h, hd, R, cnt, H->instr_begin, H->n_instr, miss, ins, slots,
+                               au);
   write_outputs(a, m, h, hd, R);
 }
 
@@ -656,23 +777,24 @@ __device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t*
 }
 
 // KIND_FULL: every lane of the chunk is evaluated completely.
-template <int MODE>
+template <int MODE, bool SURR>
 __device__ __forceinline__ void chunk_full(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
                                            Counters& cnt) {
   LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
   cnt.v[CNT_HITS] += (uint32_t)L.active;
   uint32_t ins = 0u, slots = 0u;
-  const uint32_t miss =
-      probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
+  uint32_t miss = probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
   uint64_t pending = __ballot(L.active);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
     const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
     const bool mine = L.active && L.mat == m;
     pending &= ~__ballot(mine);
+    Audit au = no_audit();
+    if (SURR) surrogate_fill<MODE>(a, m, mine, L.h, L.hd, R, cnt, miss, ins, au);
     if (mine) {
       if (m < a.n_mats) {
-        shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
+        shade_full<MODE, false, SURR>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
       } else {
         cnt.v[CNT_INVALID]++;
         shade_default(a, L.h, L.hd);
@@ -694,15 +816,17 @@ struct DeferBuf {
 
 // Evaluate the staged hits (all 64 lanes active on entry).  The lookups are
 // repeated: in CACHED mode they may now find values inserted since.
-template <int MODE>
+template <int MODE, bool SURR>
 __device__ __forceinline__ void flush_deferred(const ShadeArgs& a, DeferBuf& B, const LaneRegs& R,
                                             Counters& cnt) {
   const uint32_t m = B.mat;
   const bool act = (uint32_t)lane_id() < B.count;
   LaneHit L = load_lane(a, B.ids, B.count, 0u, cnt);
   uint32_t ins = 0u, slots = 0u;
-  const uint32_t miss = probe_chunk<MODE, false>(a, act, m, L.h, L.hd, R, cnt, &ins, &slots);
-  if (act) shade_full<MODE, true>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
+  uint32_t miss = probe_chunk<MODE, false>(a, act, m, L.h, L.hd, R, cnt, &ins, &slots);
+  Audit au = no_audit();
+  if (SURR) surrogate_fill<MODE>(a, m, act, L.h, L.hd, R, cnt, miss, ins, au);
+  if (act) shade_full<MODE, true, SURR>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
   B.count = 0u;
 }
 
@@ -710,14 +834,13 @@ __device__ __forceinline__ void flush_deferred(const ShadeArgs& a, DeferBuf& B, 
 // program.  If more than defer_max lanes of the chunk missed, the chunk is
 // dense enough to be evaluated in place; otherwise its missing lanes go to the
 // wave's staging buffer.
-template <int MODE>
+template <int MODE, bool SURR>
 __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
                                             Counters& cnt, DeferBuf& B) {
   LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
   cnt.v[CNT_HITS] += (uint32_t)L.active;
   uint32_t ins = 0u, slots = 0u;
-  const uint32_t miss =
-      probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
+  uint32_t miss = probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
   bool deferred = false;
   uint64_t pending = __ballot(L.active);
   while (pending) {
@@ -725,17 +848,21 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
     const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
     const bool mine = L.active && L.mat == m;
     pending &= ~__ballot(mine);
+    const uint32_t d = (uint32_t)__popcll(__ballot(mine && miss != 0u));
+    const bool dense = d > a.defer_max;
+    Audit au = no_audit();
+    if (SURR && dense) surrogate_fill<MODE>(a, m, mine, L.h, L.hd, R, cnt, miss, ins, au);
     if (mine) {
       if (m < a.n_mats) {
         const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
-        const uint32_t d = (uint32_t)__popcll(__ballot(miss != 0u));
-        if (d > a.defer_max) {
-          shade_full<MODE, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots);
+        if (dense) {
+          shade_full<MODE, false, SURR>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
         } else if (miss != 0u) {
           deferred = true;
         } else {
           cnt.v[CNT_NODES_TOTAL] += H->n_instr;
-          run_program<MODE, false>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u, 0u, 0u);
+          run_program<MODE, false, SURR>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u, 0u,
+                                         0u, au);
           write_outputs(a, m, L.h, L.hd, R);
         }
       } else {
@@ -754,7 +881,7 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
     const bool member = deferred && L.mat == m;
     const uint64_t mm = __ballot(member);
     dm &= ~mm;
-    if (B.count != 0u && B.mat != m) flush_deferred<MODE>(a, B, R, cnt);
+    if (B.count != 0u && B.mat != m) flush_deferred<MODE, SURR>(a, B, R, cnt);
     B.mat = m;
     const uint32_t n_new = (uint32_t)__popcll(mm);
     const uint32_t room = 64u - B.count;
@@ -762,7 +889,7 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, 
     if (member && r < room) B.ids[B.count + r] = L.h;
     if (n_new >= room) {
       B.count = 64u;
-      flush_deferred<MODE>(a, B, R, cnt);
+      flush_deferred<MODE, SURR>(a, B, R, cnt);
       if (member && r >= room) B.ids[r - room] = L.h;
       B.count = n_new - room;
     } else {
@@ -782,15 +909,15 @@ __device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt
 }
 
 // One run = `chunk_waves` consecutive chunks handled by one wave.
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool SURR>
 __device__ __forceinline__ void do_run(const ShadeArgs& a, uint32_t first, uint32_t n_chunks,
                                        const LaneRegs& R, Counters& cnt, DeferBuf& B) {
   const uint32_t last = min(first + a.chunk_waves, n_chunks);
   for (uint32_t c = first; c < last; ++c) {
-    if (KIND == KIND_PROBE) chunk_probe<MODE>(a, c, R, cnt, B);
-    else chunk_full<MODE>(a, c, R, cnt);
+    if (KIND == KIND_PROBE) chunk_probe<MODE, SURR>(a, c, R, cnt, B);
+    else chunk_full<MODE, SURR>(a, c, R, cnt);
   }
-  if (KIND == KIND_PROBE && B.count != 0u) flush_deferred<MODE>(a, B, R, cnt);
+  if (KIND == KIND_PROBE && B.count != 0u) flush_deferred<MODE, SURR>(a, B, R, cnt);
 }
 
 // LDS per wave: the register file [n_regs][64] floats, then 64 staging ids.
@@ -799,7 +926,7 @@ __device__ __forceinline__ float* wave_lds(float* lds, const ShadeArgs& a) {
 }
 
 // STATS = false: the counters are dead code and take no registers.
-template <int MODE, int KIND, bool STATS>
+template <int MODE, int KIND, bool STATS, bool SURR>
 __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
@@ -811,7 +938,7 @@ __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   const uint32_t n_chunks = (a.n + 63u) / 64u;
   const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint32_t first = w * a.chunk_waves;
-  if (first < n_chunks) do_run<MODE, KIND>(a, first, n_chunks, R, cnt, B);
+  if (first < n_chunks) do_run<MODE, KIND, SURR>(a, first, n_chunks, R, cnt, B);
   if (STATS) flush_counters(a, cnt);
 }
 
@@ -819,7 +946,7 @@ __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
 // (no shared work counter: same-address atomics serialise across the XCDs).
 // The material sort orders hits by decreasing program length, so the stride
 // deals the long programs out first.
-template <int MODE, int KIND, bool STATS>
+template <int MODE, int KIND, bool STATS, bool SURR>
 __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
@@ -832,7 +959,7 @@ __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   for (uint32_t first = w * a.chunk_waves; first < n_chunks; first += waves * a.chunk_waves)
-    do_run<MODE, KIND>(a, first, n_chunks, R, cnt, B);
+    do_run<MODE, KIND, SURR>(a, first, n_chunks, R, cnt, B);
   if (STATS) flush_counters(a, cnt);
 }
 
@@ -840,36 +967,41 @@ __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
 
 size_t shade_lds_bytes(uint32_t n_regs) { return (size_t)4 * (n_regs * 64 + 64) * sizeof(float); }
 
-template <int MODE, int KIND, bool STATS>
+template <int MODE, int KIND, bool STATS, bool SURR>
 static void launch_one(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
                        hipStream_t s) {
   if (persistent)
-    hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds,
+                       s, a);
   else
-    hipLaunchKernelGGL((k_shade_flat<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_shade_flat<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds, s, a);
 }
 
 template <int KIND, bool STATS>
-static void launch_kind(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
+static void launch_kind(const ShadeArgs& a, bool persistent, bool surr, uint32_t grid, size_t lds,
                         hipStream_t s) {
   if (a.mode == PMC_MODE_UNCACHED)
-    launch_one<PMC_MODE_UNCACHED, KIND, STATS>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_UNCACHED, KIND, STATS, false>(a, persistent, grid, lds, s);
+  else if (a.mode == PMC_MODE_CACHED && surr)
+    launch_one<PMC_MODE_CACHED, KIND, STATS, true>(a, persistent, grid, lds, s);
   else if (a.mode == PMC_MODE_CACHED)
-    launch_one<PMC_MODE_CACHED, KIND, STATS>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_CACHED, KIND, STATS, false>(a, persistent, grid, lds, s);
+  else if (surr)
+    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS, true>(a, persistent, grid, lds, s);
   else
-    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS, false>(a, persistent, grid, lds, s);
 }
 
-hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, uint32_t grid,
+hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, bool surr, uint32_t grid,
                         hipStream_t s) {
   const size_t lds = shade_lds_bytes(a.n_regs);
   const bool stats = a.stat_slots != nullptr;
   if (kind == KIND_PROBE) {
-    if (stats) launch_kind<KIND_PROBE, true>(a, persistent, grid, lds, s);
-    else launch_kind<KIND_PROBE, false>(a, persistent, grid, lds, s);
+    if (stats) launch_kind<KIND_PROBE, true>(a, persistent, surr, grid, lds, s);
+    else launch_kind<KIND_PROBE, false>(a, persistent, surr, grid, lds, s);
   } else {
-    if (stats) launch_kind<KIND_FULL, true>(a, persistent, grid, lds, s);
-    else launch_kind<KIND_FULL, false>(a, persistent, grid, lds, s);
+    if (stats) launch_kind<KIND_FULL, true>(a, persistent, surr, grid, lds, s);
+    else launch_kind<KIND_FULL, false>(a, persistent, surr, grid, lds, s);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,204 @@
+// surrogate.h - the per-material surrogate network: device layout, the
+// wave-wide forward pass on the matrix cores, and host launchers.
+//
+// Beyond the paper (which stores exact sub-graph values only, Sec. 3): a
+// 32 -> 64 -> 64 -> 4 ReLU network of Fourier features of UV may replace the
+// deepest cacheable sub-graphs of a material on a cache miss.
+//
+// Matrix-core mapping (gfx950, wave64, v_mfma_f32_16x16x16_f16).  For a 16x16
+// tile with K = 16 the operand layouts are
+//   A[i][k]: lane i + 16 (k / 4), element k % 4
+//   B[k][j]: lane j + 16 (k / 4), element k % 4
+//   D[i][j]: lane j + 16 (i / 4), element i % 4
+// so D of one product is, lane for lane, the B operand of the next one when
+// the samples run along j.  Every layer is therefore computed transposed,
+// H^T = W X^T: weights are the A operand (read straight from memory, 8 bytes
+// per lane), activations stay in registers from layer to layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pmc.h"
+
+namespace pmc {
+
+constexpr int kFeat = 32, kHid = 64, kOut = 4;
+constexpr int kParams = 6532;
+// offsets of the flat parameter vector
+constexpr int P_W1 = 0, P_B1 = 2048, P_W2 = 2112, P_B2 = 6208, P_W3 = 6272, P_B3 = 6528;
+constexpr int kParamStride = 6656;   // floats per parameter block (params, m, v) of a slot
+constexpr uint64_t kSeedAudit = 0xD6E8FEB86659FD93ull;
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Inference copy of one slot: binary16 weights [out][in] row-major, FP32 biases.
+struct SurrW {
+  _Float16 w1[64 * 32];
+  _Float16 w2[64 * 64];
+  _Float16 w3[16 * 64];        // rows 4..15 zero (the output tile is 16 rows)
+  float b1[64], b2[64], b3[4];
+  float pad[124];
+};
+static_assert(sizeof(SurrW) == 15360, "SurrW layout");
+
+// Per-slot state (device), 128 bytes.
+struct SurrState {
+  uint32_t trusted, steps, n_train, n_heldout;
+  float max_err, mean_err, loss;
+  uint32_t live_err_bits;      // largest audited error (bits of a float >= 0)
+  uint32_t live_n;             // audited outputs
+  uint32_t material;
+  uint32_t ordmap[8];          // per ordinal: bits 0-3 first channel, bits 4-7 width (0: none)
+  float thresh;                // trust threshold
+  uint32_t pad[13];
+};
+static_assert(sizeof(SurrState) == 128, "SurrState layout");
+
+
+__device__ __forceinline__ f4 mfma16(h4 a, h4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// Features 4q .. 4q+3: sin and cos of w_q u and of w_q v, w_q = 2 pi 2^(q-3).
+// sin(2 pi 2^(q-3) u) = sinpi(2^(q-2) u); the scaling by a power of two is exact.
+__device__ __forceinline__ h4 fourier4(float u, float v, int q) {
+  const float s = __builtin_ldexpf(1.0f, q - 2);
+  float su, cu, sv, cv;
+  sincospif(u * s, &su, &cu);
+  sincospif(v * s, &sv, &cv);
+  h4 r;
+  r.x = (_Float16)su;
+  r.y = (_Float16)cu;
+  r.z = (_Float16)sv;
+  r.w = (_Float16)cv;
+  return r;
+}
+
+// relu(acc + b) rounded to binary16 (round to nearest even)
+__device__ __forceinline__ h4 relu_h4(f4 acc, const float* b) {
+  h4 r;
+  r.x = (_Float16)fmaxf(acc.x + b[0], 0.0f);
+  r.y = (_Float16)fmaxf(acc.y + b[1], 0.0f);
+  r.z = (_Float16)fmaxf(acc.z + b[2], 0.0f);
+  r.w = (_Float16)fmaxf(acc.w + b[3], 0.0f);
+  return r;
+}
+
+// The network at 64 points, one per lane (all 64 lanes must be active): lane l
+// gives (u, v) and receives y[0..3] of its own point.  112 matrix products.
+__device__ __forceinline__ void mlp_wave(const SurrW* __restrict__ W, float u, float v,
+                                         float y[4]) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int j = lane & 15, g = lane >> 4;
+  // layer-1 B operands: features of sample 16 n + j, feature rows 16 t + 4 g ..
+  h4 X[2][4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const float un = __shfl(u, 16 * n + j, 64), vn = __shfl(v, 16 * n + j, 64);
+    X[0][n] = fourier4(un, vn, g);
+    X[1][n] = fourier4(un, vn, 4 + g);
+  }
+  h4 H1[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const h4 a0 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 4 * g);
+    const h4 a1 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 16 + 4 * g);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma16(a0, X[0][n], acc);
+      acc = mfma16(a1, X[1][n], acc);
+      H1[m][n] = relu_h4(acc, W->b1 + 16 * m + 4 * g);
+    }
+  }
+  // layer 2, and layer 3 accumulated tile by tile (K tile m of layer 3 = M tile m of layer 2)
+  f4 Y[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) Y[n] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    h4 a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      a[t] = *reinterpret_cast<const h4*>(W->w2 + (16 * m + j) * 64 + 16 * t + 4 * g);
+    const h4 a3 = *reinterpret_cast<const h4*>(W->w3 + j * 64 + 16 * m + 4 * g);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc = mfma16(a[t], H1[t][n], acc);
+      const h4 h2 = relu_h4(acc, W->b2 + 16 * m + 4 * g);
+      Y[n] = mfma16(a3, h2, Y[n]);
+    }
+  }
+  // sample 16 n + j's outputs are rows 0..3 of tile n, held by lane j
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float r = 0.0f;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const float t = __shfl(Y[n][c], j, 64);
+      r = (g == n) ? t : r;
+    }
+    y[c] = r + W->b3[c];
+  }
+}
+
+__device__ __forceinline__ float pick4(const float y[4], uint32_t c) {
+  return c == 0u ? y[0] : (c == 1u ? y[1] : (c == 2u ? y[2] : y[3]));
+}
+
+// Audit rule: 1 in 64 surrogate-eligible hits are evaluated by the graph.
+__device__ __forceinline__ bool surrogate_audited(uint32_t frame, uint32_t h) {
+  uint64_t z = ((((uint64_t)frame) << 32) | (uint64_t)h) ^ kSeedAudit;
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (z >> 58) == 0ull;
+}
+
+// ------------------------------------------------------------- launchers ---
+
+struct TrainArgs {
+  const pmc_log_record* rec;   // records (grouped by slot when slot_begin is set)
+  const uint32_t* slot_begin;  // per slot: first record; NULL: 0
+  const uint32_t* slot_count;  // per slot: records; NULL: n_fixed
+  uint32_t n_fixed;
+  uint32_t slot_fixed;         // slot of block 0 when slot_begin is NULL
+  uint32_t holdout;            // grouped mode: held-out records per slot (capped at a quarter)
+  uint32_t min_records;        // grouped mode: fewer training records -> slot skipped
+  float* master;               // [slot][3][kParamStride]: params, Adam m, Adam v
+  SurrW* w;                    // [slot] inference copies (written at the end)
+  SurrState* state;            // [slot]
+  uint32_t steps, batch;       // batch: multiple of 128
+  float lr;
+  uint64_t seed;
+  uint32_t sample;             // 1: Adam steps on sampled batches; 0: one gradient pass
+  float* grad_out;             // gradient pass: 6532 FP32
+  float* loss_out;             // gradient pass: loss
+};
+
+size_t surr_train_lds_bytes();
+hipError_t launch_surr_train(const TrainArgs& a, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_surr_export(const float* master, SurrW* w, uint32_t n_slots, hipStream_t s);
+// held-out error -> trust, per slot (grouped records)
+hipError_t launch_surr_probe(const pmc_log_record* rec, const uint32_t* slot_begin,
+                             const uint32_t* slot_count, uint32_t holdout, uint32_t min_records,
+                             const SurrW* w, SurrState* state, uint32_t n_slots, hipStream_t s);
+hipError_t launch_surr_infer(const SurrW* w, const float* uv, uint32_t n, float* y,
+                             hipStream_t s);
+// trust flag of one slot (and its audit record cleared); reset_steps also zeroes the step count
+hipError_t launch_surr_set_trust(SurrState* state, uint32_t slot, uint32_t trusted,
+                                 uint32_t reset_steps, hipStream_t s);
+hipError_t launch_surr_live_update(SurrState* state, uint32_t n_slots, hipStream_t s);
+// group the insert log by slot: counts, offsets (exclusive scan) and the grouped copy
+hipError_t launch_log_group(const pmc_log_record* log, const uint32_t* region_count,
+                            uint32_t region_cap, const uint32_t* mat_slot, uint32_t n_mats,
+                            uint32_t n_slots, uint32_t* slot_count, uint32_t* slot_begin,
+                            uint32_t* slot_cursor, uint32_t* scan_sums, pmc_log_record* grouped,
+                            hipStream_t s);
+
+}  // namespace pmc

@@ -463,6 +463,44 @@ def lognormal_sizes(rng, n, lo, hi, mu=3.0, sigma=1.0):
     return np.clip(np.rint(rng.lognormal(mu, sigma, n)), lo, hi).astype(int)
 
 
+def smooth_material(seed: int, m: int, groups: int = 9) -> Material:
+    """A material whose deep sub-graphs are smooth functions of UV (low-frequency
+    value and Perlin noise through 4 * groups MUL/POW nodes that undo each other
+    pairwise), so a small network can represent them: base colour (COLOR, one
+    cacheable output of 4 * groups + 4 nodes) and roughness (FLOAT, 4 * groups + 2)."""
+    rng = _rng(seed, _P_GRAPH, 7, m)
+    L, C = Input.link, Input.const
+    ca, cb, cc = (tuple(float(x) for x in rng.uniform(0.1, 0.9, 3)) for _ in range(3))
+    nodes = [
+        Node("UV_INPUT"),                                                        # 0
+        Node("VALUE_NOISE", [L(0)], freq=1.0, octaves=1, seed=int(rng.integers(1 << 30))),
+        Node("PERLIN_NOISE", [L(0)], freq=1.0, octaves=2, seed=int(rng.integers(1 << 30))),
+        Node("MIX", [L(1), C(*ca), C(*cb)]),                                     # 3
+    ]
+    x = 2
+    for _ in range(groups):
+        c = float(rng.uniform(0.8, 1.25))
+        e = float(rng.uniform(0.8, 1.25))
+        for op, k in (("MUL", c), ("MUL", 1.0 / c), ("POW", e), ("POW", 1.0 / e)):
+            nodes.append(Node("MATH", [L(x), C(k)], math_op=op))
+            x = len(nodes) - 1
+    nodes.append(Node("MIX", [L(x), L(3), C(*cc)]))                              # base colour
+    base = len(nodes) - 1
+    nodes.append(Node("MATH", [L(x), C(0.8)], math_op="MUL", clamp=True))       # roughness
+    rough = len(nodes) - 1
+    nodes.append(Node("BSDF_OUTPUT", [L(base), L(rough), C()]))
+    return Material(nodes)
+
+
+def smooth_scene(seed: int = 0, n_mats: int = 4, width: int = 480, height: int = 240,
+                 frames: int = 4, slots: int = 1 << 18) -> Scene:
+    """Scene of smooth_material graphs on 40-px objects with UV scale U[0.5, 1]."""
+    mats = [smooth_material(seed, m) for m in range(n_mats)]
+    frame, n = _object_screen(seed, n_mats, width, height, 40, frames, scale=(0.5, 1.0),
+                              name="smooth")
+    return Scene("smooth", mats, [], frames, n, CacheConfig(slots), seed, frame)
+
+
 def batching_scene(seed: int = 0, n_mats: int = 1000, width: int = 1920, height: int = 1080,
                    frames: int = 64, slots: int = 1 << 24, n_textures: int = 64,
                    tex_size: int = 1024) -> Scene:

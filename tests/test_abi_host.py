@@ -35,11 +35,16 @@ def test_struct_layouts_match_the_header():
                             B.pmc_material_info, B.pmc_cache_params, B.pmc_shade_params,
                             B.pmc_stats, B.pmc_hits, B.pmc_bsdf_out, B.pmc_debug_out,
                             B.pmc_key_record, B.pmc_frame_plan, B.pmc_tune_result,
-                            B.pmc_profile]):
+                            B.pmc_profile, B.pmc_surrogate_opts, B.pmc_surrogate_slot,
+                            None, B.pmc_train_params, B.pmc_surrogate_stat]):
+        if st is None:                      # pmc_log_record: 32 bytes, numpy dtype
+            assert B.pmc_abi_sizeof(i) == B.LOG_RECORD_DTYPE.itemsize == 32
+            continue
         assert B.pmc_abi_sizeof(i) == C.sizeof(st), st.__name__
     assert B.pmc_abi_sizeof(99) == 0
     assert C.sizeof(B.pmc_node_desc) == 244
     assert C.sizeof(B.pmc_stats) == 256
+    assert C.sizeof(B.pmc_surrogate_stat) == 48
 
 
 def test_host_only_context_refuses_device_work():
@@ -128,3 +133,31 @@ def test_compiler_rejects_bad_graphs(bad):
         ctx.compile([scenes.Material(nodes)])
     assert e.value.code == B.PMC_ERR_GRAPH
     assert "material 0" in str(e.value)
+
+
+def test_surrogate_slots_follow_the_subgraph_rule():
+    """Slot selection on a host-only context: outputs whose sub-graph (UV inputs
+    excluded, as the oracle counts it) has more than 32 nodes, packed in
+    ordinal order into 4 channels (COLOR 3, FLOAT 1)."""
+    sc = scenes.mid_scene(frames=1, width=64, height=32)
+    ctx = _compile(sc.materials)
+    n = ctx.surrogate_setup()
+    expect = []
+    for m, mat in enumerate(sc.materials):
+        mask, chans, used = 0, {}, 0
+        for c, (node, sock) in enumerate(graph.cacheable_outputs(mat)):
+            size = sum(1 for j in graph.subgraph(mat, node) if mat.nodes[j].op != "UV_INPUT")
+            w = 3 if graph.output_type(mat, node, sock) == "COLOR" else 1
+            if size > 32 and used + w <= 4:
+                mask |= 1 << c
+                chans[c] = used
+                used += w
+        if mask:
+            expect.append((m, mask, chans, used))
+    assert n == len(expect) > 0
+    for k, (m, mask, chans, used) in enumerate(expect):
+        sl = ctx.surrogate_slot(k)
+        assert sl["material"] == m and sl["ordinal_mask"] == mask and sl["n_channels"] == used
+        for c, ch in chans.items():
+            assert sl["channel"][c] == ch
+    ctx.close()

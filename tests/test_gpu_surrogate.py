@@ -1,0 +1,297 @@
+"""The surrogate networks on the GPU against the FP64 reference (oracle/mlp.py):
+inference, gradients, Adam steps, shading with a trusted network (snapshot
+mode, deterministic), the insert log, and training on the log.
+
+Tolerances.  The GPU rounds features, weights and activations to binary16 at
+the same points as mlp.forward(round16=True) and accumulates in FP32.  Two
+things separate it from the reference: FP32 accumulation order (about 1e-6
+relative) and the rare binary16 rounding flip of a feature or activation
+whose FP32 and FP64 values straddle a rounding boundary (one binary16 ulp,
+2^-11 relative, times a weight).  Network outputs are compared with
+|gpu - ref| <= 2e-3 (1 + |ref|) everywhere and a mean below 1e-5; gradients
+by relative L2 <= 1e-3 and cosine >= 0.999 per parameter block.
+"""
+import numpy as np
+import pytest
+
+from oracle import graph, mlp, render, table
+from paper_2305_07238_amd import scenes
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2305_07238_amd import binding as B  # noqa: E402
+
+Y_ATOL, Y_RTOL = 2e-3, 2e-3
+
+
+def _params(seed, scale_b=0.1):
+    """He-uniform weights (scenes.mlp_init) plus small random biases, flat FP32."""
+    p = scenes.mlp_init(seed, 1)[0]
+    rng = np.random.default_rng(seed + 17)
+    for k in (1, 3, 5):
+        p[k] = rng.uniform(-scale_b, scale_b, p[k].shape).astype(np.float32)
+    return np.concatenate([a.ravel() for a in p]).astype(np.float32)
+
+
+def _ctx_with_slots(scene, **kw):
+    ctx = G.setup(scene)
+    n = ctx.surrogate_setup(**kw)
+    assert n > 0
+    return ctx, n
+
+
+def _ordmap(ctx, scene, slot):
+    sl = ctx.surrogate_slot(slot)
+    mat = scene.materials[sl["material"]]
+    cach = graph.cacheable_outputs(mat)
+    om = {}
+    for c in range(8):
+        if (sl["ordinal_mask"] >> c) & 1:
+            node, sock = cach[c]
+            w = 3 if graph.output_type(mat, node, sock) == "COLOR" else 1
+            om[c] = (sl["channel"][c], w)
+    return sl["material"], om
+
+
+def test_inference_matches_reference():
+    sc = scenes.smooth_scene(frames=1)
+    ctx, _ = _ctx_with_slots(sc)
+    flat = _params(3)
+    ctx.surrogate_set_params(0, flat)
+    assert np.array_equal(ctx.surrogate_get_params(0), flat)
+    rng = np.random.default_rng(5)
+    n = 1000                                             # 15 full waves and a ragged one
+    uv = rng.uniform(-2.0, 8.0, (n, 2)).astype(np.float32)
+    y = torch.full((n, 4), float("nan"), device="cuda")
+    ctx.surrogate_infer(0, torch.from_numpy(uv).cuda(), y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    ref, _ = mlp.forward(mlp.unflatten(flat), mlp.features(uv), round16=True)
+    err = np.abs(got - ref)
+    print("infer max", err.max(), "mean", err.mean())
+    assert np.all(err <= Y_ATOL + Y_RTOL * np.abs(ref))
+    assert err.mean() < 1e-5
+
+
+def _records(rng, n, material, ordmap, uv_hi=2.0):
+    rec = np.zeros(n, B.LOG_RECORD_DTYPE)
+    ords = np.array(sorted(ordmap))
+    rec["material"] = material
+    rec["ordinal"] = ords[rng.integers(0, len(ords), n)]
+    rec["u"] = rng.uniform(0, uv_hi, n)
+    rec["v"] = rng.uniform(0, uv_hi, n)
+    for i in range(n):
+        w = ordmap[int(rec["ordinal"][i])][1]
+        rec["value"][i, :w] = rng.uniform(0.0, 1.0, w)
+    return rec
+
+
+@pytest.mark.parametrize("n", [1000, 4096])
+def test_gradients_match_reference(n):
+    sc = scenes.smooth_scene(frames=1)
+    ctx, _ = _ctx_with_slots(sc)
+    mat, om = _ordmap(ctx, sc, 0)
+    flat = _params(11)
+    ctx.surrogate_set_params(0, flat)
+    rec = _records(np.random.default_rng(n), n, mat, om)
+    grads = torch.zeros(B.N_PARAMS, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    ctx.surrogate_grad(0, B.records_to_device(rec), grads, loss)
+    torch.cuda.synchronize()
+    g = grads.cpu().numpy().astype(np.float64)
+    t, m = mlp.targets(rec, om)
+    x = mlp.features(np.stack([rec["u"], rec["v"]], 1))
+    ref_loss, ref = mlp.loss_and_grads(mlp.unflatten(flat), x, t, m, round16=True)
+    assert abs(float(loss.item()) - ref_loss) <= 1e-4 * ref_loss
+    parts = mlp.unflatten(g)
+    for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), parts, ref):
+        a, b = a.ravel(), b.ravel()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        cos = a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
+        print(name, "rel L2", rel, "cos", cos)
+        assert rel <= 1e-3 and cos >= 0.999, name
+    # the full-precision gradient agrees to the binary16 rounding of the method
+    _, ref64 = mlp.loss_and_grads(mlp.unflatten(flat), x, t, m, round16=False)
+    a, b = g, mlp.flatten(ref64)
+    assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b)) >= 0.99
+
+
+def test_adam_steps_match_reference():
+    sc = scenes.smooth_scene(frames=1)
+    ctx, _ = _ctx_with_slots(sc)
+    mat, om = _ordmap(ctx, sc, 0)
+    flat = _params(23)
+    ctx.surrogate_set_params(0, flat)
+    n, steps, batch, lr, seed = 3000, 3, 256, 1e-3, 99
+    rec = _records(np.random.default_rng(1), n, mat, om)
+    ctx.surrogate_train_records(0, B.records_to_device(rec), steps=steps, batch=batch, lr=lr,
+                                seed=seed)
+    torch.cuda.synchronize()
+    got = ctx.surrogate_get_params(0).astype(np.float64)
+    # the reference: same sampler, FP16 rounding points, FP64 Adam
+    t, m = mlp.targets(rec, om)
+    x = mlp.features(np.stack([rec["u"], rec["v"]], 1))
+    p = mlp.unflatten(flat)
+    mm = [np.zeros_like(a) for a in p]
+    vv = [np.zeros_like(a) for a in p]
+    for step in range(1, steps + 1):
+        idx = mlp.batch_indices(seed, step, batch, n)
+        _, gr = mlp.loss_and_grads(p, x[idx], t[idx], m[idx], round16=True)
+        p, mm, vv = mlp.adam_update(p, gr, mm, vv, step, lr=lr)
+    ref = mlp.flatten(p)
+    d = np.abs(got - ref)
+    moved = np.abs(ref - flat)
+    print("adam max diff", d.max(), "p99", np.quantile(d, 0.99), "moved", moved.mean())
+    # Adam normalises each update to about lr: a parameter whose gradient is at the
+    # rounding noise may take a different sign; nearly all must agree closely
+    assert np.quantile(d, 0.99) <= 1e-5
+    assert d.max() <= 2 * lr * steps
+    assert moved.mean() > 0.3 * lr
+
+
+def _snapshot_case(flags):
+    sc = G.small_mid_scene(frames=3)
+    ctx, n_slots = _ctx_with_slots(sc)
+    sinfo = {}
+    for k in range(n_slots):
+        mat, om = _ordmap(ctx, sc, k)
+        flat = _params(100 + k)
+        ctx.surrogate_set_params(k, flat)
+        ctx.surrogate_set_trust(k, True)
+        sinfo[mat] = dict(params=mlp.unflatten(flat), ordmap=om, trusted=True)
+    return sc, ctx, n_slots, sinfo
+
+
+def _outputs_with(sc, h, state, value):
+    """FP64 evaluation of every hit with the entries of state 1 (cache hit) and 4
+    (network) replaced by the GPU's values."""
+    out = {"base_color": np.zeros((len(h), 3)), "roughness": np.zeros(len(h)),
+           "normal": np.zeros((len(h), 3))}
+    for m in np.unique(h.material):
+        idx = np.nonzero(h.material == m)[0]
+        mat = sc.materials[int(m)]
+        subst = {}
+        for c, (node, sock) in enumerate(graph.cacheable_outputs(mat)):
+            sel = (state[idx, c] == 1) | (state[idx, c] == 4)
+            if sel.any():
+                col = graph.output_type(mat, node, sock) == "COLOR"
+                v = value[idx, c, :3] if col else value[idx, c, 0]
+                subst[(node, sock)] = (sel, np.nan_to_num(v.astype(np.float64)))
+        o, _ = graph.evaluate(mat, h.uv[idx], h.normal[idx], sc.textures, subst)
+        for k in out:
+            out[k][idx] = o[k]
+    return out
+
+
+@pytest.mark.parametrize("flags", [B.PMC_FLAG_SORT, B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER])
+def test_snapshot_with_trusted_networks_matches_reference(flags):
+    """Snapshot mode is deterministic, so which outputs the networks replace
+    (missed, not bypassed, not audited) is exact; the replaced values match the
+    reference network; every output downstream matches the FP64 graph with the
+    GPU's network values substituted; the table stays bit-exact (replaced values
+    are not inserted); the log holds exactly the inserted surrogated outputs."""
+    sc, ctx, n_slots, sinfo = _snapshot_case(flags)
+    n_cells = 1 << 14
+    cache = ctx.cache(n_cells, 8, 16)
+    ref_t = table.Table(n_cells, 8, 16)
+    ctx.log_clear()
+    n_log = 0
+    ref_log = []
+    for f in range(3):
+        h = sc.frame(f).take(np.arange(0, 115200, 2))
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                        flags=flags | B.PMC_FLAG_SURROGATE | B.PMC_FLAG_LOG,
+                                        debug=True)
+        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f,
+                                          surrogate=sinfo, surrogate_values=value)
+        assert np.array_equal(state == 1, ref.found)
+        assert np.array_equal(state == 4, ref.surrogate)
+        assert st["surrogate_used"] == ref.stats["surrogate_used"] > 0
+        assert st["audited"] == int(ref.audited.sum())
+        # network values against the reference network
+        for mat, info in sinfo.items():
+            sel = np.nonzero((h.material == mat) & ref.surrogate.any(1))[0]
+            if len(sel) == 0:
+                continue
+            y, _ = mlp.forward(info["params"], mlp.features(h.uv[sel]), round16=True)
+            for c, (base, w) in info["ordmap"].items():
+                rows = np.nonzero(ref.surrogate[sel, c])[0]
+                e = np.abs(value[sel[rows], c, :w] - y[rows, base:base + w])
+                assert np.all(e <= Y_ATOL + Y_RTOL * np.abs(y[rows, base:base + w])), (mat, c)
+        # outputs: the FP64 graph with the GPU's found and network values substituted
+        o = _outputs_with(sc, h, state, value)
+        for k in ("base_color", "roughness", "normal"):
+            assert G.max_rel(out[k], o[k]) <= G.RTOL, k
+        gw = cache.words()[:, 0]
+        assert np.array_equal(gw >> np.uint64(32), ref_t.words() >> np.uint64(32))
+        ref_log += ref.log
+        n_log += st["logged"]
+    log = ctx.log_read()
+    assert len(log) == n_log == len(ref_log)
+    got = sorted((int(r["material"]), int(r["ordinal"]), float(r["u"]), float(r["v"])) for r in log)
+    exp = sorted((m, c, float(np.float32(u)), float(np.float32(v))) for m, c, u, v, _ in ref_log)
+    assert got == exp
+    rep = ctx.surrogate_report()
+    assert sum(r["live_checked"] for r in rep) > 0
+
+
+def test_untrained_network_is_not_trusted_and_not_used():
+    """A network trained for one step on the log fails the held-out probe
+    (max error far above 1e-2) and is never used."""
+    sc = G.small_mid_scene(frames=2)
+    ctx, n_slots = _ctx_with_slots(sc)
+    cache = ctx.cache(1 << 16, 8, 16)
+    h = sc.frame(0)
+    G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=0,
+            flags=B.PMC_FLAG_SORT | B.PMC_FLAG_LOG)
+    ctx.surrogate_train(steps=1, batch=128, min_records=64, holdout=256)
+    torch.cuda.synchronize()
+    rep = ctx.surrogate_report()
+    assert any(r["n_heldout"] > 0 for r in rep)
+    assert not any(r["trusted"] for r in rep)
+    cache.clear()
+    _, _, _, st = G.shade(ctx, sc.frame(1), cache, mode=B.PMC_MODE_CACHED, frame=1,
+                          flags=B.PMC_FLAG_SORT | B.PMC_FLAG_SURROGATE)
+    assert st["surrogate_used"] == 0
+
+
+def test_training_on_the_log_gains_over_cache_only():
+    """End to end on the smooth scene: frames shaded with the log on collect
+    training pairs; training makes every network trusted (held-out max error
+    <= 1e-2); a fresh render from an empty table with the networks executes
+    fewer interpreter instructions than without, and its BSDF inputs stay
+    within 1e-2 of the FP64 graph."""
+    sc = scenes.smooth_scene(frames=4)
+    ctx, n_slots = _ctx_with_slots(sc, seed=7)
+    cache = ctx.cache(sc.cache.n_cells, 8, 16)
+    ctx.log_clear()
+    for f in range(4):
+        G.shade(ctx, sc.frame(f), cache, mode=B.PMC_MODE_CACHED, frame=f,
+                flags=B.PMC_FLAG_SORT | B.PMC_FLAG_LOG)
+    ctx.surrogate_train(steps=2000, batch=4096, seed=3)
+    torch.cuda.synchronize()
+    rep = ctx.surrogate_report()
+    print(rep)
+    assert all(r["trusted"] for r in rep), rep
+    assert all(0 <= r["max_err"] <= 1e-2 for r in rep)
+    h = sc.frame(0)
+    nodes = {}
+    for use in (False, True):
+        cache.clear()
+        flags = B.PMC_FLAG_SORT | (B.PMC_FLAG_SURROGATE if use else 0)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=0,
+                                        flags=flags, debug=True)
+        nodes[use] = st["nodes_executed"]
+        if use:
+            assert st["surrogate_used"] > 0
+            ref = render.shade_uncached(sc.materials, sc.textures, h)
+            err = max(np.abs(out[k] - ref[k]).max() for k in ("base_color", "roughness"))
+            print("surrogate max abs error vs FP64 graph", err)
+            assert err <= 1e-2
+    print("nodes executed: cache only", nodes[False], "with networks", nodes[True])
+    assert nodes[True] < 0.5 * nodes[False]
