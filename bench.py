@@ -86,6 +86,108 @@ def workload(name, frames=None):
     return sc, desc
 
 
+SURR_FLOP_PER_POINT = 2 * (32 * 64 + 64 * 64 + 64 * 4)     # 12,800 per network evaluation
+FP16_PEAK_TFLOPS = 2500.0
+TRAIN = dict(steps=8000, batch=1024, lr=2e-2, lr_end=1e-5, seed=0)
+
+
+def _median_ms(fn, reps=5):
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn(pre=True)
+        e0.record()
+        fn(pre=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
+    """Learned surrogate (the mid scene after its progressive render): train every
+    network on the insert log the render collected, then shade the next pass
+    (its first 2^20 hits) from the render's final table: uncached, cache only,
+    and networks + cache; errors against the FP64 graph on a sample of hits."""
+    import torch
+    from oracle import render
+    from paper_2305_07238_amd import binding as B
+    n_slots = ctx.surrogate_setup(seed=0)
+    flags = best["flags"] & ~(B.PMC_FLAG_LOG | B.PMC_FLAG_SURROGATE)
+    kw = dict(chunk_waves=best["chunk_waves"], defer_max=best["defer_max"],
+              blocks_per_cu=best["blocks_per_cu"])
+    cache.clear()
+    ctx.log_clear()
+    for f in range(sc.frames):
+        ctx.shade(frame_views[f], out, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                  flags=flags | B.PMC_FLAG_LOG, **kw)
+    torch.cuda.synchronize()
+    n_log = len(ctx.log_read())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.surrogate_train(**TRAIN)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    rep = ctx.surrogate_report()
+    trained = [r for r in rep if r["steps"] > 0]
+    trusted = [k for k, r in enumerate(rep) if r["trusted"]]
+    log(f"surrogate: {n_slots} slots, {len(trained)} trained on {n_log} log records in "
+        f"{train_ms:.1f} ms, {len(trusted)} trusted")
+    train_flop = 3.0 * SURR_FLOP_PER_POINT * TRAIN["batch"] * TRAIN["steps"] * len(trained)
+
+    table = cache.export()
+    n17 = min(1 << 20, sc.hits_per_frame)
+    h17 = sc.frame(sc.frames).take(np.arange(n17))
+    d17 = B.hits_to_device(h17)
+    o17 = B.alloc_outputs(n17)
+    results = {}
+    for name, use_cache, f in (("uncached", False, 0), ("cache_only", True, 0),
+                               ("surrogate_cache", True, B.PMC_FLAG_SURROGATE)):
+        def run(pre, use_cache=use_cache, f=f):
+            if pre:
+                if use_cache:
+                    cache.import_(table)
+                for k in trusted:
+                    ctx.surrogate_set_trust(k, True)
+                torch.cuda.synchronize()
+                return
+            ctx.shade(d17, o17, cache if use_cache else None,
+                      mode=B.PMC_MODE_CACHED if use_cache else B.PMC_MODE_UNCACHED,
+                      frame=sc.frames, flags=flags | f, **kw)
+        ms = _median_ms(run)
+        got = {k: v.cpu().numpy().astype(np.float64) for k, v in o17.items()}
+        results[name] = {"samples_per_s": n17 / (ms * 1e-3), "ms": ms, "_out": got}
+    # accuracy against the FP64 graph on an evenly spaced sample of the pass
+    pick = np.linspace(0, n17 - 1, 2048).astype(np.int64)
+    ref = render.shade_uncached(sc.materials, sc.textures, h17.take(pick))
+    for name, r in results.items():
+        got = r.pop("_out")
+        errs = np.concatenate([np.abs(got[k][pick] - ref[k]).ravel()
+                               for k in ("base_color", "roughness", "normal")])
+        r["max_abs_err"] = float(errs.max())
+        r["mean_abs_err"] = float(errs.mean())
+    # network inference on the matrix cores: 2^20 points through one slot
+    uv = d17["uv"]
+    y = torch.empty((n17, 4), dtype=torch.float32, device="cuda")
+    ms_inf = _median_ms(lambda pre: None if pre else ctx.surrogate_infer(0, uv, y))
+    inf_tflops = SURR_FLOP_PER_POINT * n17 / (ms_inf * 1e-3) / 1e12
+    return {
+        "slots": n_slots, "trusted": len(trusted), "log_records": n_log,
+        "train": dict(TRAIN, ms=train_ms, slots_trained=len(trained),
+                      tflops=train_flop / (train_ms * 1e-3) / 1e12),
+        "heldout_max_err": [r["max_err"] for r in rep],
+        "heldout_mean_err": [r["mean_err"] for r in rep],
+        "pass_hits": n17, "pass": results,
+        "gain_vs_cache_only": results["cache_only"]["ms"] / results["surrogate_cache"]["ms"],
+        "infer": {"points": n17, "ms": ms_inf, "tflops": inf_tflops,
+                  "roofline": {"bound": "mfma", "achieved": inf_tflops,
+                               "peak": FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": inf_tflops / FP16_PEAK_TFLOPS}},
+    }
+
+
 def cpu_baseline(sc, sample_hits=262144, frames=3):
     """The FP64 oracle (snapshot-mode progressive shading) on a bounded sample."""
     from oracle import render, table
@@ -113,6 +215,8 @@ def main():
     ap.add_argument("--uncached-steps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-parameter search (use sort + deferral, 4-chunk runs)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-surrogate leg (training on the insert log)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (for HBM counter scaling)")
     args = ap.parse_args()
@@ -258,6 +362,8 @@ def main():
                      "bytes_per_launch": kb / sc.frames,
                      "avg_launch_ms": shade_ms / max(shade_launches, 1)},
     }
+    if not args.no_surrogate and use_cache and args.workload == "mid":
+        res["surrogate"] = surrogate_leg(ctx, sc, frame_views, out, cache, best, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(sc)

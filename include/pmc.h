@@ -363,7 +363,7 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
  *                       4 channels (COLOR 3, FLOAT 1) while they fit; one
  *                       network ("slot") per material that has any
  *   features            x[4k..4k+3] = sin(w_k u), cos(w_k u), sin(w_k v), cos(w_k v),
- *                       w_k = 2 pi 2^(k-3), k = 0..7
+ *                       w_k = 2 pi 2^(k-4), k = 0..7 (periods 16 .. 1/8 of a UV unit)
  *   network             h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3
  *                       with W1 64x32, W2 64x64, W3 4x64: 6532 parameters, stored
  *                       flat as W1 (row-major [out][in]), b1, W2, b2, W3, b3
@@ -435,7 +435,8 @@ typedef struct pmc_train_params {
     uint32_t holdout;              /* held-out records per slot (at most a quarter of them);
                                       0 = 4096 */
     uint32_t min_records;          /* slots with fewer log records are skipped; 0 = 1024 */
-    uint32_t reserved;
+    float lr_end;                  /* > 0: the step size decays geometrically from lr to lr_end
+                                      over the call's steps; 0 = constant lr */
     uint64_t seed;                 /* batch sampling */
 } pmc_train_params;
 /* Train every slot on its records of the insert log, all slots at once (one

@@ -6,7 +6,7 @@ trusted only where its measured error is small.  Definitions used by both
 this reference and the HIP kernels:
 
   features   x = [sin(w_k u), cos(w_k u), sin(w_k v), cos(w_k v)] for
-             k = 0..7, w_k = 2 pi 2^(k - 3)  (32 values; periods 8 .. 1/16 UV)
+             k = 0..7, w_k = 2 pi 2^(k - 4)  (32 values; periods 16 .. 1/8 UV)
   network    h1 = relu(W1 x + b1)   W1: 64 x 32
              h2 = relu(W2 h1 + b2)  W2: 64 x 64
              y  = W3 h2 + b3        W3: 4 x 64
@@ -37,7 +37,7 @@ N_FEAT, N_HID, N_OUT = 32, 64, 4
 N_PARAMS = 6532
 SEED_AUDIT = 0xD6E8FEB86659FD93
 _SHAPES = ((64, 32), (64,), (64, 64), (64,), (4, 64), (4,))
-OMEGA = 2.0 * np.pi * 2.0 ** (np.arange(8) - 3.0)
+OMEGA = 2.0 * np.pi * 2.0 ** (np.arange(8) - 4.0)
 
 
 def features(uv):

@@ -127,7 +127,7 @@ class pmc_surrogate_slot(C.Structure):
 
 class pmc_train_params(C.Structure):
     _fields_ = [("steps", C.c_uint32), ("batch", C.c_uint32), ("lr", C.c_float),
-                ("holdout", C.c_uint32), ("min_records", C.c_uint32), ("reserved", C.c_uint32),
+                ("holdout", C.c_uint32), ("min_records", C.c_uint32), ("lr_end", C.c_float),
                 ("seed", C.c_uint64)]
 
 
@@ -428,15 +428,15 @@ class Context:
                                            _stream_ptr(stream)))
 
     def surrogate_train(self, steps: int = 0, batch: int = 0, lr: float = 0.0, holdout: int = 0,
-                        min_records: int = 0, seed: int = 0, stream=None):
-        p = pmc_train_params(steps, batch, lr, holdout, min_records, 0, seed)
+                        min_records: int = 0, seed: int = 0, lr_end: float = 0.0, stream=None):
+        p = pmc_train_params(steps, batch, lr, holdout, min_records, lr_end, seed)
         self.check(pmc_surrogate_train(self.h, C.byref(p), _stream_ptr(stream)))
 
     def surrogate_train_records(self, slot: int, records, steps: int = 0, batch: int = 0,
-                                lr: float = 0.0, seed: int = 0, stream=None):
+                                lr: float = 0.0, seed: int = 0, lr_end: float = 0.0, stream=None):
         """records: torch uint8/int32 CUDA tensor holding n packed pmc_log_record."""
         n = records.numel() * records.element_size() // 32
-        p = pmc_train_params(steps, batch, lr, 0, 0, 0, seed)
+        p = pmc_train_params(steps, batch, lr, 0, 0, lr_end, seed)
         self.check(pmc_surrogate_train_records(self.h, slot, _ptr(records), n, C.byref(p),
                                                _stream_ptr(stream)))
 

@@ -60,10 +60,10 @@ __device__ __forceinline__ f4 mfma16(h4 a, h4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
-// Features 4q .. 4q+3: sin and cos of w_q u and of w_q v, w_q = 2 pi 2^(q-3).
-// sin(2 pi 2^(q-3) u) = sinpi(2^(q-2) u); the scaling by a power of two is exact.
+// Features 4q .. 4q+3: sin and cos of w_q u and of w_q v, w_q = 2 pi 2^(q-4).
+// sin(2 pi 2^(q-4) u) = sinpi(2^(q-3) u); the scaling by a power of two is exact.
 __device__ __forceinline__ h4 fourier4(float u, float v, int q) {
-  const float s = __builtin_ldexpf(1.0f, q - 2);
+  const float s = __builtin_ldexpf(1.0f, q - 3);
   float su, cu, sv, cv;
   sincospif(u * s, &su, &cu);
   sincospif(v * s, &sv, &cv);
@@ -174,7 +174,7 @@ struct TrainArgs {
   SurrW* w;                    // [slot] inference copies (written at the end)
   SurrState* state;            // [slot]
   uint32_t steps, batch;       // batch: multiple of 128
-  float lr;
+  float lr, lr_end;             // lr_end > 0: geometric decay over the call's steps
   uint64_t seed;
   uint32_t sample;             // 1: Adam steps on sampled batches; 0: one gradient pass
   float* grad_out;             // gradient pass: 6532 FP32

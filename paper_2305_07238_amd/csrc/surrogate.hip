@@ -204,19 +204,24 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
       gb3[m] = 0.0f;
     }
     const uint32_t n_chunks = a.sample ? a.batch / 32u : (n_train + 31u) / 32u;
-    for (uint32_t c = (uint32_t)wave; c < n_chunks; c += kTW) {
-      // lanes 0..31 hold the chunk's 32 samples (lanes 32..63 repeat them)
+    // lanes 0..31 hold a chunk's 32 samples (lanes 32..63 repeat them); the
+    // records of the wave's next chunk are loaded while this one is processed
+    auto record_of = [&](uint32_t c, bool* valid) -> uint32_t {
       const uint32_t i = c * 32u + (uint32_t)(lane & 31);
-      uint32_t r;
-      bool valid;
       if (a.sample) {
-        valid = true;
-        r = (uint32_t)(mix64(a.seed ^ (((uint64_t)t_step << 32) | i)) % n_train);
-      } else {
-        valid = i < n_train;
-        r = valid ? i : 0u;
+        *valid = true;
+        return (uint32_t)(mix64(a.seed ^ (((uint64_t)t_step << 32) | i)) % n_train);
       }
-      const pmc_log_record R = load_record(rec + r);
+      *valid = i < n_train;
+      return *valid ? i : 0u;
+    };
+    bool valid_next = false;
+    pmc_log_record R_next;
+    if ((uint32_t)wave < n_chunks) R_next = load_record(rec + record_of((uint32_t)wave, &valid_next));
+    for (uint32_t c = (uint32_t)wave; c < n_chunks; c += kTW) {
+      const pmc_log_record R = R_next;
+      const bool valid = valid_next;
+      if (c + kTW < n_chunks) R_next = load_record(rec + record_of(c + kTW, &valid_next));
       float tg[4], mk[4];
       record_target(R, st, tg, mk);
       if (!valid) {
@@ -448,13 +453,16 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
       for (int p = tid; p < kParams; p += 256) a.grad_out[p] = L.g[p] * inv;
       if (tid == 0) *a.loss_out = L.red[0] * inv;
     } else {
+      const float lr = a.lr_end > 0.0f && steps > 1u
+                           ? a.lr * powf(a.lr_end / a.lr, (float)s / (float)(steps - 1u))
+                           : a.lr;
       const float bc1 = 1.0f - powf(0.9f, (float)t_step);
       const float bc2 = 1.0f - powf(0.999f, (float)t_step);
       for (int p = tid; p < kParams; p += 256) {
         const float gr = L.g[p] * inv;
         const float m = 0.9f * M1[p] + 0.1f * gr;
         const float v = 0.999f * V1[p] + 0.001f * gr * gr;
-        const float w = P[p] - a.lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
+        const float w = P[p] - lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
         P[p] = w;
         M1[p] = m;
         V1[p] = v;

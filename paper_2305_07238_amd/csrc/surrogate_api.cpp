@@ -60,6 +60,8 @@ pmc_status check_train(pmc_ctx* ctx, const pmc_train_params* p, pmc_train_params
     return ctx->fail(PMC_ERR_INVALID, "batch must be a multiple of 128, at most 2^20");
   if (q.steps > 1000000u) return ctx->fail(PMC_ERR_INVALID, "at most 10^6 steps per call");
   if (!(q.lr > 0.0f) || !std::isfinite(q.lr)) return ctx->fail(PMC_ERR_INVALID, "bad lr");
+  if (!(q.lr_end >= 0.0f) || !std::isfinite(q.lr_end))
+    return ctx->fail(PMC_ERR_INVALID, "bad lr_end");
   *out = q;
   return PMC_OK;
 }
@@ -272,6 +274,7 @@ pmc_status pmc_surrogate_train(pmc_ctx* ctx, const pmc_train_params* params, voi
   a.steps = q.steps;
   a.batch = q.batch;
   a.lr = q.lr;
+  a.lr_end = q.lr_end;
   a.seed = q.seed;
   a.sample = 1;
   HIP_TRY(ctx, launch_surr_train(a, S.n_slots, s));
@@ -299,6 +302,7 @@ pmc_status pmc_surrogate_train_records(pmc_ctx* ctx, uint32_t slot, const pmc_lo
   a.steps = q.steps;
   a.batch = q.batch;
   a.lr = q.lr;
+  a.lr_end = q.lr_end;
   a.seed = q.seed;
   a.sample = 1;
   HIP_TRY(ctx, launch_surr_train(a, 1, (hipStream_t)stream));

@@ -463,7 +463,8 @@ def lognormal_sizes(rng, n, lo, hi, mu=3.0, sigma=1.0):
     return np.clip(np.rint(rng.lognormal(mu, sigma, n)), lo, hi).astype(int)
 
 
-def smooth_material(seed: int, m: int, groups: int = 9) -> Material:
+def smooth_material(seed: int, m: int, groups: int = 9, perlin_freq: float = 1.0,
+                    perlin_octaves: int = 2, value_freq: float = 1.0) -> Material:
     """A material whose deep sub-graphs are smooth functions of UV (low-frequency
     value and Perlin noise through 4 * groups MUL/POW nodes that undo each other
     pairwise), so a small network can represent them: base colour (COLOR, one
@@ -473,8 +474,9 @@ def smooth_material(seed: int, m: int, groups: int = 9) -> Material:
     ca, cb, cc = (tuple(float(x) for x in rng.uniform(0.1, 0.9, 3)) for _ in range(3))
     nodes = [
         Node("UV_INPUT"),                                                        # 0
-        Node("VALUE_NOISE", [L(0)], freq=1.0, octaves=1, seed=int(rng.integers(1 << 30))),
-        Node("PERLIN_NOISE", [L(0)], freq=1.0, octaves=2, seed=int(rng.integers(1 << 30))),
+        Node("VALUE_NOISE", [L(0)], freq=value_freq, octaves=1, seed=int(rng.integers(1 << 30))),
+        Node("PERLIN_NOISE", [L(0)], freq=perlin_freq, octaves=perlin_octaves,
+             seed=int(rng.integers(1 << 30))),
         Node("MIX", [L(1), C(*ca), C(*cb)]),                                     # 3
     ]
     x = 2
@@ -493,9 +495,11 @@ def smooth_material(seed: int, m: int, groups: int = 9) -> Material:
 
 
 def smooth_scene(seed: int = 0, n_mats: int = 4, width: int = 480, height: int = 240,
-                 frames: int = 4, slots: int = 1 << 18) -> Scene:
+                 frames: int = 4, slots: int = 1 << 18, perlin_freq: float = 1.0,
+                 perlin_octaves: int = 2, value_freq: float = 1.0) -> Scene:
     """Scene of smooth_material graphs on 40-px objects with UV scale U[0.5, 1]."""
-    mats = [smooth_material(seed, m) for m in range(n_mats)]
+    mats = [smooth_material(seed, m, perlin_freq=perlin_freq, perlin_octaves=perlin_octaves,
+                            value_freq=value_freq) for m in range(n_mats)]
     frame, n = _object_screen(seed, n_mats, width, height, 40, frames, scale=(0.5, 1.0),
                               name="smooth")
     return Scene("smooth", mats, [], frames, n, CacheConfig(slots), seed, frame)

@@ -14,13 +14,18 @@ def test_features_closed_forms():
     x = mlp.features(np.array([[0.0, 0.0], [2.0, 0.25]]))
     assert x.shape == (2, 32)
     assert np.allclose(x[0, 0::2], 0.0) and np.allclose(x[0, 1::2], 1.0)
-    # u = 2 is a quarter period of w_0 = 2 pi / 8: sin = 1, cos = 0
-    assert np.isclose(x[1, 0], 1.0) and np.isclose(x[1, 1], 0.0, atol=1e-15)
-    # v = 1/4 is a whole period of w_5 = 2 pi 4
-    assert np.isclose(x[1, 4 * 5 + 2], 0.0, atol=1e-12) and np.isclose(x[1, 4 * 5 + 3], 1.0)
-    # periodicity of the slowest feature: period 8
+    # u = 2 is an eighth of the period of w_0 = 2 pi / 16: sin = cos = 1 / sqrt 2
+    assert np.isclose(x[1, 0], np.sqrt(0.5)) and np.isclose(x[1, 1], np.sqrt(0.5))
+    # u = 2 is a quarter period of w_1 = 2 pi / 8: sin = 1, cos = 0
+    assert np.isclose(x[1, 4], 1.0) and np.isclose(x[1, 5], 0.0, atol=1e-15)
+    # v = 1/4 is a whole period of w_6 = 2 pi 4
+    assert np.isclose(x[1, 4 * 6 + 2], 0.0, atol=1e-12) and np.isclose(x[1, 4 * 6 + 3], 1.0)
+    # v = 1/8 is a whole period of the fastest feature, w_7 = 2 pi 8
+    c = mlp.features(np.array([[0.0, 0.125]]))
+    assert np.isclose(c[0, 30], 0.0, atol=1e-12) and np.isclose(c[0, 31], 1.0)
+    # periodicity of the slowest feature: period 16
     a = mlp.features(np.array([[0.3, 0.7]]))
-    b = mlp.features(np.array([[8.3, 8.7]]))
+    b = mlp.features(np.array([[16.3, 16.7]]))
     assert np.allclose(a[0, :4], b[0, :4])
 
 
