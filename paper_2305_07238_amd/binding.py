@@ -17,6 +17,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmc.so")
 
+# torch ships its own HIP runtime libraries; load them before libpmc.so so that
+# both find the device (loaded the other way round, one of them sees none)
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                       "(python -c 'import __graft_entry__ as g; g.build()')")

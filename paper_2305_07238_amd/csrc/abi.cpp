@@ -130,7 +130,8 @@ pmc_status pmc_create(int device, pmc_ctx** out) {
     if (ensure(ctx, ctx->stat_slots, sizeof(unsigned long long) * kStatSlots * kStatStride) ||
         ensure(ctx, ctx->misc, 256) ||
         hipMemset(ctx->stat_slots.p, 0, ctx->stat_slots.bytes) != hipSuccess ||
-        hipMemset(ctx->misc.p, 0, ctx->misc.bytes) != hipSuccess) {
+        hipMemset(ctx->misc.p, 0, ctx->misc.bytes) != hipSuccess ||
+        prepare_sort_kernels() != hipSuccess || prepare_surrogate_kernels() != hipSuccess) {
       pmc_destroy(ctx);
       return PMC_ERR_HIP;
     }

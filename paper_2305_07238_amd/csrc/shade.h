@@ -95,6 +95,9 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t n, uint32_t* out, 
 // mat_counts / offsets need (n_mats + 1) * sort_tiles(n) entries; scan_sums
 // scan_blocks(that) + 1.  reset[0..n_reset) is zeroed.
 uint32_t sort_tiles(uint32_t n);
+// Kernel attributes (large dynamic LDS) set once per device, at context creation.
+hipError_t prepare_sort_kernels();
+hipError_t prepare_surrogate_kernels();
 hipError_t launch_material_sort_tiled(const uint32_t* material, uint32_t n, uint32_t n_mats,
                                       const uint32_t* rank, uint32_t* mat_counts,
                                       uint32_t* offsets, uint32_t* scan_sums, uint32_t* perm,

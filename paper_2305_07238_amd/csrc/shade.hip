@@ -752,19 +752,33 @@ struct LaneHit {
   HitData hd;
 };
 
-__device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t* list,
-                                             uint32_t list_n, uint32_t chunk, Counters& cnt) {
-  LaneHit L;
+// A lane's hit: its index (through the processing order) and then its data.
+// The two halves are separate so a wave can fetch the next chunk's hits while
+// it works on the current one.
+struct LaneIdx {
+  bool active;
+  uint32_t h;
+};
+
+__device__ __forceinline__ LaneIdx lane_index(const uint32_t* list, uint32_t list_n,
+                                              uint32_t chunk) {
+  LaneIdx I;
   const uint32_t idx = chunk * 64u + (uint32_t)lane_id();
-  L.active = idx < list_n;
-  L.h = 0;
+  I.active = idx < list_n;
+  I.h = I.active ? (list ? list[idx] : idx) : 0u;
+  return I;
+}
+
+__device__ __forceinline__ LaneHit fetch_lane(const ShadeArgs& a, LaneIdx I) {
+  LaneHit L;
+  L.active = I.active;
+  L.h = I.h;
   L.mat = 0xFFFFFFFFu;
   L.hd.u = L.hd.v = 0.0f;
   L.hd.g = make_float4(0.f, 0.f, 0.f, 0.f);
   L.hd.n = make_float3(0.f, 0.f, 1.f);
   if (L.active) {
-    const uint32_t h = list ? list[idx] : idx;
-    L.h = h;
+    const uint32_t h = I.h;
     L.mat = a.material[h];
     float2 uv = reinterpret_cast<const float2*>(a.uv)[h];
     L.hd.u = uv.x;
@@ -776,14 +790,22 @@ __device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t*
   return L;
 }
 
+__device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t* list,
+                                             uint32_t list_n, uint32_t chunk) {
+  return fetch_lane(a, lane_index(list, list_n, chunk));
+}
+
 // KIND_FULL: every lane of the chunk is evaluated completely.
+// The chunk's hits arrive in L; `next` (when valid) is the index of the wave's
+// next chunk, whose hits are fetched into *Ln once the probes of this chunk
+// are consumed, so the loads overlap the evaluation below.
 template <int MODE, bool SURR>
-__device__ __forceinline__ void chunk_full(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
-                                           Counters& cnt) {
-  LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
+__device__ __forceinline__ void chunk_full(const ShadeArgs& a, const LaneHit& L, LaneIdx next,
+                                           LaneHit* Ln, const LaneRegs& R, Counters& cnt) {
   cnt.v[CNT_HITS] += (uint32_t)L.active;
   uint32_t ins = 0u, slots = 0u;
   uint32_t miss = probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
+  *Ln = fetch_lane(a, next);
   uint64_t pending = __ballot(L.active);
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -821,7 +843,7 @@ __device__ __forceinline__ void flush_deferred(const ShadeArgs& a, DeferBuf& B, 
                                             Counters& cnt) {
   const uint32_t m = B.mat;
   const bool act = (uint32_t)lane_id() < B.count;
-  LaneHit L = load_lane(a, B.ids, B.count, 0u, cnt);
+  LaneHit L = load_lane(a, B.ids, B.count, 0u);
   uint32_t ins = 0u, slots = 0u;
   uint32_t miss = probe_chunk<MODE, false>(a, act, m, L.h, L.hd, R, cnt, &ins, &slots);
   Audit au = no_audit();
@@ -835,12 +857,13 @@ __device__ __forceinline__ void flush_deferred(const ShadeArgs& a, DeferBuf& B, 
 // dense enough to be evaluated in place; otherwise its missing lanes go to the
 // wave's staging buffer.
 template <int MODE, bool SURR>
-__device__ __forceinline__ void chunk_probe(const ShadeArgs& a, uint32_t chunk, const LaneRegs& R,
-                                            Counters& cnt, DeferBuf& B) {
-  LaneHit L = load_lane(a, a.perm, a.n, chunk, cnt);
+__device__ __forceinline__ void chunk_probe(const ShadeArgs& a, const LaneHit& L, LaneIdx next,
+                                            LaneHit* Ln, const LaneRegs& R, Counters& cnt,
+                                            DeferBuf& B) {
   cnt.v[CNT_HITS] += (uint32_t)L.active;
   uint32_t ins = 0u, slots = 0u;
   uint32_t miss = probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
+  *Ln = fetch_lane(a, next);
   bool deferred = false;
   uint64_t pending = __ballot(L.active);
   while (pending) {
@@ -913,9 +936,18 @@ template <int MODE, int KIND, bool SURR>
 __device__ __forceinline__ void do_run(const ShadeArgs& a, uint32_t first, uint32_t n_chunks,
                                        const LaneRegs& R, Counters& cnt, DeferBuf& B) {
   const uint32_t last = min(first + a.chunk_waves, n_chunks);
+  LaneHit L = load_lane(a, a.perm, a.n, first);
   for (uint32_t c = first; c < last; ++c) {
-    if (KIND == KIND_PROBE) chunk_probe<MODE, SURR>(a, c, R, cnt, B);
-    else chunk_full<MODE, SURR>(a, c, R, cnt);
+    // index of the next chunk now (its load is in flight during the probes),
+    // its hit data once this chunk's probes are consumed
+    LaneIdx next;
+    next.active = false;
+    next.h = 0u;
+    if (c + 1u < last) next = lane_index(a.perm, a.n, c + 1u);
+    LaneHit Ln;
+    if (KIND == KIND_PROBE) chunk_probe<MODE, SURR>(a, L, next, &Ln, R, cnt, B);
+    else chunk_full<MODE, SURR>(a, L, next, &Ln, R, cnt);
+    L = Ln;
   }
   if (KIND == KIND_PROBE && B.count != 0u) flush_deferred<MODE, SURR>(a, B, R, cnt);
 }
@@ -927,7 +959,7 @@ __device__ __forceinline__ float* wave_lds(float* lds, const ShadeArgs& a) {
 
 // STATS = false: the counters are dead code and take no registers.
 template <int MODE, int KIND, bool STATS, bool SURR>
-__global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
+__device__ __forceinline__ void shade_flat_body(const ShadeArgs& a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
   LaneRegs R{wl, lane_id()};
@@ -947,7 +979,7 @@ __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
 // The material sort orders hits by decreasing program length, so the stride
 // deals the long programs out first.
 template <int MODE, int KIND, bool STATS, bool SURR>
-__global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
+__device__ __forceinline__ void shade_persistent_body(const ShadeArgs& a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
   LaneRegs R{wl, lane_id()};
@@ -963,6 +995,32 @@ __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   if (STATS) flush_counters(a, cnt);
 }
 
+// Kernels.  The cached variants without networks are compiled for 4 waves per
+// SIMD (at most 128 VGPRs): the probe-heavy path is latency bound and gains more
+// from the extra wave than it loses to a few spilled registers.  The uncached
+// and network variants keep the compiler's own register budget.
+template <int MODE, int KIND, bool STATS, bool SURR>
+__global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
+  shade_flat_body<MODE, KIND, STATS, SURR>(a);
+}
+
+template <int MODE, int KIND, bool STATS, bool SURR>
+__global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
+  shade_persistent_body<MODE, KIND, STATS, SURR>(a);
+}
+
+template <int MODE, int KIND, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_shade_flat_w4(ShadeArgs a) {
+  shade_flat_body<MODE, KIND, STATS, false>(a);
+}
+
+template <int MODE, int KIND, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_shade_persistent_w4(ShadeArgs a) {
+  shade_persistent_body<MODE, KIND, STATS, false>(a);
+}
+
 // ---------------------------------------------------------- host launchers ---
 
 size_t shade_lds_bytes(uint32_t n_regs) { return (size_t)4 * (n_regs * 64 + 64) * sizeof(float); }
@@ -970,7 +1028,13 @@ size_t shade_lds_bytes(uint32_t n_regs) { return (size_t)4 * (n_regs * 64 + 64) 
 template <int MODE, int KIND, bool STATS, bool SURR>
 static void launch_one(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
                        hipStream_t s) {
-  if (persistent)
+  constexpr bool w4 = MODE != PMC_MODE_UNCACHED && !SURR;
+  if (w4 && persistent)
+    hipLaunchKernelGGL((k_shade_persistent_w4<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s,
+                       a);
+  else if (w4)
+    hipLaunchKernelGGL((k_shade_flat_w4<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s, a);
+  else if (persistent)
     hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds,
                        s, a);
   else

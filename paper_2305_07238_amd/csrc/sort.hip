@@ -81,6 +81,61 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const uint32_t* material, 
   }
 }
 
+// Exclusive scan of a small count matrix by one block: the matrix is loaded
+// into LDS with coalesced reads, each thread scans a contiguous segment, a
+// block-wide scan of the segment totals gives their offsets, and the result
+// goes back with coalesced writes.  Also clears reset[0 .. n_reset).
+constexpr uint32_t kSmallScanMax = 36864;            // 144 KiB of LDS
+constexpr uint32_t kSmallScanThreads = 1024;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_t n,
+                                                     uint32_t* out, uint32_t* reset,
+                                                     uint32_t n_reset) {
+  extern __shared__ uint32_t buf[];
+  __shared__ uint32_t wsum[kSmallScanThreads / 64];
+  const uint32_t t = threadIdx.x;
+  for (uint32_t i = t; i < n; i += kSmallScanThreads) buf[i] = in[i];
+  if (t < n_reset) reset[t] = 0u;
+  __syncthreads();
+  const uint32_t per = (n + kSmallScanThreads - 1) / kSmallScanThreads;
+  const uint32_t beg = min(t * per, n), end = min(beg + per, n);
+  uint32_t s = 0;
+  for (uint32_t i = beg; i < end; ++i) s += buf[i];
+  // block exclusive scan of s: inclusive scan within the wave, then over wave totals
+  uint32_t x = s;
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[t >> 6] = x;
+  __syncthreads();
+  if (t < 64) {
+    uint32_t w = t < kSmallScanThreads / 64 ? wsum[t] : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(w, o, 64);
+      if (lane >= o) w += y;
+    }
+    if (t < kSmallScanThreads / 64) wsum[t] = w;
+  }
+  __syncthreads();
+  uint32_t run = x - s + ((t >> 6) ? wsum[(t >> 6) - 1] : 0u);
+  for (uint32_t i = beg; i < end; ++i) {
+    const uint32_t v = buf[i];
+    buf[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < n; i += kSmallScanThreads) out[i] = buf[i];
+}
+
+hipError_t prepare_sort_kernels() {
+  return hipFuncSetAttribute((const void*)k_scan_small,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kSmallScanMax * 4);
+}
+
 uint32_t sort_tiles(uint32_t n) {
   uint32_t t = (n + 4095) / 4096;
   return t < 1 ? 1 : (t > 512 ? 512 : t);
@@ -96,12 +151,18 @@ hipError_t launch_material_sort_tiled(const uint32_t* material, uint32_t n, uint
   const size_t lds = (size_t)nb * sizeof(uint32_t);
   hipLaunchKernelGGL(k_tile_hist, dim3(n_tiles), dim3(256), lds, s, material, n, n_mats, tile,
                      n_tiles, rank, mat_counts);
-  hipError_t e = launch_exclusive_scan(mat_counts, nb * n_tiles, offsets, nullptr, scan_sums,
-                                       nullptr, s);
-  if (e != hipSuccess) return e;
-  if (n_reset) {
-    e = launch_fill_u32(reset, 0u, n_reset, s);
+  const uint32_t cells = nb * n_tiles;
+  hipError_t e;
+  if (cells <= kSmallScanMax && n_reset <= kSmallScanThreads) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallScanThreads), (size_t)cells * 4, s,
+                       mat_counts, cells, offsets, reset, n_reset);
+  } else {
+    e = launch_exclusive_scan(mat_counts, cells, offsets, nullptr, scan_sums, nullptr, s);
     if (e != hipSuccess) return e;
+    if (n_reset) {
+      e = launch_fill_u32(reset, 0u, n_reset, s);
+      if (e != hipSuccess) return e;
+    }
   }
   hipLaunchKernelGGL(k_tile_scatter, dim3(n_tiles), dim3(256), lds, s, material, n, n_mats, tile,
                      n_tiles, rank, offsets, perm);

@@ -481,14 +481,12 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
   }
 }
 
+hipError_t prepare_surrogate_kernels() {
+  return hipFuncSetAttribute((const void*)k_surr_train,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, LDS_TOTAL);
+}
+
 hipError_t launch_surr_train(const TrainArgs& a, uint32_t n_blocks, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_surr_train,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, LDS_TOTAL);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
   hipLaunchKernelGGL(k_surr_train, dim3(n_blocks), dim3(256), LDS_TOTAL, s, a);
   return hipGetLastError();
 }
