@@ -6,6 +6,8 @@
 
 namespace pmc {
 
+constexpr uint32_t kSortBatch = 8;    // material ids loaded per thread before they are used
+
 // Tiled counting sort without global atomics: tile k (a block) histograms
 // its hits in LDS and writes hist[rank(b)][k]; an exclusive scan over that
 // matrix (bucket rank major, tile minor) gives every (bucket, tile) its output
@@ -22,21 +24,26 @@ __global__ __launch_bounds__(256) void k_tile_hist(const uint32_t* material, uin
   __syncthreads();
   const uint32_t beg = blockIdx.x * tile;
   const uint32_t end = min(beg + tile, n);
-  for (uint32_t i0 = beg; i0 < end; i0 += blockDim.x) {
-    const uint32_t i = i0 + threadIdx.x;
-    const bool valid = i < end;
-    uint32_t b = 0;
-    if (valid) {
-      uint32_t m = material[i];
-      b = m < n_mats ? m : n_mats;
+  for (uint32_t g0 = beg; g0 < end; g0 += kSortBatch * 256u) {
+    uint32_t bb[kSortBatch];
+#pragma unroll
+    for (uint32_t k = 0; k < kSortBatch; ++k) {     // all loads of the batch in flight at once
+      const uint32_t i = g0 + k * 256u + threadIdx.x;
+      const uint32_t m = i < end ? material[i] : 0xFFFFFFFFu;
+      bb[k] = i < end ? (m < n_mats ? m : n_mats) : 0xFFFFFFFFu;
     }
-    uint64_t act = __ballot(valid);
-    while (act) {
-      const int leader = __ffsll((unsigned long long)act) - 1;
-      const uint32_t bl = __builtin_amdgcn_readlane(b, leader);
-      const uint64_t match = __ballot(valid && b == bl);
-      if (lane_id() == leader) atomicAdd(&hist[bl], (uint32_t)__popcll(match));
-      act &= ~match;
+#pragma unroll
+    for (uint32_t k = 0; k < kSortBatch; ++k) {
+      const uint32_t b = bb[k];
+      const bool valid = b != 0xFFFFFFFFu;
+      uint64_t act = __ballot(valid);
+      while (act) {
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const uint32_t bl = __builtin_amdgcn_readlane(b, leader);
+        const uint64_t match = __ballot(valid && b == bl);
+        if (lane_id() == leader) atomicAdd(&hist[bl], (uint32_t)__popcll(match));
+        act &= ~match;
+      }
     }
   }
   __syncthreads();
@@ -59,24 +66,32 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const uint32_t* material, 
   __syncthreads();
   const uint32_t beg = blockIdx.x * tile;
   const uint32_t end = min(beg + tile, n);
-  for (uint32_t i0 = beg; i0 < end; i0 += blockDim.x) {
-    const uint32_t i = i0 + threadIdx.x;
-    const bool valid = i < end;
-    uint32_t b = 0;
-    if (valid) {
-      uint32_t m = material[i];
-      b = m < n_mats ? m : n_mats;
+  for (uint32_t g0 = beg; g0 < end; g0 += kSortBatch * 256u) {
+    uint32_t bb[kSortBatch];
+#pragma unroll
+    for (uint32_t k = 0; k < kSortBatch; ++k) {
+      const uint32_t i = g0 + k * 256u + threadIdx.x;
+      const uint32_t m = i < end ? material[i] : 0xFFFFFFFFu;
+      bb[k] = i < end ? (m < n_mats ? m : n_mats) : 0xFFFFFFFFu;
     }
-    uint64_t act = __ballot(valid);
-    while (act) {
-      const int leader = __ffsll((unsigned long long)act) - 1;
-      const uint32_t bl = __builtin_amdgcn_readlane(b, leader);
-      const uint64_t match = __ballot(valid && b == bl);
-      uint32_t old = 0;
-      if (lane_id() == leader) old = atomicAdd(&base[bl], (uint32_t)__popcll(match));
-      old = __shfl(old, leader, 64);
-      if (valid && b == bl) perm[old + (uint32_t)__popcll(match & lanemask_lt())] = i;
-      act &= ~match;
+    // ranks inside a bucket follow the order of the LDS atomics across the
+    // block's waves; the order of hits within a bucket carries no meaning
+#pragma unroll
+    for (uint32_t k = 0; k < kSortBatch; ++k) {
+      const uint32_t i = g0 + k * 256u + threadIdx.x;
+      const uint32_t b = bb[k];
+      const bool valid = b != 0xFFFFFFFFu;
+      uint64_t act = __ballot(valid);
+      while (act) {
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const uint32_t bl = __builtin_amdgcn_readlane(b, leader);
+        const uint64_t match = __ballot(valid && b == bl);
+        uint32_t old = 0;
+        if (lane_id() == leader) old = atomicAdd(&base[bl], (uint32_t)__popcll(match));
+        old = __shfl(old, leader, 64);
+        if (valid && b == bl) perm[old + (uint32_t)__popcll(match & lanemask_lt())] = i;
+        act &= ~match;
+      }
     }
   }
 }
@@ -94,6 +109,7 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_
   extern __shared__ uint32_t buf[];
   __shared__ uint32_t wsum[kSmallScanThreads / 64];
   const uint32_t t = threadIdx.x;
+#pragma unroll 8
   for (uint32_t i = t; i < n; i += kSmallScanThreads) buf[i] = in[i];
   if (t < n_reset) reset[t] = 0u;
   __syncthreads();
@@ -128,6 +144,7 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_
     run += v;
   }
   __syncthreads();
+#pragma unroll 8
   for (uint32_t i = t; i < n; i += kSmallScanThreads) out[i] = buf[i];
 }
 
