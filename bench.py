@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--uncached-steps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-parameter search (use sort + deferral, 4-chunk runs)")
+    ap.add_argument("--min-subgraph", type=int, default=0,
+                    help="smallest cacheable sub-graph in nodes (compile option; 0 = library default 2)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training on the insert log)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -252,7 +254,7 @@ def main():
 
     ctx = B.Context(0)
     ctx.set_textures(sc.textures)
-    ctx.compile(sc.materials)
+    ctx.compile(sc.materials, min_subgraph_nodes=args.min_subgraph)
     cc = sc.cache
     policy = B.PMC_POLICY_OVERWRITE if cc.policy == "OVERWRITE" else B.PMC_POLICY_FIRST
     cache = ctx.cache(cc.n_cells, cc.n_entries, cc.entry_bytes, policy)

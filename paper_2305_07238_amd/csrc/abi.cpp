@@ -361,6 +361,7 @@ static void fill_program_args(pmc_ctx* ctx, ShadeArgs& a) {
 static void fill_cache_args(pmc_cache* c, ShadeArgs& a) {
   a.table = (uint64_t*)c->mem;
   a.n_cells = (uint32_t)c->params.n_cells;
+  a.cells = make_cell_map(a.n_cells);
   a.n_entries = c->params.n_entries;
   a.entry_words = c->params.entry_bytes / 8;
   a.policy = c->params.policy;

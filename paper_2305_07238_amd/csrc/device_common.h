@@ -29,6 +29,28 @@ constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kSeedCell = 0x9E3779B97F4A7C15ull;    // Hash: cell index
 constexpr uint64_t kSeedVerify = 0xC2B2AE3D27D4EB4Full;  // Hash2: verification key
 
+// ---- x mod N_c without a division ------------------------------------------
+// N_c a power of two: a mask.  Otherwise the direct remainder of Lemire, Kaser
+// and Kurz ("Faster remainder by direct computation", 2019): with
+// M = ceil(2^64 / n), x mod n = hi64((M * x mod 2^64) * n), exact for 32-bit x, n.
+struct CellMap {
+  uint32_t n, mask;          // mask = n - 1 when n is a power of two above 1, else 0
+  uint64_t magic;            // ceil(2^64 / n); 0 for n = 1
+};
+
+__host__ __device__ inline CellMap make_cell_map(uint32_t n) {
+  CellMap c;
+  c.n = n;
+  c.mask = (n > 1u && (n & (n - 1u)) == 0u) ? n - 1u : 0u;
+  c.magic = n > 1u ? ~0ull / n + 1ull : 0ull;
+  return c;
+}
+
+__device__ __forceinline__ uint32_t cell_of(const CellMap& c, uint32_t x) {
+  if (c.mask) return x & c.mask;
+  return (uint32_t)__umul64hi(c.magic * (uint64_t)x, (uint64_t)c.n);
+}
+
 // ---- descriptor of a cacheable output (Sec. 3.1 Eq. 1, Sec. 3.2) -----------
 struct Key {
   uint32_t cell, hash2;
@@ -40,7 +62,7 @@ struct Key {
 // squared norms; frexp gives m2 = f 2^e, f in [1/2, 1), and then
 // floor(lambda) = floor((-e + [f == 1/2]) / 2).
 __device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float u, float v,
-                                        float4 g, int bias, int lmax, uint32_t n_cells) {
+                                        float4 g, int bias, int lmax, const CellMap& cells) {
   Key k;
   k.cell = 0; k.hash2 = 1; k.level = 0; k.tx = 0; k.ty = 0; k.bypass = true;
   if (!(isfinite(u) && isfinite(v) && isfinite(g.x) && isfinite(g.y) && isfinite(g.z) &&
@@ -69,7 +91,7 @@ __device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float 
   uint64_t k1 = ((uint64_t)(uint32_t)tx << 32) | (uint64_t)(uint32_t)ty;
   uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
   uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
-  k.cell = (uint32_t)(hc >> 32) % n_cells;
+  k.cell = cell_of(cells, (uint32_t)(hc >> 32));
   k.hash2 = (uint32_t)hv;
   if (k.hash2 == 0) k.hash2 = 1;
   k.level = L; k.tx = tx; k.ty = ty; k.bypass = false;
@@ -77,11 +99,11 @@ __device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float 
 }
 
 // Descriptor hashes of raw descriptor words (Algorithm 1 surface).
-__device__ __forceinline__ void raw_hash(uint64_t k0, uint64_t k1, uint32_t n_cells,
+__device__ __forceinline__ void raw_hash(uint64_t k0, uint64_t k1, const CellMap& cells,
                                          uint32_t* cell, uint32_t* hash2) {
   uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
   uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
-  *cell = (uint32_t)(hc >> 32) % n_cells;
+  *cell = cell_of(cells, (uint32_t)(hc >> 32));
   uint32_t h = (uint32_t)hv;
   *hash2 = h ? h : 1u;
 }

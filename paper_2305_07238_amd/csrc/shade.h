@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "../../include/pmc.h"
+#include "device_common.h"
 #include "program.h"
 #include "surrogate.h"
 
@@ -46,6 +47,7 @@ struct ShadeArgs {
   // cache
   uint64_t* table;
   uint32_t n_cells;
+  CellMap cells;                 // x -> x mod n_cells
   uint32_t n_entries;
   uint32_t entry_words;          // 64-bit words per entry: 1 (8 B) or 2 (16 B)
   uint32_t policy;

@@ -520,7 +520,7 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
     k.bypass = true; k.cell = 0u; k.hash2 = 0u;
     if (has) {
       cd = a.cach[cbeg + c];
-      k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.n_cells);
+      k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.cells);
     }
     const uint32_t h2 = (has && !k.bypass) ? k.hash2 : 0u;
     uint32_t code = 0u, slot = 0xFFu;
@@ -660,7 +660,7 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
             code = is_c ? rgb9e5_encode(val.x, val.y, val.z) : __float_as_uint(val.x);
             const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + ord;
             Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max,
-                             a.n_cells);
+                             a.cells);
             cell = k.cell;
             hash2 = k.hash2;
           }
@@ -1084,7 +1084,7 @@ __global__ void k_debug_keys(ShadeArgs a, pmc_key_record* out) {
     r.cell = 0; r.hash2 = 0; r.level = 0; r.tx = 0; r.ty = 0; r.bypass = 2;
     if (c < n_cach) {
       const CachDesc cd = a.cach[a.hdr[m].cach_begin + c];
-      Key k = make_key(m, cd.node_sock, uv.x, uv.y, g, a.level_bias, a.level_max, a.n_cells);
+      Key k = make_key(m, cd.node_sock, uv.x, uv.y, g, a.level_bias, a.level_max, a.cells);
       r.bypass = k.bypass ? 1u : 0u;
       if (!k.bypass) {
         r.cell = k.cell; r.hash2 = k.hash2; r.level = k.level; r.tx = k.tx; r.ty = k.ty;
@@ -1110,7 +1110,7 @@ __global__ void k_insert_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1
   int o = INS_FULL;
   if (i < n) {
     uint32_t cell, hash2;
-    raw_hash(k0[i], k1[i], a.n_cells, &cell, &hash2);
+    raw_hash(k0[i], k1[i], a.cells, &cell, &hash2);
     o = cache_insert(a, cell, hash2, enc[i]);
   }
   count_insert(cnt, i < n, o);
@@ -1122,7 +1122,7 @@ __global__ void k_lookup_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t cell, hash2, code = 0;
-  raw_hash(k0[i], k1[i], a.n_cells, &cell, &hash2);
+  raw_hash(k0[i], k1[i], a.cells, &cell, &hash2);
   uint32_t slot;
   bool f = cache_lookup(a, cell, hash2, &code, &slot);
   hit[i] = f ? 1 : 0;

@@ -66,11 +66,17 @@ def test_keys_bit_exact_tiny_all_hits():
     assert np.all(got["level"][:, :2] == 6)
 
 
-@pytest.mark.parametrize("bias,lmax,n_cells", [(0, 20, 524288), (1, 20, 99991), (-2, 5, 1000003)])
+@pytest.mark.parametrize("bias,lmax,n_cells", [(0, 20, 524288), (1, 20, 99991), (-2, 5, 1000003),
+                                              (0, 20, 10000000), (0, 20, 1), (0, 20, 3),
+                                              (0, 20, 536870909)])
 def test_keys_bit_exact_mid(bias, lmax, n_cells):
+    """Keys bit-exact; the cell counts cover powers of two (a mask), the paper's
+    10^7, primes up to 2^29 and 1 (the division-free remainder)."""
     sc = G.small_mid_scene(frames=1)
     ctx = G.setup(sc)
-    cache = ctx.cache(n_cells, 8, 16, level_bias=bias, level_max=lmax)
+    big = n_cells > (1 << 26)
+    cache = ctx.cache(n_cells, 1 if big else 8, 8 if big else 16, level_bias=bias,
+                      level_max=lmax)
     h = sc.frame(0)
     got = _gpu_keys(ctx, cache, h)
     want = _oracle_keys(sc, h, n_cells, bias, lmax)
