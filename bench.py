@@ -188,7 +188,7 @@ def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
     }
 
 
-def cpu_baseline(sc, sample_hits=262144, frames=3):
+def cpu_baseline(sc, sample_hits=786432, frames=3):
     """The FP64 oracle (snapshot-mode progressive shading) on a bounded sample."""
     from oracle import render, table
     t = table.Table(sc.cache.n_cells, sc.cache.n_entries, sc.cache.entry_bytes)

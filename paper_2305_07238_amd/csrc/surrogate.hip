@@ -635,33 +635,61 @@ hipError_t launch_surr_live_update(SurrState* state, uint32_t n_slots, hipStream
 }
 
 // ------------------------------------------------------ grouping the log ---
+// One block per log region.  Counts per network are kept in LDS and reach
+// global memory with one atomic per (region, network); the scatter reserves a
+// range per (region, network) the same way and places records with LDS atomics.
 
-__global__ __launch_bounds__(256) void k_log_count(const pmc_log_record* log,
-                                                    const uint32_t* region_count,
-                                                    uint32_t region_cap, const uint32_t* mat_slot,
-                                                    uint32_t n_mats, uint32_t* slot_count) {
-  const uint32_t region = blockIdx.y;
+constexpr uint32_t kGroupThreads = 1024;
+constexpr uint32_t kGroupMaxSlots = 16384;           // 64 KiB of LDS counters
+
+__global__ __launch_bounds__(1024) void k_log_count(const pmc_log_record* log,
+                                                     const uint32_t* region_count,
+                                                     uint32_t region_cap, const uint32_t* mat_slot,
+                                                     uint32_t n_mats, uint32_t n_slots,
+                                                     uint32_t* slot_count) {
+  extern __shared__ uint32_t cnt[];
+  for (uint32_t k = threadIdx.x; k < n_slots; k += blockDim.x) cnt[k] = 0u;
+  __syncthreads();
+  const uint32_t region = blockIdx.x;
   const uint32_t n = min(region_count[region], region_cap);
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-    const uint32_t mat = log[(uint64_t)region * region_cap + p].material;
+  const pmc_log_record* base = log + (uint64_t)region * region_cap;
+  for (uint32_t p = threadIdx.x; p < n; p += blockDim.x) {
+    const uint32_t mat = base[p].material;
     const uint32_t sl = mat < n_mats ? mat_slot[mat] : 0xFFFFFFFFu;
-    if (sl != 0xFFFFFFFFu) atomicAdd(slot_count + sl, 1u);
+    if (sl < n_slots) atomicAdd(cnt + sl, 1u);
   }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < n_slots; k += blockDim.x)
+    if (cnt[k]) atomicAdd(slot_count + k, cnt[k]);
 }
 
-__global__ __launch_bounds__(256) void k_log_scatter(const pmc_log_record* log,
-                                                      const uint32_t* region_count,
-                                                      uint32_t region_cap, const uint32_t* mat_slot,
-                                                      uint32_t n_mats, uint32_t* cursor,
-                                                      pmc_log_record* grouped) {
-  const uint32_t region = blockIdx.y;
+__global__ __launch_bounds__(1024) void k_log_scatter(const pmc_log_record* log,
+                                                       const uint32_t* region_count,
+                                                       uint32_t region_cap, const uint32_t* mat_slot,
+                                                       uint32_t n_mats, uint32_t n_slots,
+                                                       uint32_t* cursor, pmc_log_record* grouped) {
+  extern __shared__ uint32_t cnt[];
+  for (uint32_t k = threadIdx.x; k < n_slots; k += blockDim.x) cnt[k] = 0u;
+  __syncthreads();
+  const uint32_t region = blockIdx.x;
   const uint32_t n = min(region_count[region], region_cap);
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-    const pmc_log_record* src = log + (uint64_t)region * region_cap + p;
+  const pmc_log_record* base = log + (uint64_t)region * region_cap;
+  for (uint32_t p = threadIdx.x; p < n; p += blockDim.x) {
+    const uint32_t mat = base[p].material;
+    const uint32_t sl = mat < n_mats ? mat_slot[mat] : 0xFFFFFFFFu;
+    if (sl < n_slots) atomicAdd(cnt + sl, 1u);
+  }
+  __syncthreads();
+  // reserve this region's range of every network; cnt becomes the local cursor
+  for (uint32_t k = threadIdx.x; k < n_slots; k += blockDim.x)
+    if (cnt[k]) cnt[k] = atomicAdd(cursor + k, cnt[k]);
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < n; p += blockDim.x) {
+    const pmc_log_record* src = base + p;
     const uint32_t mat = src->material;
     const uint32_t sl = mat < n_mats ? mat_slot[mat] : 0xFFFFFFFFu;
-    if (sl == 0xFFFFFFFFu) continue;
-    const uint32_t pos = atomicAdd(cursor + sl, 1u);
+    if (sl >= n_slots) continue;
+    const uint32_t pos = atomicAdd(cnt + sl, 1u);
     const uint4* q = reinterpret_cast<const uint4*>(src);
     uint4* d = reinterpret_cast<uint4*>(grouped + pos);
     d[0] = q[0];
@@ -675,15 +703,16 @@ hipError_t launch_log_group(const pmc_log_record* log, const uint32_t* region_co
                             uint32_t* slot_cursor, uint32_t* scan_sums, pmc_log_record* grouped,
                             hipStream_t s) {
   if (n_slots == 0) return hipSuccess;
+  if (n_slots > kGroupMaxSlots) return hipErrorInvalidValue;
   hipError_t e = launch_fill_u32(slot_count, 0u, n_slots, s);
   if (e != hipSuccess) return e;
-  const dim3 grid((region_cap + 255u) / 256u < 64u ? (region_cap + 255u) / 256u : 64u, 64);
-  hipLaunchKernelGGL(k_log_count, grid, dim3(256), 0, s, log, region_count, region_cap, mat_slot,
-                     n_mats, slot_count);
+  const size_t lds = (size_t)n_slots * 4;
+  hipLaunchKernelGGL(k_log_count, dim3(64), dim3(kGroupThreads), lds, s, log, region_count,
+                     region_cap, mat_slot, n_mats, n_slots, slot_count);
   e = launch_exclusive_scan(slot_count, n_slots, slot_begin, slot_cursor, scan_sums, nullptr, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_log_scatter, grid, dim3(256), 0, s, log, region_count, region_cap,
-                     mat_slot, n_mats, slot_cursor, grouped);
+  hipLaunchKernelGGL(k_log_scatter, dim3(64), dim3(kGroupThreads), lds, s, log, region_count,
+                     region_cap, mat_slot, n_mats, n_slots, slot_cursor, grouped);
   return hipGetLastError();
 }
 

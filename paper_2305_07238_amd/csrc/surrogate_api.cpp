@@ -119,6 +119,7 @@ pmc_status pmc_surrogate_setup(pmc_ctx* ctx, const pmc_surrogate_opts* opts, uin
     }
   }
   const uint32_t n = (uint32_t)slots.size();
+  if (n > 16384u) return ctx->fail(PMC_ERR_UNSUPPORTED, "at most 16384 surrogate networks");
   if (!ctx->host_only) {
     if (pmc_status st = need_device(ctx)) return st;
     HIP_TRY(ctx, hipDeviceSynchronize());
