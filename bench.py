@@ -188,6 +188,82 @@ def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
     }
 
 
+def surrogate_smooth_leg(log):
+    """The networks where they can be trusted: a 1920x1080 scene of 4 materials whose
+    deep sub-graphs are expensive but low-frequency functions of UV (12 Perlin layers
+    averaged).  Snapshot frames with the log on collect training pairs; every network
+    is trained (one launch) and trusted when its held-out maximum error is at most
+    5e-3; then the first frame alone (cold table) and a 4-frame progressive render, each
+    from an empty table, are timed uncached, cache only, and networks + cache."""
+    import torch
+    from oracle import render
+    from paper_2305_07238_amd import binding as B
+    from paper_2305_07238_amd import scenes
+    sc = scenes.smooth_scene(width=1920, height=1080, frames=4, slots=1 << 22)
+    n = sc.hits_per_frame
+    frames = [B.hits_to_device(sc.frame(f)) for f in range(sc.frames)]
+    out = B.alloc_outputs(n)
+    ctx = B.Context(0)
+    ctx.set_textures(sc.textures)
+    ctx.compile(sc.materials)
+    n_slots = ctx.surrogate_setup(seed=0, max_err=5e-3)
+    cache = ctx.cache(sc.cache.n_cells, 8, 16)
+    ctx.log_clear()
+    for f in range(sc.frames):
+        ctx.shade(frames[f], out, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                  flags=B.PMC_FLAG_SORT | B.PMC_FLAG_LOG)
+    torch.cuda.synchronize()
+    n_log = len(ctx.log_read())
+    train = dict(steps=48000, batch=512, lr=2e-2, lr_end=2e-6, seed=0, min_records=256)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.surrogate_train(**train)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    rep = ctx.surrogate_report()
+    trusted = [k for k, r in enumerate(rep) if r["trusted"]]
+    log(f"smooth scene: {len(trusted)} of {n_slots} networks trusted after {train_ms:.0f} ms")
+    results, cold = {}, {}
+    for name, use_cache, f in (("uncached", False, 0), ("cache_only", True, 0),
+                               ("surrogate_cache", True, B.PMC_FLAG_SURROGATE)):
+        def run(pre, use_cache=use_cache, f=f, n_frames=sc.frames):
+            if pre:
+                for k in trusted:
+                    ctx.surrogate_set_trust(k, True)
+                if use_cache:
+                    cache.clear()
+                torch.cuda.synchronize()
+                return
+            for fr in range(n_frames):
+                ctx.shade(frames[fr], out, cache if use_cache else None,
+                          mode=B.PMC_MODE_CACHED if use_cache else B.PMC_MODE_UNCACHED,
+                          frame=fr, flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER | f)
+        ms1 = _median_ms(lambda pre, run=run: run(pre, n_frames=1))
+        cold[name] = {"samples_per_s": n / (ms1 * 1e-3), "ms": ms1}
+        ms = _median_ms(run)
+        last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+        results[name] = {"samples_per_s": n * sc.frames / (ms * 1e-3), "ms": ms, "_out": last}
+    pick = np.linspace(0, n - 1, 2048).astype(np.int64)
+    ref = render.shade_uncached(sc.materials, sc.textures, sc.frame(sc.frames - 1).take(pick))
+    for name, r in results.items():
+        got = r.pop("_out")
+        errs = np.concatenate([np.abs(got[k][pick] - ref[k]).ravel()
+                               for k in ("base_color", "roughness", "normal")])
+        r["max_abs_err"] = float(errs.max())
+        r["mean_abs_err"] = float(errs.mean())
+    ctx.close()
+    return {"workload": "smooth: 4 materials of 38 nodes (12 low-frequency Perlin layers averaged, "
+                        "MUL/POW chain), 1920x1080 x 4 progressive frames, table 2^22 slots, "
+                        "trust at held-out max error 5e-3",
+            "log_records": n_log, "train": dict(train, ms=train_ms), "trusted": len(trusted),
+            "slots": n_slots, "heldout_max_err": [r["max_err"] for r in rep],
+            "render": results, "cold_first_frame": cold,
+            "cold_gain_vs_cache_only": cold["cache_only"]["ms"] / cold["surrogate_cache"]["ms"],
+            "gain_vs_cache_only": results["cache_only"]["ms"] / results["surrogate_cache"]["ms"],
+            "gain_vs_uncached": results["uncached"]["ms"] / results["surrogate_cache"]["ms"]}
+
+
 def cpu_baseline(sc, sample_hits=786432, frames=3):
     """The FP64 oracle (snapshot-mode progressive shading) on a bounded sample."""
     from oracle import render, table
@@ -366,6 +442,7 @@ def main():
     }
     if not args.no_surrogate and use_cache and args.workload == "mid":
         res["surrogate"] = surrogate_leg(ctx, sc, frame_views, out, cache, best, log)
+        res["surrogate_smooth"] = surrogate_smooth_leg(log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(sc)

@@ -151,7 +151,8 @@ void pmc_destroy(pmc_ctx* ctx) {
     for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->lpt_rank,
                       &ctx->sort_counts, &ctx->sort_offsets, &ctx->sort_sums, &ctx->texels,
                       &ctx->texdesc, &ctx->perm, &ctx->misc,
-                      &ctx->cand, &ctx->stat_slots, &ctx->surr.w, &ctx->surr.master,
+                      &ctx->cand, &ctx->stat_slots, &ctx->surr_queue, &ctx->surr_val,
+                      &ctx->surr.w, &ctx->surr.master,
                       &ctx->surr.state, &ctx->surr.mat_slot_dev, &ctx->surr.log,
                       &ctx->surr.log_count, &ctx->surr.slot_count, &ctx->surr.slot_begin,
                       &ctx->surr.slot_cursor, &ctx->surr.scan_sums, &ctx->surr.grouped})
@@ -423,6 +424,11 @@ pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mo
         (st = ensure(ctx, ctx->sort_sums, ((size_t)scan_blocks((uint32_t)cells) + 1) * 4)))
       return st;
   }
+  if ((flags & PMC_FLAG_SURROGATE) && mode != PMC_MODE_UNCACHED && cache) {
+    if ((st = ensure(ctx, ctx->surr_queue, (size_t)n * 8)) ||
+        (st = ensure(ctx, ctx->surr_val, (size_t)n * 16)))
+      return st;
+  }
   if (mode == PMC_MODE_SNAPSHOT && cache) {
     const size_t cap = (size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1);
     if ((st = ensure(ctx, ctx->cand, cap * 16)) || (st = ensure(ctx, cache->sorted, cap * 16)))
@@ -474,6 +480,11 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.surr_w = (const SurrW*)ctx->surr.w.p;
     a.surr_state = (SurrState*)ctx->surr.state.p;
   }
+  if (surr) {
+    a.surr_queue = (uint2*)ctx->surr_queue.p;
+    a.surr_val = (float4*)ctx->surr_val.p;
+    a.surr_queue_cap = n;
+  }
   if (logged) {
     a.log = (pmc_log_record*)ctx->surr.log.p;
     a.log_count = (uint32_t*)ctx->surr.log_count.p;
@@ -517,8 +528,14 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     grid = (runs + 3) / 4;
   }
   PhaseTimer t1(ctx, 1, s);
+  a.surr_queue_count = misc + 2;     // cleared with misc[0..3] above
   HIP_TRY(ctx,
           launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, surr, grid, s));
+  if (surr) {
+    const uint32_t qgrid = (uint32_t)ctx->num_cus * 4u;
+    HIP_TRY(ctx, launch_surr_queue(a, qgrid, s));
+    HIP_TRY(ctx, launch_surr_finish(a, qgrid, s));
+  }
   t1.finish();
   if (mode == PMC_MODE_SNAPSHOT) {
     SnapshotArgs sa;

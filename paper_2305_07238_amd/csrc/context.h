@@ -44,6 +44,7 @@ struct pmc_ctx {
   uint32_t n_tex = 0;
   // workspace
   DevBuf perm, misc, cand, stat_slots;
+  DevBuf surr_queue, surr_val;                   // parked hits of the surrogate passes
   DevBuf sort_counts, sort_offsets, sort_sums;   // tiled material sort
   SurrHost surr;
   bool no_alloc = false;       // set while a frame graph is captured

@@ -70,12 +70,20 @@ struct ShadeArgs {
   pmc_log_record* log;           // NULL: no logging
   uint32_t* log_count;           // 64 region counters
   uint32_t log_region_cap;       // records per region
+  uint2* surr_queue;             // parked hits {hit, surrogated ordinals | audited << 8}
+  uint32_t* surr_queue_count;
+  uint32_t surr_queue_cap;
+  float4* surr_val;              // the networks' outputs for the parked hits
 };
 
 // surr: the variant that consults the surrogate networks (cached modes only).
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, bool surr, uint32_t grid,
                         hipStream_t s);
 size_t shade_lds_bytes(uint32_t n_regs);
+// After a surrogate first pass: the networks over the parked hits, then their finish
+// pass (both size themselves from the queue count on the device).
+hipError_t launch_surr_queue(const ShadeArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_surr_finish(const ShadeArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_debug_keys(const ShadeArgs& a, pmc_key_record* out, hipStream_t s);
 hipError_t launch_insert_raw(const ShadeArgs& a, const uint64_t* k0, const uint64_t* k1,
                              const uint32_t* enc, uint64_t n, hipStream_t s);

@@ -431,45 +431,65 @@ __device__ __forceinline__ Audit no_audit() {
   return au;
 }
 
-// The material's network stands in for its missed surrogated outputs (whole
-// wave active; m wave-uniform; `mine` marks the lanes of material m).  The
-// values go to the outputs' registers, which removes them from the misses (no
-// sub-graph evaluation, no insert).  One eligible hit in 64 is audited
-// instead: evaluated by the graph, with the network's output kept in *au.
+// Surrogate networks, first pass (whole wave active; m wave-uniform; `mine`
+// marks the lanes of material m).  A lane of a trusted material whose
+// surrogated outputs missed is parked: its hit index and those outputs go to
+// the queue (one in 64 marked audited) and it is not evaluated now.  After the
+// pass the networks run over the queue in dense waves, and the finish pass
+// completes the parked hits with the networks' values.  Returns true for the
+// lanes parked.
 template <int MODE>
-__device__ __forceinline__ void surrogate_fill(const ShadeArgs& a, uint32_t m, bool mine,
-                                               uint32_t h, const HitData& hd, const LaneRegs& R,
-                                               Counters& cnt, uint32_t& miss, uint32_t& ins,
-                                               Audit& au) {
-  if (m >= a.n_mats) return;
+__device__ __forceinline__ bool surrogate_park(const ShadeArgs& a, uint32_t m, bool mine,
+                                               uint32_t h, uint32_t ins, Counters& cnt) {
+  if (m >= a.n_mats) return false;
   const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
   const uint32_t smask = H->surr_mask;
-  if (smask == 0u) return;
-  const uint32_t slot = H->surr_slot;
-  if (as_const(a.surr_state)[slot].trusted == 0u) return;
+  if (smask == 0u) return false;
+  if (as_const(a.surr_state)[H->surr_slot].trusted == 0u) return false;
   const uint32_t sm = mine ? (ins & smask) : 0u;
-  if (__ballot(sm != 0u) == 0ull) return;
-  float y[4];
-  mlp_wave(a.surr_w + slot, hd.u, hd.v, y);
+  const uint64_t mk = __ballot(sm != 0u);
+  if (mk == 0ull) return false;
+  const int leader = __ffsll((unsigned long long)mk) - 1;
+  uint32_t base = 0u;
+  if (lane_id() == leader) base = atomicAdd(a.surr_queue_count, (uint32_t)__popcll(mk));
+  base = __shfl(base, leader, 64);
+  if (sm == 0u) return false;
+  const uint32_t pos = base + (uint32_t)__popcll(mk & lanemask_lt());
+  if (pos >= a.surr_queue_cap) return false;          // cannot happen: one entry per hit at most
+  const uint32_t audit = surrogate_audited(a.frame, h) ? 0x100u : 0u;
+  a.surr_queue[pos] = make_uint2(h, sm | audit);
+  return true;
+}
+
+// Finish pass: the network's outputs y stand in for the parked outputs `sm`
+// that still miss (they go to the outputs' registers and leave the misses: no
+// sub-graph evaluation, no insert).  An audited lane instead keeps them in *au
+// and is evaluated by the graph.
+__device__ __forceinline__ void surrogate_substitute(const ShadeArgs& a, uint32_t m, uint32_t h,
+                                                     uint32_t sm, bool audit, float4 yv,
+                                                     const LaneRegs& R, Counters& cnt,
+                                                     uint32_t& miss, uint32_t& ins, Audit& au) {
+  sm &= ins;
   if (sm == 0u) return;
-  if (surrogate_audited(a.frame, h)) {
+  const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
+  const float y[4] = {yv.x, yv.y, yv.z, yv.w};
+  if (audit) {
     au.mask = sm;
-    au.slot = slot;
+    au.slot = H->surr_slot;
     au.y[0] = y[0]; au.y[1] = y[1]; au.y[2] = y[2]; au.y[3] = y[3];
     cnt.v[CNT_AUDITED] += (uint32_t)__popc(sm);
     return;
   }
   const uint32_t cbeg = H->cach_begin;
   for (uint32_t c = 0; c < 8u; ++c) {
-    if (!((smask >> c) & 1u)) continue;
     if (!((sm >> c) & 1u)) continue;
-    const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + c;
+    const CachDesc cd = a.cach[cbeg + c];
     const uint32_t ch = (H->surr_chan >> (4u * c)) & 0xFu;
-    const int r = cd->reg;
+    const int r = cd.reg;
     const float v0 = pick4(y, ch);
     R.set(r, v0);
     float v1 = v0, v2 = v0;
-    if (cd->otype == OT_COLOR) {
+    if (cd.otype == OT_COLOR) {
       v1 = pick4(y, ch + 1u);
       v2 = pick4(y, ch + 2u);
       R.set(r + 1, v1);
@@ -812,11 +832,10 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const LaneHit& L,
     const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
     const bool mine = L.active && L.mat == m;
     pending &= ~__ballot(mine);
-    Audit au = no_audit();
-    if (SURR) surrogate_fill<MODE>(a, m, mine, L.h, L.hd, R, cnt, miss, ins, au);
-    if (mine) {
+    const bool parked = SURR && surrogate_park<MODE>(a, m, mine, L.h, ins, cnt);
+    if (mine && !parked) {
       if (m < a.n_mats) {
-        shade_full<MODE, false, SURR>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
+        shade_full<MODE, false, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, no_audit());
       } else {
         cnt.v[CNT_INVALID]++;
         shade_default(a, L.h, L.hd);
@@ -846,9 +865,9 @@ __device__ __forceinline__ void flush_deferred(const ShadeArgs& a, DeferBuf& B, 
   LaneHit L = load_lane(a, B.ids, B.count, 0u);
   uint32_t ins = 0u, slots = 0u;
   uint32_t miss = probe_chunk<MODE, false>(a, act, m, L.h, L.hd, R, cnt, &ins, &slots);
-  Audit au = no_audit();
-  if (SURR) surrogate_fill<MODE>(a, m, act, L.h, L.hd, R, cnt, miss, ins, au);
-  if (act) shade_full<MODE, true, SURR>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
+  const bool parked = SURR && surrogate_park<MODE>(a, m, act, L.h, ins, cnt);
+  if (act && !parked)
+    shade_full<MODE, true, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, no_audit());
   B.count = 0u;
 }
 
@@ -873,19 +892,18 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, const LaneHit& L
     pending &= ~__ballot(mine);
     const uint32_t d = (uint32_t)__popcll(__ballot(mine && miss != 0u));
     const bool dense = d > a.defer_max;
-    Audit au = no_audit();
-    if (SURR && dense) surrogate_fill<MODE>(a, m, mine, L.h, L.hd, R, cnt, miss, ins, au);
-    if (mine) {
+    const bool parked = SURR && dense && surrogate_park<MODE>(a, m, mine, L.h, ins, cnt);
+    if (mine && !parked) {
       if (m < a.n_mats) {
         const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
         if (dense) {
-          shade_full<MODE, false, SURR>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
+          shade_full<MODE, false, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, no_audit());
         } else if (miss != 0u) {
           deferred = true;
         } else {
           cnt.v[CNT_NODES_TOTAL] += H->n_instr;
-          run_program<MODE, false, SURR>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u, 0u,
-                                         0u, au);
+          run_program<MODE, false, false>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u,
+                                          0u, 0u, no_audit());
           write_outputs(a, m, L.h, L.hd, R);
         }
       } else {
@@ -995,10 +1013,10 @@ __device__ __forceinline__ void shade_persistent_body(const ShadeArgs& a) {
   if (STATS) flush_counters(a, cnt);
 }
 
-// Kernels.  The cached variants without networks are compiled for 4 waves per
-// SIMD (at most 128 VGPRs): the probe-heavy path is latency bound and gains more
-// from the extra wave than it loses to a few spilled registers.  The uncached
-// and network variants keep the compiler's own register budget.
+// Kernels.  The cached variants are compiled for 4 waves per SIMD (at most 128
+// VGPRs): the probe-heavy path is latency bound and gains more from the extra
+// wave than it loses to a few spilled registers.  The uncached variants keep
+// the compiler's own register budget.
 template <int MODE, int KIND, bool STATS, bool SURR>
 __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   shade_flat_body<MODE, KIND, STATS, SURR>(a);
@@ -1009,16 +1027,113 @@ __global__ __launch_bounds__(256) void k_shade_persistent(ShadeArgs a) {
   shade_persistent_body<MODE, KIND, STATS, SURR>(a);
 }
 
-template <int MODE, int KIND, bool STATS>
+template <int MODE, int KIND, bool STATS, bool SURR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_shade_flat_w4(ShadeArgs a) {
-  shade_flat_body<MODE, KIND, STATS, false>(a);
+  shade_flat_body<MODE, KIND, STATS, SURR>(a);
 }
 
-template <int MODE, int KIND, bool STATS>
+template <int MODE, int KIND, bool STATS, bool SURR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_shade_persistent_w4(ShadeArgs a) {
-  shade_persistent_body<MODE, KIND, STATS, false>(a);
+  shade_persistent_body<MODE, KIND, STATS, SURR>(a);
+}
+
+// ------------------------------------------------- surrogate second passes ---
+
+// The networks over the queue of parked hits: one wave per 64 entries (grid
+// stride); a wave whose entries span materials runs each material's network
+// with all lanes active and keeps the lanes of that material.
+__global__ __launch_bounds__(256) void k_surr_queue(ShadeArgs a) {
+  const uint32_t n = min(*a.surr_queue_count, a.surr_queue_cap);
+  const uint32_t n_chunks = (n + 63u) / 64u;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks;
+       c += waves) {
+    const uint32_t idx = c * 64u + (uint32_t)lane_id();
+    const bool act = idx < n;
+    const uint32_t h = act ? a.surr_queue[idx].x : 0u;
+    const uint32_t mat = act ? a.material[h] : 0xFFFFFFFFu;
+    const float2 uv = act ? reinterpret_cast<const float2*>(a.uv)[h] : make_float2(0.f, 0.f);
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint64_t pending = __ballot(act);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t m = __builtin_amdgcn_readlane(mat, leader);
+      const bool mine = act && mat == m;
+      pending &= ~__ballot(mine);
+      float y[4];
+      mlp_wave(a.surr_w + (as_const(a.hdr) + m)->surr_slot, uv.x, uv.y, y);
+      if (mine) out = make_float4(y[0], y[1], y[2], y[3]);
+    }
+    if (act) a.surr_val[idx] = out;
+  }
+}
+
+// Finish pass over the parked hits: probe again, take the networks' values for
+// the parked outputs that still miss (or audit them), evaluate the rest.
+template <int MODE, bool STATS>
+__device__ __forceinline__ void shade_finish_body(const ShadeArgs& a) {
+  extern __shared__ float lds[];
+  float* wl = wave_lds(lds, a);
+  LaneRegs R{wl, lane_id()};
+  Counters cnt;
+#pragma unroll
+  for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
+  const uint32_t n = min(*a.surr_queue_count, a.surr_queue_cap);
+  const uint32_t n_chunks = (n + 63u) / 64u;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks;
+       c += waves) {
+    const uint32_t idx = c * 64u + (uint32_t)lane_id();
+    const bool act = idx < n;
+    const uint2 e = act ? a.surr_queue[idx] : make_uint2(0u, 0u);
+    LaneIdx I;
+    I.active = act;
+    I.h = e.x;
+    const LaneHit L = fetch_lane(a, I);
+    const float4 yv = act ? a.surr_val[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t ins = 0u, slots = 0u;
+    uint32_t miss = probe_chunk<MODE, false>(a, act, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
+    uint64_t pending = __ballot(act);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
+      const bool mine = act && L.mat == m;
+      pending &= ~__ballot(mine);
+      if (mine) {
+        Audit au = no_audit();
+        surrogate_substitute(a, m, L.h, e.y & 0xFFu, (e.y & 0x100u) != 0u, yv, R, cnt, miss,
+                             ins, au);
+        shade_full<MODE, true, true>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
+      }
+    }
+  }
+  if (STATS) flush_counters(a, cnt);
+}
+
+template <int MODE, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_shade_finish(ShadeArgs a) {
+  shade_finish_body<MODE, STATS>(a);
+}
+
+hipError_t launch_surr_queue(const ShadeArgs& a, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_surr_queue, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_surr_finish(const ShadeArgs& a, uint32_t grid, hipStream_t s) {
+  const size_t lds = shade_lds_bytes(a.n_regs);
+  const bool stats = a.stat_slots != nullptr;
+  if (a.mode == PMC_MODE_SNAPSHOT) {
+    if (stats) hipLaunchKernelGGL((k_shade_finish<PMC_MODE_SNAPSHOT, true>), dim3(grid), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_shade_finish<PMC_MODE_SNAPSHOT, false>), dim3(grid), dim3(256), lds, s, a);
+  } else {
+    if (stats) hipLaunchKernelGGL((k_shade_finish<PMC_MODE_CACHED, true>), dim3(grid), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_shade_finish<PMC_MODE_CACHED, false>), dim3(grid), dim3(256), lds, s, a);
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------- host launchers ---
@@ -1028,12 +1143,13 @@ size_t shade_lds_bytes(uint32_t n_regs) { return (size_t)4 * (n_regs * 64 + 64) 
 template <int MODE, int KIND, bool STATS, bool SURR>
 static void launch_one(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
                        hipStream_t s) {
-  constexpr bool w4 = MODE != PMC_MODE_UNCACHED && !SURR;
+  constexpr bool w4 = MODE != PMC_MODE_UNCACHED;
   if (w4 && persistent)
-    hipLaunchKernelGGL((k_shade_persistent_w4<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s,
-                       a);
+    hipLaunchKernelGGL((k_shade_persistent_w4<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256),
+                       lds, s, a);
   else if (w4)
-    hipLaunchKernelGGL((k_shade_flat_w4<MODE, KIND, STATS>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_shade_flat_w4<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds, s,
+                       a);
   else if (persistent)
     hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds,
                        s, a);

@@ -87,61 +87,47 @@ __device__ __forceinline__ h4 relu_h4(f4 acc, const float* b) {
 
 // The network at 64 points, one per lane (all 64 lanes must be active): lane l
 // gives (u, v) and receives y[0..3] of its own point.  112 matrix products.
+// The four 16-point tiles are done one after another so few registers are
+// live (the weights are re-read per tile, from the first-level cache).
 __device__ __forceinline__ void mlp_wave(const SurrW* __restrict__ W, float u, float v,
                                          float y[4]) {
   const int lane = (int)(threadIdx.x & 63u);
   const int j = lane & 15, g = lane >> 4;
-  // layer-1 B operands: features of sample 16 n + j, feature rows 16 t + 4 g ..
-  h4 X[2][4];
-#pragma unroll
+  y[0] = y[1] = y[2] = y[3] = 0.0f;
+#pragma unroll 1
   for (int n = 0; n < 4; ++n) {
+    // layer-1 B operands: features of point 16 n + j, feature rows 16 t + 4 g ..
     const float un = __shfl(u, 16 * n + j, 64), vn = __shfl(v, 16 * n + j, 64);
-    X[0][n] = fourier4(un, vn, g);
-    X[1][n] = fourier4(un, vn, 4 + g);
-  }
-  h4 H1[4][4];
+    const h4 x0 = fourier4(un, vn, g);
+    const h4 x1 = fourier4(un, vn, 4 + g);
+    h4 H1[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const h4 a0 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 4 * g);
-    const h4 a1 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 16 + 4 * g);
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int m = 0; m < 4; ++m) {
+      const h4 a0 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 4 * g);
+      const h4 a1 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 16 + 4 * g);
       f4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma16(a0, X[0][n], acc);
-      acc = mfma16(a1, X[1][n], acc);
-      H1[m][n] = relu_h4(acc, W->b1 + 16 * m + 4 * g);
+      acc = mfma16(a0, x0, acc);
+      acc = mfma16(a1, x1, acc);
+      H1[m] = relu_h4(acc, W->b1 + 16 * m + 4 * g);
     }
-  }
-  // layer 2, and layer 3 accumulated tile by tile (K tile m of layer 3 = M tile m of layer 2)
-  f4 Y[4];
+    // layer 2, and layer 3 accumulated tile by tile (K tile m of layer 3 = M tile m of layer 2)
+    f4 Y = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int n = 0; n < 4; ++n) Y[n] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    h4 a[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      a[t] = *reinterpret_cast<const h4*>(W->w2 + (16 * m + j) * 64 + 16 * t + 4 * g);
-    const h4 a3 = *reinterpret_cast<const h4*>(W->w3 + j * 64 + 16 * m + 4 * g);
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int m = 0; m < 4; ++m) {
       f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc = mfma16(a[t], H1[t][n], acc);
+      for (int t = 0; t < 4; ++t)
+        acc = mfma16(*reinterpret_cast<const h4*>(W->w2 + (16 * m + j) * 64 + 16 * t + 4 * g),
+                     H1[t], acc);
       const h4 h2 = relu_h4(acc, W->b2 + 16 * m + 4 * g);
-      Y[n] = mfma16(a3, h2, Y[n]);
+      Y = mfma16(*reinterpret_cast<const h4*>(W->w3 + j * 64 + 16 * m + 4 * g), h2, Y);
     }
-  }
-  // sample 16 n + j's outputs are rows 0..3 of tile n, held by lane j
+    // point 16 n + j's outputs are rows 0..3 of the tile, held by lane j
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    float r = 0.0f;
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const float t = __shfl(Y[n][c], j, 64);
-      r = (g == n) ? t : r;
+    for (int c = 0; c < 4; ++c) {
+      const float t = __shfl(Y[c], j, 64);
+      y[c] = (g == n) ? t + W->b3[c] : y[c];
     }
-    y[c] = r + W->b3[c];
   }
 }
 

@@ -463,30 +463,42 @@ def lognormal_sizes(rng, n, lo, hi, mu=3.0, sigma=1.0):
     return np.clip(np.rint(rng.lognormal(mu, sigma, n)), lo, hi).astype(int)
 
 
-def smooth_material(seed: int, m: int, groups: int = 9, perlin_freq: float = 1.0,
-                    perlin_octaves: int = 2, value_freq: float = 1.0) -> Material:
-    """A material whose deep sub-graphs are smooth functions of UV (low-frequency
-    value and Perlin noise through 4 * groups MUL/POW nodes that undo each other
-    pairwise), so a small network can represent them: base colour (COLOR, one
-    cacheable output of 4 * groups + 4 nodes) and roughness (FLOAT, 4 * groups + 2)."""
+def smooth_material(seed: int, m: int, groups: int = 2, n_noise: int = 12,
+                    perlin_freq: float = 0.25, perlin_octaves: int = 2,
+                    value_freq: float = 0.25) -> Material:
+    """A material whose deep sub-graphs are expensive but smooth functions of UV:
+    n_noise low-frequency Perlin layers averaged (ADD chain, then a scale), then
+    4 * groups MUL/POW nodes that undo each other pairwise, mixing a value-noise
+    colour.  Base colour (COLOR) and roughness (FLOAT) are cacheable outputs of
+    more than 32 nodes each, which a small network can represent."""
     rng = _rng(seed, _P_GRAPH, 7, m)
     L, C = Input.link, Input.const
     ca, cb, cc = (tuple(float(x) for x in rng.uniform(0.1, 0.9, 3)) for _ in range(3))
     nodes = [
         Node("UV_INPUT"),                                                        # 0
-        Node("VALUE_NOISE", [L(0)], freq=value_freq, octaves=1, seed=int(rng.integers(1 << 30))),
-        Node("PERLIN_NOISE", [L(0)], freq=perlin_freq, octaves=perlin_octaves,
-             seed=int(rng.integers(1 << 30))),
-        Node("MIX", [L(1), C(*ca), C(*cb)]),                                     # 3
+        Node("VALUE_NOISE", [L(0)], freq=value_freq, octaves=1,
+             seed=int(rng.integers(1 << 30))),                                   # 1
+        Node("MIX", [L(1), C(*ca), C(*cb)]),                                     # 2
     ]
-    x = 2
+    layers = []
+    for _ in range(n_noise):
+        f = perlin_freq * float(rng.uniform(0.75, 1.25))
+        nodes.append(Node("PERLIN_NOISE", [L(0)], freq=f, octaves=perlin_octaves,
+                          seed=int(rng.integers(1 << 30))))
+        layers.append(len(nodes) - 1)
+    x = layers[0]
+    for q in layers[1:]:
+        nodes.append(Node("MATH", [L(x), L(q)], math_op="ADD"))
+        x = len(nodes) - 1
+    nodes.append(Node("MATH", [L(x), C(1.0 / n_noise)], math_op="MUL"))
+    x = len(nodes) - 1
     for _ in range(groups):
         c = float(rng.uniform(0.8, 1.25))
         e = float(rng.uniform(0.8, 1.25))
         for op, k in (("MUL", c), ("MUL", 1.0 / c), ("POW", e), ("POW", 1.0 / e)):
             nodes.append(Node("MATH", [L(x), C(k)], math_op=op))
             x = len(nodes) - 1
-    nodes.append(Node("MIX", [L(x), L(3), C(*cc)]))                              # base colour
+    nodes.append(Node("MIX", [L(x), L(2), C(*cc)]))                              # base colour
     base = len(nodes) - 1
     nodes.append(Node("MATH", [L(x), C(0.8)], math_op="MUL", clamp=True))       # roughness
     rough = len(nodes) - 1
@@ -495,11 +507,9 @@ def smooth_material(seed: int, m: int, groups: int = 9, perlin_freq: float = 1.0
 
 
 def smooth_scene(seed: int = 0, n_mats: int = 4, width: int = 480, height: int = 240,
-                 frames: int = 4, slots: int = 1 << 18, perlin_freq: float = 1.0,
-                 perlin_octaves: int = 2, value_freq: float = 1.0) -> Scene:
+                 frames: int = 4, slots: int = 1 << 18, **material_kw) -> Scene:
     """Scene of smooth_material graphs on 40-px objects with UV scale U[0.5, 1]."""
-    mats = [smooth_material(seed, m, perlin_freq=perlin_freq, perlin_octaves=perlin_octaves,
-                            value_freq=value_freq) for m in range(n_mats)]
+    mats = [smooth_material(seed, m, **material_kw) for m in range(n_mats)]
     frame, n = _object_screen(seed, n_mats, width, height, 40, frames, scale=(0.5, 1.0),
                               name="smooth")
     return Scene("smooth", mats, [], frames, n, CacheConfig(slots), seed, frame)

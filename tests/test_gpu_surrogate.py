@@ -292,7 +292,7 @@ def test_training_on_the_log_gains_over_cache_only():
     points.  A snapshot render from an empty table with the networks executes
     fewer interpreter instructions than without, and every value a network
     supplied is within 1e-2 of the FP64 graph."""
-    sc = scenes.smooth_scene(frames=4, perlin_octaves=1, perlin_freq=0.25, value_freq=0.25)
+    sc = scenes.smooth_scene(frames=4)
     ctx, n_slots = _ctx_with_slots(sc, seed=7)
     cache = ctx.cache(sc.cache.n_cells, 8, 16)
     ctx.log_clear()
