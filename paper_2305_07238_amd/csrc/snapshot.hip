@@ -26,8 +26,50 @@ __global__ __launch_bounds__(256) void k_cand_scatter(SnapshotArgs a) {
   }
 }
 
-// One thread per cell: Algorithm 1 applied sequentially to the cell's candidates
-// in ascending seq; stamps = frame + 1.  Clears the cell's count for the next batch.
+// Algorithm 1 on one cell for one candidate key (FIRST, or OVERWRITE with
+// 16-byte entries); returns 0 inserted, 1 present, 2 full, 3 overwritten.
+__device__ __forceinline__ int apply_one(uint64_t* w0, const SnapshotArgs& a, uint32_t hash2,
+                                         uint32_t code, uint32_t stamp) {
+  const uint64_t neu = ((uint64_t)hash2 << 32) | code;
+  int idx = -1;
+  for (uint32_t i = 0; i < a.n_entries; ++i) {
+    uint32_t h = (uint32_t)(w0[(uint64_t)i * a.entry_words] >> 32);
+    if (h == hash2 || h == 0u) { idx = (int)i; break; }
+  }
+  if (idx >= 0) {
+    uint64_t* p = w0 + (uint64_t)idx * a.entry_words;
+    if (*p != 0ull) return 1;
+    *p = neu;
+    if (a.entry_words == 2) ((uint32_t*)p)[2] = stamp;
+    return 0;
+  }
+  if (a.policy == PMC_POLICY_OVERWRITE && a.entry_words == 2) {
+    uint32_t bs = 0xFFFFFFFFu;
+    int victim = -1;
+    for (uint32_t i = 0; i < a.n_entries; ++i) {
+      uint32_t st = ((uint32_t*)(w0 + (uint64_t)i * 2))[2];
+      if (st < bs) { bs = st; victim = (int)i; }
+    }
+    if (victim >= 0 && bs < stamp) {
+      uint64_t* p = w0 + (uint64_t)victim * 2;
+      *p = neu;
+      ((uint32_t*)p)[2] = stamp;
+      return 3;
+    }
+  }
+  return 2;
+}
+
+// One thread per cell applies its candidates as Algorithm 1 would in
+// ascending seq, with stamps = frame + 1; it also clears the cell's count.
+// Candidates of a key after its first (lowest seq) one never change the
+// cell: the key is then present, or the cell was full and stays full (under
+// FIRST nothing leaves a cell; under OVERWRITE a failed attempt means every
+// entry was written in this frame, so later ones fail too).  So the distinct
+// keys are applied in order of their lowest seq and the rest only counted;
+// with more distinct keys than kDistinct the candidates are taken one by one.
+constexpr int kDistinct = 8;
+
 __global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
   uint32_t c_ins = 0, c_present = 0, c_full = 0, c_over = 0;
   const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -38,49 +80,68 @@ __global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
       const uint32_t base = a.cell_start[cell];
       uint64_t* w0 = a.table + (uint64_t)cell * a.n_entries * a.entry_words;
       const uint32_t stamp = a.frame + 1u;
-      int64_t last = -1;
-      for (uint32_t step = 0; step < n; ++step) {
-        // next candidate in seq order (seqs are distinct)
-        uint32_t best = 0xFFFFFFFFu, bi = 0;
-        for (uint32_t j = 0; j < n; ++j) {
-          uint32_t sq = a.sorted[base + j].y;
-          if ((int64_t)sq > last && sq <= best) { best = sq; bi = j; }
+      // distinct keys: hash2, lowest seq, its code, candidate count
+      uint32_t kh[kDistinct], ks[kDistinct], kc[kDistinct], kn[kDistinct];
+      uint32_t d = 0;
+      bool overflow = false;
+      for (uint32_t j = 0; j < n && !overflow; ++j) {
+        const uint4 c = a.sorted[base + j];
+        bool seen = false;
+#pragma unroll
+        for (int k = 0; k < kDistinct; ++k) {
+          if ((uint32_t)k < d && kh[k] == c.w) {
+            seen = true;
+            kn[k] += 1u;
+            if (c.y < ks[k]) { ks[k] = c.y; kc[k] = c.z; }
+          }
         }
-        last = best;
-        const uint4 c = a.sorted[base + bi];
-        const uint32_t hash2 = c.w;
-        const uint64_t neu = ((uint64_t)hash2 << 32) | c.z;
-        int idx = -1;
-        for (uint32_t i = 0; i < a.n_entries; ++i) {
-          uint32_t h = (uint32_t)(w0[(uint64_t)i * a.entry_words] >> 32);
-          if (h == hash2 || h == 0u) { idx = (int)i; break; }
+        if (!seen) {
+          if (d == (uint32_t)kDistinct) {
+            overflow = true;
+          } else {
+#pragma unroll
+            for (int k = 0; k < kDistinct; ++k)
+              if ((uint32_t)k == d) { kh[k] = c.w; ks[k] = c.y; kc[k] = c.z; kn[k] = 1u; }
+            ++d;
+          }
         }
-        if (idx >= 0) {
-          uint64_t* p = w0 + (uint64_t)idx * a.entry_words;
-          if (*p == 0ull) {
-            *p = neu;
-            if (a.entry_words == 2) ((uint32_t*)p)[2] = stamp;
-            c_ins++;
-          } else {
-            c_present++;
+      }
+      if (!overflow) {
+        for (uint32_t step = 0; step < d; ++step) {
+          // the distinct key with the next lowest seq
+          uint32_t best = 0xFFFFFFFFu;
+          int bi = 0;
+#pragma unroll
+          for (int k = 0; k < kDistinct; ++k)
+            if ((uint32_t)k < d && ks[k] < best) { best = ks[k]; bi = k; }
+          uint32_t h2 = 0, code = 0, cntk = 0;
+#pragma unroll
+          for (int k = 0; k < kDistinct; ++k)
+            if (k == bi) { h2 = kh[k]; code = kc[k]; cntk = kn[k]; ks[k] = 0xFFFFFFFFu; }
+          const int o = apply_one(w0, a, h2, code, stamp);
+          c_ins += o == 0;
+          c_over += o == 3;
+          c_present += o == 1;
+          c_full += o == 2;
+          // the key's later candidates
+          if (o == 2) c_full += cntk - 1u;
+          else c_present += cntk - 1u;
+        }
+      } else {
+        int64_t last = -1;
+        for (uint32_t step = 0; step < n; ++step) {
+          uint32_t best = 0xFFFFFFFFu, bi = 0;
+          for (uint32_t j = 0; j < n; ++j) {
+            uint32_t sq = a.sorted[base + j].y;
+            if ((int64_t)sq > last && sq <= best) { best = sq; bi = j; }
           }
-        } else if (a.policy == PMC_POLICY_OVERWRITE && a.entry_words == 2) {
-          uint32_t bs = 0xFFFFFFFFu;
-          int victim = -1;
-          for (uint32_t i = 0; i < a.n_entries; ++i) {
-            uint32_t st = ((uint32_t*)(w0 + (uint64_t)i * 2))[2];
-            if (st < bs) { bs = st; victim = (int)i; }
-          }
-          if (victim >= 0 && bs < stamp) {
-            uint64_t* p = w0 + (uint64_t)victim * 2;
-            *p = neu;
-            ((uint32_t*)p)[2] = stamp;
-            c_over++;
-          } else {
-            c_full++;
-          }
-        } else {
-          c_full++;
+          last = best;
+          const uint4 c = a.sorted[base + bi];
+          const int o = apply_one(w0, a, c.w, c.z, stamp);
+          c_ins += o == 0;
+          c_over += o == 3;
+          c_present += o == 1;
+          c_full += o == 2;
         }
       }
     }
