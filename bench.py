@@ -226,7 +226,9 @@ def surrogate_smooth_leg(log):
     log(f"smooth scene: {len(trusted)} of {n_slots} networks trusted after {train_ms:.0f} ms")
     results, cold = {}, {}
     for name, use_cache, f in (("uncached", False, 0), ("cache_only", True, 0),
-                               ("surrogate_cache", True, B.PMC_FLAG_SURROGATE)):
+                               ("surrogate_cache", True, B.PMC_FLAG_SURROGATE),
+                               ("surrogate_insert_cache", True,
+                                B.PMC_FLAG_SURROGATE | B.PMC_FLAG_SURROGATE_INSERT)):
         def run(pre, use_cache=use_cache, f=f, n_frames=sc.frames):
             if pre:
                 for k in trusted:
@@ -261,6 +263,8 @@ def surrogate_smooth_leg(log):
             "render": results, "cold_first_frame": cold,
             "cold_gain_vs_cache_only": cold["cache_only"]["ms"] / cold["surrogate_cache"]["ms"],
             "gain_vs_cache_only": results["cache_only"]["ms"] / results["surrogate_cache"]["ms"],
+            "insert_gain_vs_cache_only": (results["cache_only"]["ms"] /
+                                          results["surrogate_insert_cache"]["ms"]),
             "gain_vs_uncached": results["uncached"]["ms"] / results["surrogate_cache"]["ms"]}
 
 

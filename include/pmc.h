@@ -225,9 +225,13 @@ enum pmc_flags {
     PMC_FLAG_LOG = 8u,         /* cached modes: append a pmc_log_record for each value of a
                                   surrogated output that is inserted (CACHED: the CAS or eviction
                                   succeeded; SNAPSHOT: a candidate was emitted) */
-    PMC_FLAG_SURROGATE = 16u   /* cached modes: a missed surrogated output of a trusted material
+    PMC_FLAG_SURROGATE = 16u,  /* cached modes: a missed surrogated output of a trusted material
                                   takes its value from the material's network (not inserted);
                                   see the surrogate section below */
+    PMC_FLAG_SURROGATE_INSERT = 32u  /* with PMC_FLAG_SURROGATE: the network's value is also
+                                  inserted (Algorithm 1, or a snapshot candidate), so later
+                                  lookups find it; the table then holds approximations within
+                                  the trust threshold besides exact graph values */
 };
 
 typedef struct pmc_shade_params {

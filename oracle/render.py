@@ -70,7 +70,8 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
                          level_max: int = K.LEVEL_MAX_DEFAULT, min_subgraph_nodes: int = 2,
                          kmax: int = 8, cacheables: Optional[list] = None,
                          surrogate: Optional[dict] = None,
-                         surrogate_values: Optional[np.ndarray] = None) -> FrameResult:
+                         surrogate_values: Optional[np.ndarray] = None,
+                         surrogate_insert: bool = False) -> FrameResult:
     """One snapshot-mode frame; mutates ``table`` into T_f and returns the frame's results.
 
     surrogate: optional {material: dict(params=[W1, b1, W2, b2, W3, b3],
@@ -81,6 +82,8 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
     surrogated outputs are logged.  surrogate_values [n, kmax, 3], if given,
     replaces the network's values at the substituted entries (to check what
     follows them against another implementation's network outputs).
+    surrogate_insert: the substituted values are inserted too (as candidates of
+    their hits, like graph values).
     """
     n = len(hits)
     res = FrameResult(n, kmax)
@@ -173,6 +176,15 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
             encs = encode(vals, otype)
             for j, enc in zip(miss, encs):
                 candidates.append((int(idx[j]), c, int(ky.cell[j]), int(ky.hash2[j]), int(enc)))
+            if surrogate_insert:
+                sub_rows = np.nonzero(res.surrogate[idx, c])[0]
+                if len(sub_rows):
+                    sv = res.surrogate_value[idx[sub_rows], c, :3 if otype == "COLOR" else 1]
+                    sv = sv if otype == "COLOR" else sv[:, 0]
+                    fin = np.isfinite(sv) if sv.ndim == 1 else np.all(np.isfinite(sv), axis=1)
+                    for j, enc in zip(sub_rows[fin], encode(sv[fin], otype)):
+                        candidates.append((int(idx[j]), c, int(ky.cell[j]), int(ky.hash2[j]),
+                                           int(enc)))
             if sinfo is not None and c in sinfo["ordmap"]:
                 base, width = sinfo["ordmap"][c]
                 for j, val in zip(miss, vals):

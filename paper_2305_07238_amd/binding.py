@@ -39,6 +39,7 @@ PMC_NODE_CLAMP = 1
 PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE = 0, 1
 PMC_MODE_UNCACHED, PMC_MODE_CACHED, PMC_MODE_SNAPSHOT = 0, 1, 2
 PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_DEFER, PMC_FLAG_LOG, PMC_FLAG_SURROGATE = 1, 2, 4, 8, 16
+PMC_FLAG_SURROGATE_INSERT = 32
 N_PARAMS = 6532
 MAX_CACHEABLE = 8
 

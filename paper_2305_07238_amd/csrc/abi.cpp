@@ -400,7 +400,7 @@ pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits
   if (!params) return ctx->fail(PMC_ERR_INVALID, "null params");
   if (params->mode > PMC_MODE_SNAPSHOT) return ctx->fail(PMC_ERR_INVALID, "unknown mode");
   if (params->flags & ~(uint32_t)(PMC_FLAG_SORT | PMC_FLAG_PERSISTENT | PMC_FLAG_DEFER |
-                                  PMC_FLAG_LOG | PMC_FLAG_SURROGATE))
+                                  PMC_FLAG_LOG | PMC_FLAG_SURROGATE | PMC_FLAG_SURROGATE_INSERT))
     return ctx->fail(PMC_ERR_INVALID, "unknown flags");
   if ((params->flags & (PMC_FLAG_LOG | PMC_FLAG_SURROGATE)) && !ctx->surr.ready)
     return ctx->fail(PMC_ERR_STATE, "PMC_FLAG_LOG / PMC_FLAG_SURROGATE need pmc_surrogate_setup");
@@ -481,6 +481,7 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.surr_state = (SurrState*)ctx->surr.state.p;
   }
   if (surr) {
+    a.surr_insert = (params->flags & PMC_FLAG_SURROGATE_INSERT) ? 1u : 0u;
     a.surr_queue = (uint2*)ctx->surr_queue.p;
     a.surr_val = (float4*)ctx->surr_val.p;
     a.surr_queue_cap = n;
@@ -528,7 +529,7 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     grid = (runs + 3) / 4;
   }
   PhaseTimer t1(ctx, 1, s);
-  a.surr_queue_count = misc + 2;     // cleared with misc[0..3] above
+  a.surr_queue_count = misc + 2;     // misc[2], misc[3]: cleared with misc[0..3] above
   HIP_TRY(ctx,
           launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, surr, grid, s));
   if (surr) {

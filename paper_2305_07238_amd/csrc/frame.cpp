@@ -161,7 +161,8 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
   std::vector<Cand> cands;
   // the surrogate choice is the caller's (it changes results); logging is not
   // wanted while tuning
-  const uint32_t base = PMC_FLAG_SORT | (plan->params.flags & PMC_FLAG_SURROGATE);
+  const uint32_t base =
+      PMC_FLAG_SORT | (plan->params.flags & (PMC_FLAG_SURROGATE | PMC_FLAG_SURROGATE_INSERT));
   for (uint32_t pers = 0; pers < 2; ++pers) {
     const uint32_t pf = pers ? PMC_FLAG_PERSISTENT : 0u;
     for (uint32_t cw : {1u, 2u, 4u}) cands.push_back({base | pf, cw, 0u, 0u, 0.0});

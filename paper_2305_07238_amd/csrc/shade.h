@@ -71,9 +71,10 @@ struct ShadeArgs {
   uint32_t* log_count;           // 64 region counters
   uint32_t log_region_cap;       // records per region
   uint2* surr_queue;             // parked hits {hit, surrogated ordinals | audited << 8}
-  uint32_t* surr_queue_count;
+  uint32_t* surr_queue_count;    // [0] plain entries (from the front), [1] audited (from the back)
   uint32_t surr_queue_cap;
   float4* surr_val;              // the networks' outputs for the parked hits
+  uint32_t surr_insert;          // 1: the networks' values are inserted as well
 };
 
 // surr: the variant that consults the surrogate networks (cached modes only).

@@ -447,27 +447,50 @@ __device__ __forceinline__ bool surrogate_park(const ShadeArgs& a, uint32_t m, b
   if (smask == 0u) return false;
   if (as_const(a.surr_state)[H->surr_slot].trusted == 0u) return false;
   const uint32_t sm = mine ? (ins & smask) : 0u;
-  const uint64_t mk = __ballot(sm != 0u);
-  if (mk == 0ull) return false;
-  const int leader = __ffsll((unsigned long long)mk) - 1;
-  uint32_t base = 0u;
-  if (lane_id() == leader) base = atomicAdd(a.surr_queue_count, (uint32_t)__popcll(mk));
-  base = __shfl(base, leader, 64);
+  if (__ballot(sm != 0u) == 0ull) return false;
+  // plain entries fill the queue from the front, audited ones from the back, so
+  // the finish pass gives the audited hits (full evaluation) waves of their own
+  const bool audit = sm != 0u && surrogate_audited(a.frame, h);
+  const uint64_t mk = __ballot(sm != 0u && !audit);
+  const uint64_t ma = __ballot(audit);
+  uint32_t base = 0u, abase = 0u;
+  if (lane_id() == 0) {
+    if (mk) base = atomicAdd(a.surr_queue_count, (uint32_t)__popcll(mk));
+    if (ma) abase = atomicAdd(a.surr_queue_count + 1, (uint32_t)__popcll(ma));
+  }
+  base = __shfl(base, 0, 64);
+  abase = __shfl(abase, 0, 64);
   if (sm == 0u) return false;
-  const uint32_t pos = base + (uint32_t)__popcll(mk & lanemask_lt());
-  if (pos >= a.surr_queue_cap) return false;          // cannot happen: one entry per hit at most
-  const uint32_t audit = surrogate_audited(a.frame, h) ? 0x100u : 0u;
-  a.surr_queue[pos] = make_uint2(h, sm | audit);
+  const uint32_t pos = audit ? a.surr_queue_cap - 1u - (abase + (uint32_t)__popcll(ma & lanemask_lt()))
+                             : base + (uint32_t)__popcll(mk & lanemask_lt());
+  a.surr_queue[pos] = make_uint2(h, sm | (audit ? 0x100u : 0u));
   return true;
+}
+
+// Queue chunk c of the second passes: plain entries [0, n0) in chunks first, then
+// the audited ones [cap - n1, cap).  Returns the entry index (valid when *act).
+__device__ __forceinline__ uint32_t queue_entry(const ShadeArgs& a, uint32_t c, uint32_t n0,
+                                                uint32_t n1, bool* act) {
+  const uint32_t c0 = (n0 + 63u) / 64u;
+  const uint32_t lane = (uint32_t)lane_id();
+  if (c < c0) {
+    const uint32_t idx = c * 64u + lane;
+    *act = idx < n0;
+    return idx;
+  }
+  const uint32_t r = (c - c0) * 64u + lane;
+  *act = r < n1;
+  return a.surr_queue_cap - n1 + r;
 }
 
 // Finish pass: the network's outputs y stand in for the parked outputs `sm`
 // that still miss (they go to the outputs' registers and leave the misses: no
 // sub-graph evaluation, no insert).  An audited lane instead keeps them in *au
 // and is evaluated by the graph.
+template <int MODE>
 __device__ __forceinline__ void surrogate_substitute(const ShadeArgs& a, uint32_t m, uint32_t h,
-                                                     uint32_t sm, bool audit, float4 yv,
-                                                     const LaneRegs& R, Counters& cnt,
+                                                     const HitData& hd, uint32_t sm, bool audit,
+                                                     float4 yv, const LaneRegs& R, Counters& cnt,
                                                      uint32_t& miss, uint32_t& ins, Audit& au) {
   sm &= ins;
   if (sm == 0u) return;
@@ -500,6 +523,22 @@ __device__ __forceinline__ void surrogate_substitute(const ShadeArgs& a, uint32_
       float* dv = a.dbg_value + ((uint64_t)h * 8 + c) * 3;
       dv[0] = v0; dv[1] = v1; dv[2] = v2;
     }
+    if (a.surr_insert) {
+      // the network's value goes into the table like a graph value
+      const bool is_c = cd.otype == OT_COLOR;
+      bool want = isfinite(v0) && (!is_c || (isfinite(v1) && isfinite(v2)));
+      const uint32_t code = is_c ? rgb9e5_encode(v0, v1, v2) : __float_as_uint(v0);
+      const Key k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max,
+                             a.cells);
+      want = want && !k.bypass;
+      cnt.v[CNT_INS_TRIED] += (uint32_t)want;
+      if (MODE == PMC_MODE_SNAPSHOT) {
+        append_candidate(a, want, k.cell, k.hash2, code, h * 32u + c, cnt);
+      } else {
+        const int o = want ? cache_insert(a, k.cell, k.hash2, code) : INS_FULL;
+        count_insert(cnt, want, o);
+      }
+    }
   }
   cnt.v[CNT_SURR_USED] += (uint32_t)__popc(sm);
   miss &= ~sm;
@@ -513,10 +552,13 @@ __device__ __forceinline__ void surrogate_substitute(const ShadeArgs& a, uint32_
 // per-material split.  Found values go to their registers.  Returns the miss
 // mask (bypassed outputs count as misses); *ins gets the misses that may be
 // inserted.  COUNT = false when the lookups were already counted (deferred hits).
+// Ordinals in `skip` are known misses (parked surrogate outputs): not looked up,
+// returned as insertable misses.
 template <int MODE, bool COUNT>
 __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active, uint32_t m,
                                                 uint32_t h, const HitData& hd, const LaneRegs& R,
-                                                Counters& cnt, uint32_t* ins, uint32_t* slots) {
+                                                Counters& cnt, uint32_t* ins, uint32_t* slots,
+                                                uint32_t skip = 0u) {
   uint32_t n_cach = 0u, cbeg = 0u;
   if (active && m < a.n_mats) {
     const MatHeader* H = a.hdr + m;
@@ -542,10 +584,13 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
       cd = a.cach[cbeg + c];
       k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.cells);
     }
-    const uint32_t h2 = (has && !k.bypass) ? k.hash2 : 0u;
+    const bool skipped = (skip >> c) & 1u;
+    const uint32_t h2 = (has && !k.bypass && !skipped) ? k.hash2 : 0u;
     uint32_t code = 0u, slot = 0xFFu;
     bool found;
-    if (coop) {
+    if (__ballot(h2 != 0u) == 0ull) {
+      found = false;                              // nothing to look up in this round
+    } else if (coop) {
       found = coop_lookup128(a, k.cell, h2, &code, &slot);
     } else {
       found = false;
@@ -555,7 +600,7 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
     // 4 bits per ordinal: first empty entry (15 = none or beyond 15)
     slot_bits = (slot_bits & ~(0xFu << (4 * c))) | ((slot < 15u ? slot : 15u) << (4 * c));
     if (COUNT) cnt.v[CNT_BYPASSES] += (uint32_t)k.bypass;
-    cnt.v[COUNT ? CNT_PROBES : CNT_PROBES_DEFERRED] += (uint32_t)!k.bypass;
+    cnt.v[COUNT ? CNT_PROBES : CNT_PROBES_DEFERRED] += (uint32_t)(!k.bypass && !skipped);
     if (COUNT) cnt.v[CNT_CACHE_HITS] += (uint32_t)(!k.bypass && found);
     uint8_t st = 0;
     if (k.bypass) {
@@ -1045,13 +1090,13 @@ void k_shade_persistent_w4(ShadeArgs a) {
 // stride); a wave whose entries span materials runs each material's network
 // with all lanes active and keeps the lanes of that material.
 __global__ __launch_bounds__(256) void k_surr_queue(ShadeArgs a) {
-  const uint32_t n = min(*a.surr_queue_count, a.surr_queue_cap);
-  const uint32_t n_chunks = (n + 63u) / 64u;
+  const uint32_t n0 = a.surr_queue_count[0], n1 = a.surr_queue_count[1];
+  const uint32_t n_chunks = (n0 + 63u) / 64u + (n1 + 63u) / 64u;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks;
        c += waves) {
-    const uint32_t idx = c * 64u + (uint32_t)lane_id();
-    const bool act = idx < n;
+    bool act;
+    const uint32_t idx = queue_entry(a, c, n0, n1, &act);
     const uint32_t h = act ? a.surr_queue[idx].x : 0u;
     const uint32_t mat = act ? a.material[h] : 0xFFFFFFFFu;
     const float2 uv = act ? reinterpret_cast<const float2*>(a.uv)[h] : make_float2(0.f, 0.f);
@@ -1080,13 +1125,13 @@ __device__ __forceinline__ void shade_finish_body(const ShadeArgs& a) {
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
-  const uint32_t n = min(*a.surr_queue_count, a.surr_queue_cap);
-  const uint32_t n_chunks = (n + 63u) / 64u;
+  const uint32_t n0 = a.surr_queue_count[0], n1 = a.surr_queue_count[1];
+  const uint32_t n_chunks = (n0 + 63u) / 64u + (n1 + 63u) / 64u;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks;
        c += waves) {
-    const uint32_t idx = c * 64u + (uint32_t)lane_id();
-    const bool act = idx < n;
+    bool act;
+    const uint32_t idx = queue_entry(a, c, n0, n1, &act);
     const uint2 e = act ? a.surr_queue[idx] : make_uint2(0u, 0u);
     LaneIdx I;
     I.active = act;
@@ -1094,7 +1139,9 @@ __device__ __forceinline__ void shade_finish_body(const ShadeArgs& a) {
     const LaneHit L = fetch_lane(a, I);
     const float4 yv = act ? a.surr_val[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t ins = 0u, slots = 0u;
-    uint32_t miss = probe_chunk<MODE, false>(a, act, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
+    // the parked outputs missed in the first pass: look up only the others
+    uint32_t miss = probe_chunk<MODE, false>(a, act, L.mat, L.h, L.hd, R, cnt, &ins, &slots,
+                                             e.y & 0xFFu);
     uint64_t pending = __ballot(act);
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -1103,8 +1150,8 @@ __device__ __forceinline__ void shade_finish_body(const ShadeArgs& a) {
       pending &= ~__ballot(mine);
       if (mine) {
         Audit au = no_audit();
-        surrogate_substitute(a, m, L.h, e.y & 0xFFu, (e.y & 0x100u) != 0u, yv, R, cnt, miss,
-                             ins, au);
+        surrogate_substitute<MODE>(a, m, L.h, L.hd, e.y & 0xFFu, (e.y & 0x100u) != 0u, yv, R,
+                                   cnt, miss, ins, au);
         shade_full<MODE, true, true>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, au);
       }
     }

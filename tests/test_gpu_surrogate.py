@@ -189,13 +189,17 @@ def _outputs_with(sc, h, state, value):
 
 
 @pytest.mark.parametrize("flags,max_err", [(B.PMC_FLAG_SORT, 1e-2),
-                                           (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, 1e6)])
+                                           (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, 1e6),
+                                           (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER |
+                                            B.PMC_FLAG_SURROGATE_INSERT, 1e6)])
 def test_snapshot_with_trusted_networks_matches_reference(flags, max_err):
     """Snapshot mode is deterministic, so which outputs the networks replace
     (missed, not bypassed, not audited) is exact; the replaced values match the
     reference network; every output downstream matches the FP64 graph with the
     GPU's network values substituted; the table stays bit-exact (replaced values
-    are not inserted); the log holds exactly the inserted surrogated outputs.
+    are not inserted, unless PMC_FLAG_SURROGATE_INSERT asks for it, and then they are
+    candidates like graph values); the log holds exactly the inserted surrogated
+    outputs of graph values.
     Audited hits measure the live error; with the 1e-2 threshold the random
     networks lose their trust after the first frame that audits them, on both
     sides; with a huge threshold they keep it."""
@@ -212,8 +216,9 @@ def test_snapshot_with_trusted_networks_matches_reference(flags, max_err):
         out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
                                         flags=flags | B.PMC_FLAG_SURROGATE | B.PMC_FLAG_LOG,
                                         debug=True)
-        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f,
-                                          surrogate=sinfo, surrogate_values=value)
+        ref = render.shade_snapshot_frame(
+            sc.materials, sc.textures, h, ref_t, f, surrogate=sinfo, surrogate_values=value,
+            surrogate_insert=bool(flags & B.PMC_FLAG_SURROGATE_INSERT))
         assert np.array_equal(state == 1, ref.found)
         assert np.array_equal(state == 4, ref.surrogate)
         assert st["surrogate_used"] == ref.stats["surrogate_used"]
