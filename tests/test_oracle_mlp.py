@@ -92,3 +92,55 @@ def test_batch_sampler_is_reproducible_and_in_range():
     assert a.min() >= 0 and a.max() < 1000
     counts = np.bincount(mlp.batch_indices(1, 0, 100000, 10), minlength=10)
     assert counts.min() > 9000 and counts.max() < 11000
+
+
+def test_audit_rule_selects_one_in_64():
+    h = np.arange(1 << 16)
+    for frame in (0, 5):
+        k = int(mlp.audited(frame, h).sum())
+        n, p = len(h), 1.0 / 64
+        assert abs(k - n * p) <= 4 * np.sqrt(n * p * (1 - p))
+    # the rule depends on the frame
+    assert not np.array_equal(mlp.audited(0, h), mlp.audited(1, h))
+
+
+def test_targets_place_channels_by_ordinal():
+    rec = np.zeros(3, dtype=[("ordinal", "<u4"), ("value", "<f4", (4,))])
+    rec["ordinal"] = [0, 1, 2]
+    rec["value"][0, :3] = [0.1, 0.2, 0.3]
+    rec["value"][1, 0] = 0.7
+    rec["value"][2, 0] = 0.9                     # ordinal 2 is not surrogated
+    t, m = mlp.targets(rec, {0: (0, 3), 1: (3, 1)})
+    assert np.allclose(t[0], [0.1, 0.2, 0.3, 0.0]) and np.array_equal(m[0], [1, 1, 1, 0])
+    assert np.allclose(t[1], [0, 0, 0, 0.7]) and np.array_equal(m[1], [0, 0, 0, 1])
+    assert not m[2].any()
+
+
+def test_snapshot_substitution_with_a_constant_network():
+    """A network with zero weights outputs its bias, so every substituted hit of
+    the smooth material gets base colour = b3[0:3] and roughness = b3[3]
+    (the sink takes both directly); audited hits keep their graph values and are
+    inserted; substituted outputs are not."""
+    from oracle import graph, render, table
+    sc = scenes.smooth_scene(n_mats=1, width=80, height=40, frames=1)
+    mat = sc.materials[0]
+    cach = graph.cacheable_outputs(mat)
+    assert [graph.output_type(mat, *c) for c in cach] == ["COLOR", "FLOAT"]
+    params = [np.zeros((64, 32)), np.zeros(64), np.zeros((64, 64)), np.zeros(64),
+              np.zeros((4, 64)), np.array([0.2, 0.3, 0.4, 0.5])]
+    info = {0: dict(params=params, ordmap={0: (0, 3), 1: (3, 1)}, trusted=True)}
+    h = sc.frame(0)
+    t = table.Table(1 << 12, 8, 16)
+    res = render.shade_snapshot_frame(sc.materials, sc.textures, h, t, 0, surrogate=info)
+    sub = res.surrogate[:, 0] & res.surrogate[:, 1]
+    aud = res.audited[:, 0]
+    assert sub.sum() + aud.sum() == len(h)                  # empty table: every hit missed
+    assert np.allclose(res.outputs["base_color"][sub], [0.2, 0.3, 0.4], rtol=0, atol=1e-12)
+    assert np.allclose(res.outputs["roughness"][sub], 0.5, rtol=0, atol=1e-12)
+    # only the audited hits' graph values were offered to the table
+    assert res.stats["candidates"] == 2 * int(aud.sum())
+    # and the live error is the distance of the graph values from the bias
+    if aud.any():
+        o = render.shade_uncached(sc.materials, sc.textures, h.take(np.nonzero(aud)[0]))
+        e = max(np.abs(o["base_color"] - [0.2, 0.3, 0.4]).max(), np.abs(o["roughness"] - 0.5).max())
+        assert abs(res.live_err[0] - e) < 1e-12
