@@ -21,11 +21,15 @@ SOURCES = ["abi.cpp", "compiler.cpp", "frame.cpp", "surrogate_api.cpp", "shade.h
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
+# Sources with matrix-core code: results of the matrix products go straight to
+# ordinary vector registers, which saves a copy out of the accumulation
+# registers for every element the ReLU and conversion read.
+EXTRA = {src: ["-mllvm", "-amdgpu-mfma-vgpr-form"] for src in ("shade.hip", "surrogate.hip")}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -63,6 +63,11 @@ pmc_status need_device(pmc_ctx* ctx) {
 
 namespace {
 
+// Small per-context device words: [1] the snapshot candidate count,
+// [kMiscQueue, kMiscQueue + 2 kQueueRegions) the surrogate queue's counters.
+constexpr uint32_t kMiscQueue = 64, kMiscWords = 256;
+static_assert(kMiscQueue + 2 * kQueueRegions <= kMiscWords, "misc words");
+
 template <typename T>
 pmc_status upload(pmc_ctx* ctx, DevBuf& b, const std::vector<T>& v) {
   size_t bytes = v.size() * sizeof(T);
@@ -128,7 +133,7 @@ pmc_status pmc_create(int device, pmc_ctx** out) {
     }
     ctx->num_cus = prop.multiProcessorCount;
     if (ensure(ctx, ctx->stat_slots, sizeof(unsigned long long) * kStatSlots * kStatStride) ||
-        ensure(ctx, ctx->misc, 256) ||
+        ensure(ctx, ctx->misc, kMiscWords * 4) ||
         hipMemset(ctx->stat_slots.p, 0, ctx->stat_slots.bytes) != hipSuccess ||
         hipMemset(ctx->misc.p, 0, ctx->misc.bytes) != hipSuccess ||
         prepare_sort_kernels() != hipSuccess || prepare_surrogate_kernels() != hipSuccess) {
@@ -411,7 +416,7 @@ pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits
 }
 
 pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mode,
-                         uint32_t flags, hipStream_t s) {
+                         uint32_t flags, uint32_t chunk_waves, hipStream_t s) {
   const uint32_t n_mats = (uint32_t)ctx->prog.headers.size();
   pmc_status st;
   if (flags & PMC_FLAG_SORT) {
@@ -425,8 +430,11 @@ pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mo
       return st;
   }
   if ((flags & PMC_FLAG_SURROGATE) && mode != PMC_MODE_UNCACHED && cache) {
-    if ((st = ensure(ctx, ctx->surr_queue, (size_t)n * 8)) ||
-        (st = ensure(ctx, ctx->surr_val, (size_t)n * 16)))
+    const uint32_t cap = queue_region_cap(n, chunk_waves);
+    if (cap == 0) return ctx->fail(PMC_ERR_UNSUPPORTED, "batch too large for the surrogate queue");
+    const size_t entries = (size_t)cap * kQueueRegions;
+    if ((st = ensure(ctx, ctx->surr_queue, entries * 8)) ||
+        (st = ensure(ctx, ctx->surr_val, entries * 16)))
       return st;
   }
   if (mode == PMC_MODE_SNAPSHOT && cache) {
@@ -455,7 +463,10 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   if (!cache) mode = PMC_MODE_UNCACHED;
   const bool sort = params->flags & PMC_FLAG_SORT;
   const bool persistent = params->flags & PMC_FLAG_PERSISTENT;
-  if (pmc_status st = reserve_batch(ctx, cache, n, mode, params->flags, s)) return st;
+  const bool probe_first = mode != PMC_MODE_UNCACHED && (params->flags & PMC_FLAG_DEFER);
+  const uint32_t chunk_waves = resolve_chunk_waves(params->chunk_waves, probe_first);
+  if (pmc_status st = reserve_batch(ctx, cache, n, mode, params->flags, chunk_waves, s))
+    return st;
 
   ShadeArgs a;
   fill_program_args(ctx, a);
@@ -484,7 +495,8 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.surr_insert = (params->flags & PMC_FLAG_SURROGATE_INSERT) ? 1u : 0u;
     a.surr_queue = (uint2*)ctx->surr_queue.p;
     a.surr_val = (float4*)ctx->surr_val.p;
-    a.surr_queue_cap = n;
+    a.surr_queue_cap = queue_region_cap(n, chunk_waves);
+    a.surr_queue_count = misc + kMiscQueue;
   }
   if (logged) {
     a.log = (pmc_log_record*)ctx->surr.log.p;
@@ -492,17 +504,19 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.log_region_cap = ctx->surr.log_cap / 64u;
   }
 
-  // misc[1]: snapshot candidate count (reset by the sort's scan, or filled here)
+  // misc[1]: snapshot candidate count; misc[kMiscQueue ..]: the queue's region
+  // counters (reset by the sort's scan, or filled here)
+  const uint32_t n_reset = surr ? kMiscQueue + 2u * kQueueRegions : 4u;
   if (sort) {
     PhaseTimer t0(ctx, 0, s);
     HIP_TRY(ctx, launch_material_sort_tiled(
                      hits->material, n, a.n_mats, (const uint32_t*)ctx->lpt_rank.p,
                      (uint32_t*)ctx->sort_counts.p, (uint32_t*)ctx->sort_offsets.p,
-                     (uint32_t*)ctx->sort_sums.p, (uint32_t*)ctx->perm.p, misc, 4, s));
+                     (uint32_t*)ctx->sort_sums.p, (uint32_t*)ctx->perm.p, misc, n_reset, s));
     t0.finish();
     a.perm = (const uint32_t*)ctx->perm.p;
   } else {
-    HIP_TRY(ctx, launch_fill_u32(misc, 0u, 4, s));
+    HIP_TRY(ctx, launch_fill_u32(misc, 0u, n_reset, s));
   }
   if (mode == PMC_MODE_SNAPSHOT) {
     a.cand = (uint4*)ctx->cand.p;
@@ -510,8 +524,7 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.cand_cap = (uint32_t)((size_t)n * (ctx->prog.max_cach ? ctx->prog.max_cach : 1));
   }
   const uint32_t n_chunks = (n + 63) / 64;
-  const bool probe_first = mode != PMC_MODE_UNCACHED && (params->flags & PMC_FLAG_DEFER);
-  a.chunk_waves = params->chunk_waves ? params->chunk_waves : (probe_first ? 4u : 1u);
+  a.chunk_waves = chunk_waves;
   a.defer_max = params->defer_max ? params->defer_max : 48u;
   const uint32_t runs = (n_chunks + a.chunk_waves - 1) / a.chunk_waves;
   uint32_t grid;
@@ -529,7 +542,6 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     grid = (runs + 3) / 4;
   }
   PhaseTimer t1(ctx, 1, s);
-  a.surr_queue_count = misc + 2;     // misc[2], misc[3]: cleared with misc[0..3] above
   HIP_TRY(ctx,
           launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, surr, grid, s));
   if (surr) {

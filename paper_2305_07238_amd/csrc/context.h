@@ -106,7 +106,7 @@ pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits
 // Device workspace for batches of up to n hits (all allocations and first-use
 // clears, enqueued on s).  After this, shade_batch for such batches allocates nothing.
 pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mode,
-                         uint32_t flags, hipStream_t s);
+                         uint32_t flags, uint32_t chunk_waves, hipStream_t s);
 // The per-batch pipeline: material sort -> shade -> snapshot apply -> stats.
 pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                        const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,

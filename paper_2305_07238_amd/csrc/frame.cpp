@@ -83,8 +83,10 @@ pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_fram
   hipStream_t cs = nullptr;
   HIP_TRY(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   const uint32_t mode = cache ? plan->params.mode : PMC_MODE_UNCACHED;
+  const bool probe_first = mode != PMC_MODE_UNCACHED && (plan->params.flags & PMC_FLAG_DEFER);
   pmc_status st = reserve_batch(ctx, cache, (uint32_t)plan->hits_per_frame, mode,
-                                plan->params.flags, cs);
+                                plan->params.flags,
+                                resolve_chunk_waves(plan->params.chunk_waves, probe_first), cs);
   if (st == PMC_OK && hipStreamSynchronize(cs) != hipSuccess)
     st = ctx->fail(PMC_ERR_HIP, "workspace reservation failed");
   pmc_frame_graph* g = nullptr;

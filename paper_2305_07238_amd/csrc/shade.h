@@ -70,12 +70,29 @@ struct ShadeArgs {
   pmc_log_record* log;           // NULL: no logging
   uint32_t* log_count;           // 64 region counters
   uint32_t log_region_cap;       // records per region
-  uint2* surr_queue;             // parked hits {hit, surrogated ordinals | audited << 8}
-  uint32_t* surr_queue_count;    // [0] plain entries (from the front), [1] audited (from the back)
-  uint32_t surr_queue_cap;
+  uint2* surr_queue;             // parked hits {hit, surrogated ordinals | audited << 8},
+                                 // kQueueRegions regions of surr_queue_cap entries
+  uint32_t* surr_queue_count;    // [r] plain entries of region r (from its front),
+                                 // [kQueueRegions + r] audited ones (from its back)
+  uint32_t surr_queue_cap;       // entries per region
   float4* surr_val;              // the networks' outputs for the parked hits
   uint32_t surr_insert;          // 1: the networks' values are inserted as well
 };
+
+// The queue of parked hits is split into regions so that its counters are not
+// one hot address: the run of chunks r (chunk_waves chunks handled by one wave)
+// parks into region r % kQueueRegions, and a region holds every hit of its runs.
+constexpr uint32_t kQueueRegions = 64;
+
+inline uint32_t resolve_chunk_waves(uint32_t requested, bool probe_first) {
+  return requested ? requested : (probe_first ? 4u : 1u);
+}
+
+inline uint32_t queue_region_cap(uint32_t n, uint32_t chunk_waves) {
+  const uint64_t runs = ((uint64_t)(n + 63u) / 64u + chunk_waves - 1u) / chunk_waves;
+  const uint64_t cap = (runs + kQueueRegions - 1u) / kQueueRegions * chunk_waves * 64u;
+  return (uint32_t)(cap < 0xFFFFFFFFull / kQueueRegions ? cap : 0u);
+}
 
 // surr: the variant that consults the surrogate networks (cached modes only).
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, bool surr, uint32_t grid,

@@ -440,7 +440,8 @@ __device__ __forceinline__ Audit no_audit() {
 // lanes parked.
 template <int MODE>
 __device__ __forceinline__ bool surrogate_park(const ShadeArgs& a, uint32_t m, bool mine,
-                                               uint32_t h, uint32_t ins, Counters& cnt) {
+                                               uint32_t h, uint32_t ins, uint32_t region,
+                                               Counters& cnt) {
   if (m >= a.n_mats) return false;
   const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
   const uint32_t smask = H->surr_mask;
@@ -448,39 +449,74 @@ __device__ __forceinline__ bool surrogate_park(const ShadeArgs& a, uint32_t m, b
   if (as_const(a.surr_state)[H->surr_slot].trusted == 0u) return false;
   const uint32_t sm = mine ? (ins & smask) : 0u;
   if (__ballot(sm != 0u) == 0ull) return false;
-  // plain entries fill the queue from the front, audited ones from the back, so
-  // the finish pass gives the audited hits (full evaluation) waves of their own
+  // plain entries fill the run's region from the front, audited ones from the
+  // back, so the finish pass gives the audited hits (full evaluation) waves of
+  // their own
   const bool audit = sm != 0u && surrogate_audited(a.frame, h);
   const uint64_t mk = __ballot(sm != 0u && !audit);
   const uint64_t ma = __ballot(audit);
   uint32_t base = 0u, abase = 0u;
   if (lane_id() == 0) {
-    if (mk) base = atomicAdd(a.surr_queue_count, (uint32_t)__popcll(mk));
-    if (ma) abase = atomicAdd(a.surr_queue_count + 1, (uint32_t)__popcll(ma));
+    if (mk) base = atomicAdd(a.surr_queue_count + region, (uint32_t)__popcll(mk));
+    if (ma) abase = atomicAdd(a.surr_queue_count + kQueueRegions + region, (uint32_t)__popcll(ma));
   }
   base = __shfl(base, 0, 64);
   abase = __shfl(abase, 0, 64);
   if (sm == 0u) return false;
   const uint32_t pos = audit ? a.surr_queue_cap - 1u - (abase + (uint32_t)__popcll(ma & lanemask_lt()))
                              : base + (uint32_t)__popcll(mk & lanemask_lt());
-  a.surr_queue[pos] = make_uint2(h, sm | (audit ? 0x100u : 0u));
+  a.surr_queue[(uint64_t)region * a.surr_queue_cap + pos] =
+      make_uint2(h, sm | (audit ? 0x100u : 0u));
   return true;
 }
 
-// Queue chunk c of the second passes: plain entries [0, n0) in chunks first, then
-// the audited ones [cap - n1, cap).  Returns the entry index (valid when *act).
-__device__ __forceinline__ uint32_t queue_entry(const ShadeArgs& a, uint32_t c, uint32_t n0,
-                                                uint32_t n1, bool* act) {
-  const uint32_t c0 = (n0 + 63u) / 64u;
-  const uint32_t lane = (uint32_t)lane_id();
-  if (c < c0) {
-    const uint32_t idx = c * 64u + lane;
-    *act = idx < n0;
-    return idx;
+// The second passes walk the queue in 64-entry chunks: the plain entries of
+// regions 0, 1, ... first, then the audited ones.  Lane r of a wave holds
+// region r's counts and chunk prefix sums (kQueueRegions = 64 = wave size).
+struct QueueMap {
+  uint32_t n0, n1;          // lane r: plain and audited entries of region r
+  uint32_t incl0, incl1;    // lane r: chunks of regions 0..r (inclusive prefix)
+  uint32_t c0, c1;          // total plain and audited chunks
+};
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(x, (unsigned)o, 64);
+    if (lane >= o) x += t;
   }
-  const uint32_t r = (c - c0) * 64u + lane;
-  *act = r < n1;
-  return a.surr_queue_cap - n1 + r;
+  return x;
+}
+
+__device__ __forceinline__ QueueMap queue_map(const ShadeArgs& a) {
+  static_assert(kQueueRegions == 64, "one region per lane");
+  QueueMap Q;
+  const int r = lane_id();
+  Q.n0 = a.surr_queue_count[r];
+  Q.n1 = a.surr_queue_count[kQueueRegions + r];
+  Q.incl0 = wave_incl_scan((Q.n0 + 63u) / 64u);
+  Q.incl1 = wave_incl_scan((Q.n1 + 63u) / 64u);
+  Q.c0 = __shfl(Q.incl0, 63, 64);
+  Q.c1 = __shfl(Q.incl1, 63, 64);
+  return Q;
+}
+
+// Entry index of this lane in chunk c < c0 + c1 (valid when *act).
+__device__ __forceinline__ uint64_t queue_entry(const ShadeArgs& a, const QueueMap& Q, uint32_t c,
+                                                bool* act) {
+  const bool audited = c >= Q.c0;
+  const uint32_t cc = audited ? c - Q.c0 : c;
+  const uint32_t incl = audited ? Q.incl1 : Q.incl0;
+  const uint32_t cnt = audited ? Q.n1 : Q.n0;
+  // the region holding chunk cc: the first whose inclusive prefix exceeds cc
+  const int r = (int)__popcll(__ballot(incl <= cc));
+  const uint32_t r_incl = __shfl(incl, r, 64), r_n = __shfl(cnt, r, 64);
+  const uint32_t r_first = r_incl - (r_n + 63u) / 64u;
+  const uint32_t off = (cc - r_first) * 64u + (uint32_t)lane_id();
+  *act = off < r_n;
+  const uint64_t base = (uint64_t)r * a.surr_queue_cap;
+  return audited ? base + a.surr_queue_cap - r_n + off : base + off;
 }
 
 // Finish pass: the network's outputs y stand in for the parked outputs `sm`
@@ -866,7 +902,8 @@ __device__ __forceinline__ LaneHit load_lane(const ShadeArgs& a, const uint32_t*
 // are consumed, so the loads overlap the evaluation below.
 template <int MODE, bool SURR>
 __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const LaneHit& L, LaneIdx next,
-                                           LaneHit* Ln, const LaneRegs& R, Counters& cnt) {
+                                           LaneHit* Ln, const LaneRegs& R, Counters& cnt,
+                                           uint32_t region) {
   cnt.v[CNT_HITS] += (uint32_t)L.active;
   uint32_t ins = 0u, slots = 0u;
   uint32_t miss = probe_chunk<MODE, true>(a, L.active, L.mat, L.h, L.hd, R, cnt, &ins, &slots);
@@ -877,7 +914,7 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const LaneHit& L,
     const uint32_t m = __builtin_amdgcn_readlane(L.mat, leader);
     const bool mine = L.active && L.mat == m;
     pending &= ~__ballot(mine);
-    const bool parked = SURR && surrogate_park<MODE>(a, m, mine, L.h, ins, cnt);
+    const bool parked = SURR && surrogate_park<MODE>(a, m, mine, L.h, ins, region, cnt);
     if (mine && !parked) {
       if (m < a.n_mats) {
         shade_full<MODE, false, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, no_audit());
@@ -898,6 +935,7 @@ struct DeferBuf {
   uint32_t* ids;      // 64 entries
   uint32_t count;     // wave-uniform
   uint32_t mat;       // wave-uniform
+  uint32_t region;    // surrogate queue region of the current run
 };
 
 // Evaluate the staged hits (all 64 lanes active on entry).  The lookups are
@@ -910,7 +948,7 @@ __device__ __forceinline__ void flush_deferred(const ShadeArgs& a, DeferBuf& B, 
   LaneHit L = load_lane(a, B.ids, B.count, 0u);
   uint32_t ins = 0u, slots = 0u;
   uint32_t miss = probe_chunk<MODE, false>(a, act, m, L.h, L.hd, R, cnt, &ins, &slots);
-  const bool parked = SURR && surrogate_park<MODE>(a, m, act, L.h, ins, cnt);
+  const bool parked = SURR && surrogate_park<MODE>(a, m, act, L.h, ins, B.region, cnt);
   if (act && !parked)
     shade_full<MODE, true, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, no_audit());
   B.count = 0u;
@@ -937,7 +975,7 @@ __device__ __forceinline__ void chunk_probe(const ShadeArgs& a, const LaneHit& L
     pending &= ~__ballot(mine);
     const uint32_t d = (uint32_t)__popcll(__ballot(mine && miss != 0u));
     const bool dense = d > a.defer_max;
-    const bool parked = SURR && dense && surrogate_park<MODE>(a, m, mine, L.h, ins, cnt);
+    const bool parked = SURR && dense && surrogate_park<MODE>(a, m, mine, L.h, ins, B.region, cnt);
     if (mine && !parked) {
       if (m < a.n_mats) {
         const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
@@ -999,6 +1037,7 @@ template <int MODE, int KIND, bool SURR>
 __device__ __forceinline__ void do_run(const ShadeArgs& a, uint32_t first, uint32_t n_chunks,
                                        const LaneRegs& R, Counters& cnt, DeferBuf& B) {
   const uint32_t last = min(first + a.chunk_waves, n_chunks);
+  B.region = (first / a.chunk_waves) % kQueueRegions;
   LaneHit L = load_lane(a, a.perm, a.n, first);
   for (uint32_t c = first; c < last; ++c) {
     // index of the next chunk now (its load is in flight during the probes),
@@ -1009,7 +1048,7 @@ __device__ __forceinline__ void do_run(const ShadeArgs& a, uint32_t first, uint3
     if (c + 1u < last) next = lane_index(a.perm, a.n, c + 1u);
     LaneHit Ln;
     if (KIND == KIND_PROBE) chunk_probe<MODE, SURR>(a, L, next, &Ln, R, cnt, B);
-    else chunk_full<MODE, SURR>(a, L, next, &Ln, R, cnt);
+    else chunk_full<MODE, SURR>(a, L, next, &Ln, R, cnt, B.region);
     L = Ln;
   }
   if (KIND == KIND_PROBE && B.count != 0u) flush_deferred<MODE, SURR>(a, B, R, cnt);
@@ -1026,7 +1065,7 @@ __device__ __forceinline__ void shade_flat_body(const ShadeArgs& a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
   LaneRegs R{wl, lane_id()};
-  DeferBuf B{reinterpret_cast<uint32_t*>(wl + a.n_regs * 64), 0u, 0u};
+  DeferBuf B{reinterpret_cast<uint32_t*>(wl + a.n_regs * 64), 0u, 0u, 0u};
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
@@ -1046,7 +1085,7 @@ __device__ __forceinline__ void shade_persistent_body(const ShadeArgs& a) {
   extern __shared__ float lds[];
   float* wl = wave_lds(lds, a);
   LaneRegs R{wl, lane_id()};
-  DeferBuf B{reinterpret_cast<uint32_t*>(wl + a.n_regs * 64), 0u, 0u};
+  DeferBuf B{reinterpret_cast<uint32_t*>(wl + a.n_regs * 64), 0u, 0u, 0u};
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
@@ -1086,17 +1125,23 @@ void k_shade_persistent_w4(ShadeArgs a) {
 
 // ------------------------------------------------- surrogate second passes ---
 
-// The networks over the queue of parked hits: one wave per 64 entries (grid
-// stride); a wave whose entries span materials runs each material's network
-// with all lanes active and keeps the lanes of that material.
+// The networks over the queue of parked hits, 64 entries per step of a wave; a
+// step whose entries span materials runs each material's network with all
+// lanes active and keeps the lanes of that material.
 __global__ __launch_bounds__(256) void k_surr_queue(ShadeArgs a) {
-  const uint32_t n0 = a.surr_queue_count[0], n1 = a.surr_queue_count[1];
-  const uint32_t n_chunks = (n0 + 63u) / 64u + (n1 + 63u) / 64u;
+  const QueueMap Q = queue_map(a);
+  const uint32_t n_chunks = Q.c0 + Q.c1;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks;
-       c += waves) {
+  // contiguous runs of chunks per wave: the queue follows the material order,
+  // so a wave reloads its network only where the material changes
+  const uint32_t per = (n_chunks + waves - 1u) / waves;
+  const uint32_t wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t c_end = min(n_chunks, (wv + 1u) * per);
+  NetRegs N;
+  uint32_t loaded = 0xFFFFFFFFu;
+  for (uint32_t c = wv * per; c < c_end; ++c) {
     bool act;
-    const uint32_t idx = queue_entry(a, c, n0, n1, &act);
+    const uint64_t idx = queue_entry(a, Q, c, &act);
     const uint32_t h = act ? a.surr_queue[idx].x : 0u;
     const uint32_t mat = act ? a.material[h] : 0xFFFFFFFFu;
     const float2 uv = act ? reinterpret_cast<const float2*>(a.uv)[h] : make_float2(0.f, 0.f);
@@ -1107,8 +1152,13 @@ __global__ __launch_bounds__(256) void k_surr_queue(ShadeArgs a) {
       const uint32_t m = __builtin_amdgcn_readlane(mat, leader);
       const bool mine = act && mat == m;
       pending &= ~__ballot(mine);
+      const uint32_t slot = (as_const(a.hdr) + m)->surr_slot;
+      if (slot != loaded) {
+        load_net(a.surr_w + slot, N);
+        loaded = slot;
+      }
       float y[4];
-      mlp_wave(a.surr_w + (as_const(a.hdr) + m)->surr_slot, uv.x, uv.y, y);
+      net_wave(N, uv.x, uv.y, y);
       if (mine) out = make_float4(y[0], y[1], y[2], y[3]);
     }
     if (act) a.surr_val[idx] = out;
@@ -1125,13 +1175,13 @@ __device__ __forceinline__ void shade_finish_body(const ShadeArgs& a) {
   Counters cnt;
 #pragma unroll
   for (int q = 0; q < kNumCounters; ++q) cnt.v[q] = 0u;
-  const uint32_t n0 = a.surr_queue_count[0], n1 = a.surr_queue_count[1];
-  const uint32_t n_chunks = (n0 + 63u) / 64u + (n1 + 63u) / 64u;
+  const QueueMap Q = queue_map(a);
+  const uint32_t n_chunks = Q.c0 + Q.c1;
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks;
        c += waves) {
     bool act;
-    const uint32_t idx = queue_entry(a, c, n0, n1, &act);
+    const uint64_t idx = queue_entry(a, Q, c, &act);
     const uint2 e = act ? a.surr_queue[idx] : make_uint2(0u, 0u);
     LaneIdx I;
     I.active = act;

@@ -5,15 +5,16 @@
 // 32 -> 64 -> 64 -> 4 ReLU network of Fourier features of UV may replace the
 // deepest cacheable sub-graphs of a material on a cache miss.
 //
-// Matrix-core mapping (gfx950, wave64, v_mfma_f32_16x16x16_f16).  For a 16x16
-// tile with K = 16 the operand layouts are
+// Matrix-core mapping (gfx950, wave64).  For a 16x16 tile with K = 16
+// (v_mfma_f32_16x16x16_f16) the operand layouts are
 //   A[i][k]: lane i + 16 (k / 4), element k % 4
 //   B[k][j]: lane j + 16 (k / 4), element k % 4
 //   D[i][j]: lane j + 16 (i / 4), element i % 4
 // so D of one product is, lane for lane, the B operand of the next one when
 // the samples run along j.  Every layer is therefore computed transposed,
-// H^T = W X^T: weights are the A operand (read straight from memory, 8 bytes
-// per lane), activations stay in registers from layer to layer.
+// H^T = W X^T: weights are the A operand, activations stay in registers from
+// layer to layer.  Inference uses the K = 32 product (NetRegs below); training
+// keeps the K = 16 one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -75,58 +76,95 @@ __device__ __forceinline__ h4 fourier4(float u, float v, int q) {
   return r;
 }
 
-// relu(acc + b) rounded to binary16 (round to nearest even)
-__device__ __forceinline__ h4 relu_h4(f4 acc, const float* b) {
-  h4 r;
-  r.x = (_Float16)fmaxf(acc.x + b[0], 0.0f);
-  r.y = (_Float16)fmaxf(acc.y + b[1], 0.0f);
-  r.z = (_Float16)fmaxf(acc.z + b[2], 0.0f);
-  r.w = (_Float16)fmaxf(acc.w + b[3], 0.0f);
-  return r;
+// One network held in the registers of a wave (loaded once, used for many
+// 16-point tiles), for v_mfma_f32_16x16x32_f16.  A K = 32 product pairs two
+// 16-row blocks of its input: lane group g = lane / 16 supplies, as its 8 K
+// elements, rows 4g .. 4g+3 of the first block and rows 4g .. 4g+3 of the
+// second, which is exactly what the D layout of the previous product leaves in
+// its registers.  The weights are loaded with the same pairing, and since the
+// A and B operands of a product index K the same way, each product still sums
+// over all 32 rows.  Per tile: 4 products for layer 1, 8 for layer 2, 2 for
+// layer 3.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma32(h8 a, h8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ h8 cat8(h4 lo, h4 hi) {
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+struct NetRegs {
+  h8 w1[4];        // layer 1, M tile m: W1[16m + j][4g .. 4g+3 | 16 + 4g .. 16 + 4g+3]
+  h8 w2[4][2];     // layer 2, M tile m, K step t: input blocks 2t and 2t+1
+  h8 w3[2];        // layer 3 (rows 4..15 zero), K step t
+  f4 b1[4], b2[4]; // biases of rows 16m + 4g .. 16m + 4g+3
+  float b3[4];
+};
+
+__device__ __forceinline__ h8 load_pair(const _Float16* row, int b0, int b1, int g) {
+  return cat8(*reinterpret_cast<const h4*>(row + 16 * b0 + 4 * g),
+              *reinterpret_cast<const h4*>(row + 16 * b1 + 4 * g));
+}
+
+__device__ __forceinline__ void load_net(const SurrW* __restrict__ W, NetRegs& N) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int j = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    N.w1[m] = load_pair(W->w1 + (16 * m + j) * 32, 0, 1, g);
+    N.w2[m][0] = load_pair(W->w2 + (16 * m + j) * 64, 0, 1, g);
+    N.w2[m][1] = load_pair(W->w2 + (16 * m + j) * 64, 2, 3, g);
+    N.b1[m] = *reinterpret_cast<const f4*>(W->b1 + 16 * m + 4 * g);
+    N.b2[m] = *reinterpret_cast<const f4*>(W->b2 + 16 * m + 4 * g);
+  }
+  N.w3[0] = load_pair(W->w3 + j * 64, 0, 1, g);
+  N.w3[1] = load_pair(W->w3 + j * 64, 2, 3, g);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) N.b3[c] = W->b3[c];
+}
+
+// relu(acc) rounded to binary16 (round to nearest even).  Rounding is
+// monotone and keeps zero, so the ReLU is taken after the rounding, on packed
+// halves (a negative input may become -0, which adds nothing to the products).
+__device__ __forceinline__ h4 relu_h4(f4 acc) {
+  const h4 r = __builtin_convertvector(acc, h4);
+  const h4 z = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
+  return __builtin_elementwise_max(r, z);
+}
+
+// The network at 16 points: lane (j, g) gives the coordinates of point j; lanes
+// 0..15 receive their point's 4 outputs (rows 0..3 of the output tile).
+__device__ __forceinline__ f4 net_tile(const NetRegs& N, float un, float vn) {
+  const int g = (int)((threadIdx.x & 63u) >> 4);
+  const h8 x = cat8(fourier4(un, vn, g), fourier4(un, vn, 4 + g));
+  // the biases start the accumulators (the D layout of row i is that of bias i)
+  h4 H1[4], H2[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) H1[m] = relu_h4(mfma32(N.w1[m], x, N.b1[m]));
+  const h8 p0 = cat8(H1[0], H1[1]), p1 = cat8(H1[2], H1[3]);
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    H2[m] = relu_h4(mfma32(N.w2[m][1], p1, mfma32(N.w2[m][0], p0, N.b2[m])));
+  const f4 b3 = {N.b3[0], N.b3[1], N.b3[2], N.b3[3]};
+  return mfma32(N.w3[1], cat8(H2[2], H2[3]), mfma32(N.w3[0], cat8(H2[0], H2[1]), b3));
 }
 
 // The network at 64 points, one per lane (all 64 lanes must be active): lane l
-// gives (u, v) and receives y[0..3] of its own point.  112 matrix products.
-// The four 16-point tiles are done one after another so few registers are
-// live (the weights are re-read per tile, from the first-level cache).
-__device__ __forceinline__ void mlp_wave(const SurrW* __restrict__ W, float u, float v,
-                                         float y[4]) {
+// gives (u, v) and receives y[0..3] of its own point.
+__device__ __forceinline__ void net_wave(const NetRegs& N, float u, float v, float y[4]) {
   const int lane = (int)(threadIdx.x & 63u);
   const int j = lane & 15, g = lane >> 4;
   y[0] = y[1] = y[2] = y[3] = 0.0f;
 #pragma unroll 1
   for (int n = 0; n < 4; ++n) {
-    // layer-1 B operands: features of point 16 n + j, feature rows 16 t + 4 g ..
     const float un = __shfl(u, 16 * n + j, 64), vn = __shfl(v, 16 * n + j, 64);
-    const h4 x0 = fourier4(un, vn, g);
-    const h4 x1 = fourier4(un, vn, 4 + g);
-    h4 H1[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const h4 a0 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 4 * g);
-      const h4 a1 = *reinterpret_cast<const h4*>(W->w1 + (16 * m + j) * 32 + 16 + 4 * g);
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mfma16(a0, x0, acc);
-      acc = mfma16(a1, x1, acc);
-      H1[m] = relu_h4(acc, W->b1 + 16 * m + 4 * g);
-    }
-    // layer 2, and layer 3 accumulated tile by tile (K tile m of layer 3 = M tile m of layer 2)
-    f4 Y = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        acc = mfma16(*reinterpret_cast<const h4*>(W->w2 + (16 * m + j) * 64 + 16 * t + 4 * g),
-                     H1[t], acc);
-      const h4 h2 = relu_h4(acc, W->b2 + 16 * m + 4 * g);
-      Y = mfma16(*reinterpret_cast<const h4*>(W->w3 + j * 64 + 16 * m + 4 * g), h2, Y);
-    }
-    // point 16 n + j's outputs are rows 0..3 of the tile, held by lane j
+    const f4 Y = net_tile(N, un, vn);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const float t = __shfl(Y[c], j, 64);
-      y[c] = (g == n) ? t + W->b3[c] : y[c];
+      y[c] = (g == n) ? t : y[c];
     }
   }
 }

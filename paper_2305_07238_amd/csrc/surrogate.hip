@@ -528,12 +528,14 @@ __global__ __launch_bounds__(256) void k_surr_probe(const pmc_log_record* rec,
   }
   const pmc_log_record* base = rec + slot_begin[slot] + n_train;
   float emax = 0.0f, esum = 0.0f, ecnt = 0.0f;
+  NetRegs N;
+  load_net(w + slot, N);
   for (uint32_t c = (uint32_t)wave; c * 64u < held; c += 4u) {
     const uint32_t i = c * 64u + (uint32_t)lane;
     const bool valid = i < held;
     const pmc_log_record R = load_record(base + (valid ? i : 0u));
     float y[4];
-    mlp_wave(w + slot, R.u, R.v, y);
+    net_wave(N, R.u, R.v, y);
     float tg[4], mk[4];
     record_target(R, st, tg, mk);
 #pragma unroll
@@ -579,24 +581,41 @@ hipError_t launch_surr_probe(const pmc_log_record* rec, const uint32_t* slot_beg
   return hipGetLastError();
 }
 
-// Network outputs at n points: one wave per 64 points.
+// Network outputs at n points: a grid of waves, each holding the network in
+// its registers and striding over 16-point tiles.
+constexpr uint32_t kInferMaxBlocks = 1024;
+
 __global__ __launch_bounds__(256) void k_surr_infer(const SurrW* w, const float* uv, uint32_t n,
                                                     float* y) {
-  const uint32_t chunk = blockIdx.x * 4u + (threadIdx.x >> 6);
-  if (chunk * 64u >= n) return;                      // whole waves only
-  const uint32_t i = chunk * 64u + (threadIdx.x & 63u);
-  const bool valid = i < n;
-  float2 p = valid ? reinterpret_cast<const float2*>(uv)[i] : make_float2(0.f, 0.f);
-  float r[4];
-  mlp_wave(w, p.x, p.y, r);
-  if (valid) reinterpret_cast<float4*>(y)[i] = make_float4(r[0], r[1], r[2], r[3]);
+  const uint32_t tiles = (n + 15u) / 16u;
+  const uint32_t waves = gridDim.x * 4u;
+  uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (t >= tiles) return;                            // whole waves only
+  NetRegs N;
+  load_net(w, N);
+  const uint32_t j = threadIdx.x & 15u;
+  const bool lead = (threadIdx.x & 63u) < 16u;
+  const float2* uv2 = reinterpret_cast<const float2*>(uv);
+  uint32_t i = t * 16u + j;
+  float2 p = i < n ? uv2[i] : make_float2(0.f, 0.f);
+#pragma unroll 1
+  for (; t < tiles; t += waves) {
+    // the next tile's coordinates load while this tile is computed
+    const uint32_t i_next = (t + waves) * 16u + j;
+    const float2 p_next = (t + waves < tiles && i_next < n) ? uv2[i_next] : make_float2(0.f, 0.f);
+    const f4 Y = net_tile(N, p.x, p.y);
+    if (lead && i < n) reinterpret_cast<float4*>(y)[i] = make_float4(Y.x, Y.y, Y.z, Y.w);
+    i = i_next;
+    p = p_next;
+  }
 }
 
 hipError_t launch_surr_infer(const SurrW* w, const float* uv, uint32_t n, float* y,
                              hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const uint32_t waves = (n + 63u) / 64u;
-  hipLaunchKernelGGL(k_surr_infer, dim3((waves + 3u) / 4u), dim3(256), 0, s, w, uv, n, y);
+  const uint32_t tiles = (n + 15u) / 16u;
+  const uint32_t blocks = min((tiles + 3u) / 4u, kInferMaxBlocks);
+  hipLaunchKernelGGL(k_surr_infer, dim3(blocks), dim3(256), 0, s, w, uv, n, y);
   return hipGetLastError();
 }
 
