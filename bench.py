@@ -62,6 +62,18 @@ def measured_traffic(workload_name, best):
     return rec["traffic_bytes_per_launch"]
 
 
+def shade_kernel_name(mode, flags):
+    """Name of the shade kernel a timed step launches (template arguments: mode,
+    kind (1 = probe first with deferral), counters, networks)."""
+    from paper_2305_07238_amd import binding as B
+    m = {"uncached": 0, "cached": 1, "snapshot": 2}[mode]
+    kind = 1 if (m != 0 and flags & B.PMC_FLAG_DEFER) else 0
+    base = "k_shade_persistent" if flags & B.PMC_FLAG_PERSISTENT else "k_shade_flat"
+    if m != 0:
+        base += "_w4"
+    return "%s<%d, %d, false, false>" % (base, m, kind)
+
+
 def scenes_concat(sc):
     from paper_2305_07238_amd import scenes
     return scenes.Hits.concat([sc.frame(f) for f in range(sc.frames)])
@@ -446,8 +458,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, best),
-                     "kernel": ("k_shade_persistent" if best["flags"] & B.PMC_FLAG_PERSISTENT
-                                else "k_shade_flat") + "<mode>",
+                     "kernel": shade_kernel_name(args.mode, best["flags"]),
                      "bytes_per_launch": kb / sc.frames,
                      "avg_launch_ms": shade_ms / max(shade_launches, 1)},
     }

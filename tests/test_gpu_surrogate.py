@@ -188,11 +188,18 @@ def _outputs_with(sc, h, state, value):
     return out
 
 
-@pytest.mark.parametrize("flags,max_err", [(B.PMC_FLAG_SORT, 1e-2),
-                                           (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, 1e6),
-                                           (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER |
-                                            B.PMC_FLAG_SURROGATE_INSERT, 1e6)])
-def test_snapshot_with_trusted_networks_matches_reference(flags, max_err):
+@pytest.mark.parametrize("flags,max_err,launch", [
+    (B.PMC_FLAG_SORT, 1e-2, {}),
+    (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, 1e6, {}),
+    (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER | B.PMC_FLAG_SURROGATE_INSERT, 1e6, {}),
+    # runs of 3 chunks dealt out by a persistent grid of 2 blocks per CU: every
+    # queue region collects hits of many runs, from several waves
+    (B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER | B.PMC_FLAG_PERSISTENT, 1e6,
+     dict(chunk_waves=3, blocks_per_cu=2)),
+    # unsorted, one chunk per run, every chunk evaluated in place
+    (0, 1e6, dict(chunk_waves=1)),
+])
+def test_snapshot_with_trusted_networks_matches_reference(flags, max_err, launch):
     """Snapshot mode is deterministic, so which outputs the networks replace
     (missed, not bypassed, not audited) is exact; the replaced values match the
     reference network; every output downstream matches the FP64 graph with the
@@ -215,7 +222,7 @@ def test_snapshot_with_trusted_networks_matches_reference(flags, max_err):
         h = sc.frame(f).take(np.arange(0, 115200, 2))
         out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
                                         flags=flags | B.PMC_FLAG_SURROGATE | B.PMC_FLAG_LOG,
-                                        debug=True)
+                                        debug=True, **launch)
         ref = render.shade_snapshot_frame(
             sc.materials, sc.textures, h, ref_t, f, surrogate=sinfo, surrogate_values=value,
             surrogate_insert=bool(flags & B.PMC_FLAG_SURROGATE_INSERT))
