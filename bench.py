@@ -321,7 +321,7 @@ def main():
                     help="only run a plain 1 GiB device copy 3 times (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         raise SystemExit(2)
 

@@ -47,7 +47,7 @@ enum {
     PMC_ERR_GRAPH = -2,        /* invalid material network (type, cycle, link) */
     PMC_ERR_OOM = -3,          /* device or host allocation failed */
     PMC_ERR_HIP = -4,          /* a HIP runtime call failed; message has hipGetErrorString */
-    PMC_ERR_UNSUPPORTED = -5,  /* valid request this build cannot serve */
+    PMC_ERR_UNSUPPORTED = -5,  /* valid request the library cannot serve */
     PMC_ERR_STATE = -6         /* call order (e.g. shading before compiling) */
 };
 
