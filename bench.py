@@ -387,6 +387,7 @@ def main():
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / args.steps
     log(f"{ms_step:.3f} ms/step (graph replay)")
+    graph.close()
 
     # the same work launched per frame with HIP-event phase timing on the stream
     def step(m=mode, stats=None, kw=best):
@@ -428,6 +429,7 @@ def main():
         torch.cuda.synchronize()
         unc = ev0.elapsed_time(ev1) / args.uncached_steps
         log(f"uncached {unc:.3f} ms/step")
+        g_u.close()
 
     value = n_step / (ms_step * 1e-3)
     res = {

@@ -122,7 +122,9 @@ typedef struct pmc_material_info {
  * device == -1 (compile and inspect graphs only; every device call then
  * returns PMC_ERR_STATE).  *out receives the context. */
 pmc_status pmc_create(int device, pmc_ctx** out);
-/* Destroy a context and everything it owns.  NULL is accepted. */
+/* Destroy a context and everything it owns.  NULL is accepted.  While frame
+ * graphs of the context exist, the context is only marked and is released with
+ * the last of them. */
 void pmc_destroy(pmc_ctx* ctx);
 /* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
 const char* pmc_last_error(const pmc_ctx* ctx);
@@ -135,7 +137,8 @@ uint32_t pmc_abi_version(void);
 size_t pmc_abi_sizeof(uint32_t which);
 
 /* Upload textures (copied into library-owned device memory; synchronous).
- * Replaces any previous set.  Graphs refer to textures by index. */
+ * Replaces any previous set.  Graphs refer to textures by index.
+ * PMC_ERR_STATE while frame graphs of the context exist. */
 pmc_status pmc_set_textures(pmc_ctx* ctx, const pmc_texture_desc* tex, uint32_t n_tex);
 
 /* Compile a graph set (Sec. 2 stack-machine form; Sec. 3 cacheable marking).
@@ -145,7 +148,9 @@ pmc_status pmc_set_textures(pmc_ctx* ctx, const pmc_texture_desc* tex, uint32_t 
  * (PMC_ERR_GRAPH, message names material and node), folds constant MATH /
  * MIX / COLOR_RAMP nodes, marks cacheable outputs, computes the need masks
  * and registers and, on a device context, uploads the program
- * (synchronous).  Replaces any previous graph set.  opts may be NULL. */
+ * (synchronous).  Replaces any previous graph set.  opts may be NULL.
+ * PMC_ERR_STATE while frame graphs of the context exist (they replay the
+ * current program). */
 pmc_status pmc_compile_materials(pmc_ctx* ctx, const pmc_node_desc* nodes,
                                  const uint32_t* node_offsets, uint32_t n_mats,
                                  const pmc_compile_opts* opts);
@@ -177,7 +182,9 @@ typedef struct pmc_cache_params {
 pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* params, void* device_mem,
                             pmc_cache** out);
 /* Destroy the handle (and the table if library-allocated).  NULL accepted.
- * Destroy every cache of a context before the context itself. */
+ * Destroy every cache of a context before the context itself.  While frame
+ * graphs replay into the table, it is only marked and is released with the
+ * last of them. */
 void pmc_cache_destroy(pmc_cache* cache);
 /* Empty every entry (asynchronous on stream; a fill kernel, no memset node). */
 pmc_status pmc_cache_clear(pmc_cache* cache, void* stream);
@@ -330,12 +337,18 @@ typedef struct pmc_frame_graph pmc_frame_graph;   /* opaque */
 /* Capture the whole plan (table clear, then per frame: material sort, shade,
  * snapshot apply, statistics) into one HIP graph.  All device workspace is
  * reserved before capture; launches allocate nothing.  The plan's pointers are
- * baked into the graph and must stay valid while it is used.  Synchronous. */
+ * baked into the graph and must stay valid while it is used.  Synchronous.
+ * Until the graph is destroyed, the context keeps what it bakes in: compiling,
+ * setting textures and surrogate setup return PMC_ERR_STATE, and so does a
+ * shading call that would have to replace a workspace buffer (a larger batch
+ * than any reserved so far); destroying the context or the table is deferred
+ * to the graph's destruction. */
 pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* plan,
                                   pmc_frame_graph** out);
 /* Replay the captured frames on `stream` (asynchronous). */
 pmc_status pmc_frame_graph_launch(pmc_frame_graph* graph, void* stream);
-/* Release the graph.  NULL accepted. */
+/* Release the graph (waits for the device to finish its replays).  NULL
+ * accepted. */
 void pmc_frame_graph_destroy(pmc_frame_graph* graph);
 
 /* Launch-parameter search.  Shades the plan's frames (without capture) under
@@ -396,7 +409,8 @@ typedef struct pmc_surrogate_opts {
 /* Choose the surrogated outputs of the compiled materials, create one slot per
  * material that has any, initialise their weights, and allocate the insert
  * log (device contexts).  Replaces an earlier setup.  Host-only contexts get
- * the slot table only.  *n_slots receives the slot count.  Synchronous. */
+ * the slot table only.  *n_slots receives the slot count.  Synchronous.
+ * PMC_ERR_STATE while frame graphs of the context exist. */
 pmc_status pmc_surrogate_setup(pmc_ctx* ctx, const pmc_surrogate_opts* opts, uint32_t* n_slots);
 
 typedef struct pmc_surrogate_slot {

@@ -41,6 +41,11 @@ pmc_status ensure(pmc_ctx* ctx, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return PMC_OK;
   if (ctx->no_alloc)
     return ctx->fail(PMC_ERR_STATE, "workspace of %zu bytes not reserved before capture", bytes);
+  if (b.p && ctx->live_graphs)
+    return ctx->fail(PMC_ERR_STATE,
+                     "a buffer of %zu bytes would replace one that %u frame graph(s) may use; "
+                     "destroy them first or create them for the larger batch",
+                     bytes, ctx->live_graphs);
   free_buf(b);
   if (bytes == 0) bytes = 256;
   hipError_t e = hipMalloc(&b.p, bytes);
@@ -56,6 +61,40 @@ pmc_status ensure(pmc_ctx* ctx, DevBuf& b, size_t bytes) {
 pmc_status need_device(pmc_ctx* ctx) {
   if (ctx->host_only) return ctx->fail(PMC_ERR_STATE, "host-only context has no device");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return PMC_OK;
+}
+
+void destroy_context(pmc_ctx* ctx) {
+  if (!ctx->host_only) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->lpt_rank,
+                      &ctx->sort_counts, &ctx->sort_offsets, &ctx->sort_sums, &ctx->texels,
+                      &ctx->texdesc, &ctx->perm, &ctx->misc,
+                      &ctx->cand, &ctx->stat_slots, &ctx->surr_queue, &ctx->surr_val,
+                      &ctx->surr.w, &ctx->surr.master,
+                      &ctx->surr.state, &ctx->surr.mat_slot_dev, &ctx->surr.log,
+                      &ctx->surr.log_count, &ctx->surr.slot_count, &ctx->surr.slot_begin,
+                      &ctx->surr.slot_cursor, &ctx->surr.scan_sums, &ctx->surr.grouped})
+      free_buf(*b);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+}
+
+void destroy_cache(pmc_cache* c) {
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->owned && c->mem) (void)hipFree(c->mem);
+  for (DevBuf* b : {&c->cell_count, &c->cell_start, &c->cell_cursor, &c->block_sums, &c->sorted})
+    free_buf(*b);
+  delete c;
+}
+
+pmc_status no_live_graphs(pmc_ctx* ctx, const char* what) {
+  if (ctx->live_graphs)
+    return ctx->fail(PMC_ERR_STATE, "%s: %u frame graph(s) use the current program and buffers",
+                     what, ctx->live_graphs);
   return PMC_OK;
 }
 
@@ -150,21 +189,11 @@ pmc_status pmc_create(int device, pmc_ctx** out) {
 
 void pmc_destroy(pmc_ctx* ctx) {
   if (!ctx) return;
-  if (!ctx->host_only) {
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->lpt_rank,
-                      &ctx->sort_counts, &ctx->sort_offsets, &ctx->sort_sums, &ctx->texels,
-                      &ctx->texdesc, &ctx->perm, &ctx->misc,
-                      &ctx->cand, &ctx->stat_slots, &ctx->surr_queue, &ctx->surr_val,
-                      &ctx->surr.w, &ctx->surr.master,
-                      &ctx->surr.state, &ctx->surr.mat_slot_dev, &ctx->surr.log,
-                      &ctx->surr.log_count, &ctx->surr.slot_count, &ctx->surr.slot_begin,
-                      &ctx->surr.slot_cursor, &ctx->surr.scan_sums, &ctx->surr.grouped})
-      free_buf(*b);
-    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->live_graphs) {
+    ctx->orphaned = true;
+    return;
   }
-  delete ctx;
+  destroy_context(ctx);
 }
 
 pmc_status pmc_profile_enable(pmc_ctx* ctx, int on) {
@@ -199,6 +228,7 @@ const char* pmc_last_error(const pmc_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 pmc_status pmc_set_textures(pmc_ctx* ctx, const pmc_texture_desc* tex, uint32_t n_tex) {
   if (!ctx) return PMC_ERR_INVALID;
+  if (pmc_status st = no_live_graphs(ctx, "set_textures")) return st;
   if (n_tex && !tex) return ctx->fail(PMC_ERR_INVALID, "set_textures: null texture array");
   if (pmc_status st = need_device(ctx)) return st;
   std::vector<TexDesc> desc(n_tex);
@@ -225,6 +255,7 @@ pmc_status pmc_compile_materials(pmc_ctx* ctx, const pmc_node_desc* nodes,
                                  const uint32_t* node_offsets, uint32_t n_mats,
                                  const pmc_compile_opts* opts) {
   if (!ctx) return PMC_ERR_INVALID;
+  if (pmc_status st = no_live_graphs(ctx, "compile_materials")) return st;
   Program prog;
   std::string err;
   pmc_status st = compile_program(nodes, node_offsets, n_mats, opts, prog, err);
@@ -307,12 +338,11 @@ pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* p, void* devic
 
 void pmc_cache_destroy(pmc_cache* c) {
   if (!c) return;
-  (void)hipSetDevice(c->device);
-  (void)hipDeviceSynchronize();
-  if (c->owned && c->mem) (void)hipFree(c->mem);
-  for (DevBuf* b : {&c->cell_count, &c->cell_start, &c->cell_cursor, &c->block_sums, &c->sorted})
-    free_buf(*b);
-  delete c;
+  if (c->live_graphs) {
+    c->orphaned = true;
+    return;
+  }
+  destroy_cache(c);
 }
 
 pmc_status pmc_cache_clear(pmc_cache* c, void* stream) {

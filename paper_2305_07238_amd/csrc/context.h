@@ -48,6 +48,11 @@ struct pmc_ctx {
   DevBuf sort_counts, sort_offsets, sort_sums;   // tiled material sort
   SurrHost surr;
   bool no_alloc = false;       // set while a frame graph is captured
+  // Frame graphs bake this context's buffers and program into their launches:
+  // while any exists, nothing they use may move or change shape, and
+  // pmc_destroy only marks the context (freed with its last graph).
+  uint32_t live_graphs = 0;
+  bool orphaned = false;
   // phase timing: events recorded in pairs per phase
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -72,6 +77,8 @@ struct pmc_cache {
   bool owned = false;
   size_t bytes = 0;
   DevBuf cell_count, cell_start, cell_cursor, block_sums, sorted;
+  uint32_t live_graphs = 0;      // frame graphs replaying into this table
+  bool orphaned = false;         // pmc_cache_destroy called while graphs live
 };
 
 #define HIP_TRY(ctx, call)                                                              \
@@ -84,8 +91,15 @@ struct pmc_cache {
 namespace pmc {
 
 void free_buf(DevBuf& b);
+// Release a context or a table now (pmc_destroy / pmc_cache_destroy defer to
+// these until no frame graph uses the object).
+void destroy_context(pmc_ctx* ctx);
+void destroy_cache(pmc_cache* c);
+// PMC_ERR_STATE while frame graphs use the context's program or buffers.
+pmc_status no_live_graphs(pmc_ctx* ctx, const char* what);
 // grow-only device buffer; contents are not preserved.  Fails with
-// PMC_ERR_STATE when it would allocate while ctx->no_alloc is set.
+// PMC_ERR_STATE when it would allocate while ctx->no_alloc is set, or replace
+// an existing buffer while frame graphs may use it.
 pmc_status ensure(pmc_ctx* ctx, DevBuf& b, size_t bytes);
 pmc_status need_device(pmc_ctx* ctx);
 hipEvent_t next_event(pmc_ctx* ctx);

@@ -17,7 +17,9 @@ using namespace pmc;
 
 struct pmc_frame_graph {
   pmc_ctx* ctx = nullptr;
+  pmc_cache* cache = nullptr;    // the table it replays into (NULL: uncached)
   int device = 0;
+  bool counted = false;          // registered with ctx (and cache)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -124,6 +126,12 @@ pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_fram
     pmc_frame_graph_destroy(g);
     return st;
   }
+  g->counted = true;
+  ++ctx->live_graphs;
+  if (cache) {
+    g->cache = cache;
+    ++cache->live_graphs;
+  }
   *out = g;
   return PMC_OK;
 }
@@ -139,8 +147,17 @@ pmc_status pmc_frame_graph_launch(pmc_frame_graph* g, void* stream) {
 void pmc_frame_graph_destroy(pmc_frame_graph* g) {
   if (!g) return;
   (void)hipSetDevice(g->device);
-  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->exec) {
+    (void)hipDeviceSynchronize();                 // no replay may still be running
+    (void)hipGraphExecDestroy(g->exec);
+  }
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->counted) {
+    pmc_cache* c = g->cache;
+    if (c && --c->live_graphs == 0 && c->orphaned) destroy_cache(c);
+    pmc_ctx* ctx = g->ctx;
+    if (--ctx->live_graphs == 0 && ctx->orphaned) destroy_context(ctx);
+  }
   delete g;
 }
 

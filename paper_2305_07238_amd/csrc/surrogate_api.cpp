@@ -78,6 +78,7 @@ extern "C" {
 
 pmc_status pmc_surrogate_setup(pmc_ctx* ctx, const pmc_surrogate_opts* opts, uint32_t* n_slots) {
   if (!ctx) return PMC_ERR_INVALID;
+  if (pmc_status st = no_live_graphs(ctx, "surrogate_setup")) return st;
   if (!ctx->compiled) return ctx->fail(PMC_ERR_STATE, "no compiled graph set");
   pmc_surrogate_opts o{};
   if (opts) o = *opts;

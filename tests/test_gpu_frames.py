@@ -116,3 +116,46 @@ def test_autotune_picks_a_valid_setting(tmp_path):
     assert np.array_equal(cache.export(), cache2.export())
     for k in out:
         assert torch.equal(out[k], out2[k])
+
+
+def test_frame_graph_keeps_what_it_uses():
+    """While a graph exists the context refuses to change what the graph replays
+    (program, textures, surrogate slots) or to replace a workspace buffer (a batch
+    larger than any reserved); destroying the table it replays into is deferred,
+    so a later replay still gives the same results; destroying the graph lifts
+    both."""
+    sc = G.small_mid_scene(frames=2)
+    ctx = G.setup(sc)
+    n, F = sc.hits_per_frame, 2
+    hits = _frames_on_device(sc, F)
+    out = B.alloc_outputs(n)
+    cache = ctx.cache(1 << 13)
+    graph = ctx.frame_graph(cache, ctx.frame_plan(hits, n, F, out, mode=B.PMC_MODE_SNAPSHOT,
+                                                  clear_cache=True))
+    graph.launch()
+    torch.cuda.synchronize()
+    first = G.to_numpy(out)
+    for call in (lambda: ctx.compile(sc.materials), lambda: ctx.set_textures(sc.textures),
+                 lambda: ctx.surrogate_setup(seed=0)):
+        with pytest.raises(B.PmcError) as e:
+            call()
+        assert e.value.code == B.PMC_ERR_STATE
+    out_big = B.alloc_outputs(n * F)
+    with pytest.raises(B.PmcError) as e:
+        ctx.shade(hits, out_big, cache, mode=B.PMC_MODE_SNAPSHOT)
+    assert e.value.code == B.PMC_ERR_STATE
+    # within the reservation, eager calls still run
+    ctx.shade(_slice(hits, 0, n), _slice(out_big, 0, n), None, mode=B.PMC_MODE_UNCACHED)
+    torch.cuda.synchronize()
+    cache.close()
+    for v in out.values():
+        v.fill_(-1.0)
+    graph.launch()
+    torch.cuda.synchronize()
+    got = G.to_numpy(out)
+    for k in first:
+        assert np.array_equal(got[k], first[k]), k
+    graph.close()
+    ctx.compile(sc.materials)
+    ctx.shade(hits, out_big, None, mode=B.PMC_MODE_UNCACHED)
+    torch.cuda.synchronize()
