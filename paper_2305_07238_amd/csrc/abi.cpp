@@ -70,7 +70,7 @@ void destroy_context(pmc_ctx* ctx) {
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&ctx->hdr, &ctx->instr, &ctx->cach, &ctx->pool, &ctx->lpt, &ctx->lpt_rank,
                       &ctx->sort_counts, &ctx->sort_offsets, &ctx->sort_sums, &ctx->texels,
-                      &ctx->texdesc, &ctx->perm, &ctx->misc,
+                      &ctx->texdesc, &ctx->perm, &ctx->perm2, &ctx->misc,
                       &ctx->cand, &ctx->stat_slots, &ctx->surr_queue, &ctx->surr_val,
                       &ctx->surr.w, &ctx->surr.master,
                       &ctx->surr.state, &ctx->surr.mat_slot_dev, &ctx->surr.log,
@@ -102,8 +102,9 @@ pmc_status no_live_graphs(pmc_ctx* ctx, const char* what) {
 
 namespace {
 
-// Small per-context device words: [1] the snapshot candidate count,
-// [kMiscQueue, kMiscQueue + 2 kQueueRegions) the surrogate queue's counters.
+// Small per-context device words, kWorkSets sets of kMiscWords: [1] the snapshot
+// candidate count, [kMiscQueue, kMiscQueue + 2 kQueueRegions) the surrogate
+// queue's counters.
 constexpr uint32_t kMiscQueue = 64, kMiscWords = 256;
 static_assert(kMiscQueue + 2 * kQueueRegions <= kMiscWords, "misc words");
 
@@ -172,7 +173,7 @@ pmc_status pmc_create(int device, pmc_ctx** out) {
     }
     ctx->num_cus = prop.multiProcessorCount;
     if (ensure(ctx, ctx->stat_slots, sizeof(unsigned long long) * kStatSlots * kStatStride) ||
-        ensure(ctx, ctx->misc, kMiscWords * 4) ||
+        ensure(ctx, ctx->misc, kWorkSets * kMiscWords * 4) ||
         hipMemset(ctx->stat_slots.p, 0, ctx->stat_slots.bytes) != hipSuccess ||
         hipMemset(ctx->misc.p, 0, ctx->misc.bytes) != hipSuccess ||
         prepare_sort_kernels() != hipSuccess || prepare_surrogate_kernels() != hipSuccess) {
@@ -446,7 +447,7 @@ pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits
 }
 
 pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mode,
-                         uint32_t flags, uint32_t chunk_waves, hipStream_t s) {
+                         uint32_t flags, uint32_t chunk_waves, bool all_sets, hipStream_t s) {
   const uint32_t n_mats = (uint32_t)ctx->prog.headers.size();
   pmc_status st;
   if (flags & PMC_FLAG_SORT) {
@@ -454,6 +455,7 @@ pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mo
       return ctx->fail(PMC_ERR_UNSUPPORTED, "material sort handles at most 16383 materials");
     const size_t cells = (size_t)(n_mats + 1) * sort_tiles(n);
     if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
+        (all_sets && (st = ensure(ctx, ctx->perm2, (size_t)n * 4 * (kWorkSets - 1)))) ||
         (st = ensure(ctx, ctx->sort_counts, cells * 4)) ||
         (st = ensure(ctx, ctx->sort_offsets, cells * 4)) ||
         (st = ensure(ctx, ctx->sort_sums, ((size_t)scan_blocks((uint32_t)cells) + 1) * 4)))
@@ -484,19 +486,72 @@ pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mo
   return PMC_OK;
 }
 
+namespace {
+
+uint32_t batch_mode(const pmc_shade_params* params, const pmc_cache* cache) {
+  return cache ? params->mode : (uint32_t)PMC_MODE_UNCACHED;
+}
+
+bool batch_surr(const pmc_shade_params* params, uint32_t mode) {
+  return (params->flags & PMC_FLAG_SURROGATE) && mode != PMC_MODE_UNCACHED;
+}
+
+uint32_t* misc_set(pmc_ctx* ctx, int set) { return (uint32_t*)ctx->misc.p + set * kMiscWords; }
+
+// set k > 0 of a batch of n hits: entries [(k - 1) n, k n) of perm2
+uint32_t* perm_set(pmc_ctx* ctx, int set, uint32_t n) {
+  return set ? (uint32_t*)ctx->perm2.p + (size_t)(set - 1) * n : (uint32_t*)ctx->perm.p;
+}
+
+}  // namespace
+
+pmc_status sort_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                      const pmc_shade_params* params, int set, hipStream_t s) {
+  const uint32_t n = (uint32_t)hits->n;
+  if (n == 0) return PMC_OK;
+  const uint32_t mode = batch_mode(params, cache);
+  uint32_t* misc = misc_set(ctx, set);
+  // misc[1]: snapshot candidate count; misc[kMiscQueue ..]: the queue's region
+  // counters (reset by the sort's scan, or filled here)
+  const uint32_t n_reset = batch_surr(params, mode) ? kMiscQueue + 2u * kQueueRegions : 4u;
+  if (params->flags & PMC_FLAG_SORT) {
+    PhaseTimer t0(ctx, 0, s);
+    HIP_TRY(ctx, launch_material_sort_tiled(
+                     hits->material, n, (uint32_t)ctx->prog.headers.size(),
+                     (const uint32_t*)ctx->lpt_rank.p, (uint32_t*)ctx->sort_counts.p,
+                     (uint32_t*)ctx->sort_offsets.p, (uint32_t*)ctx->sort_sums.p,
+                     perm_set(ctx, set, n), misc, n_reset, s));
+    t0.finish();
+  } else {
+    HIP_TRY(ctx, launch_fill_u32(misc, 0u, n_reset, s));
+  }
+  return PMC_OK;
+}
+
 pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                        const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
                        const pmc_debug_out* dbg, hipStream_t s) {
   const uint32_t n = (uint32_t)hits->n;
   if (n == 0) return PMC_OK;
-  uint32_t mode = params->mode;
-  if (!cache) mode = PMC_MODE_UNCACHED;
+  const uint32_t mode = batch_mode(params, cache);
+  const bool probe_first = mode != PMC_MODE_UNCACHED && (params->flags & PMC_FLAG_DEFER);
+  const uint32_t chunk_waves = resolve_chunk_waves(params->chunk_waves, probe_first);
+  if (pmc_status st = reserve_batch(ctx, cache, n, mode, params->flags, chunk_waves, false, s))
+    return st;
+  if (pmc_status st = sort_stage(ctx, cache, hits, params, 0, s)) return st;
+  return shade_stage(ctx, cache, hits, out, params, stats, dbg, 0, s);
+}
+
+pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                       const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
+                       const pmc_debug_out* dbg, int set, hipStream_t s) {
+  const uint32_t n = (uint32_t)hits->n;
+  if (n == 0) return PMC_OK;
+  const uint32_t mode = batch_mode(params, cache);
   const bool sort = params->flags & PMC_FLAG_SORT;
   const bool persistent = params->flags & PMC_FLAG_PERSISTENT;
   const bool probe_first = mode != PMC_MODE_UNCACHED && (params->flags & PMC_FLAG_DEFER);
   const uint32_t chunk_waves = resolve_chunk_waves(params->chunk_waves, probe_first);
-  if (pmc_status st = reserve_batch(ctx, cache, n, mode, params->flags, chunk_waves, s))
-    return st;
 
   ShadeArgs a;
   fill_program_args(ctx, a);
@@ -513,9 +568,9 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.stat_slots = stats ? (unsigned long long*)ctx->stat_slots.p : nullptr;
   a.dbg_state = dbg ? dbg->state : nullptr;
   a.dbg_value = dbg ? dbg->value : nullptr;
-  uint32_t* misc = (uint32_t*)ctx->misc.p;
+  uint32_t* misc = misc_set(ctx, set);
   if (mode != PMC_MODE_UNCACHED) fill_cache_args(cache, a);
-  const bool surr = (params->flags & PMC_FLAG_SURROGATE) && mode != PMC_MODE_UNCACHED;
+  const bool surr = batch_surr(params, mode);
   const bool logged = (params->flags & PMC_FLAG_LOG) && mode != PMC_MODE_UNCACHED;
   if (surr || logged) {
     a.surr_w = (const SurrW*)ctx->surr.w.p;
@@ -534,20 +589,7 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.log_region_cap = ctx->surr.log_cap / 64u;
   }
 
-  // misc[1]: snapshot candidate count; misc[kMiscQueue ..]: the queue's region
-  // counters (reset by the sort's scan, or filled here)
-  const uint32_t n_reset = surr ? kMiscQueue + 2u * kQueueRegions : 4u;
-  if (sort) {
-    PhaseTimer t0(ctx, 0, s);
-    HIP_TRY(ctx, launch_material_sort_tiled(
-                     hits->material, n, a.n_mats, (const uint32_t*)ctx->lpt_rank.p,
-                     (uint32_t*)ctx->sort_counts.p, (uint32_t*)ctx->sort_offsets.p,
-                     (uint32_t*)ctx->sort_sums.p, (uint32_t*)ctx->perm.p, misc, n_reset, s));
-    t0.finish();
-    a.perm = (const uint32_t*)ctx->perm.p;
-  } else {
-    HIP_TRY(ctx, launch_fill_u32(misc, 0u, n_reset, s));
-  }
+  if (sort) a.perm = perm_set(ctx, set, n);
   if (mode == PMC_MODE_SNAPSHOT) {
     a.cand = (uint4*)ctx->cand.p;
     a.cand_count = misc + 1;

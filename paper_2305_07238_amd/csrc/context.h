@@ -43,7 +43,10 @@ struct pmc_ctx {
   DevBuf texels, texdesc;
   uint32_t n_tex = 0;
   // workspace
-  DevBuf perm, misc, cand, stat_slots;
+  // perm (+ perm2) and misc: the sorted order and device counters of a batch,
+  // in kWorkSets sets (set 0 for single batches; frame graphs use all of them,
+  // frame f set f % kWorkSets, so that sorts can run ahead of the shading)
+  DevBuf perm, perm2, misc, cand, stat_slots;
   DevBuf surr_queue, surr_val;                   // parked hits of the surrogate passes
   DevBuf sort_counts, sort_offsets, sort_sums;   // tiled material sort
   SurrHost surr;
@@ -118,10 +121,20 @@ struct PhaseTimer {
 pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                             const pmc_bsdf_out* out, const pmc_shade_params* params);
 // Device workspace for batches of up to n hits (all allocations and first-use
-// clears, enqueued on s).  After this, shade_batch for such batches allocates nothing.
+// clears, enqueued on s).  After this, shade_batch for such batches allocates
+// nothing.  all_sets: every workspace set, not only set 0 (frame graphs).
+constexpr int kWorkSets = 8;
 pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mode,
-                         uint32_t flags, uint32_t chunk_waves, hipStream_t s);
-// The per-batch pipeline: material sort -> shade -> snapshot apply -> stats.
+                         uint32_t flags, uint32_t chunk_waves, bool all_sets, hipStream_t s);
+// The two stages of a batch, for workspace set `set` (< kWorkSets): the material
+// sort (or, unsorted, the reset of the set's counters), then shade -> surrogate
+// passes -> snapshot apply -> stats.  The workspace must be reserved.
+pmc_status sort_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                      const pmc_shade_params* params, int set, hipStream_t s);
+pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                       const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
+                       const pmc_debug_out* dbg, int set, hipStream_t s);
+// The per-batch pipeline: reserve, then both stages on s with set 0.
 pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                        const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
                        const pmc_debug_out* dbg, hipStream_t s);

@@ -58,19 +58,98 @@ pmc_status check_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p) {
   return PMC_OK;
 }
 
-// enqueue the plan's work on s (no validation)
+// Streams and events of a pipelined capture: the material sorts run on `side`,
+// one group of frames ahead of the shading on the origin stream.
+struct Pipe {
+  hipStream_t side = nullptr;
+  hipEvent_t start = nullptr, join = nullptr;
+  hipEvent_t sorted[2] = {nullptr, nullptr}, shaded[2] = {nullptr, nullptr};
+};
+
+// Enqueue the plan's work on s (no validation).  With a pipe (and a sorted,
+// multi-frame plan) the frames are taken in groups, {0}, then kPipeGroup frames
+// at a time; frame f uses workspace set f % kWorkSets, and
+//   the sorts of group g+1 run on the side stream after those of group g
+//   (stream order) and after the shading of group g-1, the last user of their
+//   sets (two consecutive groups span at most kWorkSets frames);
+//   the shading of group g on s waits once, for the sorts of group g;
+// so the sorts of the next group overlap the shading of the current one, and
+// only the first frame of a group waits on the other stream.  The workspace
+// must be reserved for all sets.
+constexpr uint32_t kPipeGroup = kWorkSets / 2;
+
 pmc_status enqueue_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p,
-                        const pmc_shade_params& prm, hipStream_t s) {
-  if (p->clear_cache && cache)
-    HIP_TRY(ctx, launch_fill_u64((uint64_t*)cache->mem, 0ull, cache->bytes / 8, s));
-  for (uint32_t f = 0; f < p->n_frames; ++f) {
-    pmc_hits h = frame_hits(p, f);
-    pmc_bsdf_out o = frame_out(p, f);
+                        const pmc_shade_params& prm, hipStream_t s, const Pipe* pipe) {
+  const bool piped = pipe && (prm.flags & PMC_FLAG_SORT) && p->n_frames >= 2;
+  if (piped) {
+    // fork before the table clear: the first sort does not wait for it
+    HIP_TRY(ctx, hipEventRecord(pipe->start, s));
+    HIP_TRY(ctx, hipStreamWaitEvent(pipe->side, pipe->start, 0));
+  }
+  if (p->clear_cache && cache) {
+    const hipError_t e = launch_fill_u64((uint64_t*)cache->mem, 0ull, cache->bytes / 8, s);
+    if (e != hipSuccess && piped) {
+      (void)hipEventRecord(pipe->join, pipe->side);
+      (void)hipStreamWaitEvent(s, pipe->join, 0);
+    }
+    HIP_TRY(ctx, e);
+  }
+  auto params_of = [&](uint32_t f) {
     pmc_shade_params q = prm;
     q.frame = p->first_frame + f;
-    if (pmc_status st = shade_batch(ctx, cache, &h, &o, &q, p->stats, nullptr, s)) return st;
+    return q;
+  };
+  if (!piped) {
+    for (uint32_t f = 0; f < p->n_frames; ++f) {
+      pmc_hits h = frame_hits(p, f);
+      pmc_bsdf_out o = frame_out(p, f);
+      const pmc_shade_params q = params_of(f);
+      if (pmc_status st = shade_batch(ctx, cache, &h, &o, &q, p->stats, nullptr, s)) return st;
+    }
+    return PMC_OK;
   }
-  return PMC_OK;
+  const hipStream_t side = pipe->side;
+  const uint32_t F = p->n_frames;
+  const uint32_t n_groups = 1u + (F - 1u + kPipeGroup - 1u) / kPipeGroup;
+  auto group_begin = [&](uint32_t g) { return g == 0 ? 0u : 1u + (g - 1u) * kPipeGroup; };
+  auto group_end = [&](uint32_t g) { return g + 1 >= n_groups ? F : group_begin(g + 1); };
+  auto sort_group = [&](uint32_t g) -> pmc_status {
+    for (uint32_t f = group_begin(g); f < group_end(g); ++f) {
+      pmc_hits h = frame_hits(p, f);
+      const pmc_shade_params q = params_of(f);
+      if (pmc_status st = sort_stage(ctx, cache, &h, &q, (int)(f % kWorkSets), side)) return st;
+    }
+    if (hipEventRecord(pipe->sorted[g & 1u], side) != hipSuccess)
+      return ctx->fail(PMC_ERR_HIP, "hipEventRecord failed");
+    return PMC_OK;
+  };
+  pmc_status st = sort_group(0);
+  for (uint32_t g = 0; st == PMC_OK && g < n_groups; ++g) {
+    if (hipStreamWaitEvent(s, pipe->sorted[g & 1u], 0) != hipSuccess) {
+      st = ctx->fail(PMC_ERR_HIP, "hipStreamWaitEvent failed");
+      break;
+    }
+    for (uint32_t f = group_begin(g); st == PMC_OK && f < group_end(g); ++f) {
+      pmc_hits h = frame_hits(p, f);
+      pmc_bsdf_out o = frame_out(p, f);
+      const pmc_shade_params q = params_of(f);
+      st = shade_stage(ctx, cache, &h, &o, &q, p->stats, nullptr, (int)(f % kWorkSets), s);
+    }
+    if (st == PMC_OK && hipEventRecord(pipe->shaded[g & 1u], s) != hipSuccess)
+      st = ctx->fail(PMC_ERR_HIP, "hipEventRecord failed");
+    if (st != PMC_OK || g + 1 == n_groups) break;
+    if (g >= 1 && hipStreamWaitEvent(side, pipe->shaded[(g - 1u) & 1u], 0) != hipSuccess) {
+      st = ctx->fail(PMC_ERR_HIP, "hipStreamWaitEvent failed");
+      break;
+    }
+    st = sort_group(g + 1);
+  }
+  // the side stream joins the origin stream again, on every path
+  if (hipEventRecord(pipe->join, side) != hipSuccess ||
+      hipStreamWaitEvent(s, pipe->join, 0) != hipSuccess) {
+    if (st == PMC_OK) st = ctx->fail(PMC_ERR_HIP, "joining the sort stream failed");
+  }
+  return st;
 }
 
 }  // namespace
@@ -88,7 +167,16 @@ pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_fram
   const bool probe_first = mode != PMC_MODE_UNCACHED && (plan->params.flags & PMC_FLAG_DEFER);
   pmc_status st = reserve_batch(ctx, cache, (uint32_t)plan->hits_per_frame, mode,
                                 plan->params.flags,
-                                resolve_chunk_waves(plan->params.chunk_waves, probe_first), cs);
+                                resolve_chunk_waves(plan->params.chunk_waves, probe_first), true,
+                                cs);
+  Pipe pipe;
+  if (st == PMC_OK) {
+    bool ok = hipStreamCreateWithFlags(&pipe.side, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t* e : {&pipe.start, &pipe.join, &pipe.sorted[0], &pipe.sorted[1],
+                          &pipe.shaded[0], &pipe.shaded[1]})
+      ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) st = ctx->fail(PMC_ERR_HIP, "stream or event creation failed");
+  }
   if (st == PMC_OK && hipStreamSynchronize(cs) != hipSuccess)
     st = ctx->fail(PMC_ERR_HIP, "workspace reservation failed");
   pmc_frame_graph* g = nullptr;
@@ -106,7 +194,7 @@ pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_fram
     if (e != hipSuccess) {
       st = ctx->fail(PMC_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     } else {
-      st = enqueue_plan(ctx, cache, plan, plan->params, cs);
+      st = enqueue_plan(ctx, cache, plan, plan->params, cs, &pipe);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(cs, &graph);
       if (st == PMC_OK && e != hipSuccess)
@@ -122,6 +210,10 @@ pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_fram
     }
   }
   (void)hipStreamDestroy(cs);
+  for (hipEvent_t e : {pipe.start, pipe.join, pipe.sorted[0], pipe.sorted[1], pipe.shaded[0],
+                       pipe.shaded[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (pipe.side) (void)hipStreamDestroy(pipe.side);
   if (st != PMC_OK) {
     pmc_frame_graph_destroy(g);
     return st;
@@ -196,7 +288,7 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
     double best = 1e30;
     for (int rep = 0; rep < 3; ++rep) {           // first run warms up
       HIP_TRY(ctx, hipEventRecord(e0, s));
-      if (pmc_status r = enqueue_plan(ctx, cache, &p, prm, s)) return r;
+      if (pmc_status r = enqueue_plan(ctx, cache, &p, prm, s, nullptr)) return r;
       HIP_TRY(ctx, hipEventRecord(e1, s));
       HIP_TRY(ctx, hipEventSynchronize(e1));
       float t = 0.f;
