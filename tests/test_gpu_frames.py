@@ -27,11 +27,16 @@ def _slice(d, f, n):
     return {k: v[f * n:(f + 1) * n] for k, v in d.items()}
 
 
-@pytest.mark.parametrize("mode", [B.PMC_MODE_SNAPSHOT, B.PMC_MODE_UNCACHED])
-def test_frame_graph_replays_match_stream_launches(mode):
-    sc = G.small_mid_scene(frames=3)
+# 3 frames: groups {0}, {1, 2}; 11 frames: {0}, {1..4}, {5..8}, {9, 10}, so frames
+# 8..10 reuse the workspace sets of frames 0..2 and the sorts wait for shading
+@pytest.mark.parametrize("mode,F", [(B.PMC_MODE_SNAPSHOT, 3), (B.PMC_MODE_UNCACHED, 3),
+                                    (B.PMC_MODE_SNAPSHOT, 11)])
+def test_frame_graph_replays_match_stream_launches(mode, F):
+    """A captured render (sorts pipelined on a second stream) equals the same
+    frames launched one by one, bit for bit, on every replay."""
+    sc = G.small_mid_scene(frames=F)
     ctx = G.setup(sc)
-    n, F = sc.hits_per_frame, 3
+    n = sc.hits_per_frame
     hits = _frames_on_device(sc, F)
     out_g = B.alloc_outputs(n * F)
     out_s = B.alloc_outputs(n * F)
