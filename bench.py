@@ -50,16 +50,16 @@ def measured_traffic(workload_name, best):
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f)
+        recs = json.load(f)
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2305_07238_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != rec["source_sha256"]:
-        return None
-    if any(rec[k] != best[k] for k in ("flags", "chunk_waves", "defer_max")):
-        return None
-    return rec["traffic_bytes_per_launch"]
+    for rec in recs:
+        if h.hexdigest() == rec["source_sha256"] and all(
+                rec[k] == best[k] for k in ("flags", "chunk_waves", "defer_max")):
+            return rec["traffic_bytes_per_launch"]
+    return None
 
 
 def shade_kernel_name(mode, flags):
@@ -315,6 +315,12 @@ def main():
                     help="skip the launch-parameter search (use sort + deferral, 4-chunk runs)")
     ap.add_argument("--min-subgraph", type=int, default=0,
                     help="smallest cacheable sub-graph in nodes (compile option; 0 = library default 2)")
+    ap.add_argument("--chunk-waves", type=int, default=0,
+                    help="with --no-autotune: chunks per wave run (default 4 cached, 1 uncached)")
+    ap.add_argument("--defer-max", type=int, default=0,
+                    help="with --no-autotune: deferral threshold (default 48)")
+    ap.add_argument("--tune-json", default=None,
+                    help="write every autotuner candidate and its time to this file")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (training on the insert log)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -364,9 +370,11 @@ def main():
     tune_frames = min(4, sc.frames)
     if args.no_autotune:
         best = dict(flags=B.PMC_FLAG_SORT | (B.PMC_FLAG_DEFER if use_cache else 0),
-                    chunk_waves=4 if use_cache else 1, defer_max=48, blocks_per_cu=0)
+                    chunk_waves=args.chunk_waves or (4 if use_cache else 1),
+                    defer_max=args.defer_max or 48, blocks_per_cu=0)
     else:
-        tune = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, tune_frames, out, mode=mode))
+        tune = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, tune_frames, out, mode=mode),
+                            args.tune_json)
         b = tune.best
         best = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
                     blocks_per_cu=b.blocks_per_cu)

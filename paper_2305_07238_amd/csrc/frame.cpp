@@ -282,6 +282,9 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
         for (uint32_t dm : {32u, 48u}) cands.push_back({base | pf | PMC_FLAG_DEFER, cw, dm, 0u, 0.0});
   }
   for (uint32_t bpc : {2u, 4u}) cands.push_back({base | PMC_FLAG_PERSISTENT, 1u, 0u, bpc, 0.0});
+  if (cached)
+    for (uint32_t cw : {1u, 2u, 4u})
+      cands.push_back({base | PMC_FLAG_PERSISTENT | PMC_FLAG_DEFER, cw, 48u, 4u, 0.0});
 
   pmc_status st = PMC_OK;
   auto time_one = [&](const pmc_shade_params& prm, double* ms) -> pmc_status {
