@@ -423,9 +423,11 @@ def main():
     shade_ms, shade_launches = prof["shade"]
     achieved = kb / (shade_ms / prof_steps * 1e-3) / 1e9
 
-    # uncached reference on the same inputs, also replayed as a graph
-    unc = None
+    # uncached reference on the same inputs, also replayed as a graph; the last
+    # frame's BSDF inputs of both give the error of the cached values
+    unc, err = None, None
     if mode != B.PMC_MODE_UNCACHED and args.uncached_steps > 0:
+        cached_last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
         g_u = ctx.frame_graph(None, ctx.frame_plan(hits, n_frame, sc.frames, out,
                                                    mode=B.PMC_MODE_UNCACHED))
         g_u.launch()
@@ -438,6 +440,10 @@ def main():
         unc = ev0.elapsed_time(ev1) / args.uncached_steps
         log(f"uncached {unc:.3f} ms/step")
         g_u.close()
+        e = np.concatenate([np.abs(out[k].cpu().numpy().astype(np.float64) - cached_last[k]).ravel()
+                            for k in ("base_color", "roughness", "normal")])
+        err = {"max_abs": float(e.max()), "mean_abs": float(e.mean()),
+               "sample": "every BSDF input of the last frame, cached vs uncached GPU path"}
 
     value = n_step / (ms_step * 1e-3)
     res = {
@@ -462,6 +468,7 @@ def main():
         "nodes_executed_fraction": st["nodes_executed"] / max(st["nodes_total"], 1),
         "uncached_samples_per_s": (n_step / (unc * 1e-3)) if unc else None,
         "speedup_vs_uncached": (unc / ms_step) if unc else None,
+        "bsdf_err_vs_uncached": err,
         "stats": st,
         "phase_ms_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
