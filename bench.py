@@ -55,8 +55,9 @@ def measured_traffic(workload_name, best):
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2305_07238_amd", "csrc", name), "rb") as f:
             h.update(f.read())
+    wpb = best.get("waves_per_block", 0) or 4
     for rec in recs:
-        if h.hexdigest() == rec["source_sha256"] and all(
+        if h.hexdigest() == rec["source_sha256"] and rec.get("waves_per_block", 4) == wpb and all(
                 rec[k] == best[k] for k in ("flags", "chunk_waves", "defer_max")):
             return rec["traffic_bytes_per_launch"]
     return None
@@ -142,7 +143,7 @@ def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
     n_slots = ctx.surrogate_setup(seed=0)
     flags = best["flags"] & ~(B.PMC_FLAG_LOG | B.PMC_FLAG_SURROGATE)
     kw = dict(chunk_waves=best["chunk_waves"], defer_max=best["defer_max"],
-              blocks_per_cu=best["blocks_per_cu"])
+              blocks_per_cu=best["blocks_per_cu"], waves_per_block=best["waves_per_block"])
     cache.clear()
     ctx.log_clear()
     for f in range(sc.frames):
@@ -319,6 +320,8 @@ def main():
                     help="with --no-autotune: chunks per wave run (default 4 cached, 1 uncached)")
     ap.add_argument("--defer-max", type=int, default=0,
                     help="with --no-autotune: deferral threshold (default 48)")
+    ap.add_argument("--waves-per-block", type=int, default=0,
+                    help="with --no-autotune: waves per workgroup of the flat grid (default 4)")
     ap.add_argument("--tune-json", default=None,
                     help="write every autotuner candidate and its time to this file")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -371,13 +374,14 @@ def main():
     if args.no_autotune:
         best = dict(flags=B.PMC_FLAG_SORT | (B.PMC_FLAG_DEFER if use_cache else 0),
                     chunk_waves=args.chunk_waves or (4 if use_cache else 1),
-                    defer_max=args.defer_max or 48, blocks_per_cu=0)
+                    defer_max=args.defer_max or 48, blocks_per_cu=0,
+                    waves_per_block=args.waves_per_block)
     else:
         tune = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, tune_frames, out, mode=mode),
                             args.tune_json)
         b = tune.best
         best = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
-                    blocks_per_cu=b.blocks_per_cu)
+                    blocks_per_cu=b.blocks_per_cu, waves_per_block=b.waves_per_block)
         log(f"autotune: {best} {tune.best_ms:.3f} ms vs defaults {tune.default_ms:.3f} ms "
             f"({tune.n_tried} settings, {tune_frames} frames)")
     graph = ctx.frame_graph(use_cache, ctx.frame_plan(hits, n_frame, sc.frames, out, mode=mode,

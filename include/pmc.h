@@ -252,7 +252,10 @@ typedef struct pmc_shade_params {
                                   missing lanes is evaluated where it was probed; sparser misses
                                   are staged per wave (in LDS) and evaluated together in dense
                                   passes over the wave's run.  0 = library default (48) */
-    uint32_t reserved[2];
+    uint32_t waves_per_block;  /* flat grid: waves per workgroup, 1, 2 or 4 (a workgroup keeps
+                                  its slot on the CU until its last wave ends); 0 = library
+                                  default (4) */
+    uint32_t reserved[1];
 } pmc_shade_params;
 
 typedef struct pmc_stats {     /* 64-bit counters, accumulated (+=) by pmc_shade */

@@ -96,7 +96,8 @@ class pmc_debug_out(C.Structure):
 class pmc_shade_params(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("flags", C.c_uint32), ("frame", C.c_uint32),
                 ("chunk_waves", C.c_uint32), ("blocks_per_cu", C.c_uint32),
-                ("defer_max", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+                ("defer_max", C.c_uint32), ("waves_per_block", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class pmc_frame_plan(C.Structure):
@@ -348,12 +349,14 @@ class Context:
     def shade(self, hits: dict, out: dict, cache: Optional["Cache"] = None,
               mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, frame: int = 0,
               stats=None, debug: Optional[dict] = None, chunk_waves: int = 0,
-              blocks_per_cu: int = 0, defer_max: int = 0, stream=None):
+              blocks_per_cu: int = 0, defer_max: int = 0, waves_per_block: int = 0,
+              stream=None):
         """hits: dict of torch CUDA tensors material/uv/duv/normal; out: base_color/roughness/normal."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), int(hits["material"].numel()))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
-        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max)
+        p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max,
+                             waves_per_block)
         dbg = None
         if debug is not None:
             dbg = C.byref(pmc_debug_out(_ptr(debug.get("state")), _ptr(debug.get("value"))))
@@ -372,12 +375,13 @@ class Context:
                    mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, first_frame: int = 0,
                    out_per_frame: bool = False, clear_cache: bool = True, stats=None,
                    chunk_waves: int = 0, blocks_per_cu: int = 0,
-                   defer_max: int = 0) -> pmc_frame_plan:
+                   defer_max: int = 0, waves_per_block: int = 0) -> pmc_frame_plan:
         """hits: torch tensors holding n_frames * hits_per_frame hits, frame-major."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), 0)
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
-        prm = pmc_shade_params(mode, flags, 0, chunk_waves, blocks_per_cu, defer_max)
+        prm = pmc_shade_params(mode, flags, 0, chunk_waves, blocks_per_cu, defer_max,
+                               waves_per_block)
         plan = pmc_frame_plan(h, hits_per_frame, n_frames, first_frame, o, int(out_per_frame),
                               int(clear_cache), prm, _ptr(stats))
         plan._keep = (hits, out, stats)

@@ -440,6 +440,9 @@ pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits
     return ctx->fail(PMC_ERR_INVALID, "unknown flags");
   if ((params->flags & (PMC_FLAG_LOG | PMC_FLAG_SURROGATE)) && !ctx->surr.ready)
     return ctx->fail(PMC_ERR_STATE, "PMC_FLAG_LOG / PMC_FLAG_SURROGATE need pmc_surrogate_setup");
+  if (params->waves_per_block != 0 && params->waves_per_block != 1 &&
+      params->waves_per_block != 2 && params->waves_per_block != 4)
+    return ctx->fail(PMC_ERR_INVALID, "waves_per_block must be 0, 1, 2 or 4");
   if (hits->n && (!out || !out->base_color || !out->roughness || !out->normal))
     return ctx->fail(PMC_ERR_INVALID, "null output array");
   if (cache && cache->ctx != ctx) return ctx->fail(PMC_ERR_INVALID, "cache of another context");
@@ -599,6 +602,7 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.chunk_waves = chunk_waves;
   a.defer_max = params->defer_max ? params->defer_max : 48u;
   const uint32_t runs = (n_chunks + a.chunk_waves - 1) / a.chunk_waves;
+  const uint32_t block_waves = params->waves_per_block ? params->waves_per_block : 4u;
   uint32_t grid;
   if (persistent) {
     uint32_t bpc = params->blocks_per_cu;
@@ -611,11 +615,12 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     const uint32_t max_useful = (runs + 3) / 4;
     if (grid > max_useful) grid = max_useful ? max_useful : 1;
   } else {
-    grid = (runs + 3) / 4;
+    grid = (runs + block_waves - 1) / block_waves;
   }
   PhaseTimer t1(ctx, 1, s);
   HIP_TRY(ctx,
-          launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, surr, grid, s));
+          launch_shade(a, probe_first ? KIND_PROBE : KIND_FULL, persistent, surr, grid,
+                       block_waves, s));
   if (surr) {
     const uint32_t qgrid = (uint32_t)ctx->num_cus * 4u;
     HIP_TRY(ctx, launch_surr_queue(a, qgrid, s));

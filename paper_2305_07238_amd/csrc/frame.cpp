@@ -268,7 +268,7 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
   p.clear_cache = cached ? 1u : 0u;
   p.stats = nullptr;
 
-  struct Cand { uint32_t flags, chunk_waves, defer_max, bpc; double ms; };
+  struct Cand { uint32_t flags, chunk_waves, defer_max, bpc, wpb; double ms; };
   std::vector<Cand> cands;
   // the surrogate choice is the caller's (it changes results); logging is not
   // wanted while tuning
@@ -276,15 +276,18 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
       PMC_FLAG_SORT | (plan->params.flags & (PMC_FLAG_SURROGATE | PMC_FLAG_SURROGATE_INSERT));
   for (uint32_t pers = 0; pers < 2; ++pers) {
     const uint32_t pf = pers ? PMC_FLAG_PERSISTENT : 0u;
-    for (uint32_t cw : {1u, 2u, 4u}) cands.push_back({base | pf, cw, 0u, 0u, 0.0});
+    for (uint32_t cw : {1u, 2u, 4u}) cands.push_back({base | pf, cw, 0u, 0u, 0u, 0.0});
     if (cached)
       for (uint32_t cw : {2u, 4u, 8u})
-        for (uint32_t dm : {32u, 48u}) cands.push_back({base | pf | PMC_FLAG_DEFER, cw, dm, 0u, 0.0});
+        for (uint32_t dm : {32u, 48u})
+          cands.push_back({base | pf | PMC_FLAG_DEFER, cw, dm, 0u, 0u, 0.0});
   }
-  for (uint32_t bpc : {2u, 4u}) cands.push_back({base | PMC_FLAG_PERSISTENT, 1u, 0u, bpc, 0.0});
+  for (uint32_t bpc : {2u, 4u}) cands.push_back({base | PMC_FLAG_PERSISTENT, 1u, 0u, bpc, 0u, 0.0});
   if (cached)
     for (uint32_t cw : {1u, 2u, 4u})
-      cands.push_back({base | PMC_FLAG_PERSISTENT | PMC_FLAG_DEFER, cw, 48u, 4u, 0.0});
+      cands.push_back({base | PMC_FLAG_PERSISTENT | PMC_FLAG_DEFER, cw, 48u, 4u, 0u, 0.0});
+  // (smaller workgroups, waves_per_block 1 or 2, measured within 0.3% of 4 on
+  // the 64-material scene and are left to the caller)
 
   pmc_status st = PMC_OK;
   auto time_one = [&](const pmc_shade_params& prm, double* ms) -> pmc_status {
@@ -305,7 +308,7 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
   ctx->profiling = false;
   pmc_shade_params def = plan->params;
   def.flags = base;
-  def.chunk_waves = def.defer_max = def.blocks_per_cu = 0;
+  def.chunk_waves = def.defer_max = def.blocks_per_cu = def.waves_per_block = 0;
   st = time_one(def, &out->default_ms);
   double best_ms = 1e30;
   size_t best_i = 0;
@@ -315,6 +318,7 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
     prm.chunk_waves = cands[i].chunk_waves;
     prm.defer_max = cands[i].defer_max;
     prm.blocks_per_cu = cands[i].bpc;
+    prm.waves_per_block = cands[i].wpb;
     st = time_one(prm, &cands[i].ms);
     if (st == PMC_OK && cands[i].ms < best_ms) {
       best_ms = cands[i].ms;
@@ -335,6 +339,7 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
   out->best.chunk_waves = cands[best_i].chunk_waves;
   out->best.defer_max = cands[best_i].defer_max;
   out->best.blocks_per_cu = cands[best_i].bpc;
+  out->best.waves_per_block = cands[best_i].wpb;
   out->best_ms = best_ms;
   out->n_tried = (uint32_t)cands.size();
   if (json_path) {
@@ -344,8 +349,9 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
                  best_i);
     for (size_t i = 0; i < cands.size(); ++i)
       std::fprintf(fp, "%s{\"flags\": %u, \"chunk_waves\": %u, \"defer_max\": %u, "
-                   "\"blocks_per_cu\": %u, \"ms\": %.6f}", i ? ", " : "", cands[i].flags,
-                   cands[i].chunk_waves, cands[i].defer_max, cands[i].bpc, cands[i].ms);
+                   "\"blocks_per_cu\": %u, \"waves_per_block\": %u, \"ms\": %.6f}",
+                   i ? ", " : "", cands[i].flags, cands[i].chunk_waves, cands[i].defer_max,
+                   cands[i].bpc, cands[i].wpb, cands[i].ms);
     std::fprintf(fp, "]}\n");
     std::fclose(fp);
   }

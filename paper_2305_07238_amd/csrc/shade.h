@@ -95,9 +95,11 @@ inline uint32_t queue_region_cap(uint32_t n, uint32_t chunk_waves) {
 }
 
 // surr: the variant that consults the surrogate networks (cached modes only).
+// block_waves: waves per workgroup of the flat grid (the persistent grid uses 4).
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, bool surr, uint32_t grid,
-                        hipStream_t s);
-size_t shade_lds_bytes(uint32_t n_regs);
+                        uint32_t block_waves, hipStream_t s);
+// LDS of a workgroup of `waves` waves: per wave the register file and 64 staging ids.
+size_t shade_lds_bytes(uint32_t n_regs, uint32_t waves = 4);
 // After a surrogate first pass: the networks over the parked hits, then their finish
 // pass (both size themselves from the queue count on the device).
 hipError_t launch_surr_queue(const ShadeArgs& a, uint32_t grid, hipStream_t s);

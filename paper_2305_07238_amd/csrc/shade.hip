@@ -1235,50 +1235,51 @@ hipError_t launch_surr_finish(const ShadeArgs& a, uint32_t grid, hipStream_t s) 
 
 // ---------------------------------------------------------- host launchers ---
 
-size_t shade_lds_bytes(uint32_t n_regs) { return (size_t)4 * (n_regs * 64 + 64) * sizeof(float); }
+size_t shade_lds_bytes(uint32_t n_regs, uint32_t waves) {
+  return (size_t)waves * (n_regs * 64 + 64) * sizeof(float);
+}
 
 template <int MODE, int KIND, bool STATS, bool SURR>
-static void launch_one(const ShadeArgs& a, bool persistent, uint32_t grid, size_t lds,
+static void launch_one(const ShadeArgs& a, bool persistent, dim3 grid, dim3 block, size_t lds,
                        hipStream_t s) {
   constexpr bool w4 = MODE != PMC_MODE_UNCACHED;
   if (w4 && persistent)
-    hipLaunchKernelGGL((k_shade_persistent_w4<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256),
-                       lds, s, a);
+    hipLaunchKernelGGL((k_shade_persistent_w4<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
   else if (w4)
-    hipLaunchKernelGGL((k_shade_flat_w4<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds, s,
-                       a);
+    hipLaunchKernelGGL((k_shade_flat_w4<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
   else if (persistent)
-    hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds,
-                       s, a);
+    hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
   else
-    hipLaunchKernelGGL((k_shade_flat<MODE, KIND, STATS, SURR>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_shade_flat<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
 }
 
 template <int KIND, bool STATS>
-static void launch_kind(const ShadeArgs& a, bool persistent, bool surr, uint32_t grid, size_t lds,
-                        hipStream_t s) {
+static void launch_kind(const ShadeArgs& a, bool persistent, bool surr, dim3 grid, dim3 block,
+                        size_t lds, hipStream_t s) {
   if (a.mode == PMC_MODE_UNCACHED)
-    launch_one<PMC_MODE_UNCACHED, KIND, STATS, false>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_UNCACHED, KIND, STATS, false>(a, persistent, grid, block, lds, s);
   else if (a.mode == PMC_MODE_CACHED && surr)
-    launch_one<PMC_MODE_CACHED, KIND, STATS, true>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_CACHED, KIND, STATS, true>(a, persistent, grid, block, lds, s);
   else if (a.mode == PMC_MODE_CACHED)
-    launch_one<PMC_MODE_CACHED, KIND, STATS, false>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_CACHED, KIND, STATS, false>(a, persistent, grid, block, lds, s);
   else if (surr)
-    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS, true>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS, true>(a, persistent, grid, block, lds, s);
   else
-    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS, false>(a, persistent, grid, lds, s);
+    launch_one<PMC_MODE_SNAPSHOT, KIND, STATS, false>(a, persistent, grid, block, lds, s);
 }
 
 hipError_t launch_shade(const ShadeArgs& a, int kind, bool persistent, bool surr, uint32_t grid,
-                        hipStream_t s) {
-  const size_t lds = shade_lds_bytes(a.n_regs);
+                        uint32_t block_waves, hipStream_t s) {
+  const uint32_t waves = persistent ? 4u : block_waves;
+  const size_t lds = shade_lds_bytes(a.n_regs, waves);
+  const dim3 g(grid), b(64u * waves);
   const bool stats = a.stat_slots != nullptr;
   if (kind == KIND_PROBE) {
-    if (stats) launch_kind<KIND_PROBE, true>(a, persistent, surr, grid, lds, s);
-    else launch_kind<KIND_PROBE, false>(a, persistent, surr, grid, lds, s);
+    if (stats) launch_kind<KIND_PROBE, true>(a, persistent, surr, g, b, lds, s);
+    else launch_kind<KIND_PROBE, false>(a, persistent, surr, g, b, lds, s);
   } else {
-    if (stats) launch_kind<KIND_FULL, true>(a, persistent, surr, grid, lds, s);
-    else launch_kind<KIND_FULL, false>(a, persistent, surr, grid, lds, s);
+    if (stats) launch_kind<KIND_FULL, true>(a, persistent, surr, g, b, lds, s);
+    else launch_kind<KIND_FULL, false>(a, persistent, surr, g, b, lds, s);
   }
   return hipGetLastError();
 }

@@ -116,7 +116,8 @@ def test_autotune_picks_a_valid_setting(tmp_path):
         h = _slice(hits, f, n)
         ctx.shade(h, out, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f)
         ctx.shade(h, out2, cache2, mode=B.PMC_MODE_SNAPSHOT, frame=f, flags=b.flags,
-                  chunk_waves=b.chunk_waves, defer_max=b.defer_max, blocks_per_cu=b.blocks_per_cu)
+                  chunk_waves=b.chunk_waves, defer_max=b.defer_max, blocks_per_cu=b.blocks_per_cu,
+                  waves_per_block=b.waves_per_block)
     torch.cuda.synchronize()
     assert np.array_equal(cache.export(), cache2.export())
     for k in out:

@@ -386,7 +386,8 @@ def test_raw_insert_and_lookup_distinct_keys():
     assert hit.cpu().numpy()[lost[:20]].all()
 
 
-@pytest.mark.parametrize("setting", ["defer", "always_defer", "persistent"])
+@pytest.mark.parametrize("setting", ["defer", "always_defer", "persistent", "one_wave_blocks",
+                                     "two_wave_blocks"])
 def test_snapshot_deferral_settings_are_bit_identical(setting):
     """Setting misses aside for dense evaluation must not change any result."""
     sc = G.small_mid_scene(frames=3)
@@ -396,7 +397,9 @@ def test_snapshot_deferral_settings_are_bit_identical(setting):
     D = B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER
     kw = {"defer": dict(flags=D),
           "always_defer": dict(flags=D, defer_max=64, chunk_waves=16),
-          "persistent": dict(flags=D | B.PMC_FLAG_PERSISTENT, chunk_waves=2)}[setting]
+          "persistent": dict(flags=D | B.PMC_FLAG_PERSISTENT, chunk_waves=2),
+          "one_wave_blocks": dict(flags=D, waves_per_block=1),
+          "two_wave_blocks": dict(flags=D, waves_per_block=2, chunk_waves=3)}[setting]
     for f in range(3):
         h = sc.frame(f)
         a, sa, va, st_a = G.shade(ctx, h, ref_cache, mode=B.PMC_MODE_SNAPSHOT, frame=f, debug=True)
