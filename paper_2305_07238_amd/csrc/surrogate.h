@@ -83,7 +83,8 @@ __device__ __forceinline__ h4 fourier4(float u, float v, int q) {
 // second, which is exactly what the D layout of the previous product leaves in
 // its registers.  The weights are loaded with the same pairing, and since the
 // A and B operands of a product index K the same way, each product still sums
-// over all 32 rows.  Per tile: 4 products for layer 1, 8 for layer 2, 2 for
+// over all 32 rows.  (Layer 1 reads features: there lane group g supplies
+// features 8g .. 8g+7, and W1 is read with the same columns.)  Per tile: 4 products for layer 1, 8 for layer 2, 2 for
 // layer 3.
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
@@ -96,7 +97,7 @@ __device__ __forceinline__ h8 cat8(h4 lo, h4 hi) {
 }
 
 struct NetRegs {
-  h8 w1[4];        // layer 1, M tile m: W1[16m + j][4g .. 4g+3 | 16 + 4g .. 16 + 4g+3]
+  h8 w1[4];        // layer 1, M tile m: W1[16m + j][8g .. 8g+7] (the features of fourier8)
   h8 w2[4][2];     // layer 2, M tile m, K step t: input blocks 2t and 2t+1
   h8 w3[2];        // layer 3 (rows 4..15 zero), K step t
   f4 b1[4], b2[4]; // biases of rows 16m + 4g .. 16m + 4g+3
@@ -113,7 +114,7 @@ __device__ __forceinline__ void load_net(const SurrW* __restrict__ W, NetRegs& N
   const int j = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    N.w1[m] = load_pair(W->w1 + (16 * m + j) * 32, 0, 1, g);
+    N.w1[m] = *reinterpret_cast<const h8*>(W->w1 + (16 * m + j) * 32 + 8 * g);
     N.w2[m][0] = load_pair(W->w2 + (16 * m + j) * 64, 0, 1, g);
     N.w2[m][1] = load_pair(W->w2 + (16 * m + j) * 64, 2, 3, g);
     N.b1[m] = *reinterpret_cast<const f4*>(W->b1 + 16 * m + 4 * g);
@@ -123,6 +124,29 @@ __device__ __forceinline__ void load_net(const SurrW* __restrict__ W, NetRegs& N
   N.w3[1] = load_pair(W->w3 + j * 64, 2, 3, g);
 #pragma unroll
   for (int c = 0; c < 4; ++c) N.b3[c] = W->b3[c];
+}
+
+// Features 8g .. 8g+7 (frequencies q = 2g and 2g + 1) for inference: the sines
+// and cosines of the higher frequency come from the lower one by the double
+// angle, sin 2x = 2 sin x cos x and cos 2x = (cos x - sin x)(cos x + sin x),
+// one sin/cos pair per coordinate instead of two.  In binary32 the doubled
+// values carry a few units in the last place more error than direct ones; after
+// rounding to binary16 a feature rarely moves, and then by one binary16 unit.
+__device__ __forceinline__ h8 fourier8(float u, float v, int g) {
+  const float s = __builtin_ldexpf(1.0f, 2 * g - 3);
+  float su, cu, sv, cv;
+  sincospif(u * s, &su, &cu);
+  sincospif(v * s, &sv, &cv);
+  h8 r;
+  r[0] = (_Float16)su;
+  r[1] = (_Float16)cu;
+  r[2] = (_Float16)sv;
+  r[3] = (_Float16)cv;
+  r[4] = (_Float16)(2.0f * su * cu);
+  r[5] = (_Float16)((cu - su) * (cu + su));
+  r[6] = (_Float16)(2.0f * sv * cv);
+  r[7] = (_Float16)((cv - sv) * (cv + sv));
+  return r;
 }
 
 // relu(acc) rounded to binary16 (round to nearest even).  Rounding is
@@ -138,7 +162,7 @@ __device__ __forceinline__ h4 relu_h4(f4 acc) {
 // 0..15 receive their point's 4 outputs (rows 0..3 of the output tile).
 __device__ __forceinline__ f4 net_tile(const NetRegs& N, float un, float vn) {
   const int g = (int)((threadIdx.x & 63u) >> 4);
-  const h8 x = cat8(fourier4(un, vn, g), fourier4(un, vn, 4 + g));
+  const h8 x = fourier8(un, vn, g);
   // the biases start the accumulators (the D layout of row i is that of bias i)
   h4 H1[4], H2[4];
 #pragma unroll
