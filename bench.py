@@ -94,6 +94,10 @@ def workload(name, frames=None):
         sc = scenes.batching_scene(frames=frames or 64)
         desc = ("batching: 1000 materials (lognormal sizes 4-400 nodes), 1920x1080 x %d frames, "
                 "table 2^24 slots x 16 B" % sc.frames)
+    elif name == "scale":
+        sc = scenes.scale_scene(frames=frames or 128)
+        desc = ("scale: 4096 materials (lognormal sizes 8-400 nodes), 3840x2160 x %d frames, "
+                "table 2^26 slots x 16 B (1 GiB), overwrite-oldest" % sc.frames)
     else:
         raise SystemExit(f"unknown workload {name}")
     return sc, desc
