@@ -41,7 +41,7 @@ def kernel_bytes(st, n_hits):
 KERNEL_SOURCES = ("shade.hip", "shade.h", "device_common.h", "program.h")
 
 
-def measured_traffic(workload_name, best):
+def measured_traffic(workload_name, best, late_frame=0, late=None):
     """HBM bytes per launch of the shade kernel from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration), or None
     when the kernel sources or the launch settings differ from the profiled ones."""
@@ -55,11 +55,17 @@ def measured_traffic(workload_name, best):
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2305_07238_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    wpb = best.get("waves_per_block", 0) or 4
+    def same(rec, want):
+        return (rec.get("waves_per_block", 4) == (want.get("waves_per_block", 0) or 4) and
+                all(rec[k] == want[k] for k in ("flags", "chunk_waves", "defer_max")))
     for rec in recs:
-        if h.hexdigest() == rec["source_sha256"] and rec.get("waves_per_block", 4) == wpb and all(
-                rec[k] == best[k] for k in ("flags", "chunk_waves", "defer_max")):
-            return rec["traffic_bytes_per_launch"]
+        if h.hexdigest() != rec["source_sha256"] or not same(rec, best):
+            continue
+        if rec.get("late_frame", 0) != late_frame:
+            continue
+        if late_frame and not same(rec["late"], late):
+            continue
+        return rec["traffic_bytes_per_launch"]
     return None
 
 
@@ -320,12 +326,19 @@ def main():
                     help="skip the launch-parameter search (use sort + deferral, 4-chunk runs)")
     ap.add_argument("--min-subgraph", type=int, default=0,
                     help="smallest cacheable sub-graph in nodes (compile option; 0 = library default 2)")
+    ap.add_argument("--flags", type=int, default=-1,
+                    help="with --no-autotune: pmc_flags bits (default sort, plus deferral cached)")
     ap.add_argument("--chunk-waves", type=int, default=0,
                     help="with --no-autotune: chunks per wave run (default 4 cached, 1 uncached)")
     ap.add_argument("--defer-max", type=int, default=0,
                     help="with --no-autotune: deferral threshold (default 48)")
     ap.add_argument("--waves-per-block", type=int, default=0,
                     help="with --no-autotune: waves per workgroup of the flat grid (default 4)")
+    ap.add_argument("--late-frame", type=int, default=0,
+                    help="with --no-autotune: frames from this one on use the --late-* setting")
+    ap.add_argument("--late-flags", type=int, default=-1)
+    ap.add_argument("--late-chunk-waves", type=int, default=0)
+    ap.add_argument("--late-defer-max", type=int, default=0)
     ap.add_argument("--tune-json", default=None,
                     help="write every autotuner candidate and its time to this file")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -376,7 +389,8 @@ def main():
 
     tune_frames = min(4, sc.frames)
     if args.no_autotune:
-        best = dict(flags=B.PMC_FLAG_SORT | (B.PMC_FLAG_DEFER if use_cache else 0),
+        best = dict(flags=args.flags if args.flags >= 0 else
+                    B.PMC_FLAG_SORT | (B.PMC_FLAG_DEFER if use_cache else 0),
                     chunk_waves=args.chunk_waves or (4 if use_cache else 1),
                     defer_max=args.defer_max or 48, blocks_per_cu=0,
                     waves_per_block=args.waves_per_block)
@@ -388,8 +402,28 @@ def main():
                     blocks_per_cu=b.blocks_per_cu, waves_per_block=b.waves_per_block)
         log(f"autotune: {best} {tune.best_ms:.3f} ms vs defaults {tune.default_ms:.3f} ms "
             f"({tune.n_tried} settings, {tune_frames} frames)")
+    # frames from late_frame on may use another setting: once the table holds
+    # most values, chunks miss rarely and the best launch shape changes
+    late_frame, late = 0, None
+    if args.no_autotune:
+        if args.late_frame:
+            late_frame = args.late_frame
+            late = dict(flags=args.late_flags if args.late_flags >= 0 else best["flags"],
+                        chunk_waves=args.late_chunk_waves, defer_max=args.late_defer_max,
+                        blocks_per_cu=0, waves_per_block=0)
+    elif use_cache and sc.frames >= 2 * tune_frames:
+        late_frame = tune_frames
+        lt = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, 2 * tune_frames, out,
+                                                    mode=mode, late_frame=late_frame, **best),
+                          args.tune_json + ".late" if args.tune_json else None)
+        b = lt.best
+        late = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
+                    blocks_per_cu=b.blocks_per_cu, waves_per_block=b.waves_per_block)
+        log(f"autotune, frames {late_frame}+: {late} ({lt.n_tried} settings, frames "
+            f"{late_frame}..{2 * tune_frames - 1} after {late_frame} with the first setting)")
     graph = ctx.frame_graph(use_cache, ctx.frame_plan(hits, n_frame, sc.frames, out, mode=mode,
-                                                      clear_cache=True, **best))
+                                                      clear_cache=True, late_frame=late_frame,
+                                                      late=late, **best))
     for _ in range(args.warmup):
         graph.launch()
     torch.cuda.synchronize()
@@ -406,10 +440,11 @@ def main():
     graph.close()
 
     # the same work launched per frame with HIP-event phase timing on the stream
-    def step(m=mode, stats=None, kw=best):
+    def step(m=mode, stats=None):
         if m != B.PMC_MODE_UNCACHED:
             cache.clear()
         for f in range(sc.frames):
+            kw = late if (late_frame and f >= late_frame) else best
             ctx.shade(frame_views[f], out, use_cache if m != B.PMC_MODE_UNCACHED else None,
                       mode=m, frame=f, stats=stats, **kw)
 
@@ -469,7 +504,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "hits_per_step": n_step, "frames": sc.frames,
                    "mode": args.mode, "launch": "one HIP graph per step (table clear + frames)",
-                   "autotuned": best},
+                   "autotuned": best, "late_frame": late_frame, "autotuned_late": late},
         "cache_hit_rate": st["cache_hits"] / max(st["probes"], 1),
         "found_per_sample": st["cache_hits"] / max(st["hits_shaded"], 1),
         "deferred_fraction": st["deferred"] / max(st["hits_shaded"], 1),
@@ -481,8 +516,12 @@ def main():
         "phase_ms_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, best),
-                     "kernel": shade_kernel_name(args.mode, best["flags"]),
+                     "traffic": measured_traffic(args.workload, best, late_frame, late),
+                     "kernel": shade_kernel_name(args.mode, best["flags"]) + (
+                         "" if not late_frame or shade_kernel_name(args.mode, late["flags"]) ==
+                         shade_kernel_name(args.mode, best["flags"]) else
+                         " (frames < %d), %s (later frames)" % (
+                             late_frame, shade_kernel_name(args.mode, late["flags"]))),
                      "bytes_per_launch": kb / sc.frames,
                      "avg_launch_ms": shade_ms / max(shade_launches, 1)},
     }

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define PMC_ABI_VERSION 1u
+#define PMC_ABI_VERSION 2u
 
 typedef int32_t pmc_status;
 enum {
@@ -331,8 +331,13 @@ typedef struct pmc_frame_plan {
     uint32_t out_per_frame;    /* 1: frame f writes entries [f * hits_per_frame, ...);
                                   0: every frame writes entries [0, hits_per_frame) */
     uint32_t clear_cache;      /* 1: empty the table before the first frame */
-    pmc_shade_params params;   /* for every frame; params.frame is ignored */
+    pmc_shade_params params;   /* for every frame before late_frame; params.frame is ignored */
     pmc_stats* stats;          /* device counters accumulated by every frame, or NULL */
+    uint32_t late_frame;       /* 0: params for every frame; else frames late_frame, ...
+                                  (< n_frames) use late_params: once the table holds most
+                                  values, other launch settings can be faster.  Same mode. */
+    uint32_t reserved;
+    pmc_shade_params late_params;
 } pmc_frame_plan;
 
 typedef struct pmc_frame_graph pmc_frame_graph;   /* opaque */
@@ -358,9 +363,11 @@ void pmc_frame_graph_destroy(pmc_frame_graph* graph);
  * each candidate setting of flags (persistence, deferral), chunk_waves,
  * defer_max and blocks_per_cu, timing each with HIP events (best of two
  * runs, the table cleared before each), and writes the fastest setting to
- * *best (mode taken from plan->params).  The table is left cleared.  If
- * json_path is not NULL, every candidate and its time are written there as
- * JSON.  Synchronous. */
+ * *best (mode taken from plan->params).  With plan->late_frame set, the
+ * candidates replace late_params only (frames before late_frame keep
+ * plan->params), which tunes the late frames on a table the early ones
+ * filled.  The table is left cleared.  If json_path is not NULL, every
+ * candidate and its time are written there as JSON.  Synchronous. */
 typedef struct pmc_tune_result {
     pmc_shade_params best;     /* fastest setting found */
     double best_ms;            /* its time for the plan's frames */

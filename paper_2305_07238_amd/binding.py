@@ -103,7 +103,9 @@ class pmc_shade_params(C.Structure):
 class pmc_frame_plan(C.Structure):
     _fields_ = [("hits", pmc_hits), ("hits_per_frame", C.c_uint64), ("n_frames", C.c_uint32),
                 ("first_frame", C.c_uint32), ("out", pmc_bsdf_out), ("out_per_frame", C.c_uint32),
-                ("clear_cache", C.c_uint32), ("params", pmc_shade_params), ("stats", C.c_void_p)]
+                ("clear_cache", C.c_uint32), ("params", pmc_shade_params), ("stats", C.c_void_p),
+                ("late_frame", C.c_uint32), ("reserved", C.c_uint32),
+                ("late_params", pmc_shade_params)]
 
 
 class pmc_tune_result(C.Structure):
@@ -375,15 +377,23 @@ class Context:
                    mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, first_frame: int = 0,
                    out_per_frame: bool = False, clear_cache: bool = True, stats=None,
                    chunk_waves: int = 0, blocks_per_cu: int = 0,
-                   defer_max: int = 0, waves_per_block: int = 0) -> pmc_frame_plan:
+                   defer_max: int = 0, waves_per_block: int = 0, late_frame: int = 0,
+                   late: Optional[dict] = None) -> pmc_frame_plan:
         """hits: torch tensors holding n_frames * hits_per_frame hits, frame-major."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
                      _ptr(hits["normal"]), 0)
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
         prm = pmc_shade_params(mode, flags, 0, chunk_waves, blocks_per_cu, defer_max,
                                waves_per_block)
+        lp = pmc_shade_params()
+        if late_frame:
+            lk = dict(flags=flags, chunk_waves=0, blocks_per_cu=0, defer_max=0,
+                      waves_per_block=0)
+            lk.update(late or {})
+            lp = pmc_shade_params(mode, lk["flags"], 0, lk["chunk_waves"], lk["blocks_per_cu"],
+                                  lk["defer_max"], lk["waves_per_block"])
         plan = pmc_frame_plan(h, hits_per_frame, n_frames, first_frame, o, int(out_per_frame),
-                              int(clear_cache), prm, _ptr(stats))
+                              int(clear_cache), prm, _ptr(stats), late_frame, 0, lp)
         plan._keep = (hits, out, stats)
         return plan
 

@@ -55,6 +55,29 @@ pmc_status check_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p) {
   if (pmc_status st = check_shade_args(ctx, cache, &h0, &o0, &p->params)) return st;
   if (p->params.mode != PMC_MODE_UNCACHED && !cache)
     return ctx->fail(PMC_ERR_INVALID, "cached plan without a cache");
+  if (p->late_frame) {
+    if (p->late_frame >= p->n_frames)
+      return ctx->fail(PMC_ERR_INVALID, "late_frame must be below n_frames");
+    if (p->late_params.mode != p->params.mode)
+      return ctx->fail(PMC_ERR_INVALID, "late_params must keep the plan's mode");
+    if (pmc_status st = check_shade_args(ctx, cache, &h0, &o0, &p->late_params)) return st;
+  }
+  return PMC_OK;
+}
+
+// Workspace for every setting the plan uses (eight sets each, for a frame graph).
+pmc_status reserve_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p,
+                        const pmc_shade_params& early, const pmc_shade_params& late,
+                        bool all_sets, hipStream_t s) {
+  const uint32_t mode = cache ? early.mode : PMC_MODE_UNCACHED;
+  for (int k = 0; k < (p->late_frame ? 2 : 1); ++k) {
+    const pmc_shade_params& q = k ? late : early;
+    const bool probe_first = mode != PMC_MODE_UNCACHED && (q.flags & PMC_FLAG_DEFER);
+    if (pmc_status st = reserve_batch(ctx, cache, (uint32_t)p->hits_per_frame, mode, q.flags,
+                                      resolve_chunk_waves(q.chunk_waves, probe_first), all_sets,
+                                      s))
+      return st;
+  }
   return PMC_OK;
 }
 
@@ -79,8 +102,18 @@ struct Pipe {
 constexpr uint32_t kPipeGroup = kWorkSets / 2;
 
 pmc_status enqueue_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p,
-                        const pmc_shade_params& prm, hipStream_t s, const Pipe* pipe) {
-  const bool piped = pipe && (prm.flags & PMC_FLAG_SORT) && p->n_frames >= 2;
+                        const pmc_shade_params& early, const pmc_shade_params& late,
+                        hipStream_t s, const Pipe* pipe) {
+  // frames from late_frame on use `late` (when the plan sets late_frame)
+  auto params_of = [&](uint32_t f) {
+    pmc_shade_params q = (p->late_frame && f >= p->late_frame) ? late : early;
+    q.frame = p->first_frame + f;
+    return q;
+  };
+  // the sort stream runs ahead only when every frame is sorted
+  const bool all_sorted = (early.flags & PMC_FLAG_SORT) &&
+                          (!p->late_frame || (late.flags & PMC_FLAG_SORT));
+  const bool piped = pipe && all_sorted && p->n_frames >= 2;
   if (piped) {
     // fork before the table clear: the first sort does not wait for it
     HIP_TRY(ctx, hipEventRecord(pipe->start, s));
@@ -94,11 +127,6 @@ pmc_status enqueue_plan(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* p,
     }
     HIP_TRY(ctx, e);
   }
-  auto params_of = [&](uint32_t f) {
-    pmc_shade_params q = prm;
-    q.frame = p->first_frame + f;
-    return q;
-  };
   if (!piped) {
     for (uint32_t f = 0; f < p->n_frames; ++f) {
       pmc_hits h = frame_hits(p, f);
@@ -163,12 +191,7 @@ pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_fram
   if (pmc_status st = check_plan(ctx, cache, plan)) return st;
   hipStream_t cs = nullptr;
   HIP_TRY(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  const uint32_t mode = cache ? plan->params.mode : PMC_MODE_UNCACHED;
-  const bool probe_first = mode != PMC_MODE_UNCACHED && (plan->params.flags & PMC_FLAG_DEFER);
-  pmc_status st = reserve_batch(ctx, cache, (uint32_t)plan->hits_per_frame, mode,
-                                plan->params.flags,
-                                resolve_chunk_waves(plan->params.chunk_waves, probe_first), true,
-                                cs);
+  pmc_status st = reserve_plan(ctx, cache, plan, plan->params, plan->late_params, true, cs);
   Pipe pipe;
   if (st == PMC_OK) {
     bool ok = hipStreamCreateWithFlags(&pipe.side, hipStreamNonBlocking) == hipSuccess;
@@ -194,7 +217,7 @@ pmc_status pmc_frame_graph_create(pmc_ctx* ctx, pmc_cache* cache, const pmc_fram
     if (e != hipSuccess) {
       st = ctx->fail(PMC_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     } else {
-      st = enqueue_plan(ctx, cache, plan, plan->params, cs, &pipe);
+      st = enqueue_plan(ctx, cache, plan, plan->params, plan->late_params, cs, &pipe);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(cs, &graph);
       if (st == PMC_OK && e != hipSuccess)
@@ -294,7 +317,9 @@ pmc_status pmc_autotune(pmc_ctx* ctx, pmc_cache* cache, const pmc_frame_plan* pl
     double best = 1e30;
     for (int rep = 0; rep < 3; ++rep) {           // first run warms up
       HIP_TRY(ctx, hipEventRecord(e0, s));
-      if (pmc_status r = enqueue_plan(ctx, cache, &p, prm, s, nullptr)) return r;
+      // with late_frame, the candidate is the late setting; the early frames keep the plan's
+      const pmc_shade_params& early = p.late_frame ? plan->params : prm;
+      if (pmc_status r = enqueue_plan(ctx, cache, &p, early, prm, s, nullptr)) return r;
       HIP_TRY(ctx, hipEventRecord(e1, s));
       HIP_TRY(ctx, hipEventSynchronize(e1));
       float t = 0.f;

@@ -29,9 +29,14 @@ def _slice(d, f, n):
 
 # 3 frames: groups {0}, {1, 2}; 11 frames: {0}, {1..4}, {5..8}, {9, 10}, so frames
 # 8..10 reuse the workspace sets of frames 0..2 and the sorts wait for shading
-@pytest.mark.parametrize("mode,F", [(B.PMC_MODE_SNAPSHOT, 3), (B.PMC_MODE_UNCACHED, 3),
-                                    (B.PMC_MODE_SNAPSHOT, 11)])
-def test_frame_graph_replays_match_stream_launches(mode, F):
+# late: frames from 5 on use another setting (another kernel variant; with
+# unsorted late frames the sorts do not run on their own stream)
+@pytest.mark.parametrize("mode,F,late", [
+    (B.PMC_MODE_SNAPSHOT, 3, None), (B.PMC_MODE_UNCACHED, 3, None),
+    (B.PMC_MODE_SNAPSHOT, 11, None),
+    (B.PMC_MODE_SNAPSHOT, 11, dict(flags=B.PMC_FLAG_SORT, chunk_waves=1)),
+    (B.PMC_MODE_SNAPSHOT, 7, dict(flags=0, chunk_waves=2))])
+def test_frame_graph_replays_match_stream_launches(mode, F, late):
     """A captured render (sorts pipelined on a second stream) equals the same
     frames launched one by one, bit for bit, on every replay."""
     sc = G.small_mid_scene(frames=F)
@@ -43,13 +48,15 @@ def test_frame_graph_replays_match_stream_launches(mode, F):
     cache_g, cache_s = ctx.cache(1 << 13), ctx.cache(1 << 13)
     stats_g = B.new_stats()
     plan = ctx.frame_plan(hits, n, F, out_g, mode=mode, out_per_frame=True, clear_cache=True,
-                          stats=stats_g)
+                          stats=stats_g, flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER,
+                          late_frame=5 if late else 0, late=late)
     graph = ctx.frame_graph(cache_g if mode != B.PMC_MODE_UNCACHED else None, plan)
     # eager reference
     stats_s = B.new_stats()
     for f in range(F):
+        kw = late if (late and f >= 5) else dict(flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER)
         ctx.shade(_slice(hits, f, n), _slice(out_s, f, n), cache_s if mode else None, mode=mode,
-                  frame=f, stats=stats_s)
+                  frame=f, stats=stats_s, **kw)
     torch.cuda.synchronize()
     ref = G.to_numpy(out_s)
     ref_table = cache_s.export()
@@ -165,3 +172,23 @@ def test_frame_graph_keeps_what_it_uses():
     ctx.compile(sc.materials)
     ctx.shade(hits, out_big, None, mode=B.PMC_MODE_UNCACHED)
     torch.cuda.synchronize()
+
+
+def test_autotune_of_the_late_frames():
+    """With late_frame set the candidates replace the late setting only; the pick is
+    valid and the table is left cleared."""
+    sc = G.small_mid_scene(frames=4)
+    ctx = G.setup(sc)
+    n, F = sc.hits_per_frame, 4
+    hits = _frames_on_device(sc, F)
+    out = B.alloc_outputs(n)
+    cache = ctx.cache(1 << 13)
+    plan = ctx.frame_plan(hits, n, F, out, mode=B.PMC_MODE_CACHED, late_frame=2,
+                          flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, chunk_waves=4)
+    res = ctx.autotune(cache, plan)
+    assert res.n_tried >= 10 and 0 < res.best_ms <= res.default_ms * 1.5
+    assert res.best.flags & B.PMC_FLAG_SORT
+    assert np.count_nonzero(cache.export()) == 0
+    bad = ctx.frame_plan(hits, n, F, out, mode=B.PMC_MODE_CACHED, late_frame=F)
+    with pytest.raises(B.PmcError):
+        ctx.autotune(cache, bad)
