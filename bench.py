@@ -283,6 +283,30 @@ def surrogate_smooth_leg(log):
         last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
         results[name] = {"samples_per_s": n * sc.frames / (ms * 1e-3), "ms": ms, "_out": last}
     _errors_vs_uncached(results)
+    # texels 8x finer than the footprints (level bias +3): the table reuses far
+    # less, so more lookups miss, and a miss of a trusted output costs one
+    # network evaluation instead of the sub-graph
+    fine = ctx.cache(sc.cache.n_cells, 8, 16, level_bias=3)
+    fine_res = {}
+    for name, f in (("cache_only", 0), ("surrogate_cache", B.PMC_FLAG_SURROGATE)):
+        st = B.new_stats()
+
+        def run_fine(pre, f=f, st=st):
+            if pre:
+                for k in trusted:
+                    ctx.surrogate_set_trust(k, True)
+                fine.clear()
+                st.zero_()
+                torch.cuda.synchronize()
+                return
+            for fr in range(sc.frames):
+                ctx.shade(frames[fr], out, fine, mode=B.PMC_MODE_CACHED, frame=fr,
+                          flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER | f, stats=st)
+        ms = _median_ms(run_fine)
+        sd = B.stats_dict(st)
+        fine_res[name] = {"samples_per_s": n * sc.frames / (ms * 1e-3), "ms": ms,
+                          "hit_rate": sd["cache_hits"] / max(sd["probes"], 1),
+                          "surrogate_used": sd["surrogate_used"]}
     ctx.close()
     return {"workload": "smooth: 4 materials of 38 nodes (12 low-frequency Perlin layers averaged, "
                         "MUL/POW chain), 1920x1080 x 4 progressive frames, table 2^22 slots, "
@@ -294,7 +318,10 @@ def surrogate_smooth_leg(log):
             "gain_vs_cache_only": results["cache_only"]["ms"] / results["surrogate_cache"]["ms"],
             "insert_gain_vs_cache_only": (results["cache_only"]["ms"] /
                                           results["surrogate_insert_cache"]["ms"]),
-            "gain_vs_uncached": results["uncached"]["ms"] / results["surrogate_cache"]["ms"]}
+            "gain_vs_uncached": results["uncached"]["ms"] / results["surrogate_cache"]["ms"],
+            "fine_texels": dict(fine_res, level_bias=3,
+                                gain_vs_cache_only=(fine_res["cache_only"]["ms"] /
+                                                    fine_res["surrogate_cache"]["ms"]))}
 
 
 def cpu_baseline(sc, sample_hits=786432, frames=3):
