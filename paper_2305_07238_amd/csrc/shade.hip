@@ -786,19 +786,35 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
         }
         if (a.log && ((MH->surr_mask >> ord) & 1u))
           log_append(a, logged, m, ord, hd.u, hd.v, val, is_c, cnt);
-        if (SURR && ((au.mask >> ord) & 1u)) {
-          // audited lane: the graph's value against the network's
-          const uint32_t ch = (MH->surr_chan >> (4u * ord)) & 0xFu;
-          float e = fabsf(val.x - pick4(au.y, ch));
-          if (is_c) {
-            const float e1 = fabsf(val.y - pick4(au.y, ch + 1u));
-            const float e2 = fabsf(val.z - pick4(au.y, ch + 2u));
-            e = (e1 > e || e1 != e1) ? e1 : e;
-            e = (e2 > e || e2 != e2) ? e2 : e;
+        if (SURR) {
+          // audited lanes: the graph's value against the network's
+          const bool aud = (au.mask >> ord) & 1u;
+          uint32_t ebits = 0u;
+          if (aud) {
+            const uint32_t ch = (MH->surr_chan >> (4u * ord)) & 0xFu;
+            float e = fabsf(val.x - pick4(au.y, ch));
+            if (is_c) {
+              const float e1 = fabsf(val.y - pick4(au.y, ch + 1u));
+              const float e2 = fabsf(val.z - pick4(au.y, ch + 2u));
+              e = (e1 > e || e1 != e1) ? e1 : e;
+              e = (e2 > e || e2 != e2) ? e2 : e;
+            }
+            ebits = e != e ? 0x7FC00000u : __float_as_uint(e);   // NaN above every error
           }
-          SurrState* ss = a.surr_state + au.slot;
-          atomicMax(&ss->live_err_bits, e != e ? 0x7FC00000u : __float_as_uint(e));
-          atomicAdd(&ss->live_n, 1u);
+          // one update per wave (the lanes share the material's slot): the per-lane
+          // atomics on a few addresses serialised the audited waves
+          const uint64_t am = __ballot(aud);
+          if (am) {
+            uint32_t mx = 0u;
+            for (uint64_t t = am; t; t &= t - 1ull)
+              mx = max(mx, (uint32_t)__builtin_amdgcn_readlane(
+                                (int)ebits, __ffsll((unsigned long long)t) - 1));
+            if (lane_id() == __ffsll((unsigned long long)am) - 1) {
+              SurrState* ss = a.surr_state + au.slot;
+              atomicMax(&ss->live_err_bits, mx);
+              atomicAdd(&ss->live_n, (uint32_t)__popcll(am));
+            }
+          }
         }
       }
     }
