@@ -20,6 +20,12 @@ Readings (the paper fixes none of these):
     k1 = (u32)tx << 32 | (u32)ty;
   * cell = hi32(H(SEED_CELL)) % N_c, hash2 = lo32(H(SEED_VERIFY)), 0 -> 1
     (a stored hash of 0 would read as an empty entry in Algorithm 1).
+
+``hash2_mask`` keeps only some bits of the verification hash before the
+0 -> 1 step.  It exists to force the verification collisions that Sec. 3.2
+says cannot be avoided (with the full 32 bits they are too rare to observe),
+so that false hits can be produced and counted; the method itself uses all
+32 bits.
 """
 import numpy as np
 
@@ -64,7 +70,7 @@ class Keys:
 
 
 def compute_keys(mat_id, node, socket, uv, duv, n_cells, level_bias=0,
-                 level_max=LEVEL_MAX_DEFAULT) -> Keys:
+                 level_max=LEVEL_MAX_DEFAULT, hash2_mask=0xFFFFFFFF) -> Keys:
     uv32 = np.asarray(uv, dtype=np.float32)
     duv32 = np.asarray(duv, dtype=np.float32)
     finite = np.all(np.isfinite(uv32), axis=1) & np.all(np.isfinite(duv32), axis=1)
@@ -84,6 +90,6 @@ def compute_keys(mat_id, node, socket, uv, duv, n_cells, level_bias=0,
     hc = descriptor_hash(k0, k1, SEED_CELL)
     hv = descriptor_hash(k0, k1, SEED_VERIFY)
     cell = ((hc >> U(32)) % U(n_cells)).astype(np.int64)
-    h2 = (hv & U(0xFFFFFFFF)).astype(np.int64)
+    h2 = (hv & U(int(hash2_mask) & 0xFFFFFFFF)).astype(np.int64)
     h2 = np.where(h2 == 0, 1, h2)
     return Keys(bypass, lv, tx, ty, k0, k1, cell, h2)

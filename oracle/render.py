@@ -71,7 +71,8 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
                          kmax: int = 8, cacheables: Optional[list] = None,
                          surrogate: Optional[dict] = None,
                          surrogate_values: Optional[np.ndarray] = None,
-                         surrogate_insert: bool = False) -> FrameResult:
+                         surrogate_insert: bool = False,
+                         hash2_mask: int = 0xFFFFFFFF) -> FrameResult:
     """One snapshot-mode frame; mutates ``table`` into T_f and returns the frame's results.
 
     surrogate: optional {material: dict(params=[W1, b1, W2, b2, W3, b3],
@@ -84,13 +85,19 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
     follows them against another implementation's network outputs).
     surrogate_insert: the substituted values are inserted too (as candidates of
     their hits, like graph values).
+    hash2_mask: bits of the verification hash kept (forces collisions; see keys).
+    Lookups pass the full descriptor, so ``stats["false_hits"]`` counts hits on
+    entries written for another descriptor (Sec. 3.2).  Under the PRIORITY
+    policy each candidate carries its hit's bounce count (``hits.bounce``,
+    0 when absent).
     """
     n = len(hits)
     res = FrameResult(n, kmax)
     mat = hits.material.astype(np.int64)
     if cacheables is None:
         cacheables = [graph.cacheable_outputs(m, min_subgraph_nodes) for m in materials]
-    candidates = []                                  # (hit, ordinal, cell, hash2, enc)
+    candidates = []                                  # (hit, ordinal, cell, hash2, enc, key)
+    false0 = table.false_hits
     for m in np.unique(mat):
         idx = np.nonzero(mat == m)[0]
         if m >= len(materials):
@@ -105,7 +112,7 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
         key_list = []
         for c, (node, sock) in enumerate(cach):
             ky = K.compute_keys(int(m), node, sock, hits.uv[idx], hits.duv[idx], table.n_cells,
-                                level_bias, level_max)
+                                level_bias, level_max, hash2_mask)
             key_list.append(ky)
             otype = graph.output_type(material, node, sock)
             found = np.zeros(len(idx), dtype=bool)
@@ -113,7 +120,8 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
             for j in range(len(idx)):
                 if ky.bypass[j]:
                     continue
-                hit, enc = table.lookup(int(ky.cell[j]), int(ky.hash2[j]))
+                hit, enc = table.lookup(int(ky.cell[j]), int(ky.hash2[j]),
+                                        (int(ky.k0[j]), int(ky.k1[j])))
                 found[j] = hit
                 encs[j] = enc
             res.valid[idx, c] = True
@@ -175,7 +183,8 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
             miss, vals = miss[fin], vals[fin]
             encs = encode(vals, otype)
             for j, enc in zip(miss, encs):
-                candidates.append((int(idx[j]), c, int(ky.cell[j]), int(ky.hash2[j]), int(enc)))
+                candidates.append((int(idx[j]), c, int(ky.cell[j]), int(ky.hash2[j]), int(enc),
+                                   (int(ky.k0[j]), int(ky.k1[j]))))
             if surrogate_insert:
                 sub_rows = np.nonzero(res.surrogate[idx, c])[0]
                 if len(sub_rows):
@@ -184,7 +193,7 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
                     fin = np.isfinite(sv) if sv.ndim == 1 else np.all(np.isfinite(sv), axis=1)
                     for j, enc in zip(sub_rows[fin], encode(sv[fin], otype)):
                         candidates.append((int(idx[j]), c, int(ky.cell[j]), int(ky.hash2[j]),
-                                           int(enc)))
+                                           int(enc), (int(ky.k0[j]), int(ky.k1[j]))))
             if sinfo is not None and c in sinfo["ordmap"]:
                 base, width = sinfo["ordmap"][c]
                 for j, val in zip(miss, vals):
@@ -200,18 +209,22 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
                         res.live_err[int(m)] = max(res.live_err.get(int(m), 0.0), float(e))
     res.stats["misses"] = res.stats["probes"] - res.stats["hits"]
     res.stats["candidates"] = len(candidates)
+    res.stats["false_hits"] = table.false_hits - false0
     candidates.sort(key=lambda t: (t[0], t[1]))
-    for h, c, cell, h2, enc in candidates:
-        res.stats[table.insert(cell, h2, enc, policy, frame)] += 1
+    bounce = getattr(hits, "bounce", None)
+    for h, c, cell, h2, enc, key in candidates:
+        b = int(bounce[h]) if bounce is not None else 0
+        res.stats[table.insert(cell, h2, enc, policy, frame, key=key, bounce=b)] += 1
     return res
 
 
 def shade_snapshot(materials, textures, frames: List, table: Table, policy: str = FIRST,
                    level_bias: int = 0, level_max: int = K.LEVEL_MAX_DEFAULT,
                    min_subgraph_nodes: int = 2, kmax: int = 8, first_frame: int = 0,
-                   surrogate: Optional[dict] = None):
+                   surrogate: Optional[dict] = None, hash2_mask: int = 0xFFFFFFFF):
     """Progressive snapshot render of a list of hit batches; returns one FrameResult each."""
     cach = [graph.cacheable_outputs(m, min_subgraph_nodes) for m in materials]
     return [shade_snapshot_frame(materials, textures, h, table, first_frame + f, policy,
-                                 level_bias, level_max, min_subgraph_nodes, kmax, cach, surrogate)
+                                 level_bias, level_max, min_subgraph_nodes, kmax, cach, surrogate,
+                                 hash2_mask=hash2_mask)
             for f, h in enumerate(frames)]
