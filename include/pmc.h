@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define PMC_ABI_VERSION 2u
+#define PMC_ABI_VERSION 3u
 
 typedef int32_t pmc_status;
 enum {
@@ -161,7 +161,15 @@ pmc_status pmc_get_material_info(const pmc_ctx* ctx, uint32_t mat, pmc_material_
 
 enum pmc_policy {
     PMC_POLICY_FIRST = 0,      /* keep the first inserted value (Sec. 3.2) */
-    PMC_POLICY_OVERWRITE = 1   /* evict the oldest-stamped entry of a full cell (16-byte entries) */
+    PMC_POLICY_OVERWRITE = 1,  /* evict the oldest-stamped entry of a full cell (16-byte entries) */
+    PMC_POLICY_PRIORITY = 2    /* prefer samples of small path depth (Sec. 5 future work: keep
+                                  directly visible samples when storage is short).  16-byte
+                                  entries; the reserved word of an entry holds the depth
+                                  (pmc_hits.bounce) of the sample that wrote it.  A full cell
+                                  gives up its entry of the largest depth, then the oldest
+                                  stamp, lowest index on ties; it is replaced when its depth
+                                  is larger than the new sample's, or equal and written
+                                  before the current frame */
 };
 
 typedef struct pmc_cache_params {
@@ -171,10 +179,14 @@ typedef struct pmc_cache_params {
     uint32_t policy;           /* enum pmc_policy */
     int32_t level_bias;        /* integer offset added to floor(lambda) (Sec. 4 level offset) */
     uint32_t level_max;        /* levels clamp to [0, level_max]; 0 = 20 */
-    uint32_t reserved;
+    uint32_t hash2_mask;       /* bits of the verification hash (Sec. 3.2) kept before the
+                                  0 -> 1 step; 0 = all 32 bits (the method).  Fewer bits force
+                                  the verification collisions that Sec. 3.2 says cannot be
+                                  avoided, for tests of false hits */
 } pmc_cache_params;
 
-/* Create a table of n_cells * n_entries * entry_bytes bytes.  device_mem NULL:
+/* Create a table of n_cells * n_entries * entry_bytes bytes (16-byte entries
+ * for OVERWRITE and PRIORITY: PMC_ERR_INVALID otherwise).  device_mem NULL:
  * the library allocates it; else the caller's device buffer of at least that
  * size (256-byte aligned) is used and stays caller-owned.  The table starts
  * cleared (synchronous).  Word layout: hash2 << 32 | 32-bit encoded value;
@@ -203,6 +215,8 @@ typedef struct pmc_hits {      /* all device pointers, caller-owned, n entries e
     const float* duv;          /* [n][4]: g1.x, g1.y, g2.x, g2.y (ray-cone UV gradients, Sec. 3.1) */
     const float* normal;       /* [n][3] unit shading normal */
     uint64_t n;                /* hits; < 2^27 per call */
+    const uint32_t* bounce;    /* [n] path depth of the hit (0 = seen from the camera), read
+                                  only under PMC_POLICY_PRIORITY; NULL = all 0 */
 } pmc_hits;
 
 typedef struct pmc_bsdf_out {  /* device pointers, caller-owned */

@@ -54,6 +54,7 @@ class FrameResult:
         self.outputs = dict(base_color=np.zeros((n, 3)), roughness=np.zeros(n),
                             normal=np.zeros((n, 3)))
         self.found = np.zeros((n, kmax), dtype=bool)        # cache hit per (hit, ordinal)
+        self.false_hit = np.zeros((n, kmax), dtype=bool)    # hit on another descriptor's entry
         self.bypass = np.zeros((n, kmax), dtype=bool)
         self.valid = np.zeros((n, kmax), dtype=bool)        # ordinal exists for the hit's material
         self.found_value = np.full((n, kmax, 3), np.nan)    # decoded value on a cache hit
@@ -120,10 +121,13 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
             for j in range(len(idx)):
                 if ky.bypass[j]:
                     continue
+                f0 = table.false_hits
                 hit, enc = table.lookup(int(ky.cell[j]), int(ky.hash2[j]),
                                         (int(ky.k0[j]), int(ky.k1[j])))
                 found[j] = hit
                 encs[j] = enc
+                if table.false_hits != f0:
+                    res.false_hit[idx[j], c] = True
             res.valid[idx, c] = True
             res.bypass[idx, c] = ky.bypass
             res.found[idx, c] = found

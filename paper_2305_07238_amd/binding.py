@@ -36,7 +36,7 @@ OPS = {"UV_INPUT": 0, "IMAGE_TEXTURE": 1, "VALUE_NOISE": 2, "PERLIN_NOISE": 3, "
        "MATH": 5, "COLOR_RAMP": 6, "NORMAL_MAP": 7, "BSDF_OUTPUT": 8}
 MATH_OPS = {"ADD": 0, "MUL": 1, "POW": 2}
 PMC_NODE_CLAMP = 1
-PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE = 0, 1
+PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE, PMC_POLICY_PRIORITY = 0, 1, 2
 PMC_MODE_UNCACHED, PMC_MODE_CACHED, PMC_MODE_SNAPSHOT = 0, 1, 2
 PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_DEFER, PMC_FLAG_LOG, PMC_FLAG_SURROGATE = 1, 2, 4, 8, 16
 PMC_FLAG_SURROGATE_INSERT = 32
@@ -77,12 +77,12 @@ class pmc_material_info(C.Structure):
 class pmc_cache_params(C.Structure):
     _fields_ = [("n_cells", C.c_uint64), ("n_entries", C.c_uint32), ("entry_bytes", C.c_uint32),
                 ("policy", C.c_uint32), ("level_bias", C.c_int32), ("level_max", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("hash2_mask", C.c_uint32)]
 
 
 class pmc_hits(C.Structure):
     _fields_ = [("material", C.c_void_p), ("uv", C.c_void_p), ("duv", C.c_void_p),
-                ("normal", C.c_void_p), ("n", C.c_uint64)]
+                ("normal", C.c_void_p), ("n", C.c_uint64), ("bounce", C.c_void_p)]
 
 
 class pmc_bsdf_out(C.Structure):
@@ -344,18 +344,19 @@ class Context:
 
     def cache(self, n_cells: int, n_entries: int = 8, entry_bytes: int = 16,
               policy: int = PMC_POLICY_FIRST, level_bias: int = 0, level_max: int = 0,
-              device_mem=None) -> "Cache":
+              device_mem=None, hash2_mask: int = 0) -> "Cache":
         return Cache(self, n_cells, n_entries, entry_bytes, policy, level_bias, level_max,
-                     device_mem)
+                     device_mem, hash2_mask)
 
     def shade(self, hits: dict, out: dict, cache: Optional["Cache"] = None,
               mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, frame: int = 0,
               stats=None, debug: Optional[dict] = None, chunk_waves: int = 0,
               blocks_per_cu: int = 0, defer_max: int = 0, waves_per_block: int = 0,
               stream=None):
-        """hits: dict of torch CUDA tensors material/uv/duv/normal; out: base_color/roughness/normal."""
+        """hits: dict of torch CUDA tensors material/uv/duv/normal (and optionally bounce);
+        out: base_color/roughness/normal."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
-                     _ptr(hits["normal"]), int(hits["material"].numel()))
+                     _ptr(hits["normal"]), int(hits["material"].numel()), _ptr(hits.get("bounce")))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
         p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max,
                              waves_per_block)
@@ -381,7 +382,7 @@ class Context:
                    late: Optional[dict] = None) -> pmc_frame_plan:
         """hits: torch tensors holding n_frames * hits_per_frame hits, frame-major."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
-                     _ptr(hits["normal"]), 0)
+                     _ptr(hits["normal"]), 0, _ptr(hits.get("bounce")))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
         prm = pmc_shade_params(mode, flags, 0, chunk_waves, blocks_per_cu, defer_max,
                                waves_per_block)
@@ -511,10 +512,10 @@ class FrameGraph:
 
 class Cache:
     def __init__(self, ctx: Context, n_cells, n_entries, entry_bytes, policy, level_bias,
-                 level_max, device_mem=None):
+                 level_max, device_mem=None, hash2_mask=0):
         self.ctx = ctx
         self.params = pmc_cache_params(int(n_cells), n_entries, entry_bytes, policy, level_bias,
-                                       level_max, 0)
+                                       level_max, int(hash2_mask) & 0xFFFFFFFF)
         h = C.c_void_p()
         ctx.check(pmc_cache_create(ctx.h, C.byref(self.params), _ptr(device_mem), C.byref(h)))
         self.h = h
@@ -565,12 +566,16 @@ class Cache:
 def hits_to_device(hits, device="cuda"):
     """scenes.Hits (numpy) -> dict of torch tensors on the device."""
     import torch
-    return {
+    d = {
         "material": torch.from_numpy(np.ascontiguousarray(hits.material, np.uint32).view(np.int32)).to(device),
         "uv": torch.from_numpy(np.ascontiguousarray(hits.uv, np.float32)).to(device),
         "duv": torch.from_numpy(np.ascontiguousarray(hits.duv, np.float32)).to(device),
         "normal": torch.from_numpy(np.ascontiguousarray(hits.normal, np.float32)).to(device),
     }
+    if getattr(hits, "bounce", None) is not None:
+        d["bounce"] = torch.from_numpy(
+            np.ascontiguousarray(hits.bounce, np.uint32).view(np.int32)).to(device)
+    return d
 
 
 def alloc_outputs(n: int, device="cuda"):

@@ -302,9 +302,9 @@ pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* p, void* devic
     return ctx->fail(PMC_ERR_INVALID, "n_entries must be in [1, 64]");
   if (p->entry_bytes != 8 && p->entry_bytes != 16)
     return ctx->fail(PMC_ERR_INVALID, "entry_bytes must be 8 or 16");
-  if (p->policy > PMC_POLICY_OVERWRITE) return ctx->fail(PMC_ERR_INVALID, "unknown policy");
-  if (p->policy == PMC_POLICY_OVERWRITE && p->entry_bytes != 16)
-    return ctx->fail(PMC_ERR_INVALID, "OVERWRITE needs 16-byte entries (stamps)");
+  if (p->policy > PMC_POLICY_PRIORITY) return ctx->fail(PMC_ERR_INVALID, "unknown policy");
+  if (p->policy != PMC_POLICY_FIRST && p->entry_bytes != 16)
+    return ctx->fail(PMC_ERR_INVALID, "OVERWRITE and PRIORITY need 16-byte entries (stamps)");
   if (p->level_max > 30) return ctx->fail(PMC_ERR_INVALID, "level_max must be <= 30");
   pmc_cache* c = new (std::nothrow) pmc_cache();
   if (!c) return PMC_ERR_OOM;
@@ -312,6 +312,7 @@ pmc_status pmc_cache_create(pmc_ctx* ctx, const pmc_cache_params* p, void* devic
   c->device = ctx->device;
   c->params = *p;
   if (c->params.level_max == 0) c->params.level_max = 20;
+  if (c->params.hash2_mask == 0) c->params.hash2_mask = 0xFFFFFFFFu;
   c->bytes = (size_t)p->n_cells * p->n_entries * p->entry_bytes;
   if (device_mem) {
     if (((uintptr_t)device_mem & 255u) != 0) {
@@ -402,6 +403,7 @@ static void fill_cache_args(pmc_cache* c, ShadeArgs& a) {
   a.n_entries = c->params.n_entries;
   a.entry_words = c->params.entry_bytes / 8;
   a.policy = c->params.policy;
+  a.hash2_mask = c->params.hash2_mask;
   a.level_bias = c->params.level_bias;
   a.level_max = (int32_t)c->params.level_max;
 }
@@ -562,6 +564,7 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.uv = hits->uv;
   a.duv = hits->duv;
   a.normal = hits->normal;
+  a.bounce = hits->bounce;
   a.n = n;
   a.mode = mode;
   a.out_base = out->base_color;
@@ -635,6 +638,7 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     sa.entry_words = a.entry_words;
     sa.policy = a.policy;
     sa.frame = a.frame;
+    sa.bounce = a.bounce;
     sa.cand = a.cand;
     sa.sorted = (uint4*)cache->sorted.p;
     sa.cand_count = a.cand_count;

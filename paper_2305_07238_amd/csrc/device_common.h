@@ -61,8 +61,11 @@ struct Key {
 // Level: floor(lambda) with lambda = -log2(min |g|) (Eq. 1), from the binary64
 // squared norms; frexp gives m2 = f 2^e, f in [1/2, 1), and then
 // floor(lambda) = floor((-e + [f == 1/2]) / 2).
+// h2mask keeps bits of the verification hash (all 32 in the method; fewer only
+// to force verification collisions in tests).
 __device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float u, float v,
-                                        float4 g, int bias, int lmax, const CellMap& cells) {
+                                        float4 g, int bias, int lmax, const CellMap& cells,
+                                        uint32_t h2mask) {
   Key k;
   k.cell = 0; k.hash2 = 1; k.level = 0; k.tx = 0; k.ty = 0; k.bypass = true;
   if (!(isfinite(u) && isfinite(v) && isfinite(g.x) && isfinite(g.y) && isfinite(g.z) &&
@@ -92,7 +95,7 @@ __device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float 
   uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
   uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
   k.cell = cell_of(cells, (uint32_t)(hc >> 32));
-  k.hash2 = (uint32_t)hv;
+  k.hash2 = (uint32_t)hv & h2mask;
   if (k.hash2 == 0) k.hash2 = 1;
   k.level = L; k.tx = tx; k.ty = ty; k.bypass = false;
   return k;
@@ -100,11 +103,11 @@ __device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float 
 
 // Descriptor hashes of raw descriptor words (Algorithm 1 surface).
 __device__ __forceinline__ void raw_hash(uint64_t k0, uint64_t k1, const CellMap& cells,
-                                         uint32_t* cell, uint32_t* hash2) {
+                                         uint32_t h2mask, uint32_t* cell, uint32_t* hash2) {
   uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
   uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
   *cell = cell_of(cells, (uint32_t)(hc >> 32));
-  uint32_t h = (uint32_t)hv;
+  uint32_t h = (uint32_t)hv & h2mask;
   *hash2 = h ? h : 1u;
 }
 

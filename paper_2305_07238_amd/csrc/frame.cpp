@@ -33,6 +33,7 @@ pmc_hits frame_hits(const pmc_frame_plan* p, uint32_t f) {
   h.uv = p->hits.uv + 2 * o;
   h.duv = p->hits.duv + 4 * o;
   h.normal = p->hits.normal + 3 * o;
+  h.bounce = p->hits.bounce ? p->hits.bounce + o : nullptr;
   h.n = p->hits_per_frame;
   return h;
 }

@@ -37,6 +37,7 @@ struct ShadeArgs {
   const float* uv;
   const float* duv;
   const float* normal;
+  const uint32_t* bounce;        // path depth per hit (PRIORITY policy), NULL = all 0
   const uint32_t* perm;          // processing order (material-sorted), NULL = identity
   uint32_t n;
   uint32_t mode;
@@ -51,6 +52,7 @@ struct ShadeArgs {
   uint32_t n_entries;
   uint32_t entry_words;          // 64-bit words per entry: 1 (8 B) or 2 (16 B)
   uint32_t policy;
+  uint32_t hash2_mask;           // bits of the verification hash kept (all 32 in the method)
   int32_t level_bias;
   int32_t level_max;
   uint32_t frame;
@@ -137,6 +139,7 @@ hipError_t launch_material_sort_tiled(const uint32_t* material, uint32_t n, uint
 struct SnapshotArgs {
   uint64_t* table;
   uint32_t n_cells, n_entries, entry_words, policy, frame;
+  const uint32_t* bounce;        // path depth of hit seq >> 5 (PRIORITY policy), NULL = all 0
   const uint4* cand;
   uint4* sorted;
   const uint32_t* cand_count;

@@ -296,12 +296,26 @@ __device__ __forceinline__ uint64_t load_relaxed(uint64_t* p) {
 
 // Algorithm 1: find the first entry holding hash2 or empty, then CAS(0 -> new).
 // OVERWRITE: a full cell evicts the entry with the smallest stamp, if older
-// than this frame.  Returns the outcome (counted by the caller without
-// branches, which keeps the counters in registers).
+// than this frame.  PRIORITY (after Sec. 5: prefer directly visible samples
+// when storage is short): a full cell gives up its entry of the largest path
+// depth (aux field), then the smallest stamp; it is replaced when its depth is
+// larger than the sample's, or equal and older than this frame, and the new
+// entry keeps the sample's depth.  Returns the outcome (counted by the caller
+// without branches, which keeps the counters in registers).
 enum { INS_DONE = 0, INS_PRESENT = 1, INS_CAS_FAIL = 2, INS_FULL = 3, INS_OVERWRITE = 4 };
 
+__device__ __forceinline__ uint32_t lane_bounce(const ShadeArgs& a, uint32_t h) {
+  return (a.policy == PMC_POLICY_PRIORITY && a.bounce) ? a.bounce[h] : 0u;
+}
+
+__device__ __forceinline__ void store_stamp(const ShadeArgs& a, uint64_t* p, uint32_t bounce) {
+  if (a.entry_words != 2) return;
+  ((uint32_t*)p)[2] = a.frame + 1u;
+  if (a.policy == PMC_POLICY_PRIORITY) ((uint32_t*)p)[3] = bounce;
+}
+
 __device__ __forceinline__ int cache_insert(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
-                                            uint32_t code) {
+                                            uint32_t code, uint32_t bounce = 0u) {
   const uint64_t neu = ((uint64_t)hash2 << 32) | code;
   int idx = -1;
   for (uint32_t i = 0; i < a.n_entries; ++i) {
@@ -317,27 +331,34 @@ __device__ __forceinline__ int cache_insert(const ShadeArgs& a, uint32_t cell, u
     uint64_t expected = 0ull;
     bool ok = __hip_atomic_compare_exchange_strong(p, &expected, neu, __ATOMIC_RELAXED,
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ok && a.entry_words == 2) ((uint32_t*)p)[2] = a.frame + 1u;
+    if (ok) store_stamp(a, p, bounce);
     return ok ? INS_DONE : ((uint32_t)(expected >> 32) == hash2 ? INS_PRESENT : INS_CAS_FAIL);
   }
-  if (a.policy == PMC_POLICY_OVERWRITE && a.entry_words == 2) {
-    uint32_t best = 0xFFFFFFFFu;
+  const bool prio = a.policy == PMC_POLICY_PRIORITY;
+  if ((a.policy == PMC_POLICY_OVERWRITE || prio) && a.entry_words == 2) {
+    // victim: smallest (-depth, stamp) (depth 0 for OVERWRITE), lowest index on ties
+    uint32_t best_st = 0xFFFFFFFFu, best_b = 0u;
     int victim = -1;
     for (uint32_t i = 0; i < a.n_entries; ++i) {
       uint32_t* sp = (uint32_t*)entry_word(a, cell, i) + 2;
       uint32_t st = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (st < best) {
-        best = st;
+      uint32_t b = prio ? __hip_atomic_load(sp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : 0u;
+      if (victim < 0 || b > best_b || (b == best_b && st < best_st)) {
+        best_st = st;
+        best_b = b;
         victim = (int)i;
       }
     }
-    if (victim >= 0 && best < a.frame + 1u) {
+    const bool older = best_st < a.frame + 1u;
+    const bool replace = prio ? (best_b > bounce || (best_b == bounce && older)) : older;
+    if (victim >= 0 && replace) {
       uint64_t* p = entry_word(a, cell, (uint32_t)victim);
       uint64_t observed = load_relaxed(p);
       bool ok = (uint32_t)(observed >> 32) != hash2 &&
                 __hip_atomic_compare_exchange_strong(p, &observed, neu, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (ok) ((uint32_t*)p)[2] = a.frame + 1u;
+      if (ok) store_stamp(a, p, bounce);
       return ok ? INS_OVERWRITE : INS_CAS_FAIL;
     }
   }
@@ -356,7 +377,7 @@ __device__ __forceinline__ int cache_insert_at(const ShadeArgs& a, uint32_t cell
   const uint64_t neu = ((uint64_t)hash2 << 32) | code;
   bool ok = __hip_atomic_compare_exchange_strong(p, &expected, neu, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (ok && a.entry_words == 2) ((uint32_t*)p)[2] = a.frame + 1u;
+  if (ok) store_stamp(a, p, 0u);
   return ok ? INS_DONE : ((uint32_t)(expected >> 32) == hash2 ? INS_PRESENT : INS_CAS_FAIL);
 }
 
@@ -565,13 +586,13 @@ __device__ __forceinline__ void surrogate_substitute(const ShadeArgs& a, uint32_
       bool want = isfinite(v0) && (!is_c || (isfinite(v1) && isfinite(v2)));
       const uint32_t code = is_c ? rgb9e5_encode(v0, v1, v2) : __float_as_uint(v0);
       const Key k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max,
-                             a.cells);
+                             a.cells, a.hash2_mask);
       want = want && !k.bypass;
       cnt.v[CNT_INS_TRIED] += (uint32_t)want;
       if (MODE == PMC_MODE_SNAPSHOT) {
         append_candidate(a, want, k.cell, k.hash2, code, h * 32u + c, cnt);
       } else {
-        const int o = want ? cache_insert(a, k.cell, k.hash2, code) : INS_FULL;
+        const int o = want ? cache_insert(a, k.cell, k.hash2, code, lane_bounce(a, h)) : INS_FULL;
         count_insert(cnt, want, o);
       }
     }
@@ -618,7 +639,8 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
     k.bypass = true; k.cell = 0u; k.hash2 = 0u;
     if (has) {
       cd = a.cach[cbeg + c];
-      k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.cells);
+      k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.cells,
+                   a.hash2_mask);
     }
     const bool skipped = (skip >> c) & 1u;
     const uint32_t h2 = (has && !k.bypass && !skipped) ? k.hash2 : 0u;
@@ -761,7 +783,7 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
             code = is_c ? rgb9e5_encode(val.x, val.y, val.z) : __float_as_uint(val.x);
             const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + ord;
             Key k = make_key(m, cd->node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max,
-                             a.cells);
+                             a.cells, a.hash2_mask);
             cell = k.cell;
             hash2 = k.hash2;
           }
@@ -778,7 +800,7 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
               // another key took that entry since the lookup: run Algorithm 1 afresh
               if (o == INS_CAS_FAIL) o = cache_insert(a, cell, hash2, code);
             } else {
-              o = cache_insert(a, cell, hash2, code);
+              o = cache_insert(a, cell, hash2, code, lane_bounce(a, h));
             }
           }
           count_insert(cnt, want, o);
@@ -1314,7 +1336,8 @@ __global__ void k_debug_keys(ShadeArgs a, pmc_key_record* out) {
     r.cell = 0; r.hash2 = 0; r.level = 0; r.tx = 0; r.ty = 0; r.bypass = 2;
     if (c < n_cach) {
       const CachDesc cd = a.cach[a.hdr[m].cach_begin + c];
-      Key k = make_key(m, cd.node_sock, uv.x, uv.y, g, a.level_bias, a.level_max, a.cells);
+      Key k = make_key(m, cd.node_sock, uv.x, uv.y, g, a.level_bias, a.level_max, a.cells,
+                       a.hash2_mask);
       r.bypass = k.bypass ? 1u : 0u;
       if (!k.bypass) {
         r.cell = k.cell; r.hash2 = k.hash2; r.level = k.level; r.tx = k.tx; r.ty = k.ty;
@@ -1340,7 +1363,7 @@ __global__ void k_insert_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1
   int o = INS_FULL;
   if (i < n) {
     uint32_t cell, hash2;
-    raw_hash(k0[i], k1[i], a.cells, &cell, &hash2);
+    raw_hash(k0[i], k1[i], a.cells, a.hash2_mask, &cell, &hash2);
     o = cache_insert(a, cell, hash2, enc[i]);
   }
   count_insert(cnt, i < n, o);
@@ -1352,7 +1375,7 @@ __global__ void k_lookup_raw(ShadeArgs a, const uint64_t* k0, const uint64_t* k1
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t cell, hash2, code = 0;
-  raw_hash(k0[i], k1[i], a.cells, &cell, &hash2);
+  raw_hash(k0[i], k1[i], a.cells, a.hash2_mask, &cell, &hash2);
   uint32_t slot;
   bool f = cache_lookup(a, cell, hash2, &code, &slot);
   hit[i] = f ? 1 : 0;

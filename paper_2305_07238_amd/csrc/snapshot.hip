@@ -26,11 +26,15 @@ __global__ __launch_bounds__(256) void k_cand_scatter(SnapshotArgs a) {
   }
 }
 
-// Algorithm 1 on one cell for one candidate key (FIRST, or OVERWRITE with
-// 16-byte entries); returns 0 inserted, 1 present, 2 full, 3 overwritten.
+// Algorithm 1 on one cell for one candidate key (FIRST; OVERWRITE or PRIORITY
+// with 16-byte entries); returns 0 inserted, 1 present, 2 full, 3 overwritten.
+// PRIORITY: the victim is the entry of the largest path depth (aux), then the
+// smallest stamp, then the lowest index; it is replaced when its depth exceeds
+// the candidate's, or equals it and the entry predates this frame.
 __device__ __forceinline__ int apply_one(uint64_t* w0, const SnapshotArgs& a, uint32_t hash2,
-                                         uint32_t code, uint32_t stamp) {
+                                         uint32_t code, uint32_t stamp, uint32_t bounce) {
   const uint64_t neu = ((uint64_t)hash2 << 32) | code;
+  const bool prio = a.policy == PMC_POLICY_PRIORITY;
   int idx = -1;
   for (uint32_t i = 0; i < a.n_entries; ++i) {
     uint32_t h = (uint32_t)(w0[(uint64_t)i * a.entry_words] >> 32);
@@ -40,24 +44,34 @@ __device__ __forceinline__ int apply_one(uint64_t* w0, const SnapshotArgs& a, ui
     uint64_t* p = w0 + (uint64_t)idx * a.entry_words;
     if (*p != 0ull) return 1;
     *p = neu;
-    if (a.entry_words == 2) ((uint32_t*)p)[2] = stamp;
+    if (a.entry_words == 2) {
+      ((uint32_t*)p)[2] = stamp;
+      if (prio) ((uint32_t*)p)[3] = bounce;
+    }
     return 0;
   }
-  if (a.policy == PMC_POLICY_OVERWRITE && a.entry_words == 2) {
-    uint32_t bs = 0xFFFFFFFFu;
+  if ((a.policy == PMC_POLICY_OVERWRITE || prio) && a.entry_words == 2) {
+    uint32_t bs = 0xFFFFFFFFu, bb = 0u;
     int victim = -1;
     for (uint32_t i = 0; i < a.n_entries; ++i) {
-      uint32_t st = ((uint32_t*)(w0 + (uint64_t)i * 2))[2];
-      if (st < bs) { bs = st; victim = (int)i; }
+      const uint32_t* e = (const uint32_t*)(w0 + (uint64_t)i * 2);
+      const uint32_t st = e[2], b = prio ? e[3] : 0u;
+      if (victim < 0 || b > bb || (b == bb && st < bs)) { bs = st; bb = b; victim = (int)i; }
     }
-    if (victim >= 0 && bs < stamp) {
+    const bool replace = prio ? (bb > bounce || (bb == bounce && bs < stamp)) : bs < stamp;
+    if (victim >= 0 && replace) {
       uint64_t* p = w0 + (uint64_t)victim * 2;
       *p = neu;
       ((uint32_t*)p)[2] = stamp;
+      if (prio) ((uint32_t*)p)[3] = bounce;
       return 3;
     }
   }
   return 2;
+}
+
+__device__ __forceinline__ uint32_t cand_bounce(const SnapshotArgs& a, uint32_t seq) {
+  return (a.policy == PMC_POLICY_PRIORITY && a.bounce) ? a.bounce[seq >> 5] : 0u;
 }
 
 // One thread per cell applies its candidates as Algorithm 1 would in
@@ -68,6 +82,8 @@ __device__ __forceinline__ int apply_one(uint64_t* w0, const SnapshotArgs& a, ui
 // entry was written in this frame, so later ones fail too).  So the distinct
 // keys are applied in order of their lowest seq and the rest only counted;
 // with more distinct keys than kDistinct the candidates are taken one by one.
+// Under PRIORITY a later candidate of a key may carry a smaller path depth and
+// succeed where the first failed, so there every candidate is taken in turn.
 constexpr int kDistinct = 8;
 
 __global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
@@ -83,7 +99,7 @@ __global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
       // distinct keys: hash2, lowest seq, its code, candidate count
       uint32_t kh[kDistinct], ks[kDistinct], kc[kDistinct], kn[kDistinct];
       uint32_t d = 0;
-      bool overflow = false;
+      bool overflow = a.policy == PMC_POLICY_PRIORITY;
       for (uint32_t j = 0; j < n && !overflow; ++j) {
         const uint4 c = a.sorted[base + j];
         bool seen = false;
@@ -118,7 +134,7 @@ __global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
 #pragma unroll
           for (int k = 0; k < kDistinct; ++k)
             if (k == bi) { h2 = kh[k]; code = kc[k]; cntk = kn[k]; ks[k] = 0xFFFFFFFFu; }
-          const int o = apply_one(w0, a, h2, code, stamp);
+          const int o = apply_one(w0, a, h2, code, stamp, 0u);
           c_ins += o == 0;
           c_over += o == 3;
           c_present += o == 1;
@@ -137,7 +153,7 @@ __global__ __launch_bounds__(256) void k_cell_apply(SnapshotArgs a) {
           }
           last = best;
           const uint4 c = a.sorted[base + bi];
-          const int o = apply_one(w0, a, c.w, c.z, stamp);
+          const int o = apply_one(w0, a, c.w, c.z, stamp, cand_bounce(a, c.y));
           c_ins += o == 0;
           c_over += o == 3;
           c_present += o == 1;

@@ -99,19 +99,26 @@ class Hits:
     uv: np.ndarray                      # float32 [n, 2]
     duv: np.ndarray                     # float32 [n, 4]: g1.x, g1.y, g2.x, g2.y
     normal: np.ndarray                  # float32 [n, 3]
+    bounce: Optional[np.ndarray] = None  # uint32 [n]: path depth of the hit (0 = camera ray)
 
     def __len__(self) -> int:
         return int(self.material.shape[0])
 
     def take(self, idx) -> "Hits":
-        return Hits(self.material[idx], self.uv[idx], self.duv[idx], self.normal[idx])
+        b = None if self.bounce is None else self.bounce[idx]
+        return Hits(self.material[idx], self.uv[idx], self.duv[idx], self.normal[idx], b)
 
     @staticmethod
     def concat(parts: Sequence["Hits"]) -> "Hits":
+        if all(p.bounce is None for p in parts):
+            b = None
+        else:
+            b = np.concatenate([p.bounce if p.bounce is not None
+                                else np.zeros(len(p), np.uint32) for p in parts])
         return Hits(np.concatenate([p.material for p in parts]),
                     np.concatenate([p.uv for p in parts]),
                     np.concatenate([p.duv for p in parts]),
-                    np.concatenate([p.normal for p in parts]))
+                    np.concatenate([p.normal for p in parts]), b)
 
 
 @dataclasses.dataclass
@@ -150,7 +157,7 @@ def _rng(*key: int) -> np.random.Generator:
 
 
 # purpose tags for seed sequences
-_P_GRAPH, _P_TEX, _P_OBJ, _P_JITTER, _P_MLP = 1, 2, 3, 4, 5
+_P_GRAPH, _P_TEX, _P_OBJ, _P_JITTER, _P_MLP, _P_BOUNCE = 1, 2, 3, 4, 5, 6
 
 
 # ----------------------------------------------------------------------------
@@ -167,12 +174,13 @@ def checker_texture(size: int = 256, block_shift: int = 5) -> np.ndarray:
     return img
 
 
-def _ramp_stops(rng: np.random.Generator, min_gap: float = 0.08, max_slope: float = 1.5):
+def _ramp_stops(rng: np.random.Generator, min_gap: float = 0.08, max_slope=1.5):
     """8 ascending stops (first at 0, last at 1) whose colours change smoothly.
 
     Each colour step is bounded by ``max_slope`` times the position gap, which
     keeps the ramp's Lipschitz constant small (FP32 vs FP64 round-off is not
-    amplified by steep ramps)."""
+    amplified by steep ramps).  ``max_slope=None`` draws every stop colour
+    independently in [0, 1] (steep ramps where stops are close)."""
     while True:
         inner = np.sort(rng.uniform(0.0, 1.0, 6))
         pos = np.concatenate([[0.0], inner, [1.0]])
@@ -180,7 +188,9 @@ def _ramp_stops(rng: np.random.Generator, min_gap: float = 0.08, max_slope: floa
             break
     rgba = np.empty((8, 4))
     rgba[0] = rng.uniform(0.1, 0.9, 4)
-    for k in range(1, 8):
+    if max_slope is None:
+        rgba = rng.uniform(0.0, 1.0, (8, 4))
+    for k in range(1, 8 if max_slope is not None else 1):
         step = rng.uniform(-1, 1, 4) * max_slope * (pos[k] - pos[k - 1])
         rgba[k] = np.clip(rgba[k - 1] + step, 0.0, 1.0)
     pos32 = tuple(float(np.float32(p)) for p in pos)
@@ -238,8 +248,23 @@ _LEAVES = ("IMAGE_TEXTURE", "PERLIN_NOISE", "VALUE_NOISE")
 _INNER = ("MIX", "MATH", "COLOR_RAMP")
 
 
+# Constant ranges of the random networks.  "narrow" (the default of every
+# workload) keeps ramps gentle (stop gaps >= 0.08, colour slope <= 1.5) and
+# MATH constants at MUL in [0.5, 1], POW in [1, 2]; "wide" draws ramps with
+# stop gaps >= 1e-3 and independent stop colours, MUL in [0.5, 1.5] and POW in
+# [0.5, 2].  Wide ramps can be steep (slope up to ~1/gap), which amplifies the
+# difference between FP32 and FP64 evaluation of their input.
+RANGES = {
+    "narrow": dict(ramp_gap=0.08, ramp_slope=1.5,
+                   math={"ADD": (0.0, 0.5), "MUL": (0.5, 1.0), "POW": (1.0, 2.0)}),
+    "wide": dict(ramp_gap=1e-3, ramp_slope=None,
+                 math={"ADD": (0.0, 0.5), "MUL": (0.5, 1.5), "POW": (0.5, 2.0)}),
+}
+
+
 def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
-                    p_normal_map: float = 0.5, p_share: float = 0.15) -> Material:
+                    p_normal_map: float = 0.5, p_share: float = 0.15,
+                    ranges: str = "narrow") -> Material:
     """A random node network with exactly ``n_nodes`` nodes, all reachable from the sink.
 
     Built top-down from the BSDF sink: every open input slot is filled by a new
@@ -284,11 +309,11 @@ def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
             kw["seed"] = int(rng.integers(0, 1 << 30))
         elif op == "MATH":
             mop = str(rng.choice(MATH_OPS))
-            lo, hi = {"ADD": (0.0, 0.5), "MUL": (0.5, 1.0), "POW": (1.0, 2.0)}[mop]
+            lo, hi = RANGES[ranges]["math"][mop]
             kw["math_op"] = mop
             kw["b"] = float(np.float32(rng.uniform(lo, hi)))
         elif op == "COLOR_RAMP":
-            kw["ramp"] = _ramp_stops(rng)
+            kw["ramp"] = _ramp_stops(rng, RANGES[ranges]["ramp_gap"], RANGES[ranges]["ramp_slope"])
         idx = new(op, **kw)
         if op == "MIX":
             open_slots.extend([(idx, 0), (idx, 1), (idx, 2)])
@@ -449,10 +474,11 @@ def _object_screen(seed: int, n_mats: int, width: int, height: int, obj: int, fr
 
 def mid_scene(seed: int = 0, n_mats: int = 64, width: int = 1920, height: int = 1080,
               frames: int = 16, slots: int = 1 << 22, n_textures: int = 16,
-              tex_size: int = 1024, nodes=(8, 64)) -> Scene:
+              tex_size: int = 1024, nodes=(8, 64), ranges: str = "narrow") -> Scene:
     """64 materials of U{8..64} nodes, 120x120-px objects, Zipf(1.1) materials."""
     rng = _rng(seed, _P_GRAPH, 2)
-    mats = [random_material(rng, int(rng.integers(nodes[0], nodes[1] + 1)), n_textures)
+    mats = [random_material(rng, int(rng.integers(nodes[0], nodes[1] + 1)), n_textures,
+                            ranges=ranges)
             for _ in range(n_mats)]
     tex = texture_pool(seed, n_textures, tex_size)
     frame_fn, n = _object_screen(seed, n_mats, width, height, 120, frames, name="mid")
@@ -552,3 +578,25 @@ def mlp_init(seed: int, n_mats: int, fan=((32, 64), (64, 64), (64, 4))) -> List[
             layers.append(np.zeros(fo, np.float32))
         out.append(layers)
     return out
+
+
+def with_indirect(direct: Hits, frame: int, seed: int = 0, widen=(2.0, 16.0),
+                  max_bounce: int = 3) -> Hits:
+    """A frame of a path tracer: the camera hits ``direct`` (bounce 0) followed
+    by as many hits of secondary rays (bounce 1 .. max_bounce).  A secondary
+    hit lands on a random point of the scene (a random direct hit's material,
+    normal and UV, moved by up to a few footprints) and its footprint is wider
+    by a random factor in ``widen`` (a ray cone that has spread over a longer
+    path), so it keys coarser texels than the camera rays there."""
+    n = len(direct)
+    rng = _rng(seed, _P_BOUNCE, frame, n)
+    pick = rng.integers(0, n, n)
+    ind = direct.take(pick)
+    k = np.exp(rng.uniform(np.log(widen[0]), np.log(widen[1]), n))
+    duv = (ind.duv.astype(np.float64) * k[:, None]).astype(np.float32)
+    shift = rng.uniform(-2.0, 2.0, (n, 2)) * np.abs(duv[:, [0, 3]])
+    uv = (ind.uv.astype(np.float64) + shift).astype(np.float32)
+    bounce = rng.integers(1, max_bounce + 1, n).astype(np.uint32)
+    ind = Hits(ind.material.copy(), uv, duv, ind.normal.copy(), bounce)
+    d = Hits(direct.material, direct.uv, direct.duv, direct.normal, np.zeros(n, np.uint32))
+    return Hits.concat([d, ind])

@@ -6,15 +6,16 @@ benchmark uses, checked on sampled hits.
 Snapshot mode makes every frame's table unique, so at full size the oracle
 can check sampled outputs one by one:
   frame 0  the table is empty: no lookup hits, and each sampled output equals
-           the FP64 graph (within RTOL);
+           the FP64 graph (value bar: 1e-5 |ref| + 1e-6 per scalar, 1e-5 for
+           the unit normal);
   frame 1  every sampled lookup hits iff its (cell, hash2) is in the exported
            table after frame 0 (same scan as Algorithm 1); a key absent from
            that table was either never seen in frame 0 or met a full cell; a
            found value is the code of the key's first writer in frame 0 (the
            lowest (hit, ordinal) sequence number with that key), re-evaluated
-           in FP64 (within one RGB9E5 step, or RTOL for raw floats); every
+           in FP64 (within one RGB9E5 step, or the scalar bar for raw floats); every
            sampled output equals the FP64 graph with the GPU's found values
-           substituted (within RTOL).
+           substituted (value bar).
 """
 import numpy as np
 import pytest
@@ -58,8 +59,7 @@ def _run(sc, flags, policy, n_sample=1500, seed=0):
     assert not np.any(state0 == 1)
     s0 = np.sort(rng.choice(len(h0), n_sample, replace=False))
     ref0 = render.shade_uncached(sc.materials, sc.textures, h0.take(s0))
-    for k in ref0:
-        assert G.max_rel(out0[k][s0], ref0[k]) <= G.RTOL, k
+    G.assert_outputs(out0, ref0, s0, "frame 0")
     words = cache.words()[:, 0].copy()
     del out0, state0
 
@@ -111,14 +111,13 @@ def _run(sc, flags, policy, n_sample=1500, seed=0):
                     step = codec.rgb9e5_step(codec.rgb9e5_encode(ref))
                     assert np.all(np.abs(got - ref) <= step[:, None] + 1e-12), (m, c)
                 else:
-                    assert G.max_rel(got[:, 0], ref) <= G.RTOL, (m, c)
+                    assert G.scalar_ok(got[:, 0], ref), (m, c)
             sel = state1[mine1, c] == 1
             if sel.any():
                 v = value1[mine1, c, :3] if otype == "COLOR" else value1[mine1, c, 0]
                 subst[(node, sock)] = (sel, np.nan_to_num(v.astype(np.float64)))
         o, _ = graph.evaluate(mat, h1.uv[mine1], h1.normal[mine1], sc.textures, subst)
-        for k in o:
-            assert G.max_rel(out1[k][mine1], o[k]) <= G.RTOL, (m, k)
+        G.assert_outputs(out1, o, mine1, m)
     print(f"{sc.name}: frame-1 stats {st1}; sampled found {n_found}, dropped by full cells "
           f"{n_absent_full}")
     assert n_found > n_sample // 4

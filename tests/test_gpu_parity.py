@@ -1,9 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
 
-Bars: descriptor fields (cell, hash2, level, texel) bit-exact; node outputs
-within RTOL of the oracle; snapshot-mode tables bit-exact in hash halves,
-positions and stamps, values within one encoding step; nondeterministic
-(CAS) runs accepted by the oracle's invariant checker.
+Bars: descriptor fields (cell, hash2, level, texel) bit-exact; BSDF inputs
+per scalar within 1e-5 |ref| + 1e-6 of the FP64 oracle and the unit normal
+within 1e-5 (Euclidean); snapshot-mode tables bit-exact in hash halves,
+positions, stamps and aux fields, value codes within one RGB9E5 step (COLOR)
+or the scalar bar (FLOAT); nondeterministic (CAS) runs accepted by the
+oracle's invariant checker.
 """
 import numpy as np
 import pytest
@@ -111,8 +113,7 @@ def test_uncached_tiny_matches_oracle():
     h = sc.frame(0)
     out, _, _, st = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED)
     ref = render.shade_uncached(sc.materials, sc.textures, h)
-    for k in ref:
-        assert G.max_rel(out[k], ref[k]) <= G.RTOL, (k, G.max_rel(out[k], ref[k]))
+    G.assert_outputs(out, ref)
     assert st["hits_shaded"] == len(h) and st["probes"] == 0
     assert st["nodes_executed"] == st["nodes_total"] == 6 * len(h)
 
@@ -124,10 +125,37 @@ def test_uncached_mid_matches_oracle(flags):
     h = sc.frame(0)
     out, _, _, st = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED, flags=flags)
     ref = render.shade_uncached(sc.materials, sc.textures, h)
-    errs = {k: G.max_rel(out[k], ref[k]) for k in ref}
-    print("uncached mid max rel err", errs)
+    errs = G.assert_outputs(out, ref)
+    print("uncached mid error / bar", errs, {k: G.max_abs(out[k], ref[k]) for k in ref})
+    assert st["hits_shaded"] == len(h)
+
+
+def test_uncached_wide_ranges_measured():
+    """Node constants over the wide ranges (ramp stop gaps down to 1e-3 with
+    independent stop colours, MUL in [0.5, 1.5], POW in [0.5, 2]).  A ramp of
+    gap d and colour step c has slope c / d (up to ~1000 here), so the FP32
+    rounding of its input (a few 1e-8) can reach ~1e-5 in its output: the bar
+    holds for all but such points; the test records the measured errors and
+    bounds the rest by the amplification the steepest ramp allows."""
+    sc = G.small_mid_scene(frames=1, ranges="wide")
+    ctx = G.setup(sc)
+    h = sc.frame(0)
+    out, _, _, st = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED, flags=B.PMC_FLAG_SORT)
+    ref = render.shade_uncached(sc.materials, sc.textures, h)
+    ratios = G.output_ratios(out, ref)
+    within = {}
     for k in ref:
-        assert errs[k] <= G.RTOL, errs
+        g, r = np.asarray(out[k], np.float64), np.asarray(ref[k], np.float64)
+        if k == "normal":
+            q = np.sqrt(np.sum((g - r) ** 2, axis=1)) / G.NTOL
+        else:
+            q = np.abs(g - r) / (G.RTOL * np.abs(r) + G.ATOL)
+        within[k] = float(np.mean(q <= 1.0))
+    print("wide ranges: error/bar", ratios, "fraction within the bar", within,
+          "max abs", {k: G.max_abs(out[k], ref[k]) for k in ref})
+    for k in ref:
+        assert within[k] >= 0.999, (k, within)
+        assert G.max_abs(out[k], ref[k]) <= 1e-3, k
     assert st["hits_shaded"] == len(h)
 
 
@@ -157,7 +185,7 @@ def test_invalid_material_and_ragged_batch():
     assert np.array_equal(out["normal"][bad], h.normal[bad])
     assert np.all(state[bad] == 3)
     ref = render.shade_uncached(sc.materials, sc.textures, h)
-    assert G.max_rel(out["base_color"], ref["base_color"]) <= 2e-3   # cached: RGB9E5 quantised
+    assert G.max_abs(out["base_color"], ref["base_color"]) <= 2e-3   # cached: RGB9E5 quantised
 
 
 def test_empty_batch_is_a_no_op():
@@ -170,16 +198,16 @@ def test_empty_batch_is_a_no_op():
 
 # ------------------------------------------------------------ snapshot --------
 
-def _table_parity(gpu_words, ref: table.Table, types_by_cellhash=None):
-    """Hash halves, positions and stamps bit-exact; value codes equal or within one step."""
-    gw = gpu_words[:, 0]
-    rw = ref.words()
-    assert np.array_equal(gw >> np.uint64(32), rw >> np.uint64(32))
-    if gpu_words.shape[1] == 2:
-        stamps = (gpu_words[:, 1] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-        assert np.array_equal(stamps, ref.stamps())
-        assert np.all(gpu_words[:, 1] >> np.uint64(32) == 0)
-    return int(np.sum(gw != rw))
+def _snapshot_frame_parity(sc, h, ref, out, state, value):
+    """Hit pattern exact; found values at the value bar (one RGB9E5 step for
+    COLOR); outputs against the FP64 graph with the device's found values
+    substituted."""
+    valid = ref.valid
+    assert np.array_equal(state == 1, ref.found)
+    assert np.array_equal(state == 2, ref.bypass & valid)
+    G.found_values_parity(sc.materials, h, state, value, ref.found_value)
+    o = G.substituted_outputs(sc.materials, sc.textures, h, state, value)
+    return G.assert_outputs(out, o)
 
 
 def test_snapshot_tiny_matches_oracle_exactly():
@@ -193,27 +221,11 @@ def test_snapshot_tiny_matches_oracle_exactly():
         ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f)
         out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
                                         debug=True)
-        assert np.array_equal(state[:, :2] == 1, ref.found[:, :2])
+        _snapshot_frame_parity(sc, h, ref, out, state, value)
         assert st["cache_hits"] == ref.stats["hits"]
         assert st["inserts"] == ref.stats.get("inserted", 0)
         total_hits += st["cache_hits"]
-        diff = _table_parity(cache.words(), ref_t)
-        # found values: equal to the oracle's table values up to one RGB9E5 step / RTOL
-        hit = state[:, 0] == 1
-        if hit.any():
-            step = codec.rgb9e5_step(codec.rgb9e5_encode(ref.found_value[hit, 0, :]))
-            assert np.all(np.abs(value[hit, 0, :] - ref.found_value[hit, 0, :]) <= step[:, None])
-            assert G.max_rel(value[hit, 1, 0], ref.found_value[hit, 1, 0]) <= G.RTOL
-        # outputs: oracle evaluation with the GPU's found values substituted
-        subst = {}
-        for c, (node, sock) in enumerate(graph.cacheable_outputs(sc.materials[0])):
-            m = state[:, c] == 1
-            if m.any():
-                v = value[:, c, :3] if c == 0 else value[:, c, 0]
-                subst[(node, sock)] = (m, v.astype(np.float64))
-        o, _ = graph.evaluate(sc.materials[0], h.uv, h.normal, sc.textures, subst)
-        for k in o:
-            assert G.max_rel(out[k], o[k]) <= G.RTOL, k
+        G.table_parity(cache.words(), ref_t, sc.materials)
     assert total_hits == 24576                        # exactly 3/4 of 32768 probes
 
 
@@ -228,10 +240,13 @@ def test_snapshot_mid_two_frames_matches_oracle():
         ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f)
         out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
                                         flags=B.PMC_FLAG_SORT, debug=True)
-        assert np.array_equal(state == 1, ref.found)
+        r = _snapshot_frame_parity(sc, h, ref, out, state, value)
         assert st["cache_hits"] == ref.stats["hits"]
         assert st["cell_full"] == ref.stats.get("full", 0)
-        _table_parity(cache.words(), ref_t)
+        assert st["inserts"] == ref.stats.get("inserted", 0)
+        nd = G.table_parity(cache.words(), ref_t, sc.materials)
+        print(f"frame {f}: error/bar {r}, value codes differing {nd}")
+    assert st["cache_hits"] > 0
     print("mid snapshot stats", st)
 
 
@@ -249,10 +264,10 @@ def test_snapshot_overwrite_matches_oracle(n_cells, n_entries):
                                           policy=table.OVERWRITE)
         out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
                                         debug=True)
-        assert np.array_equal(state == 1, ref.found)
+        _snapshot_frame_parity(sc, h, ref, out, state, value)
         assert st["overwrites"] == ref.stats.get("overwritten", 0)
         assert st["inserts"] == ref.stats.get("inserted", 0)
-        _table_parity(cache.words(), ref_t)
+        G.table_parity(cache.words(), ref_t, sc.materials)
     assert st["overwrites"] > 0
 
 
@@ -426,3 +441,135 @@ def test_cache_clear_export_import_round_trip():
     assert np.count_nonzero(cache.export()) == 0
     cache.import_(raw)
     assert np.array_equal(cache.export(), raw)
+
+
+def test_snapshot_resume_after_export_import():
+    """The table persists across passes (Sec. 1, Sec. 3): frames 0-1 shaded,
+    the table exported, imported into a new context's table, frame 2 shaded
+    there; results and table equal those of a continuous run bit for bit."""
+    sc = G.small_mid_scene(frames=3)
+    n_cells = 1 << 13
+    ctx = G.setup(sc)
+    cont = ctx.cache(n_cells, 8, 16)
+    runs = {}
+    for f in range(3):
+        runs[f] = G.shade(ctx, sc.frame(f), cont, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                          flags=B.PMC_FLAG_SORT, debug=True)
+    want_table = cont.export()
+    ctx_a = G.setup(sc)
+    ca = ctx_a.cache(n_cells, 8, 16)
+    for f in range(2):
+        G.shade(ctx_a, sc.frame(f), ca, mode=B.PMC_MODE_SNAPSHOT, frame=f, flags=B.PMC_FLAG_SORT)
+    raw = ca.export()
+    ctx_b = G.setup(sc)
+    cb = ctx_b.cache(n_cells, 8, 16)
+    cb.import_(raw)
+    out, state, value, st = G.shade(ctx_b, sc.frame(2), cb, mode=B.PMC_MODE_SNAPSHOT, frame=2,
+                                    flags=B.PMC_FLAG_SORT, debug=True)
+    o2, s2, v2, st2 = runs[2]
+    for k in out:
+        assert np.array_equal(out[k], o2[k]), k
+    assert np.array_equal(state, s2)
+    hit = state == 1
+    assert np.array_equal(value[hit], v2[hit], equal_nan=True)
+    assert np.array_equal(cb.export(), want_table)
+    assert st["cache_hits"] == st2["cache_hits"] > 0
+
+
+# ------------------------------------------- priority policy, false hits ------
+
+def test_snapshot_priority_matches_oracle():
+    """PRIORITY (Sec. 5: prefer directly visible samples when storage is short):
+    each frame's camera hits followed by as many secondary hits of depth 1-3;
+    on a table too small for them all, a full cell gives up its deepest, then
+    oldest entry.  Snapshot tables (hash halves, stamps, depth fields) match
+    the oracle bit for bit, values at the value bar."""
+    sc = G.small_mid_scene(frames=3)
+    sel = np.arange(0, sc.hits_per_frame, 6)
+    n_cells = 2048
+    ctx = G.setup(sc)
+    cache = ctx.cache(n_cells, 8, 16, policy=B.PMC_POLICY_PRIORITY)
+    ref_t = table.Table(n_cells, 8, 16)
+    over = 0
+    for f in range(3):
+        h = scenes.with_indirect(sc.frame(f).take(sel), f)
+        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f,
+                                          policy=table.PRIORITY)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        _snapshot_frame_parity(sc, h, ref, out, state, value)
+        assert st["inserts"] == ref.stats.get("inserted", 0)
+        assert st["overwrites"] == ref.stats.get("overwritten", 0)
+        assert st["cell_full"] == ref.stats.get("full", 0)
+        G.table_parity(cache.words(), ref_t, sc.materials)
+        over += st["overwrites"]
+    aux = (cache.words()[:, 1] >> np.uint64(32)).astype(np.uint32)
+    live = cache.words()[:, 0] != 0
+    assert over > 0 and aux[live].max() >= 1 and (aux[live] == 0).any()
+
+
+def test_cached_priority_invariants():
+    """Nondeterministic PRIORITY: found values still belong to their keys, live
+    entries come from keys that missed, and depth fields hold hit depths (which
+    depth a racing writer leaves is not unique: the stamp and depth follow the
+    compare-and-swap)."""
+    sc = G.small_mid_scene(frames=2)
+    sel = np.arange(0, sc.hits_per_frame, 4)
+    n_cells = 512
+    ctx = G.setup(sc)
+    cache = ctx.cache(n_cells, 8, 16, policy=B.PMC_POLICY_PRIORITY)
+    log, vals = check.KeyLog(), {}
+    for f in range(2):
+        h = scenes.with_indirect(sc.frame(f).take(sel), f)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        bad = check.check_frame(sc.materials, sc.textures, h, f, state, value, out, n_cells,
+                                log, vals)
+        w = cache.words()
+        bad += check.check_entries_come_from_keys(w[:, 0], 8, log)
+        assert not bad, (f, bad[:5])
+        live = w[:, 0] != 0
+        depth = (w[:, 1] >> np.uint64(32)).astype(np.int64)
+        assert set(np.unique(depth[live])) <= set(np.unique(h.bounce).tolist())
+        assert np.all(depth[~live] == 0)
+    assert st["overwrites"] > 0
+
+
+@pytest.mark.parametrize("mask", [0xF, 0xFF])
+def test_snapshot_false_hits_with_masked_hash2(mask):
+    """Sec. 3.2: collisions of the verification hash cannot be avoided.  With
+    only a few bits of it kept, lookups find entries written for other
+    descriptors; the device's hit pattern, counts and table equal the oracle's,
+    whose shadow map of full descriptors counts the false hits."""
+    sc = G.small_mid_scene(frames=2)
+    n_cells = 1 << 12
+    ctx = G.setup(sc)
+    cache = ctx.cache(n_cells, 8, 16, hash2_mask=mask)
+    ref_t = table.Table(n_cells, 8, 16)
+    false_hits = 0
+    for f in range(2):
+        h = sc.frame(f).take(np.arange(0, sc.hits_per_frame, 2))
+        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f,
+                                          hash2_mask=mask)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        assert np.array_equal(state == 1, ref.found)
+        # a false hit returns another descriptor's code, possibly of the other
+        # type (a raw float read as RGB9E5 or the reverse, up to 1e38): such a
+        # value, and outputs computed from it, are not comparable at the value
+        # bar, so values and outputs are compared where every lookup was a true
+        # hit or a miss
+        true_state = np.where(ref.false_hit, 9, state)
+        G.found_values_parity(sc.materials, h, true_state, value, ref.found_value)
+        o = G.substituted_outputs(sc.materials, sc.textures, h, state, value)
+        clean = np.nonzero(~ref.false_hit.any(axis=1))[0]
+        G.assert_outputs(out, {k: v[clean] for k, v in o.items()}, clean)
+        assert len(clean) > len(h) // 4
+        assert st["cache_hits"] == ref.stats["hits"]
+        assert st["inserts"] == ref.stats.get("inserted", 0)
+        G.table_parity(cache.words(), ref_t, sc.materials)
+        false_hits += ref.stats["false_hits"]
+        assert int(ref.false_hit.sum()) == ref.stats["false_hits"]
+    print(f"hash2 mask {mask:#x}: false hits {false_hits} of {st['cache_hits']} hits "
+          "(last frame)")
+    assert false_hits > 0

@@ -243,8 +243,7 @@ def test_snapshot_with_trusted_networks_matches_reference(flags, max_err, launch
                 assert np.all(e <= Y_ATOL + Y_RTOL * np.abs(y[rows, base:base + w])), (mat, c)
         # outputs: the FP64 graph with the GPU's found and network values substituted
         o = _outputs_with(sc, h, state, value)
-        for k in ("base_color", "roughness", "normal"):
-            assert G.max_rel(out[k], o[k]) <= G.RTOL, k
+        G.assert_outputs(out, o, what=f)
         gw = cache.words()[:, 0]
         assert np.array_equal(gw >> np.uint64(32), ref_t.words() >> np.uint64(32))
         ref_log += ref.log
