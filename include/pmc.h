@@ -307,6 +307,27 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                      const pmc_bsdf_out* out, const pmc_shade_params* params,
                      pmc_stats* stats, const pmc_debug_out* dbg, void* stream);
 
+/* For callers that cannot allocate device memory (code under their own HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pmc_shade with the batch workspace (sorted order, the sort's tile matrix,
+ * batch counters, statistics slots) in a fixed device array of
+ * PMC_STATIC_SCRATCH_BYTES that every device the library runs on holds from
+ * its first context until the process ends.  Same arguments, kernels and
+ * results as pmc_shade, for modes UNCACHED and CACHED with flags SORT,
+ * PERSISTENT and DEFER.  PMC_ERR_UNSUPPORTED, before anything is enqueued,
+ * for SNAPSHOT mode, LOG or SURROGATE flags, more than PMC_STATIC_MAX_HITS
+ * hits, or a sorted batch whose tile matrix ((materials + 1) x ceil(n / 4096)
+ * words, twice) does not fit the array.  Calls no hipMalloc or hipFree (the
+ * caller passes inputs, outputs, stats and the table) and records no phase
+ * timing.  All calls on one device share the array and each one overwrites
+ * it: calls that overlap on one device (several streams, threads or
+ * contexts) race and give undefined results. */
+#define PMC_STATIC_SCRATCH_BYTES (16u << 20)
+#define PMC_STATIC_MAX_HITS (1u << 20)
+pmc_status pmc_shade_static(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
+                            const pmc_bsdf_out* out, const pmc_shade_params* params,
+                            pmc_stats* stats, const pmc_debug_out* dbg, void* stream);
+
 /* Per-(hit, ordinal) descriptor fields, for bit-exact checks (Sec. 3.1, Eq. 1,
  * Sec. 3.2).  out: device array of n * 8 records; ordinals beyond the hit's
  * material K get bypass = 2.  Asynchronous. */

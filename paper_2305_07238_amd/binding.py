@@ -40,6 +40,7 @@ PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE, PMC_POLICY_PRIORITY = 0, 1, 2
 PMC_MODE_UNCACHED, PMC_MODE_CACHED, PMC_MODE_SNAPSHOT = 0, 1, 2
 PMC_FLAG_SORT, PMC_FLAG_PERSISTENT, PMC_FLAG_DEFER, PMC_FLAG_LOG, PMC_FLAG_SURROGATE = 1, 2, 4, 8, 16
 PMC_FLAG_SURROGATE_INSERT = 32
+PMC_STATIC_SCRATCH_BYTES, PMC_STATIC_MAX_HITS = 16 << 20, 1 << 20
 N_PARAMS = 6532
 MAX_CACHEABLE = 8
 
@@ -193,6 +194,8 @@ _proto = {
     "pmc_cache_import": (_S, [_P, _P, C.c_size_t, _P]),
     "pmc_shade": (_S, [_P, _P, C.POINTER(pmc_hits), C.POINTER(pmc_bsdf_out),
                        C.POINTER(pmc_shade_params), _P, C.POINTER(pmc_debug_out), _P]),
+    "pmc_shade_static": (_S, [_P, _P, C.POINTER(pmc_hits), C.POINTER(pmc_bsdf_out),
+                              C.POINTER(pmc_shade_params), _P, C.POINTER(pmc_debug_out), _P]),
     "pmc_debug_keys": (_S, [_P, _P, C.POINTER(pmc_hits), _P, _P]),
     "pmc_cache_insert_raw": (_S, [_P, _P, _P, _P, C.c_uint64, C.c_uint32, _P, _P]),
     "pmc_cache_lookup_raw": (_S, [_P, _P, _P, C.c_uint64, _P, _P, _P]),
@@ -352,7 +355,7 @@ class Context:
               mode: int = PMC_MODE_CACHED, flags: int = PMC_FLAG_SORT, frame: int = 0,
               stats=None, debug: Optional[dict] = None, chunk_waves: int = 0,
               blocks_per_cu: int = 0, defer_max: int = 0, waves_per_block: int = 0,
-              stream=None):
+              stream=None, static: bool = False):
         """hits: dict of torch CUDA tensors material/uv/duv/normal (and optionally bounce);
         out: base_color/roughness/normal."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
@@ -363,8 +366,9 @@ class Context:
         dbg = None
         if debug is not None:
             dbg = C.byref(pmc_debug_out(_ptr(debug.get("state")), _ptr(debug.get("value"))))
-        self.check(pmc_shade(self.h, cache.h if cache else None, C.byref(h), C.byref(o),
-                             C.byref(p), _ptr(stats), dbg, _stream_ptr(stream)))
+        fn = pmc_shade_static if static else pmc_shade
+        self.check(fn(self.h, cache.h if cache else None, C.byref(h), C.byref(o),
+                      C.byref(p), _ptr(stats), dbg, _stream_ptr(stream)))
 
     def profile_enable(self, on: bool = True):
         self.check(pmc_profile_enable(self.h, 1 if on else 0))

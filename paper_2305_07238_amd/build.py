@@ -16,8 +16,8 @@ OUT = os.path.join(HERE, "libpmc.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abi.cpp", "compiler.cpp", "frame.cpp", "surrogate_api.cpp", "shade.hip", "sort.hip",
-           "snapshot.hip", "surrogate.hip", "util.hip"]
+SOURCES = ["abi.cpp", "compiler.cpp", "frame.cpp", "surrogate_api.cpp", "static_shade.cpp",
+           "shade.hip", "sort.hip", "snapshot.hip", "surrogate.hip", "util.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

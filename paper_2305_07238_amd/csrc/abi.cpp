@@ -105,7 +105,6 @@ namespace {
 // Small per-context device words, kWorkSets sets of kMiscWords: [1] the snapshot
 // candidate count, [kMiscQueue, kMiscQueue + 2 kQueueRegions) the surrogate
 // queue's counters.
-constexpr uint32_t kMiscQueue = 64, kMiscWords = 256;
 static_assert(kMiscQueue + 2 * kQueueRegions <= kMiscWords, "misc words");
 
 template <typename T>
@@ -176,7 +175,8 @@ pmc_status pmc_create(int device, pmc_ctx** out) {
         ensure(ctx, ctx->misc, kWorkSets * kMiscWords * 4) ||
         hipMemset(ctx->stat_slots.p, 0, ctx->stat_slots.bytes) != hipSuccess ||
         hipMemset(ctx->misc.p, 0, ctx->misc.bytes) != hipSuccess ||
-        prepare_sort_kernels() != hipSuccess || prepare_surrogate_kernels() != hipSuccess) {
+        prepare_sort_kernels() != hipSuccess || prepare_surrogate_kernels() != hipSuccess ||
+        static_scratch_init(ctx) != PMC_OK) {
       pmc_destroy(ctx);
       return PMC_ERR_HIP;
     }
@@ -511,21 +511,25 @@ uint32_t* perm_set(pmc_ctx* ctx, int set, uint32_t n) {
 }  // namespace
 
 pmc_status sort_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
-                      const pmc_shade_params* params, int set, hipStream_t s) {
+                      const pmc_shade_params* params, int set, hipStream_t s,
+                      const Workspace* ws) {
   const uint32_t n = (uint32_t)hits->n;
   if (n == 0) return PMC_OK;
   const uint32_t mode = batch_mode(params, cache);
-  uint32_t* misc = misc_set(ctx, set);
+  uint32_t* misc = ws && ws->misc ? ws->misc : misc_set(ctx, set);
   // misc[1]: snapshot candidate count; misc[kMiscQueue ..]: the queue's region
   // counters (reset by the sort's scan, or filled here)
   const uint32_t n_reset = batch_surr(params, mode) ? kMiscQueue + 2u * kQueueRegions : 4u;
   if (params->flags & PMC_FLAG_SORT) {
     PhaseTimer t0(ctx, 0, s);
+    const bool own = ws && ws->perm;
     HIP_TRY(ctx, launch_material_sort_tiled(
                      hits->material, n, (uint32_t)ctx->prog.headers.size(),
-                     (const uint32_t*)ctx->lpt_rank.p, (uint32_t*)ctx->sort_counts.p,
-                     (uint32_t*)ctx->sort_offsets.p, (uint32_t*)ctx->sort_sums.p,
-                     perm_set(ctx, set, n), misc, n_reset, s));
+                     (const uint32_t*)ctx->lpt_rank.p,
+                     own ? ws->sort_counts : (uint32_t*)ctx->sort_counts.p,
+                     own ? ws->sort_offsets : (uint32_t*)ctx->sort_offsets.p,
+                     own ? ws->sort_sums : (uint32_t*)ctx->sort_sums.p,
+                     own ? ws->perm : perm_set(ctx, set, n), misc, n_reset, s));
     t0.finish();
   } else {
     HIP_TRY(ctx, launch_fill_u32(misc, 0u, n_reset, s));
@@ -549,7 +553,7 @@ pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
 
 pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                        const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
-                       const pmc_debug_out* dbg, int set, hipStream_t s) {
+                       const pmc_debug_out* dbg, int set, hipStream_t s, const Workspace* ws) {
   const uint32_t n = (uint32_t)hits->n;
   if (n == 0) return PMC_OK;
   const uint32_t mode = batch_mode(params, cache);
@@ -571,10 +575,12 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.out_rough = out->roughness;
   a.out_normal = out->normal;
   a.frame = params->frame;
-  a.stat_slots = stats ? (unsigned long long*)ctx->stat_slots.p : nullptr;
+  unsigned long long* slots = ws && ws->stat_slots ? ws->stat_slots
+                                                   : (unsigned long long*)ctx->stat_slots.p;
+  a.stat_slots = stats ? slots : nullptr;
   a.dbg_state = dbg ? dbg->state : nullptr;
   a.dbg_value = dbg ? dbg->value : nullptr;
-  uint32_t* misc = misc_set(ctx, set);
+  uint32_t* misc = ws && ws->misc ? ws->misc : misc_set(ctx, set);
   if (mode != PMC_MODE_UNCACHED) fill_cache_args(cache, a);
   const bool surr = batch_surr(params, mode);
   const bool logged = (params->flags & PMC_FLAG_LOG) && mode != PMC_MODE_UNCACHED;
@@ -595,7 +601,7 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
     a.log_region_cap = ctx->surr.log_cap / 64u;
   }
 
-  if (sort) a.perm = perm_set(ctx, set, n);
+  if (sort) a.perm = ws && ws->perm ? ws->perm : perm_set(ctx, set, n);
   if (mode == PMC_MODE_SNAPSHOT) {
     a.cand = (uint4*)ctx->cand.p;
     a.cand_count = misc + 1;
@@ -656,7 +662,7 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                                                  ctx->surr.n_slots, s));
   if (stats) {
     PhaseTimer t3(ctx, 3, s);
-    HIP_TRY(ctx, launch_stats_reduce((unsigned long long*)ctx->stat_slots.p, stats, s));
+    HIP_TRY(ctx, launch_stats_reduce(slots, stats, s));
     t3.finish();
   }
   return PMC_OK;

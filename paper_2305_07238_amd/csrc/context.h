@@ -50,6 +50,7 @@ struct pmc_ctx {
   DevBuf surr_queue, surr_val;                   // parked hits of the surrogate passes
   DevBuf sort_counts, sort_offsets, sort_sums;   // tiled material sort
   SurrHost surr;
+  void* static_scratch = nullptr;  // this device's fixed scratch array (pmc_shade_static)
   bool no_alloc = false;       // set while a frame graph is captured
   // Frame graphs bake this context's buffers and program into their launches:
   // while any exists, nothing they use may move or change shape, and
@@ -126,14 +127,33 @@ pmc_status check_shade_args(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits
 constexpr int kWorkSets = 8;
 pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mode,
                          uint32_t flags, uint32_t chunk_waves, bool all_sets, hipStream_t s);
+// Per-batch device workspace of the modes without snapshot candidates or
+// surrogate queues: the sorted order, the sort's tile matrix and scan sums,
+// the batch counters and the statistics slots.  NULL members are taken from
+// the context's buffers (workspace set `set`).
+struct Workspace {
+  uint32_t* perm = nullptr;
+  uint32_t* sort_counts = nullptr;
+  uint32_t* sort_offsets = nullptr;
+  uint32_t* sort_sums = nullptr;
+  uint32_t* misc = nullptr;                  // kMiscWords words
+  unsigned long long* stat_slots = nullptr;  // kStatSlots * kStatStride, zero between batches
+};
+constexpr uint32_t kMiscQueue = 64, kMiscWords = 256;
 // The two stages of a batch, for workspace set `set` (< kWorkSets): the material
 // sort (or, unsorted, the reset of the set's counters), then shade -> surrogate
-// passes -> snapshot apply -> stats.  The workspace must be reserved.
+// passes -> snapshot apply -> stats.  The workspace must be reserved, or given
+// in ws (its members replace the context's).
 pmc_status sort_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
-                      const pmc_shade_params* params, int set, hipStream_t s);
+                      const pmc_shade_params* params, int set, hipStream_t s,
+                      const Workspace* ws = nullptr);
 pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                        const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
-                       const pmc_debug_out* dbg, int set, hipStream_t s);
+                       const pmc_debug_out* dbg, int set, hipStream_t s,
+                       const Workspace* ws = nullptr);
+// Address of this device's fixed scratch array (static_shade.cpp), looked up
+// once per device with the device current; kept in ctx->static_scratch.
+pmc_status static_scratch_init(pmc_ctx* ctx);
 // The per-batch pipeline: reserve, then both stages on s with set 0.
 pmc_status shade_batch(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
                        const pmc_bsdf_out* out, const pmc_shade_params* params, pmc_stats* stats,
