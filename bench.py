@@ -4,8 +4,13 @@
 One step = one progressive render of the workload from an empty table: every
 frame (one batch of hits, one sample per pixel) goes through material sort,
 key computation, probes, the node interpreter on misses and lock-free inserts
-(the paper's GPU update, Sec. 3.3).  Inputs are generated on the host, seeded,
-and resident in HBM before timing starts.  Prints one JSON line.
+(the paper's GPU update, Sec. 3.3), all frames replayed as one HIP graph.
+Inputs are generated on the host, seeded, and resident in HBM before timing
+starts.  The headline is the scale workload (4096 materials, 3840x2160 x 128
+frames, 1 GiB overwrite table); the batching workload (1000 materials,
+1920x1080 x 64 frames), the mid workload with the learned surrogate, and the
+table-size and level-offset sweeps (Sec. 4) run as further legs.  Prints one
+JSON line.
 """
 import argparse
 import json
@@ -21,21 +26,30 @@ sys.path.insert(0, ROOT)
 METRIC = "shading samples/s + cache hit rate, cached/surrogate vs uncached, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes of the shade kernel (per unit of work)
+# algorithmic bytes of the shade kernel (per unit of the method's work)
 B_HIT_IN = 40          # material 4, uv 8, duv 16, normal 12
 B_HIT_OUT = 28         # base colour 12, roughness 4, normal 12
 B_PERM = 4             # sorted index read
 B_PROBE = 128          # one N_e x 16 B cell scanned per lookup
-B_INSERT = 16          # one entry written per miss that inserts
+B_INSERT = 16          # one entry written per stored value
 B_TEXEL = 16           # four RGBA8 texels per evaluated image-texture node
+B_DEFER = B_HIT_IN + B_PERM   # a deferred hit's data read again for its dense pass
 
 
 def kernel_bytes(st, n_hits):
-    """Algorithmic bytes of one step of the shade kernel (all its launches)."""
-    return (n_hits * (B_HIT_IN + B_PERM + B_HIT_OUT) +
-            (st["probes"] + st["probes_deferred"]) * B_PROBE +
-            st["deferred"] * (B_HIT_IN + 4) +
-            st["insert_attempts"] * B_INSERT + st["texture_evals"] * B_TEXEL)
+    """Algorithmic bytes of the method in the shade kernel (all its launches):
+    hit data in and out, the sorted index, one cell per lookup, one entry per
+    value stored, four texels per image-texture evaluation."""
+    return (n_hits * (B_HIT_IN + B_PERM + B_HIT_OUT) + st["probes"] * B_PROBE +
+            (st["inserts"] + st["overwrites"]) * B_INSERT + st["texture_evals"] * B_TEXEL)
+
+
+def overhead_bytes(st):
+    """Bytes the implementation adds to the method's: lookups repeated for
+    deferred hits, deferred hits' data read twice, insert attempts that stored
+    nothing (lost races, full cells, keys already present)."""
+    failed = max(st["insert_attempts"] - st["inserts"] - st["overwrites"], 0)
+    return st["probes_deferred"] * B_PROBE + st["deferred"] * B_DEFER + failed * B_INSERT
 
 
 KERNEL_SOURCES = ("shade.hip", "shade.h", "device_common.h", "program.h")
@@ -55,6 +69,7 @@ def measured_traffic(workload_name, best, late_frame=0, late=None):
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2305_07238_amd", "csrc", name), "rb") as f:
             h.update(f.read())
+
     def same(rec, want):
         return (rec.get("waves_per_block", 4) == (want.get("waves_per_block", 0) or 4) and
                 all(rec[k] == want[k] for k in ("flags", "chunk_waves", "defer_max")))
@@ -65,7 +80,7 @@ def measured_traffic(workload_name, best, late_frame=0, late=None):
             continue
         if late_frame and not same(rec["late"], late):
             continue
-        return rec["traffic_bytes_per_launch"]
+        return rec
     return None
 
 
@@ -81,11 +96,6 @@ def shade_kernel_name(mode, flags):
     return "%s<%d, %d, false, false>" % (base, m, kind)
 
 
-def scenes_concat(sc):
-    from paper_2305_07238_amd import scenes
-    return scenes.Hits.concat([sc.frame(f) for f in range(sc.frames)])
-
-
 def workload(name, frames=None):
     from paper_2305_07238_amd import scenes
     if name == "mid":
@@ -99,19 +109,122 @@ def workload(name, frames=None):
     elif name == "batching":
         sc = scenes.batching_scene(frames=frames or 64)
         desc = ("batching: 1000 materials (lognormal sizes 4-400 nodes), 1920x1080 x %d frames, "
-                "table 2^24 slots x 16 B" % sc.frames)
+                "Zipf(1.1) materials on 40-px objects, table 2^24 slots x 16 B, keep-first"
+                % sc.frames)
     elif name == "scale":
         sc = scenes.scale_scene(frames=frames or 128)
         desc = ("scale: 4096 materials (lognormal sizes 8-400 nodes), 3840x2160 x %d frames, "
-                "table 2^26 slots x 16 B (1 GiB), overwrite-oldest" % sc.frames)
+                "Zipf(1.1) materials on 40-px objects, table 2^26 slots x 16 B (1 GiB), "
+                "overwrite-oldest" % sc.frames)
     else:
         raise SystemExit(f"unknown workload {name}")
     return sc, desc
 
 
-SURR_FLOP_PER_POINT = 2 * (32 * 64 + 64 * 64 + 64 * 4)     # 12,800 per network evaluation
-FP16_PEAK_TFLOPS = 2500.0
-TRAIN = dict(steps=8000, batch=1024, lr=2e-2, lr_end=1e-5, seed=0)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------ CPU baseline ---
+
+_CPU = {}          # scene and hits shared with forked workers
+
+
+def _cpu_uncached_chunk(rows):
+    from oracle import render
+    sc, h = _CPU["scene"], _CPU["hits"]
+    t0 = time.perf_counter()
+    out = render.shade_uncached(sc.materials, sc.textures, h.take(rows))
+    return rows, out, time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sc, frame, n_parallel=1 << 19, n_single=65536, n_snapshot=8192,
+                 workers=None):
+    """The FP64 oracle timed on the host, on a bounded sample of the workload.
+    Runs before the process touches the GPU (the worker pool forks).
+
+    * uncached, one worker process per core (at most 16, the host share of one
+      GPU): the first n_parallel hits of ``frame``;
+    * uncached, one process: the first n_single hits of that frame;
+    * snapshot-mode progressive shading (lookups, evaluation on misses,
+      Algorithm 1 inserts into the full-size table), one process: the first
+      n_snapshot hits of frames 0 and 1.
+    Returns the cpu_baseline record and the FP64 outputs of the parallel sample
+    (the reference for the GPU outputs of the same hits)."""
+    import multiprocessing as mp
+    from oracle import render, table
+    workers = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    h = sc.frame(frame)
+    n_parallel = min(n_parallel, len(h))
+    _CPU["scene"], _CPU["hits"] = sc, h
+    chunks = np.array_split(np.arange(n_parallel), workers * 4)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_cpu_uncached_chunk, chunks)
+    t_par = time.perf_counter() - t0
+    ref = dict(base_color=np.zeros((n_parallel, 3)), roughness=np.zeros(n_parallel),
+               normal=np.zeros((n_parallel, 3)))
+    for rows, out, _ in parts:
+        for k in ref:
+            ref[k][rows] = out[k]
+    t0 = time.perf_counter()
+    render.shade_uncached(sc.materials, sc.textures, h.take(np.arange(n_single)))
+    t_single = time.perf_counter() - t0
+    t = table.Table(sc.cache.n_cells, sc.cache.n_entries, sc.cache.entry_bytes)
+    batches = [sc.frame(f).take(np.arange(n_snapshot)) for f in range(2)]
+    t0 = time.perf_counter()
+    res = render.shade_snapshot(sc.materials, sc.textures, batches, t,
+                                policy=sc.cache.policy)
+    t_snap = time.perf_counter() - t0
+    probes = sum(r.stats["probes"] for r in res)
+    hits = sum(r.stats["hits"] for r in res)
+    rec = {"value": n_parallel / t_par, "unit": "samples/s", "cores": workers, "kind": "oracle",
+           "cpu": cpu_model(), "mode": "uncached (FP64 graph evaluation)",
+           "sample": f"first {n_parallel} hits (screen order) of frame {frame}, "
+                     f"{workers} worker processes, {t_par:.1f} s wall",
+           "single_process_uncached": {"value": n_single / t_single, "cores": 1,
+                                       "sample": f"first {n_single} hits of frame {frame}, "
+                                                 f"{t_single:.1f} s"},
+           "single_process_snapshot": {"value": 2 * n_snapshot / t_snap, "cores": 1,
+                                       "hit_rate": hits / max(probes, 1),
+                                       "sample": f"first {n_snapshot} hits of frames 0-1, "
+                                                 f"table {sc.cache.n_cells} x "
+                                                 f"{sc.cache.n_entries}, {t_snap:.1f} s"}}
+    _CPU.clear()
+    return rec, ref
+
+
+# --------------------------------------------------------------- GPU legs ---
+
+def device_frames(sc, n_frames, first=0):
+    """Hits of frames first .. first + n_frames - 1, frame-major, generated one
+    frame at a time straight into device buffers."""
+    import torch
+    n = sc.hits_per_frame
+    N = n * n_frames
+    d = {"material": torch.empty(N, dtype=torch.int32, device="cuda"),
+         "uv": torch.empty((N, 2), dtype=torch.float32, device="cuda"),
+         "duv": torch.empty((N, 4), dtype=torch.float32, device="cuda"),
+         "normal": torch.empty((N, 3), dtype=torch.float32, device="cuda")}
+    for f in range(n_frames):
+        h = sc.frame(first + f)
+        s = slice(f * n, (f + 1) * n)
+        d["material"][s].copy_(torch.from_numpy(np.ascontiguousarray(h.material).view(np.int32)))
+        d["uv"][s].copy_(torch.from_numpy(h.uv))
+        d["duv"][s].copy_(torch.from_numpy(h.duv))
+        d["normal"][s].copy_(torch.from_numpy(h.normal))
+    return d
 
 
 def _median_ms(fn, reps=5):
@@ -128,37 +241,292 @@ def _median_ms(fn, reps=5):
     return float(np.median(ts))
 
 
-def _errors_vs_uncached(results):
-    """Max and mean absolute error of every BSDF output of each variant against the
-    variant "uncached" (the same hits, plain evaluation on the GPU)."""
-    ref = results["uncached"]["_out"]
-    for r in results.values():
-        got = r["_out"]
-        errs = np.concatenate([np.abs(got[k] - ref[k]).ravel()
-                               for k in ("base_color", "roughness", "normal")])
-        r["max_abs_err_vs_uncached"] = float(errs.max())
-        r["mean_abs_err_vs_uncached"] = float(errs.mean())
-    for r in results.values():
-        del r["_out"]
+def _abs_err(got, ref, rows=None):
+    e = np.concatenate([np.abs(np.asarray(got[k], np.float64)[rows if rows is not None else
+                                                              slice(None)] - ref[k]).ravel()
+                        for k in ("base_color", "roughness", "normal")])
+    return {"max_abs": float(e.max()), "mean_abs": float(e.mean())}
 
 
-def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
-    """Learned surrogate (the mid scene after its progressive render): train every
-    network on the insert log the render collected, then shade the next pass
-    (its first 2^20 hits) from the render's final table: uncached, cache only,
-    and networks + cache; errors of every output against the uncached GPU path (the
-    plain evaluation, which the parity tests hold to the FP64 graph within 1e-5)."""
+def tune_settings(ctx, cache, mode, sc, args, n_tune=4):
+    """Launch settings from the autotuner, run on a warm-up scene (the same
+    materials on another screen layout and jitter): one setting for the first
+    n_tune frames, one for the later frames tuned on a table the first ones
+    filled."""
+    import torch
+    from paper_2305_07238_amd import binding as B, scenes
+    use_cache = cache if mode != B.PMC_MODE_UNCACHED else None
+    if args.no_autotune:
+        best = dict(flags=args.flags if args.flags >= 0 else
+                    B.PMC_FLAG_SORT | (B.PMC_FLAG_DEFER if use_cache else 0),
+                    chunk_waves=args.chunk_waves or (4 if use_cache else 1),
+                    defer_max=args.defer_max or 48, blocks_per_cu=0,
+                    waves_per_block=args.waves_per_block)
+        late_frame, late = 0, None
+        if args.late_frame:
+            late_frame = args.late_frame
+            late = dict(flags=args.late_flags if args.late_flags >= 0 else best["flags"],
+                        chunk_waves=args.late_chunk_waves, defer_max=args.late_defer_max,
+                        blocks_per_cu=0, waves_per_block=0)
+        return best, late_frame, late, None
+    warm = scenes.relayout(sc, seed=sc.seed + 1) if sc.layout is not None else sc
+    n_frames = min(2 * n_tune, sc.frames)
+    wh = device_frames(warm, n_frames)
+    n = sc.hits_per_frame
+    out = B.alloc_outputs(n)
+    tune = ctx.autotune(use_cache, ctx.frame_plan(wh, n, min(n_tune, n_frames), out, mode=mode),
+                        args.tune_json)
+    b = tune.best
+    best = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
+                blocks_per_cu=b.blocks_per_cu, waves_per_block=b.waves_per_block)
+    info = {"warmup_scene": warm.name, "early_ms": tune.best_ms, "default_ms": tune.default_ms,
+            "tried": tune.n_tried}
+    late_frame, late = 0, None
+    if use_cache and sc.frames >= 2 * n_tune:
+        late_frame = n_tune
+        lt = ctx.autotune(use_cache, ctx.frame_plan(wh, n, 2 * n_tune, out, mode=mode,
+                                                    late_frame=late_frame, **best),
+                          args.tune_json + ".late" if args.tune_json else None)
+        b = lt.best
+        late = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
+                    blocks_per_cu=b.blocks_per_cu, waves_per_block=b.waves_per_block)
+        info["late_tried"] = lt.n_tried
+    del wh
+    torch.cuda.synchronize()
+    return best, late_frame, late, info
+
+
+def path_leg(name, sc, desc, args, steps, warmup, ref=None, ref_frame=None,
+             uncached_steps=3, prof_steps=3):
+    """Progressive renders of one workload: HIP-graph replays of all frames
+    (timed), the same frames launched one by one with phase timing (the shade
+    kernel's own launch time), one render with counters (hit rate, bytes), and
+    the uncached path on the same inputs."""
     import torch
     from paper_2305_07238_amd import binding as B
+    mode = {"cached": B.PMC_MODE_CACHED, "snapshot": B.PMC_MODE_SNAPSHOT,
+            "uncached": B.PMC_MODE_UNCACHED}[args.mode]
+    n_frame = sc.hits_per_frame
+    n_step = n_frame * sc.frames
+    ctx = B.Context(0)
+    ctx.set_textures(sc.textures)
+    ctx.compile(sc.materials, min_subgraph_nodes=args.min_subgraph)
+    cc = sc.cache
+    policy = {"FIRST": B.PMC_POLICY_FIRST, "OVERWRITE": B.PMC_POLICY_OVERWRITE,
+              "PRIORITY": B.PMC_POLICY_PRIORITY}[cc.policy]
+    cache = ctx.cache(cc.n_cells, cc.n_entries, cc.entry_bytes, policy)
+    use_cache = cache if mode != B.PMC_MODE_UNCACHED else None
+    best, late_frame, late, tune_info = tune_settings(ctx, cache, mode, sc, args)
+    log(f"{name}: launch settings {best}, from frame {late_frame}: {late} ({tune_info})")
+    t0 = time.perf_counter()
+    hits = device_frames(sc, sc.frames)
+    log(f"{name}: {sc.frames} frames x {n_frame} hits resident in HBM "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    out = B.alloc_outputs(n_frame)          # the renderer consumes each frame's BSDF inputs
+    graph = ctx.frame_graph(use_cache, ctx.frame_plan(hits, n_frame, sc.frames, out, mode=mode,
+                                                      clear_cache=True, late_frame=late_frame,
+                                                      late=late, **best))
+    for _ in range(warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        graph.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / steps
+    log(f"{name}: {ms_step:.3f} ms/step (graph replay), {n_step / ms_step / 1e6:.3f} G samples/s")
+    graph.close()
+    views = [{k: v[f * n_frame:(f + 1) * n_frame] for k, v in hits.items()}
+             for f in range(sc.frames)]
+
+    def step(stats=None):
+        if mode != B.PMC_MODE_UNCACHED:
+            cache.clear()
+        for f in range(sc.frames):
+            kw = late if (late_frame and f >= late_frame) else best
+            ctx.shade(views[f], out, use_cache, mode=mode, frame=f, stats=stats, **kw)
+
+    prof = None
+    if prof_steps:
+        ctx.profile_enable(True)
+        for _ in range(prof_steps):
+            step()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read(reset=True)
+        ctx.profile_enable(False)
+    stats = B.new_stats()
+    step(stats=stats)
+    torch.cuda.synchronize()
+    st = B.stats_dict(stats)
+    cached_last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    res = {"workload": desc, "samples_per_s": n_step / (ms_step * 1e-3), "ms_per_step": ms_step,
+           "hits_per_step": n_step, "frames": sc.frames, "mode": args.mode,
+           "launch": {"autotuned": best, "late_frame": late_frame, "autotuned_late": late,
+                      "tuning": tune_info},
+           "cache_hit_rate": st["cache_hits"] / max(st["probes"], 1),
+           "found_per_sample": st["cache_hits"] / max(st["hits_shaded"], 1),
+           "deferred_fraction": st["deferred"] / max(st["hits_shaded"], 1),
+           "nodes_executed_fraction": st["nodes_executed"] / max(st["nodes_total"], 1),
+           "stats": st}
+    if prof:
+        kb = kernel_bytes(st, n_step)
+        ob = overhead_bytes(st)
+        shade_ms, shade_launches = prof["shade"]
+        avg_ms = shade_ms / max(shade_launches, 1)
+        achieved = kb / (shade_ms / prof_steps * 1e-3) / 1e9
+        trec = measured_traffic(name, best, late_frame, late)
+        kname = shade_kernel_name(args.mode, best["flags"])
+        if late_frame and shade_kernel_name(args.mode, late["flags"]) != kname:
+            kname += " (frames < %d), %s (later frames)" % (
+                late_frame, shade_kernel_name(args.mode, late["flags"]))
+        res["phase_ms_per_step"] = {k: v[0] / prof_steps for k, v in prof.items()}
+        res["roofline"] = {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": trec["traffic_bytes_per_launch"] if trec else None,
+            "kernel": kname, "bytes_per_launch": kb / sc.frames,
+            "overhead_bytes_per_launch": ob / sc.frames,
+            "avg_launch_ms": avg_ms, "launches_timed": shade_launches}
+        if trec:
+            res["roofline"]["traffic_source"] = trec.get("summary")
+    # uncached path on the same inputs (also a graph); last-frame outputs of both
+    if mode != B.PMC_MODE_UNCACHED and uncached_steps > 0:
+        g_u = ctx.frame_graph(None, ctx.frame_plan(hits, n_frame, sc.frames, out,
+                                                   mode=B.PMC_MODE_UNCACHED))
+        g_u.launch()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(uncached_steps):
+            g_u.launch()
+        ev1.record()
+        torch.cuda.synchronize()
+        unc = ev0.elapsed_time(ev1) / uncached_steps
+        g_u.close()
+        unc_last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+        res["uncached_samples_per_s"] = n_step / (unc * 1e-3)
+        res["uncached_ms_per_step"] = unc
+        res["speedup_vs_uncached"] = unc / ms_step
+        res["bsdf_err_vs_uncached_gpu"] = dict(
+            _abs_err(cached_last, unc_last),
+            sample="every BSDF input of the last frame, cached vs the uncached GPU path")
+        log(f"{name}: uncached {unc:.3f} ms/step, speedup {unc / ms_step:.2f}x")
+    if ref is not None and ref_frame == sc.frames - 1:
+        rows = np.arange(len(ref["roughness"]))
+        res["bsdf_err_vs_fp64_oracle"] = dict(
+            _abs_err(cached_last, ref, rows),
+            sample=f"first {len(rows)} hits of the last frame, cached GPU outputs vs the FP64 "
+                   "oracle's plain evaluation (the CPU baseline's sample)")
+    del views, hits
+    ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def sweeps_leg(args, steps=3):
+    """The paper's two experiments (Sec. 4) on the mid workload: table sizes
+    N_c x N_e (16-byte entries) and the level offset (an integer bias on
+    floor(lambda), finer texels for positive values).  Samples/s of the
+    progressive render (one graph, 16 frames), hit rate, and the BSDF error of
+    the last frame against the uncached GPU path (held within 1e-5 of the FP64
+    graph by the parity tests)."""
+    import torch
+    from paper_2305_07238_amd import binding as B
+    sc, _ = workload("mid")
+    n = sc.hits_per_frame
+    hits = device_frames(sc, sc.frames)
+    out = B.alloc_outputs(n)
+    ctx = B.Context(0)
+    ctx.set_textures(sc.textures)
+    ctx.compile(sc.materials)
+    early = dict(flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, chunk_waves=4, defer_max=48)
+    late = dict(flags=B.PMC_FLAG_SORT, chunk_waves=1, defer_max=0)
+    g_u = ctx.frame_graph(None, ctx.frame_plan(hits, n, sc.frames, out,
+                                               mode=B.PMC_MODE_UNCACHED))
+    g_u.launch()
+    torch.cuda.synchronize()
+    ref = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    ms_u = _median_ms(lambda pre: None if pre else g_u.launch(), reps=steps)
+    g_u.close()
+
+    def point(n_cells, n_entries, bias):
+        cache = ctx.cache(n_cells, n_entries, 16, level_bias=bias)
+        st_t = B.new_stats()
+        g = ctx.frame_graph(cache, ctx.frame_plan(hits, n, sc.frames, out, clear_cache=True,
+                                                  late_frame=4, late=late, **early))
+        g.launch()
+        ms = _median_ms(lambda pre: None if pre else g.launch(), reps=steps)
+        g.close()
+        last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+        gs = ctx.frame_graph(cache, ctx.frame_plan(hits, n, sc.frames, out, clear_cache=True,
+                                                   stats=st_t, late_frame=4, late=late, **early))
+        gs.launch()
+        torch.cuda.synchronize()
+        gs.close()
+        sd = B.stats_dict(st_t)
+        cache.close()
+        return dict(n_cells=n_cells, n_entries=n_entries, level_bias=bias,
+                    table_mib=n_cells * n_entries * 16 / 2 ** 20,
+                    samples_per_s=n * sc.frames / (ms * 1e-3), ms=ms,
+                    hit_rate=sd["cache_hits"] / max(sd["probes"], 1),
+                    found_per_sample=sd["cache_hits"] / max(sd["hits_shaded"], 1),
+                    cell_full=sd["cell_full"], inserts=sd["inserts"],
+                    speedup_vs_uncached=ms_u / ms, err_vs_uncached=_abs_err(last, ref))
+
+    grid = []
+    for n_entries in (4, 8, 16):
+        for slots in (1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 24):
+            grid.append(point(slots // n_entries, n_entries, 0))
+            log("sweep N_c x N_e: %d x %d: %.2f G samples/s, hit rate %.3f" % (
+                slots // n_entries, n_entries, grid[-1]["samples_per_s"] / 1e9,
+                grid[-1]["hit_rate"]))
+    bias = []
+    for b in (-1, 0, 1, 2, 3):
+        bias.append(point((1 << 22) // 8, 8, b))
+        log("sweep level bias %+d: %.2f G samples/s, hit rate %.3f, err max %.3g mean %.3g" % (
+            b, bias[-1]["samples_per_s"] / 1e9, bias[-1]["hit_rate"],
+            bias[-1]["err_vs_uncached"]["max_abs"], bias[-1]["err_vs_uncached"]["mean_abs"]))
+    ctx.close()
+    del hits
+    torch.cuda.empty_cache()
+    return {"workload": "mid (64 materials, 1920x1080 x 16 frames), keep-first",
+            "uncached_samples_per_s": n * sc.frames / (ms_u * 1e-3),
+            "table_size": grid, "level_bias": bias}
+
+
+SURR_FLOP_PER_POINT = 2 * (32 * 64 + 64 * 64 + 64 * 4)     # 12,800 per network evaluation
+FP16_PEAK_TFLOPS = 2500.0
+TRAIN = dict(steps=8000, batch=1024, lr=2e-2, lr_end=1e-5, seed=0)
+
+
+def surrogate_leg(args):
+    """Learned surrogate on the mid workload: a progressive render (16 frames,
+    cached mode, insert log on) collects training pairs; every network is
+    trained (one launch) and trusted by its own held-out error; then the next
+    pass (its first 2^20 hits) is shaded from the render's final table:
+    uncached, cache only, and networks + cache.  Errors of every output
+    against the uncached GPU path (held within 1e-5 of the FP64 graph by the
+    parity tests)."""
+    import torch
+    from paper_2305_07238_amd import binding as B
+    sc, _ = workload("mid")
+    n = sc.hits_per_frame
+    hits = device_frames(sc, sc.frames)
+    views = [{k: v[f * n:(f + 1) * n] for k, v in hits.items()} for f in range(sc.frames)]
+    out = B.alloc_outputs(n)
+    ctx = B.Context(0)
+    ctx.set_textures(sc.textures)
+    ctx.compile(sc.materials)
+    cache = ctx.cache(sc.cache.n_cells, 8, 16)
     n_slots = ctx.surrogate_setup(seed=0)
-    flags = best["flags"] & ~(B.PMC_FLAG_LOG | B.PMC_FLAG_SURROGATE)
-    kw = dict(chunk_waves=best["chunk_waves"], defer_max=best["defer_max"],
-              blocks_per_cu=best["blocks_per_cu"], waves_per_block=best["waves_per_block"])
-    cache.clear()
+    kw = dict(flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, chunk_waves=4, defer_max=48)
     ctx.log_clear()
     for f in range(sc.frames):
-        ctx.shade(frame_views[f], out, cache, mode=B.PMC_MODE_CACHED, frame=f,
-                  flags=flags | B.PMC_FLAG_LOG, **kw)
+        k = dict(kw) if f < 4 else dict(flags=B.PMC_FLAG_SORT, chunk_waves=1, defer_max=0)
+        k["flags"] |= B.PMC_FLAG_LOG
+        ctx.shade(views[f], out, cache, mode=B.PMC_MODE_CACHED, frame=f, **k)
     torch.cuda.synchronize()
     n_log = len(ctx.log_read())
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -173,9 +541,8 @@ def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
     log(f"surrogate: {n_slots} slots, {len(trained)} trained on {n_log} log records in "
         f"{train_ms:.1f} ms, {len(trusted)} trusted")
     train_flop = 3.0 * SURR_FLOP_PER_POINT * TRAIN["batch"] * TRAIN["steps"] * len(trained)
-
     table = cache.export()
-    n17 = min(1 << 20, sc.hits_per_frame)
+    n17 = min(1 << 20, n)
     h17 = sc.frame(sc.frames).take(np.arange(n17))
     d17 = B.hits_to_device(h17)
     o17 = B.alloc_outputs(n17)
@@ -192,15 +559,17 @@ def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
                 return
             ctx.shade(d17, o17, cache if use_cache else None,
                       mode=B.PMC_MODE_CACHED if use_cache else B.PMC_MODE_UNCACHED,
-                      frame=sc.frames, flags=flags | f, **kw)
+                      frame=sc.frames, flags=B.PMC_FLAG_SORT | f)
         ms = _median_ms(run)
         got = {k: v.cpu().numpy().astype(np.float64) for k, v in o17.items()}
         results[name] = {"samples_per_s": n17 / (ms * 1e-3), "ms": ms, "_out": got}
-    _errors_vs_uncached(results)
-    # network inference on the matrix cores: 2^20 points through one slot
+    ref = results["uncached"]["_out"]
+    for r in results.values():
+        r["err_vs_uncached"] = _abs_err(r["_out"], ref)
+    for r in results.values():
+        del r["_out"]
     uv = d17["uv"]
     y = torch.empty((n17, 4), dtype=torch.float32, device="cuda")
-    # back-to-back launches, so the host's launch time does not enter the figure
     reps = 20
 
     def infer_batch(pre):
@@ -209,8 +578,10 @@ def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
                 ctx.surrogate_infer(0, uv, y)
     ms_inf = _median_ms(infer_batch) / reps
     inf_tflops = SURR_FLOP_PER_POINT * n17 / (ms_inf * 1e-3) / 1e12
-    return {
-        "slots": n_slots, "trusted": len(trusted), "log_records": n_log,
+    res = {
+        "workload": "mid after its 16-frame render; next pass, first 2^20 hits",
+        "slots": n_slots, "trusted": len(trusted),
+        "trusted_materials": [int(rep[k]["material"]) for k in trusted], "log_records": n_log,
         "train": dict(TRAIN, ms=train_ms, slots_trained=len(trained),
                       tflops=train_flop / (train_ms * 1e-3) / 1e12),
         "heldout_max_err": [r["max_err"] for r in rep],
@@ -222,9 +593,13 @@ def surrogate_leg(ctx, sc, frame_views, out, cache, best, log):
                                "peak": FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": inf_tflops / FP16_PEAK_TFLOPS}},
     }
+    ctx.close()
+    del hits, views
+    torch.cuda.empty_cache()
+    return res
 
 
-def surrogate_smooth_leg(log):
+def surrogate_smooth_leg(args):
     """The networks where they can be trusted: a 1920x1080 scene of 4 materials whose
     deep sub-graphs are expensive but low-frequency functions of UV (12 Perlin layers
     averaged).  Snapshot frames with the log on collect training pairs; every network
@@ -282,7 +657,11 @@ def surrogate_smooth_leg(log):
         ms = _median_ms(run)
         last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
         results[name] = {"samples_per_s": n * sc.frames / (ms * 1e-3), "ms": ms, "_out": last}
-    _errors_vs_uncached(results)
+    ref = results["uncached"]["_out"]
+    for r in results.values():
+        r["err_vs_uncached"] = _abs_err(r["_out"], ref)
+    for r in results.values():
+        del r["_out"]
     # texels 8x finer than the footprints (level bias +3): the table reuses far
     # less, so more lookups miss, and a miss of a trusted output costs one
     # network evaluation instead of the sub-graph
@@ -324,31 +703,24 @@ def surrogate_smooth_leg(log):
                                                     fine_res["surrogate_cache"]["ms"]))}
 
 
-def cpu_baseline(sc, sample_hits=786432, frames=3):
-    """The FP64 oracle (snapshot-mode progressive shading) on a bounded sample."""
-    from oracle import render, table
-    t = table.Table(sc.cache.n_cells, sc.cache.n_entries, sc.cache.entry_bytes)
-    batches = [sc.frame(f).take(np.arange(min(sample_hits, sc.hits_per_frame)))
-               for f in range(min(frames, sc.frames))]
-    t0 = time.perf_counter()
-    render.shade_snapshot(sc.materials, sc.textures, batches, t)
-    dt = time.perf_counter() - t0
-    n = sum(len(b) for b in batches)
-    return {"value": n / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {len(batches[0])} hits (screen order) of frames 0-{len(batches)-1}, "
-                      f"snapshot-mode shading in FP64, {dt:.1f} s"}
+LEGS = ("batching", "mid", "surrogate", "sweeps")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--workload", default="scale",
+                    help="headline workload: scale (default), batching, mid or tiny")
     ap.add_argument("--frames", type=int, default=0)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="further legs, comma separated (%s) or 'none'" % ", ".join(LEGS))
     ap.add_argument("--mode", default="cached", choices=["cached", "snapshot", "uncached"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uncached-steps", type=int, default=3)
+    ap.add_argument("--prof-steps", type=int, default=3,
+                    help="renders launched frame by frame with HIP-event phase timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-parameter search (use sort + deferral, 4-chunk runs)")
     ap.add_argument("--min-subgraph", type=int, default=0,
@@ -368,20 +740,21 @@ def main():
     ap.add_argument("--late-defer-max", type=int, default=0)
     ap.add_argument("--tune-json", default=None,
                     help="write every autotuner candidate and its time to this file")
-    ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the learned-surrogate leg (training on the insert log)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the path is shown on "
+                                   "one GPU's share of the work); --gpus must be 1",
                           "n_gpus": args.gpus}))
         raise SystemExit(2)
-
-    import torch
-    from paper_2305_07238_amd import binding as B
+    legs = [] if args.legs in ("", "none") else args.legs.split(",")
+    for leg in legs:
+        if leg not in LEGS:
+            raise SystemExit(f"unknown leg {leg}")
 
     if args.calibrate_copy:
+        import torch
         n = 1 << 28                                    # 2^28 int32 = 1 GiB each way
         src = torch.ones(n, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
@@ -391,173 +764,63 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
         return
 
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
     sc, desc = workload(args.workload, args.frames or None)
     log(f"workload {args.workload}: {sc.frames} frames x {sc.hits_per_frame} hits")
-    n_frame = sc.hits_per_frame
-    n_step = n_frame * sc.frames
-    hits = B.hits_to_device(scenes_concat(sc))
-    frame_views = [{k: v[f * n_frame:(f + 1) * n_frame] for k, v in hits.items()}
-                   for f in range(sc.frames)]
-    out = B.alloc_outputs(n_frame)          # the renderer consumes each frame's BSDF inputs
+    cpu, ref, ref_frame = None, None, None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the oracle's worker pool forks
+        ref_frame = sc.frames - 1
+        log("timing the CPU oracle on a bounded sample")
+        cpu, ref = cpu_baseline(sc, ref_frame)
+        log(f"CPU oracle: {cpu['value']:.0f} samples/s on {cpu['cores']} cores")
 
-    ctx = B.Context(0)
-    ctx.set_textures(sc.textures)
-    ctx.compile(sc.materials, min_subgraph_nodes=args.min_subgraph)
-    cc = sc.cache
-    policy = B.PMC_POLICY_OVERWRITE if cc.policy == "OVERWRITE" else B.PMC_POLICY_FIRST
-    cache = ctx.cache(cc.n_cells, cc.n_entries, cc.entry_bytes, policy)
-    mode = {"cached": B.PMC_MODE_CACHED, "snapshot": B.PMC_MODE_SNAPSHOT,
-            "uncached": B.PMC_MODE_UNCACHED}[args.mode]
-    use_cache = cache if mode != B.PMC_MODE_UNCACHED else None
-    log("inputs resident; autotuning launch parameters on the first frames")
+    import torch  # noqa: F401
+    from paper_2305_07238_amd import binding as B  # noqa: F401  (fails loudly if not built)
 
-    tune_frames = min(4, sc.frames)
-    if args.no_autotune:
-        best = dict(flags=args.flags if args.flags >= 0 else
-                    B.PMC_FLAG_SORT | (B.PMC_FLAG_DEFER if use_cache else 0),
-                    chunk_waves=args.chunk_waves or (4 if use_cache else 1),
-                    defer_max=args.defer_max or 48, blocks_per_cu=0,
-                    waves_per_block=args.waves_per_block)
-    else:
-        tune = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, tune_frames, out, mode=mode),
-                            args.tune_json)
-        b = tune.best
-        best = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
-                    blocks_per_cu=b.blocks_per_cu, waves_per_block=b.waves_per_block)
-        log(f"autotune: {best} {tune.best_ms:.3f} ms vs defaults {tune.default_ms:.3f} ms "
-            f"({tune.n_tried} settings, {tune_frames} frames)")
-    # frames from late_frame on may use another setting: once the table holds
-    # most values, chunks miss rarely and the best launch shape changes
-    late_frame, late = 0, None
-    if args.no_autotune:
-        if args.late_frame:
-            late_frame = args.late_frame
-            late = dict(flags=args.late_flags if args.late_flags >= 0 else best["flags"],
-                        chunk_waves=args.late_chunk_waves, defer_max=args.late_defer_max,
-                        blocks_per_cu=0, waves_per_block=0)
-    elif use_cache and sc.frames >= 2 * tune_frames:
-        late_frame = tune_frames
-        lt = ctx.autotune(use_cache, ctx.frame_plan(hits, n_frame, 2 * tune_frames, out,
-                                                    mode=mode, late_frame=late_frame, **best),
-                          args.tune_json + ".late" if args.tune_json else None)
-        b = lt.best
-        late = dict(flags=b.flags, chunk_waves=b.chunk_waves, defer_max=b.defer_max,
-                    blocks_per_cu=b.blocks_per_cu, waves_per_block=b.waves_per_block)
-        log(f"autotune, frames {late_frame}+: {late} ({lt.n_tried} settings, frames "
-            f"{late_frame}..{2 * tune_frames - 1} after {late_frame} with the first setting)")
-    graph = ctx.frame_graph(use_cache, ctx.frame_plan(hits, n_frame, sc.frames, out, mode=mode,
-                                                      clear_cache=True, late_frame=late_frame,
-                                                      late=late, **best))
-    for _ in range(args.warmup):
-        graph.launch()
-    torch.cuda.synchronize()
+    head = path_leg(args.workload, sc, desc, args, args.steps, args.warmup, ref, ref_frame,
+                    args.uncached_steps, args.prof_steps)
+    del sc
+    out_legs = {}
+    for leg in legs:
+        t0 = time.perf_counter()
+        if leg in ("batching", "mid") and leg != args.workload:
+            lsc, ldesc = workload(leg)
+            out_legs[leg] = path_leg(leg, lsc, ldesc, args, 3, 1, None, None, 2, 2)
+            del lsc
+        elif leg == "surrogate":
+            out_legs["surrogate"] = surrogate_leg(args)
+            out_legs["surrogate_smooth"] = surrogate_smooth_leg(args)
+        elif leg == "sweeps":
+            out_legs["sweeps"] = sweeps_leg(args)
+        log(f"leg {leg}: {time.perf_counter() - t0:.0f} s")
 
-    # timed region: whole progressive renders, each from an empty table
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        graph.launch()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"{ms_step:.3f} ms/step (graph replay)")
-    graph.close()
-
-    # the same work launched per frame with HIP-event phase timing on the stream
-    def step(m=mode, stats=None):
-        if m != B.PMC_MODE_UNCACHED:
-            cache.clear()
-        for f in range(sc.frames):
-            kw = late if (late_frame and f >= late_frame) else best
-            ctx.shade(frame_views[f], out, use_cache if m != B.PMC_MODE_UNCACHED else None,
-                      mode=m, frame=f, stats=stats, **kw)
-
-    prof_steps = 3
-    ctx.profile_enable(True)
-    for _ in range(prof_steps):
-        step()
-    torch.cuda.synchronize()
-    prof = ctx.profile_read(reset=True)
-    ctx.profile_enable(False)
-    log(f"phases over {prof_steps} steps: {prof}")
-
-    # one more step with counters (same work) for hit rate and algorithmic bytes
-    stats = B.new_stats()
-    step(stats=stats)
-    torch.cuda.synchronize()
-    st = B.stats_dict(stats)
-    kb = kernel_bytes(st, n_step)
-    shade_ms, shade_launches = prof["shade"]
-    achieved = kb / (shade_ms / prof_steps * 1e-3) / 1e9
-
-    # uncached reference on the same inputs, also replayed as a graph; the last
-    # frame's BSDF inputs of both give the error of the cached values
-    unc, err = None, None
-    if mode != B.PMC_MODE_UNCACHED and args.uncached_steps > 0:
-        cached_last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
-        g_u = ctx.frame_graph(None, ctx.frame_plan(hits, n_frame, sc.frames, out,
-                                                   mode=B.PMC_MODE_UNCACHED))
-        g_u.launch()
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(args.uncached_steps):
-            g_u.launch()
-        ev1.record()
-        torch.cuda.synchronize()
-        unc = ev0.elapsed_time(ev1) / args.uncached_steps
-        log(f"uncached {unc:.3f} ms/step")
-        g_u.close()
-        e = np.concatenate([np.abs(out[k].cpu().numpy().astype(np.float64) - cached_last[k]).ravel()
-                            for k in ("base_color", "roughness", "normal")])
-        err = {"max_abs": float(e.max()), "mean_abs": float(e.mean()),
-               "sample": "every BSDF input of the last frame, cached vs uncached GPU path"}
-
-    value = n_step / (ms_step * 1e-3)
     res = {
         "metric": METRIC,
-        "value": value,
+        "value": head["samples_per_s"],
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "hits_per_step": n_step, "frames": sc.frames,
-                   "mode": args.mode, "launch": "one HIP graph per step (table clear + frames)",
-                   "autotuned": best, "late_frame": late_frame, "autotuned_late": late},
-        "cache_hit_rate": st["cache_hits"] / max(st["probes"], 1),
-        "found_per_sample": st["cache_hits"] / max(st["hits_shaded"], 1),
-        "deferred_fraction": st["deferred"] / max(st["hits_shaded"], 1),
-        "nodes_executed_fraction": st["nodes_executed"] / max(st["nodes_total"], 1),
-        "uncached_samples_per_s": (n_step / (unc * 1e-3)) if unc else None,
-        "speedup_vs_uncached": (unc / ms_step) if unc else None,
-        "bsdf_err_vs_uncached": err,
-        "stats": st,
-        "phase_ms_per_step": {k: v[0] / prof_steps for k, v in prof.items()},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, best, late_frame, late),
-                     "kernel": shade_kernel_name(args.mode, best["flags"]) + (
-                         "" if not late_frame or shade_kernel_name(args.mode, late["flags"]) ==
-                         shade_kernel_name(args.mode, best["flags"]) else
-                         " (frames < %d), %s (later frames)" % (
-                             late_frame, shade_kernel_name(args.mode, late["flags"]))),
-                     "bytes_per_launch": kb / sc.frames,
-                     "avg_launch_ms": shade_ms / max(shade_launches, 1)},
+        "config": {"workload": head["workload"], "hits_per_step": head["hits_per_step"],
+                   "frames": head["frames"], "mode": args.mode,
+                   "launch": "one HIP graph per step (table clear + every frame)",
+                   **head["launch"]},
     }
-    if not args.no_surrogate and use_cache and args.workload == "mid":
-        res["surrogate"] = surrogate_leg(ctx, sc, frame_views, out, cache, best, log)
-        res["surrogate_smooth"] = surrogate_smooth_leg(log)
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        res["cpu_baseline"] = cpu_baseline(sc)
+    for k in ("cache_hit_rate", "found_per_sample", "deferred_fraction",
+              "nodes_executed_fraction", "uncached_samples_per_s", "speedup_vs_uncached",
+              "bsdf_err_vs_fp64_oracle", "bsdf_err_vs_uncached_gpu", "stats",
+              "phase_ms_per_step", "roofline"):
+        if k in head:
+            res[k] = head[k]
+    res["legs"] = out_legs
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
 
 

@@ -143,6 +143,7 @@ class Scene:
     cache: CacheConfig
     seed: int
     _frame_fn: object = dataclasses.field(repr=False, default=None)
+    layout: Optional[dict] = None       # _object_screen arguments of the screen layout
 
     def frame(self, f: int) -> Hits:
         """Hits of progressive pass ``f`` (deterministic)."""
@@ -482,7 +483,8 @@ def mid_scene(seed: int = 0, n_mats: int = 64, width: int = 1920, height: int = 
             for _ in range(n_mats)]
     tex = texture_pool(seed, n_textures, tex_size)
     frame_fn, n = _object_screen(seed, n_mats, width, height, 120, frames, name="mid")
-    return Scene("mid", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn)
+    return Scene("mid", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn,
+                 dict(n_mats=n_mats, width=width, height=height, obj=120))
 
 
 def lognormal_sizes(rng, n, lo, hi, mu=3.0, sigma=1.0):
@@ -550,7 +552,8 @@ def batching_scene(seed: int = 0, n_mats: int = 1000, width: int = 1920, height:
     mats = [random_material(rng, int(k), n_textures) for k in sizes]
     tex = texture_pool(seed + 1, n_textures, tex_size)
     frame_fn, n = _object_screen(seed, n_mats, width, height, 40, frames, name="batching")
-    return Scene("batching", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn)
+    return Scene("batching", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn,
+                 dict(n_mats=n_mats, width=width, height=height, obj=40))
 
 
 def scale_scene(seed: int = 0, n_mats: int = 4096, width: int = 3840, height: int = 2160,
@@ -563,7 +566,7 @@ def scale_scene(seed: int = 0, n_mats: int = 4096, width: int = 3840, height: in
     tex = texture_pool(seed + 2, n_textures, tex_size)
     frame_fn, n = _object_screen(seed, n_mats, width, height, 40, frames, name="scale")
     return Scene("scale", mats, tex, frames, n, CacheConfig(slots, policy="OVERWRITE"), seed,
-                 frame_fn)
+                 frame_fn, dict(n_mats=n_mats, width=width, height=height, obj=40))
 
 
 def mlp_init(seed: int, n_mats: int, fan=((32, 64), (64, 64), (64, 4))) -> List[List[np.ndarray]]:
@@ -600,3 +603,15 @@ def with_indirect(direct: Hits, frame: int, seed: int = 0, widen=(2.0, 16.0),
     ind = Hits(ind.material.copy(), uv, duv, ind.normal.copy(), bounce)
     d = Hits(direct.material, direct.uv, direct.duv, direct.normal, np.zeros(n, np.uint32))
     return Hits.concat([d, ind])
+
+
+def relayout(sc: Scene, seed: int) -> Scene:
+    """The same materials, textures and table on another screen layout: objects,
+    their materials, UV scales and normals, and the per-frame jitter all drawn
+    from ``seed`` (a warm-up scene for tuning launch settings)."""
+    if sc.layout is None:
+        raise ValueError(f"scene {sc.name} has no object layout")
+    L = sc.layout
+    frame_fn, n = _object_screen(seed, L["n_mats"], L["width"], L["height"], L["obj"], sc.frames)
+    return Scene(sc.name + "-layout%d" % seed, sc.materials, sc.textures, sc.frames, n, sc.cache,
+                 seed, frame_fn, dict(L))

@@ -13,10 +13,15 @@ SORT, DEFER = B.PMC_FLAG_SORT, B.PMC_FLAG_DEFER
 
 
 def test_kernel_bytes_model():
-    st = dict(probes=10, probes_deferred=2, deferred=3, insert_attempts=5, texture_evals=7)
+    """Method bytes: hit data, sorted index, one cell per first lookup, one entry
+    per stored value, four texels per image-texture evaluation; the rest
+    (repeated lookups and hit reads of deferred hits, attempts that stored
+    nothing) is overhead."""
+    st = dict(probes=10, probes_deferred=2, deferred=3, insert_attempts=9, inserts=4,
+              overwrites=1, texture_evals=7)
     n = 100
-    want = (n * (40 + 4 + 28) + 12 * 128 + 3 * 44 + 5 * 16 + 7 * 16)
-    assert bench.kernel_bytes(st, n) == want
+    assert bench.kernel_bytes(st, n) == n * (40 + 4 + 28) + 10 * 128 + 5 * 16 + 7 * 16
+    assert bench.overhead_bytes(st) == 2 * 128 + 3 * 44 + 4 * 16
 
 
 def test_kernel_names_follow_the_launch_setting():
@@ -54,8 +59,8 @@ def test_traffic_only_for_the_profiled_sources_and_settings(tmp_path, monkeypatc
                  traffic_bytes_per_launch=2.0)]
     dst = _tree(tmp_path, recs)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("w", early) == 1.0
-    assert bench.measured_traffic("w", early, 4, late) == 2.0
+    assert bench.measured_traffic("w", early)["traffic_bytes_per_launch"] == 1.0
+    assert bench.measured_traffic("w", early, 4, late)["traffic_bytes_per_launch"] == 2.0
     assert bench.measured_traffic("w", dict(early, defer_max=32)) is None
     assert bench.measured_traffic("w", dict(early, waves_per_block=1)) is None
     assert bench.measured_traffic("w", early, 5, late) is None
