@@ -71,8 +71,11 @@ def measured_traffic(workload_name, best, late_frame=0, late=None):
             h.update(f.read())
 
     def same(rec, want):
+        # the deferral threshold only matters with deferral on
+        keys = ("flags", "chunk_waves", "defer_max") if want["flags"] & 4 else \
+            ("flags", "chunk_waves")
         return (rec.get("waves_per_block", 4) == (want.get("waves_per_block", 0) or 4) and
-                all(rec[k] == want[k] for k in ("flags", "chunk_waves", "defer_max")))
+                all(rec[k] == want[k] for k in keys))
     for rec in recs:
         if h.hexdigest() != rec["source_sha256"] or not same(rec, best):
             continue

@@ -616,8 +616,18 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
                                                 uint32_t h, const HitData& hd, const LaneRegs& R,
                                                 Counters& cnt, uint32_t* ins, uint32_t* slots,
                                                 uint32_t skip = 0u) {
+  // sorted batches: the chunk's lanes usually share one material, whose header
+  // and descriptors then come through the scalar cache (per-lane vector loads
+  // of them put two more dependent memory round trips before the first key)
+  const uint64_t act = __ballot(active);
+  const uint32_t m0 = __builtin_amdgcn_readlane(m, act ? __ffsll((unsigned long long)act) - 1 : 0);
+  const bool uni = act != 0ull && __ballot(active && m != m0) == 0ull && m0 < a.n_mats;
   uint32_t n_cach = 0u, cbeg = 0u;
-  if (active && m < a.n_mats) {
+  if (uni) {
+    const PMC_CONST MatHeader* H = as_const(a.hdr) + m0;
+    n_cach = active ? H->n_cach : 0u;
+    cbeg = H->cach_begin;
+  } else if (active && m < a.n_mats) {
     const MatHeader* H = a.hdr + m;
     n_cach = H->n_cach;
     cbeg = H->cach_begin;
@@ -638,7 +648,15 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
     Key k;
     k.bypass = true; k.cell = 0u; k.hash2 = 0u;
     if (has) {
-      cd = a.cach[cbeg + c];
+      if (uni) {
+        const PMC_CONST CachDesc* cp =
+            as_const(a.cach) + (__builtin_amdgcn_readfirstlane(cbeg) + c);
+        cd.node_sock = cp->node_sock;
+        cd.reg = cp->reg;
+        cd.otype = cp->otype;
+      } else {
+        cd = a.cach[cbeg + c];
+      }
       k = make_key(m, cd.node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.cells,
                    a.hash2_mask);
     }
@@ -953,8 +971,18 @@ __device__ __forceinline__ void chunk_full(const ShadeArgs& a, const LaneHit& L,
     const bool mine = L.active && L.mat == m;
     pending &= ~__ballot(mine);
     const bool parked = SURR && surrogate_park<MODE>(a, m, mine, L.h, ins, region, cnt);
+    // every lookup of the material's lanes hit: only the always-needed nodes run,
+    // so the short hit program replaces the walk over the whole program (which
+    // fetches every instruction to test its need mask)
+    const bool all_hit = __ballot(mine && !parked && miss != 0u) == 0ull;
     if (mine && !parked) {
-      if (m < a.n_mats) {
+      if (m < a.n_mats && all_hit) {
+        const PMC_CONST MatHeader* H = as_const(a.hdr) + m;
+        cnt.v[CNT_NODES_TOTAL] += H->n_instr;
+        run_program<MODE, false, false>(a, m, L.h, L.hd, R, cnt, H->hit_begin, H->n_hit, 0u, 0u,
+                                        0u, no_audit());
+        write_outputs(a, m, L.h, L.hd, R);
+      } else if (m < a.n_mats) {
         shade_full<MODE, false, false>(a, m, L.h, L.hd, R, cnt, miss, ins, slots, no_audit());
       } else {
         cnt.v[CNT_INVALID]++;
