@@ -499,6 +499,29 @@ def sweeps_leg(args, steps=3):
             "table_size": grid, "level_bias": bias}
 
 
+def cones_leg(args, n=3840 * 2160, reps=20):
+    """Ray-cone footprints (Sec. 3.1) for one 3840x2160 frame of hits: the
+    kernel reads 56 bytes per hit (direction, radius, triangle and UV edges)
+    and writes the 16-byte gradients; HBM-bound elementwise work."""
+    import torch
+    from paper_2305_07238_amd import binding as B
+    from paper_2305_07238_amd import scenes
+    c = {k: torch.from_numpy(v).cuda() for k, v in scenes.cone_hits(0, n).items()}
+    duv = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    ctx = B.Context(0)
+
+    def run(pre):
+        if not pre:
+            for _ in range(reps):
+                ctx.ray_cone_gradients(c, duv)
+    ms = _median_ms(run) / reps
+    gbs = n * 72 / (ms * 1e-3) / 1e9
+    ctx.close()
+    return {"hits": n, "ms": ms, "samples_per_s": n / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_hit": 72}}
+
+
 SURR_FLOP_PER_POINT = 2 * (32 * 64 + 64 * 64 + 64 * 4)     # 12,800 per network evaluation
 FP16_PEAK_TFLOPS = 2500.0
 TRAIN = dict(steps=8000, batch=1024, lr=2e-2, lr_end=1e-5, seed=0)
@@ -706,7 +729,7 @@ def surrogate_smooth_leg(args):
                                                     fine_res["surrogate_cache"]["ms"]))}
 
 
-LEGS = ("batching", "mid", "surrogate", "sweeps")
+LEGS = ("batching", "mid", "surrogate", "sweeps", "cones")
 
 
 def main():
@@ -795,6 +818,8 @@ def main():
             out_legs["surrogate_smooth"] = surrogate_smooth_leg(args)
         elif leg == "sweeps":
             out_legs["sweeps"] = sweeps_leg(args)
+        elif leg == "cones":
+            out_legs["cones"] = cones_leg(args)
         log(f"leg {leg}: {time.perf_counter() - t0:.0f} s")
 
     res = {

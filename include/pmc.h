@@ -129,10 +129,11 @@ void pmc_destroy(pmc_ctx* ctx);
 /* Message of the last failing call on ctx ("" if none).  Owned by ctx. */
 const char* pmc_last_error(const pmc_ctx* ctx);
 /* ABI version (PMC_ABI_VERSION) and sizeof of the public structs, by index
- * 0..19 (node_desc, input, texture_desc, compile_opts, material_info,
+ * 0..20 (node_desc, input, texture_desc, compile_opts, material_info,
  * cache_params, shade_params, stats, hits, bsdf_out, debug_out, key_record,
  * frame_plan, tune_result, profile, surrogate_opts, surrogate_slot,
- * log_record, train_params, surrogate_stat); 0 for an unknown index. */
+ * log_record, train_params, surrogate_stat, cone_hits); 0 for an unknown
+ * index. */
 uint32_t pmc_abi_version(void);
 size_t pmc_abi_sizeof(uint32_t which);
 
@@ -539,6 +540,32 @@ typedef struct pmc_surrogate_stat {
 /* Copy the per-slot statistics of slots [0, n) to host memory.  Synchronous. */
 pmc_status pmc_surrogate_report(pmc_ctx* ctx, pmc_surrogate_stat* host_out, uint32_t n,
                                 void* stream);
+
+/* ------------------------------------------------------------ ray cones */
+
+/* Texture-coordinate gradients of hits from their ray cones, for renderers
+ * that track a cone per path (Sec. 3.1: the cone's intersection with the
+ * surface is an ellipse; its two axes carried into UV space are g1 and g2,
+ * after Akenine-Moller et al. 2021).  The surface is the hit triangle's plane
+ * (normal e1 x e2); the ellipse of a cone of radius r around the ray has
+ * semi-axes r / |cos| along the ray's projection onto the plane and r across
+ * it, |cos| = |d.n| / (|d| |n|) clamped below at 1/1024; a ray within 1e-4 rad
+ * of the normal uses the tangent frame of Duff et al. 2017 for the axes.  An
+ * in-plane offset a moves the UV by du t1 + dv t2 with
+ * du = ((a x e2).n) / (n.n), dv = ((e1 x a).n) / (n.n).  The output has the
+ * layout of pmc_hits.duv (g1.x, g1.y, g2.x, g2.y), so it can be passed to
+ * pmc_shade as is.  A degenerate triangle, a zero direction or a non-finite
+ * input gives NaN gradients, which make the hit bypass the cache. */
+typedef struct pmc_cone_hits {  /* device pointers, caller-owned, n entries each */
+    const float* dir;          /* [n][3] ray direction (any length) */
+    const float* radius;       /* [n] cone radius at the hit */
+    const float* edge;         /* [n][6] triangle edges P1 - P0, then P2 - P0; 8-byte aligned */
+    const float* uv_edge;      /* [n][4] UV edges uv1 - uv0, then uv2 - uv0; 16-byte aligned */
+    uint64_t n;
+} pmc_cone_hits;
+/* duv: device [n][4], 16-byte aligned.  Asynchronous on stream. */
+pmc_status pmc_ray_cone_gradients(pmc_ctx* ctx, const pmc_cone_hits* hits, float* duv,
+                                  void* stream);
 
 /* ------------------------------------------------------------- profiling */
 

@@ -86,6 +86,11 @@ class pmc_hits(C.Structure):
                 ("normal", C.c_void_p), ("n", C.c_uint64), ("bounce", C.c_void_p)]
 
 
+class pmc_cone_hits(C.Structure):
+    _fields_ = [("dir", C.c_void_p), ("radius", C.c_void_p), ("edge", C.c_void_p),
+                ("uv_edge", C.c_void_p), ("n", C.c_uint64)]
+
+
 class pmc_bsdf_out(C.Structure):
     _fields_ = [("base_color", C.c_void_p), ("roughness", C.c_void_p), ("normal", C.c_void_p)]
 
@@ -197,6 +202,7 @@ _proto = {
     "pmc_shade_static": (_S, [_P, _P, C.POINTER(pmc_hits), C.POINTER(pmc_bsdf_out),
                               C.POINTER(pmc_shade_params), _P, C.POINTER(pmc_debug_out), _P]),
     "pmc_debug_keys": (_S, [_P, _P, C.POINTER(pmc_hits), _P, _P]),
+    "pmc_ray_cone_gradients": (_S, [_P, C.POINTER(pmc_cone_hits), _P, _P]),
     "pmc_cache_insert_raw": (_S, [_P, _P, _P, _P, C.c_uint64, C.c_uint32, _P, _P]),
     "pmc_cache_lookup_raw": (_S, [_P, _P, _P, C.c_uint64, _P, _P, _P]),
     "pmc_frame_graph_create": (_S, [_P, _P, C.POINTER(pmc_frame_plan), C.POINTER(C.c_void_p)]),
@@ -481,6 +487,13 @@ class Context:
         arr = (pmc_surrogate_stat * max(n, 1))()
         self.check(pmc_surrogate_report(self.h, arr, n, _stream_ptr(stream)))
         return [{f: getattr(arr[k], f) for f in SURROGATE_STAT_FIELDS} for k in range(n)]
+
+    def ray_cone_gradients(self, cone: dict, duv, stream=None):
+        """cone: torch CUDA tensors dir [n, 3], radius [n], edge [n, 6], uv_edge [n, 4];
+        duv: float32 [n, 4] output (the layout of the hits' duv)."""
+        h = pmc_cone_hits(_ptr(cone["dir"]), _ptr(cone["radius"]), _ptr(cone["edge"]),
+                          _ptr(cone["uv_edge"]), int(cone["radius"].numel()))
+        self.check(pmc_ray_cone_gradients(self.h, C.byref(h), _ptr(duv), _stream_ptr(stream)))
 
     def debug_keys(self, cache: "Cache", hits: dict, out, stream=None):
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),

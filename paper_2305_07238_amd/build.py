@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["abi.cpp", "compiler.cpp", "frame.cpp", "surrogate_api.cpp", "static_shade.cpp",
-           "shade.hip", "sort.hip", "snapshot.hip", "surrogate.hip", "util.hip"]
+           "shade.hip", "sort.hip", "snapshot.hip", "surrogate.hip", "util.hip", "cones.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]

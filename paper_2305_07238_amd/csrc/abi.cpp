@@ -144,6 +144,7 @@ size_t pmc_abi_sizeof(uint32_t which) {
     case 17: return sizeof(pmc_log_record);
     case 18: return sizeof(pmc_train_params);
     case 19: return sizeof(pmc_surrogate_stat);
+    case 20: return sizeof(pmc_cone_hits);
     default: return 0;
   }
 }

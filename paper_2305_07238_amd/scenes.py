@@ -615,3 +615,48 @@ def relayout(sc: Scene, seed: int) -> Scene:
     frame_fn, n = _object_screen(seed, L["n_mats"], L["width"], L["height"], L["obj"], sc.frames)
     return Scene(sc.name + "-layout%d" % seed, sc.materials, sc.textures, sc.frames, n, sc.cache,
                  seed, frame_fn, dict(L))
+
+
+def cone_hits(seed: int, n: int, min_sin: float = 0.1, min_cos: float = 0.05,
+              head_on: float = 0.01) -> Dict[str, np.ndarray]:
+    """Hit geometry of a path tracer for the ray-cone footprint: per hit a ray
+    direction, the cone radius at the hit, the hit triangle's edges and UV
+    edges (float32).  Triangles of scale log-uniform in [1e-3, 1] with angles
+    whose sine is at least ``min_sin``; rays at least ``min_cos`` from grazing;
+    a ``head_on`` fraction exactly along the triangle normal; radii
+    log-uniform in [1e-4, 1e-1] times the triangle scale; UV edges of lengths
+    log-uniform in [1e-3, 10]."""
+    rng = _rng(seed, _P_BOUNCE, 7, n)
+    out = {"dir": np.zeros((n, 3), np.float32), "radius": np.zeros(n, np.float32),
+           "edge": np.zeros((n, 6), np.float32), "uv_edge": np.zeros((n, 4), np.float32)}
+    done = 0
+    while done < n:
+        k = 2 * (n - done) + 16
+        s = np.exp(rng.uniform(np.log(1e-3), 0.0, k))
+        e1 = rng.normal(size=(k, 3)) * s[:, None]
+        e2 = rng.normal(size=(k, 3)) * s[:, None]
+        nrm = np.cross(e1, e2)
+        sin = np.linalg.norm(nrm, axis=1) / (np.linalg.norm(e1, axis=1) * np.linalg.norm(e2, axis=1))
+        d = rng.normal(size=(k, 3))
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        m = nrm / np.linalg.norm(nrm, axis=1)[:, None]
+        cos = np.abs(np.sum(d * m, axis=1))
+        on = rng.random(k) < head_on
+        e1f, e2f = e1.astype(np.float32), e2.astype(np.float32)
+        # exactly along the normal of the float32 triangle
+        nf = np.cross(e1f.astype(np.float64), e2f.astype(np.float64))
+        d = np.where(on[:, None], -nf / np.linalg.norm(nf, axis=1)[:, None], d)
+        ok = (sin >= min_sin) & ((cos >= min_cos) | on)
+        sel = np.nonzero(ok)[0][:n - done]
+        m_ = len(sel)
+        r = np.exp(rng.uniform(np.log(1e-4), np.log(1e-1), k)) * s
+        uvl = np.exp(rng.uniform(np.log(1e-3), np.log(10.0), (k, 2)))
+        ang = rng.uniform(0, 2 * np.pi, (k, 2))
+        t = np.stack([uvl[:, 0] * np.cos(ang[:, 0]), uvl[:, 0] * np.sin(ang[:, 0]),
+                      uvl[:, 1] * np.cos(ang[:, 1]), uvl[:, 1] * np.sin(ang[:, 1])], 1)
+        out["dir"][done:done + m_] = d[sel]
+        out["radius"][done:done + m_] = r[sel]
+        out["edge"][done:done + m_] = np.concatenate([e1f[sel], e2f[sel]], 1)
+        out["uv_edge"][done:done + m_] = t[sel]
+        done += m_
+    return out

@@ -36,7 +36,8 @@ def test_struct_layouts_match_the_header():
                             B.pmc_stats, B.pmc_hits, B.pmc_bsdf_out, B.pmc_debug_out,
                             B.pmc_key_record, B.pmc_frame_plan, B.pmc_tune_result,
                             B.pmc_profile, B.pmc_surrogate_opts, B.pmc_surrogate_slot,
-                            None, B.pmc_train_params, B.pmc_surrogate_stat]):
+                            None, B.pmc_train_params, B.pmc_surrogate_stat,
+                            B.pmc_cone_hits]):
         if st is None:                      # pmc_log_record: 32 bytes, numpy dtype
             assert B.pmc_abi_sizeof(i) == B.LOG_RECORD_DTYPE.itemsize == 32
             continue
