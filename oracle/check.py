@@ -137,8 +137,8 @@ def check_frame(materials, textures, hits, frame, state, value, outputs, n_cells
         subst = {}
         kys = []
         for c, (node, sock) in enumerate(cach):
-            ky = K.compute_keys(int(m), node, sock, hits.uv[idx], hits.duv[idx], n_cells,
-                                level_bias, level_max)
+            ky = K.keys_for(material, int(m), node, sock, hits, idx, n_cells, level_bias,
+                            level_max)
             kys.append(ky)
             otype = graph.output_type(material, node, sock)
             st = state[idx, c]
@@ -151,7 +151,9 @@ def check_frame(materials, textures, hits, frame, state, value, outputs, n_cells
                 for j in np.nonzero(hit)[0]:
                     pending_hits.append((int(idx[j]), c, (int(ky.k0[j]), int(ky.k1[j])), otype,
                                          v[j]))
-        out, vals = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures, subst)
+        pos = None if getattr(hits, "position", None) is None else hits.position[idx]
+        out, vals = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures, subst,
+                                   position=pos)
         ratios = output_ratios(outputs, out, idx)
         for k, q in ratios.items():
             if not q <= 1.0:
@@ -168,7 +170,7 @@ def check_frame(materials, textures, hits, frame, state, value, outputs, n_cells
             if (node, sock) in subst:
                 others = {k: v for k, v in subst.items() if k != (node, sock)}
                 _, own = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures,
-                                        others)
+                                        others, position=pos)
             dv = decoded_candidates(own[(node, sock)], otype)
             for j in missed:
                 frame_vals[(int(idx[j]), c)] = dv[j]

@@ -8,14 +8,17 @@ Sec. 3.1: a sub-graph that reads any other shading-point datum is not
 cacheable.
 
 Readings used here (the paper gives no formal rule):
-  * dependency class of a node: CONST (reads no shading-point data),
-    UV (reads UV, nothing else), SP (reads another shading-point datum: the
-    normal-map node reads the hit normal);
-  * an output socket (node, socket) is cacheable when the node is UV-class,
-    is not the UV input itself, its sub-graph holds at least
-    ``min_subgraph_nodes`` nodes besides UV inputs, and at least one
-    consumer of that socket is an SP-class node or the BSDF sink, i.e. the
-    socket sits at the UV/SP boundary (the highest UV-only level);
+  * dependency class of a node: the set of shading-point data its value
+    depends on, among UV, POS (the world position, read by the position-noise
+    node: Sec. 3.1 names world position as other shading-point information a
+    descriptor can use) and SP (any other datum: the normal-map node reads the
+    hit normal); CONST is the empty set;
+  * an output socket (node, socket) is cacheable when the node's class is
+    exactly UV or exactly POS, the node is not the UV input itself, its
+    sub-graph holds at least ``min_subgraph_nodes`` nodes besides UV inputs,
+    and at least one consumer of that socket has another class or is the BSDF
+    sink, i.e. the socket is the highest level of its class; a UV-class output
+    is keyed by a UV texel, a POS-class output by a world-space cell;
   * only nodes reachable from the sink take part;
   * a multi-output node gets one descriptor per cacheable output socket;
   * ordinals c = 0..K-1 follow ascending (node index, socket).
@@ -34,13 +37,15 @@ IN_TYPES = {
     "UV_INPUT": (), "IMAGE_TEXTURE": ("UV",), "VALUE_NOISE": ("UV",), "PERLIN_NOISE": ("UV",),
     "MIX": ("FLOAT", "COLOR", "COLOR"), "MATH": ("FLOAT", "FLOAT"), "COLOR_RAMP": ("FLOAT",),
     "NORMAL_MAP": ("COLOR", "FLOAT"), "BSDF_OUTPUT": ("COLOR", "FLOAT", "VECTOR"),
+    "POSITION_NOISE": (),
 }
 OUT_TYPES = {
     "UV_INPUT": ("UV",), "IMAGE_TEXTURE": ("COLOR", "FLOAT"), "VALUE_NOISE": ("FLOAT",),
     "PERLIN_NOISE": ("FLOAT",), "MIX": ("COLOR",), "MATH": ("FLOAT",),
     "COLOR_RAMP": ("COLOR", "FLOAT"), "NORMAL_MAP": ("VECTOR",), "BSDF_OUTPUT": (),
+    "POSITION_NOISE": ("FLOAT",),
 }
-CONST, UV, SP = 0, 1, 2
+CONST, UV, POS, SP = 0, 1, 2, 4          # class = union (bitwise or) of these flags
 
 DEFAULT_BASE = (0.8, 0.8, 0.8)
 DEFAULT_ROUGHNESS = 0.5
@@ -115,18 +120,11 @@ def dependency_classes(material) -> List[int]:
         if i in memo:
             return memo[i]
         n = nodes[i]
-        if n.op in ("UV_INPUT", "IMAGE_TEXTURE", "VALUE_NOISE", "PERLIN_NOISE"):
-            c = UV
-            for inp in n.inputs:
-                if inp.node >= 0:
-                    c = max(c, cls(inp.node))
-        elif n.op == "NORMAL_MAP":
-            c = SP
-        else:
-            c = CONST
-            for inp in n.inputs:
-                if inp.node >= 0:
-                    c = max(c, cls(inp.node))
+        c = {"UV_INPUT": UV, "IMAGE_TEXTURE": UV, "VALUE_NOISE": UV, "PERLIN_NOISE": UV,
+             "POSITION_NOISE": POS, "NORMAL_MAP": SP}.get(n.op, CONST)
+        for inp in n.inputs:
+            if inp.node >= 0:
+                c |= cls(inp.node)
         memo[i] = c
         return c
 
@@ -145,14 +143,19 @@ def subgraph(material, i) -> set:
     return out
 
 
+MAX_CACHEABLE = 8
+
+
 def cacheable_outputs(material, min_subgraph_nodes: int = 2) -> List[Tuple[int, int]]:
-    """Ordered list of cacheable (node, socket) pairs (ordinal = list index)."""
+    """Ordered list of cacheable (node, socket) pairs (ordinal = list index); at
+    most MAX_CACHEABLE per material, the first in (node, socket) order (the
+    rest are evaluated every time, as if not cacheable)."""
     nodes = material.nodes
     live = reachable(material)
     cls = dependency_classes(material)
     out = []
     for i, n in enumerate(nodes):
-        if not live[i] or cls[i] != UV or n.op == "UV_INPUT" or n.op == "BSDF_OUTPUT":
+        if not live[i] or cls[i] not in (UV, POS) or n.op == "UV_INPUT" or n.op == "BSDF_OUTPUT":
             continue
         size = sum(1 for j in subgraph(material, i) if nodes[j].op != "UV_INPUT")
         if size < min_subgraph_nodes:
@@ -163,15 +166,21 @@ def cacheable_outputs(material, min_subgraph_nodes: int = 2) -> List[Tuple[int, 
                 if not live[q]:
                     continue
                 for inp in m.inputs:
-                    if inp.node == i and inp.socket == s and (m.op == "BSDF_OUTPUT" or cls[q] == SP):
+                    if inp.node == i and inp.socket == s and (m.op == "BSDF_OUTPUT" or
+                                                              cls[q] != cls[i]):
                         boundary = True
-            if boundary:
+            if boundary and len(out) < MAX_CACHEABLE:
                 out.append((i, s))
     return out
 
 
 def output_type(material, node, socket) -> str:
     return OUT_TYPES[material.nodes[node].op][socket]
+
+
+def key_kind(material, node) -> int:
+    """UV for a UV-texel descriptor, POS for a world-space cell (cacheable outputs)."""
+    return dependency_classes(material)[node]
 
 
 def _convert(val, src: str, dst: str):
@@ -184,10 +193,11 @@ def _convert(val, src: str, dst: str):
     raise GraphError(f"cannot convert {src} to {dst}")
 
 
-def evaluate(material, uv, normal, textures, subst: Optional[dict] = None):
+def evaluate(material, uv, normal, textures, subst: Optional[dict] = None, position=None):
     """Evaluate one material at n shading points.
 
     uv: [n, 2], normal: [n, 3] (float arrays; promoted to FP64).
+    position: [n, 3] world positions (needed when the material reads them).
     subst: optional {(node, socket): (mask [n] bool, value array)}; where the
     mask is set, that output takes the given value instead of its computed
     one (this is how a cache hit replaces a sub-graph's result, Sec. 3).
@@ -238,6 +248,11 @@ def evaluate(material, uv, normal, textures, subst: Optional[dict] = None):
             r = N.color_ramp(read(i, 0, "FLOAT"), nd.ramp_pos, nd.ramp_rgba)
         elif op == "NORMAL_MAP":
             r = (N.normal_map(read(i, 0, "COLOR"), read(i, 1, "FLOAT"), normal),)
+        elif op == "POSITION_NOISE":
+            if position is None:
+                raise GraphError("the material reads the world position, none given")
+            r = (N.position_noise(np.asarray(position, dtype=np.float64), nd.freq, nd.octaves,
+                                  nd.seed),)
         else:
             raise GraphError(f"cannot evaluate {op}")
         r = list(r)

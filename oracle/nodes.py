@@ -17,6 +17,11 @@ stated once here and independently in the HIP interpreter:
                  constant outside [pos_0, pos_7].
   NORMAL_MAP     tangent-space colour -> world normal with the orthonormal
                  basis of Duff et al. 2017 (JCGT 6(1)), strength blend.
+  POSITION_NOISE value noise of the world position: octave o at frequency
+                 f0 2^o, lattice corner (i, j, k) valued
+                 hash32(((u32)i << 32 | (u32)j) ^ mix64((u32)k ^ (seed + o) G)) 2^-32
+                 (G the 64-bit golden constant), trilinear interpolation with
+                 smoothstep weights, octaves weighted 2^-o and normalised.
 """
 import numpy as np
 
@@ -169,3 +174,34 @@ def normal_map(color, strength, n):
     v = t[:, 0:1] * tx + t[:, 1:2] * bx + t[:, 2:3] * n
     v = _normalize(v, n)
     return _normalize(n + strength[:, None] * (v - n), n)
+
+
+def position_noise(p, f0, octaves, seed):
+    """p: [n, 3] world positions; returns [n] in [0, 1)."""
+    from .hashing import GOLDEN, mix64
+    p = np.asarray(p, dtype=np.float64)
+    total = np.zeros(p.shape[0])
+    norm = 0.0
+    for o in range(int(octaves)):
+        freq = f0 * 2.0 ** o
+        x = p * freq
+        c0 = np.floor(x)
+        f = x - c0
+        w = f * f * (3.0 - 2.0 * f)
+        ci = c0.astype(np.int64)
+        sg = np.uint64((((int(seed) + o) & 0xFFFFFFFF) * int(GOLDEN)) & 0xFFFFFFFFFFFFFFFF)
+        val = np.zeros(p.shape[0])
+        for dz in (0, 1):
+            kz = mix64((ci[:, 2] + dz).astype(np.uint32).astype(np.uint64) ^ sg)
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    ij = ((ci[:, 0] + dx).astype(np.uint32).astype(np.uint64) << np.uint64(32)) | \
+                        (ci[:, 1] + dy).astype(np.uint32).astype(np.uint64)
+                    h = (mix64(ij ^ kz) & np.uint64(0xFFFFFFFF)).astype(np.float64) * INV_2_32
+                    wx = w[:, 0] if dx else 1.0 - w[:, 0]
+                    wy = w[:, 1] if dy else 1.0 - w[:, 1]
+                    wz = w[:, 2] if dz else 1.0 - w[:, 2]
+                    val += wx * wy * wz * h
+        total += 0.5 ** o * val
+        norm += 0.5 ** o
+    return total / norm

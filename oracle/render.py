@@ -33,6 +33,11 @@ def encode(value, out_type):
     return codec.float_encode(value)
 
 
+def _pos(hits, idx):
+    p = getattr(hits, "position", None)
+    return None if p is None else p[idx]
+
+
 def shade_uncached(materials, textures, hits):
     """Plain evaluation of every hit (cache disabled).  Returns dict of FP64 arrays."""
     n = len(hits)
@@ -43,7 +48,8 @@ def shade_uncached(materials, textures, hits):
         if m >= len(materials):
             o = graph.default_outputs(hits.normal[idx])
         else:
-            o, _ = graph.evaluate(materials[m], hits.uv[idx], hits.normal[idx], textures)
+            o, _ = graph.evaluate(materials[m], hits.uv[idx], hits.normal[idx], textures,
+                                  position=_pos(hits, idx))
         for k in out:
             out[k][idx] = o[k]
     return out
@@ -112,8 +118,8 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
         subst = {}
         key_list = []
         for c, (node, sock) in enumerate(cach):
-            ky = K.compute_keys(int(m), node, sock, hits.uv[idx], hits.duv[idx], table.n_cells,
-                                level_bias, level_max, hash2_mask)
+            ky = K.keys_for(material, int(m), node, sock, hits, idx, table.n_cells,
+                            level_bias, level_max, hash2_mask)
             key_list.append(ky)
             otype = graph.output_type(material, node, sock)
             found = np.zeros(len(idx), dtype=bool)
@@ -173,7 +179,8 @@ def shade_snapshot_frame(materials, textures, hits, table: Table, frame: int,
                 else:
                     full[sm] = vals[sm, 0]
                 subst[(node, sock)] = (mask | sm, full)
-        out, values = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures, subst)
+        out, values = graph.evaluate(material, hits.uv[idx], hits.normal[idx], textures, subst,
+                                     position=_pos(hits, idx))
         for k in res.outputs:
             res.outputs[k][idx] = out[k]
         for c, (node, sock) in enumerate(cach):

@@ -24,7 +24,7 @@ import numpy as np
 # ----------------------------------------------------------------------------
 
 OPS = ("UV_INPUT", "IMAGE_TEXTURE", "VALUE_NOISE", "PERLIN_NOISE", "MIX",
-       "MATH", "COLOR_RAMP", "NORMAL_MAP", "BSDF_OUTPUT")
+       "MATH", "COLOR_RAMP", "NORMAL_MAP", "BSDF_OUTPUT", "POSITION_NOISE")
 MATH_OPS = ("ADD", "MUL", "POW")
 
 # socket types of each op: inputs and outputs
@@ -38,6 +38,7 @@ IN_TYPES = {
     "COLOR_RAMP": ("FLOAT",),
     "NORMAL_MAP": ("COLOR", "FLOAT"),
     "BSDF_OUTPUT": ("COLOR", "FLOAT", "VECTOR"),
+    "POSITION_NOISE": (),
 }
 OUT_TYPES = {
     "UV_INPUT": ("UV",),
@@ -49,6 +50,7 @@ OUT_TYPES = {
     "COLOR_RAMP": ("COLOR", "FLOAT"),
     "NORMAL_MAP": ("VECTOR",),
     "BSDF_OUTPUT": (),
+    "POSITION_NOISE": ("FLOAT",),
 }
 
 
@@ -100,25 +102,34 @@ class Hits:
     duv: np.ndarray                     # float32 [n, 4]: g1.x, g1.y, g2.x, g2.y
     normal: np.ndarray                  # float32 [n, 3]
     bounce: Optional[np.ndarray] = None  # uint32 [n]: path depth of the hit (0 = camera ray)
+    position: Optional[np.ndarray] = None  # float32 [n, 3]: world position
+    width: Optional[np.ndarray] = None     # float32 [n]: world-space footprint width
+
+    OPTIONAL = ("bounce", "position", "width")
 
     def __len__(self) -> int:
         return int(self.material.shape[0])
 
     def take(self, idx) -> "Hits":
-        b = None if self.bounce is None else self.bounce[idx]
-        return Hits(self.material[idx], self.uv[idx], self.duv[idx], self.normal[idx], b)
+        opt = {k: (None if getattr(self, k) is None else getattr(self, k)[idx])
+               for k in self.OPTIONAL}
+        return Hits(self.material[idx], self.uv[idx], self.duv[idx], self.normal[idx], **opt)
 
     @staticmethod
     def concat(parts: Sequence["Hits"]) -> "Hits":
-        if all(p.bounce is None for p in parts):
-            b = None
-        else:
-            b = np.concatenate([p.bounce if p.bounce is not None
-                                else np.zeros(len(p), np.uint32) for p in parts])
+        opt = {}
+        for k in Hits.OPTIONAL:
+            if all(getattr(p, k) is None for p in parts):
+                opt[k] = None
+            elif k == "bounce":
+                opt[k] = np.concatenate([p.bounce if p.bounce is not None
+                                         else np.zeros(len(p), np.uint32) for p in parts])
+            else:
+                opt[k] = np.concatenate([getattr(p, k) for p in parts])
         return Hits(np.concatenate([p.material for p in parts]),
                     np.concatenate([p.uv for p in parts]),
                     np.concatenate([p.duv for p in parts]),
-                    np.concatenate([p.normal for p in parts]), b)
+                    np.concatenate([p.normal for p in parts]), **opt)
 
 
 @dataclasses.dataclass
@@ -265,7 +276,7 @@ RANGES = {
 
 def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
                     p_normal_map: float = 0.5, p_share: float = 0.15,
-                    ranges: str = "narrow") -> Material:
+                    ranges: str = "narrow", p_position: float = 0.0) -> Material:
     """A random node network with exactly ``n_nodes`` nodes, all reachable from the sink.
 
     Built top-down from the BSDF sink: every open input slot is filled by a new
@@ -302,7 +313,12 @@ def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
 
     def make_node(op):
         kw = {}
-        if op == "IMAGE_TEXTURE":
+        if p_position > 0.0 and op in _LEAVES and rng.random() < p_position:
+            op = "POSITION_NOISE"                   # a leaf reading the world position
+            kw["freq"] = float(rng.choice([0.5, 1.0, 2.0, 4.0]))
+            kw["octaves"] = 2
+            kw["seed"] = int(rng.integers(0, 1 << 30))
+        elif op == "IMAGE_TEXTURE":
             kw["texture"] = int(rng.integers(0, n_textures))
         elif op in ("PERLIN_NOISE", "VALUE_NOISE"):
             kw["freq"] = float(rng.choice([2.0, 4.0, 8.0, 16.0]))
@@ -345,7 +361,7 @@ def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
                 op = str(rng.choice(types, p=probs))
             budget -= 1
             src = make_node(op)
-            created[owner]["slots"][slot] = ("node", src, out_socket(op))
+            created[owner]["slots"][slot] = ("node", src, out_socket(created[src]["op"]))
         else:
             if later and rng.random() < 0.7:
                 src = int(rng.choice(later))
@@ -365,7 +381,7 @@ def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
         op = d["op"]
         if op in ("IMAGE_TEXTURE", "PERLIN_NOISE", "VALUE_NOISE"):
             ins = [Input.link(remap[uv_id], 0)]
-        elif op == "UV_INPUT":
+        elif op in ("UV_INPUT", "POSITION_NOISE"):
             ins = []
         else:
             n_in = len(IN_TYPES[op])
@@ -385,7 +401,7 @@ def random_material(rng: np.random.Generator, n_nodes: int, n_textures: int,
         node = Node(op, ins)
         if op == "IMAGE_TEXTURE":
             node.texture = d["texture"]
-        elif op in ("PERLIN_NOISE", "VALUE_NOISE"):
+        elif op in ("PERLIN_NOISE", "VALUE_NOISE", "POSITION_NOISE"):
             node.freq, node.octaves, node.seed = d["freq"], d["octaves"], d["seed"]
         elif op == "MATH":
             node.math_op, node.clamp = d["math_op"], True
@@ -432,7 +448,7 @@ def _zipf_choice(rng: np.random.Generator, n_items: int, size: int, s: float = 1
 
 
 def _object_screen(seed: int, n_mats: int, width: int, height: int, obj: int, frames: int,
-                   scale=(1.0, 8.0), name: str = "scene"):
+                   scale=(1.0, 8.0), name: str = "scene", world: bool = False):
     """Screen split into obj x obj pixel objects; each object has one material,
     a UV scale and offset, an anisotropy and a normal.  Returns the frame function."""
     gx, gy = width // obj, height // obj
@@ -462,13 +478,32 @@ def _object_screen(seed: int, n_mats: int, width: int, height: int, obj: int, fr
     duv[:, 3] = aniso[oid] * s_h / obj
     nrm_h = nrm[oid].astype(np.float32)
 
+    if world:
+        # each object a planar patch in the world: an origin in [-8, 8]^3, two
+        # orthonormal in-plane axes, a pixel size U[0.005, 0.04] world units
+        # (drawn from a stream of their own, so the screen layout is unchanged)
+        wr = _rng(seed, _P_OBJ, n_mats, width, 7)
+        origin = wr.uniform(-8.0, 8.0, (n_obj, 3))
+        ax = wr.normal(size=(n_obj, 3))
+        ax /= np.linalg.norm(ax, axis=1)[:, None]
+        ay = np.cross(nrm, ax)
+        ay /= np.linalg.norm(ay, axis=1)[:, None]
+        ax = np.cross(ay, nrm)
+        px = wr.uniform(0.005, 0.04, n_obj)
+        width_h = px[oid].astype(np.float32)
+
     def frame(f: int) -> Hits:
         jr = _rng(seed, _P_JITTER, n_mats, f)
         j = jr.random((n, 2))
         uv = np.empty((n, 2), np.float32)
         uv[:, 0] = off[oid, 0] + s_h * (xl + j[:, 0]) / obj
         uv[:, 1] = off[oid, 1] + s_h * (yl + j[:, 1]) / obj
-        return Hits(mat_h.copy(), uv, duv.copy(), nrm_h.copy())
+        if not world:
+            return Hits(mat_h.copy(), uv, duv.copy(), nrm_h.copy())
+        p = origin[oid] + (px[oid] * (xl + j[:, 0]))[:, None] * ax[oid] + \
+            (px[oid] * (yl + j[:, 1]))[:, None] * ay[oid]
+        return Hits(mat_h.copy(), uv, duv.copy(), nrm_h.copy(), position=p.astype(np.float32),
+                    width=width_h.copy())
 
     return frame, n
 
@@ -484,6 +519,23 @@ def mid_scene(seed: int = 0, n_mats: int = 64, width: int = 1920, height: int = 
     tex = texture_pool(seed, n_textures, tex_size)
     frame_fn, n = _object_screen(seed, n_mats, width, height, 120, frames, name="mid")
     return Scene("mid", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn,
+                 dict(n_mats=n_mats, width=width, height=height, obj=120))
+
+
+def spatial_scene(seed: int = 0, n_mats: int = 64, width: int = 480, height: int = 240,
+                  frames: int = 2, slots: int = 1 << 18, n_textures: int = 16,
+                  tex_size: int = 1024, nodes=(8, 64), p_position: float = 0.35) -> Scene:
+    """The mid material mix with a share ``p_position`` of its leaves reading the
+    world position (3D value noise), on 120-px objects that are planar patches
+    in the world; hits carry world positions and one pixel's world width."""
+    rng = _rng(seed, _P_GRAPH, 11)
+    mats = [random_material(rng, int(rng.integers(nodes[0], nodes[1] + 1)), n_textures,
+                            p_position=p_position)
+            for _ in range(n_mats)]
+    tex = texture_pool(seed, n_textures, tex_size)
+    frame_fn, n = _object_screen(seed, n_mats, width, height, 120, frames, name="spatial",
+                                 world=True)
+    return Scene("spatial", mats, tex, frames, n, CacheConfig(slots), seed, frame_fn,
                  dict(n_mats=n_mats, width=width, height=height, obj=120))
 
 

@@ -353,7 +353,7 @@ def test_cacheable_marking_cases():
               N("BSDF_OUTPUT", [L(2, 0), C(0.5), L(3)])])
     assert graph.cacheable_outputs(m) == [(2, 0)]
     classes = graph.dependency_classes(m)
-    assert classes[:4] == [graph.UV, graph.UV, graph.UV, graph.SP]
+    assert classes[:4] == [graph.UV, graph.UV, graph.UV, graph.UV | graph.SP]
     # a single texture fetch straight into the sink is below the minimum sub-graph size
     m2 = _mat([N("UV_INPUT"), N("IMAGE_TEXTURE", [L(0)]), N("BSDF_OUTPUT", [L(1, 0), L(1, 1), C()])])
     assert graph.cacheable_outputs(m2) == []
