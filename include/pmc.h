@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define PMC_ABI_VERSION 3u
+#define PMC_ABI_VERSION 4u
 
 typedef int32_t pmc_status;
 enum {
@@ -66,7 +66,9 @@ enum pmc_op {
     PMC_OP_MATH = 5,           /* in: FLOAT a, FLOAT b; out 0: FLOAT */
     PMC_OP_COLOR_RAMP = 6,     /* in 0: FLOAT fac; out 0: COLOR, out 1: FLOAT alpha */
     PMC_OP_NORMAL_MAP = 7,     /* in: COLOR, FLOAT strength; out 0: VECTOR (reads the hit normal) */
-    PMC_OP_BSDF_OUTPUT = 8     /* in: COLOR base colour, FLOAT roughness, VECTOR normal */
+    PMC_OP_BSDF_OUTPUT = 8,    /* in: COLOR base colour, FLOAT roughness, VECTOR normal */
+    PMC_OP_POSITION_NOISE = 9  /* no inputs (reads the hit's world position); out 0: FLOAT value
+                                  noise of the position (freq, octaves, seed as the UV noises) */
 };
 enum pmc_math_op { PMC_MATH_ADD = 0, PMC_MATH_MUL = 1, PMC_MATH_POW = 2 };
 #define PMC_NODE_CLAMP 1u      /* MATH: clamp the result to [0, 1] */
@@ -116,6 +118,9 @@ typedef struct pmc_material_info {
     uint32_t cacheable_socket[PMC_MAX_CACHEABLE];
     uint32_t subgraph_nodes[PMC_MAX_CACHEABLE];  /* sub-graph size of each, UV inputs excluded */
     uint32_t cacheable_type[PMC_MAX_CACHEABLE];  /* 0 FLOAT (raw float32 code), 1 COLOR (RGB9E5) */
+    uint32_t cacheable_key[PMC_MAX_CACHEABLE];   /* 0 keyed by a UV texel (Sec. 3.1), 1 by a
+                                                    world-space cell (the output depends on
+                                                    the world position and not on UV) */
 } pmc_material_info;
 
 /* Create a context on HIP device `device`, or a host-only context when
@@ -218,6 +223,14 @@ typedef struct pmc_hits {      /* all device pointers, caller-owned, n entries e
     uint64_t n;                /* hits; < 2^27 per call */
     const uint32_t* bounce;    /* [n] path depth of the hit (0 = seen from the camera), read
                                   only under PMC_POLICY_PRIORITY; NULL = all 0 */
+    const float* position;     /* [n][3] world position; required (else PMC_ERR_INVALID) when
+                                  the compiled graphs read it (POSITION_NOISE); NULL otherwise */
+    const float* width;        /* [n] world-space footprint width (e.g. the ray cone's width at
+                                  the hit); required with position.  A cacheable output that
+                                  depends on the position is keyed by a world-space cell:
+                                  level L from Eq. 1 with min(|g1|, |g2|) replaced by width,
+                                  2^L cells per world unit, k0 with bit 7 set, k1 = (qx << 42 |
+                                  qy << 21 | qz), each index mod 2^21 */
 } pmc_hits;
 
 typedef struct pmc_bsdf_out {  /* device pointers, caller-owned */

@@ -33,7 +33,7 @@ lib = C.CDLL(LIB_PATH)
 PMC_OK, PMC_ERR_INVALID, PMC_ERR_GRAPH, PMC_ERR_OOM, PMC_ERR_HIP, PMC_ERR_UNSUPPORTED, \
     PMC_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 OPS = {"UV_INPUT": 0, "IMAGE_TEXTURE": 1, "VALUE_NOISE": 2, "PERLIN_NOISE": 3, "MIX": 4,
-       "MATH": 5, "COLOR_RAMP": 6, "NORMAL_MAP": 7, "BSDF_OUTPUT": 8}
+       "MATH": 5, "COLOR_RAMP": 6, "NORMAL_MAP": 7, "BSDF_OUTPUT": 8, "POSITION_NOISE": 9}
 MATH_OPS = {"ADD": 0, "MUL": 1, "POW": 2}
 PMC_NODE_CLAMP = 1
 PMC_POLICY_FIRST, PMC_POLICY_OVERWRITE, PMC_POLICY_PRIORITY = 0, 1, 2
@@ -72,7 +72,8 @@ class pmc_material_info(C.Structure):
                 ("cacheable_node", C.c_uint32 * MAX_CACHEABLE),
                 ("cacheable_socket", C.c_uint32 * MAX_CACHEABLE),
                 ("subgraph_nodes", C.c_uint32 * MAX_CACHEABLE),
-                ("cacheable_type", C.c_uint32 * MAX_CACHEABLE)]
+                ("cacheable_type", C.c_uint32 * MAX_CACHEABLE),
+                ("cacheable_key", C.c_uint32 * MAX_CACHEABLE)]
 
 
 class pmc_cache_params(C.Structure):
@@ -83,7 +84,8 @@ class pmc_cache_params(C.Structure):
 
 class pmc_hits(C.Structure):
     _fields_ = [("material", C.c_void_p), ("uv", C.c_void_p), ("duv", C.c_void_p),
-                ("normal", C.c_void_p), ("n", C.c_uint64), ("bounce", C.c_void_p)]
+                ("normal", C.c_void_p), ("n", C.c_uint64), ("bounce", C.c_void_p),
+                ("position", C.c_void_p), ("width", C.c_void_p)]
 
 
 class pmc_cone_hits(C.Structure):
@@ -234,6 +236,11 @@ for _name, (_res, _args) in _proto.items():
 
 EXPORTED = tuple(_proto)
 
+ABI_VERSION = 4                     # the layouts above follow this version of include/pmc.h
+if pmc_abi_version() != ABI_VERSION:
+    raise ImportError(f"{LIB_PATH} has ABI {pmc_abi_version()}, the binding expects "
+                      f"{ABI_VERSION}: rebuild it with __graft_entry__.build()")
+
 
 class PmcError(RuntimeError):
     def __init__(self, code, msg):
@@ -365,7 +372,8 @@ class Context:
         """hits: dict of torch CUDA tensors material/uv/duv/normal (and optionally bounce);
         out: base_color/roughness/normal."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
-                     _ptr(hits["normal"]), int(hits["material"].numel()), _ptr(hits.get("bounce")))
+                     _ptr(hits["normal"]), int(hits["material"].numel()), _ptr(hits.get("bounce")),
+                     _ptr(hits.get("position")), _ptr(hits.get("width")))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
         p = pmc_shade_params(mode, flags, frame, chunk_waves, blocks_per_cu, defer_max,
                              waves_per_block)
@@ -392,7 +400,8 @@ class Context:
                    late: Optional[dict] = None) -> pmc_frame_plan:
         """hits: torch tensors holding n_frames * hits_per_frame hits, frame-major."""
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
-                     _ptr(hits["normal"]), 0, _ptr(hits.get("bounce")))
+                     _ptr(hits["normal"]), 0, _ptr(hits.get("bounce")),
+                     _ptr(hits.get("position")), _ptr(hits.get("width")))
         o = pmc_bsdf_out(_ptr(out["base_color"]), _ptr(out["roughness"]), _ptr(out["normal"]))
         prm = pmc_shade_params(mode, flags, 0, chunk_waves, blocks_per_cu, defer_max,
                                waves_per_block)
@@ -497,7 +506,8 @@ class Context:
 
     def debug_keys(self, cache: "Cache", hits: dict, out, stream=None):
         h = pmc_hits(_ptr(hits["material"]), _ptr(hits["uv"]), _ptr(hits["duv"]),
-                     _ptr(hits["normal"]), int(hits["material"].numel()))
+                     _ptr(hits["normal"]), int(hits["material"].numel()), _ptr(hits.get("bounce")),
+                     _ptr(hits.get("position")), _ptr(hits.get("width")))
         self.check(pmc_debug_keys(self.h, cache.h, C.byref(h), _ptr(out), _stream_ptr(stream)))
 
 
@@ -592,6 +602,9 @@ def hits_to_device(hits, device="cuda"):
     if getattr(hits, "bounce", None) is not None:
         d["bounce"] = torch.from_numpy(
             np.ascontiguousarray(hits.bounce, np.uint32).view(np.int32)).to(device)
+    if getattr(hits, "position", None) is not None:
+        d["position"] = torch.from_numpy(np.ascontiguousarray(hits.position, np.float32)).to(device)
+        d["width"] = torch.from_numpy(np.ascontiguousarray(hits.width, np.float32)).to(device)
     return d
 
 

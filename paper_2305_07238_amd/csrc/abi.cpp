@@ -416,6 +416,10 @@ static pmc_status check_hits(pmc_ctx* ctx, const pmc_hits* h) {
     return ctx->fail(PMC_ERR_INVALID, "null hit array");
   if (((uintptr_t)h->uv & 7u) || ((uintptr_t)h->duv & 15u))
     return ctx->fail(PMC_ERR_INVALID, "uv must be 8-byte and duv 16-byte aligned");
+  if (!h->position != !h->width)
+    return ctx->fail(PMC_ERR_INVALID, "position and width go together");
+  if (h->n && ctx->compiled && ctx->prog.uses_position && !h->position)
+    return ctx->fail(PMC_ERR_INVALID, "the compiled graphs read the world position");
   return PMC_OK;
 }
 
@@ -570,6 +574,8 @@ pmc_status shade_stage(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.duv = hits->duv;
   a.normal = hits->normal;
   a.bounce = hits->bounce;
+  a.position = hits->position;
+  a.width = hits->width;
   a.n = n;
   a.mode = mode;
   a.out_base = out->base_color;
@@ -694,6 +700,8 @@ pmc_status pmc_debug_keys(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
   a.material = hits->material;
   a.uv = hits->uv;
   a.duv = hits->duv;
+  a.position = hits->position;
+  a.width = hits->width;
   a.n = (uint32_t)hits->n;
   HIP_TRY(ctx, launch_debug_keys(a, out, (hipStream_t)stream));
   return PMC_OK;

@@ -10,9 +10,13 @@
 //            material can have several.
 //   Sec. 3.1 sub-graphs reading other shading-point data are not cacheable.
 //
-// Rule used for "highest level": an output socket of a UV-class node is
-// cacheable when one of its consumers is an SP-class node or the BSDF sink,
-// and its sub-graph has at least `min_subgraph_nodes` nodes besides UV inputs.
+// Rule used for "highest level": a node's class is the set of shading-point
+// data its value depends on (UV; POS, the world position, which Sec. 3.1 names
+// as other information a descriptor can hold; SP, any other datum).  An output
+// socket of a node whose class is exactly UV or exactly POS is cacheable when
+// one of its consumers has another class or is the BSDF sink, and its
+// sub-graph has at least `min_subgraph_nodes` nodes besides UV inputs.  A UV
+// output is keyed by a UV texel, a POS output by a world-space cell.
 //
 // Need masks: with miss_mask the per-lane set of cacheable outputs that were
 // not found, a node runs for a lane iff (exec & kAlways) || (exec & miss_mask).
@@ -33,11 +37,11 @@
 namespace pmc {
 namespace {
 
-enum Cls { C_CONST = 0, C_UV = 1, C_SP = 2 };
+enum Cls { C_CONST = 0, C_UV = 1, C_POS = 2, C_SP = 4 };   // a class is a union of these
 
-constexpr int kNumOps = 9;
-const int kNumIn[kNumOps] = {0, 1, 1, 1, 3, 2, 1, 2, 3};
-const int kNumOut[kNumOps] = {1, 2, 1, 1, 1, 1, 2, 1, 0};
+constexpr int kNumOps = 10;
+const int kNumIn[kNumOps] = {0, 1, 1, 1, 3, 2, 1, 2, 3, 0};
+const int kNumOut[kNumOps] = {1, 2, 1, 1, 1, 1, 2, 1, 0, 1};
 
 uint8_t in_type(uint32_t op, int k) {
   switch (op) {
@@ -145,7 +149,8 @@ struct MatCompiler {
         if (sink >= 0) return fail(i, "more than one BSDF_OUTPUT");
         sink = int(i);
       }
-      if ((d.op == PMC_OP_VALUE_NOISE || d.op == PMC_OP_PERLIN_NOISE) &&
+      if ((d.op == PMC_OP_VALUE_NOISE || d.op == PMC_OP_PERLIN_NOISE ||
+           d.op == PMC_OP_POSITION_NOISE) &&
           (d.octaves < 1 || d.octaves > 8 || !std::isfinite(d.freq)))
         return fail(i, "noise needs 1..8 octaves and a finite frequency");
       if (d.op == PMC_OP_MATH && d.variant > PMC_MATH_POW) return fail(i, "unknown math op");
@@ -277,9 +282,10 @@ struct MatCompiler {
       if (d.op == PMC_OP_UV_INPUT || d.op == PMC_OP_IMAGE_TEXTURE || d.op == PMC_OP_VALUE_NOISE ||
           d.op == PMC_OP_PERLIN_NOISE)
         c = C_UV;
+      if (d.op == PMC_OP_POSITION_NOISE) c = C_POS;
       if (d.op == PMC_OP_NORMAL_MAP) c = C_SP;
       for (int k = 0; k < kNumIn[d.op]; ++k)
-        if (d.in[k].node >= 0) c = std::max<int>(c, cls[d.in[k].node]);
+        if (d.in[k].node >= 0) c |= cls[d.in[k].node];
       cls[i] = uint8_t(c);
     }
     consumers.assign(n, {});
@@ -360,14 +366,15 @@ struct MatCompiler {
     sock_ord[1].assign(n, -1);
     for (uint32_t i = 0; i < n; ++i) {
       uint32_t op = nd[i].op;
-      if (!live[i] || cls[i] != C_UV || op == PMC_OP_UV_INPUT || op == PMC_OP_BSDF_OUTPUT)
+      if (!live[i] || (cls[i] != C_UV && cls[i] != C_POS) || op == PMC_OP_UV_INPUT ||
+          op == PMC_OP_BSDF_OUTPUT)
         continue;
       int size = -1;
       for (int s = 0; s < kNumOut[op]; ++s) {
         bool boundary = false;
         for (auto& ck : consumers[i]) {
           if (int(nd[ck.first].in[ck.second].socket) != s) continue;
-          if (ck.first == sink || cls[ck.first] == C_SP) boundary = true;
+          if (ck.first == sink || cls[ck.first] != cls[i]) boundary = true;
         }
         if (!boundary) continue;
         if (size < 0) size = subgraph_size(int(i));
@@ -503,8 +510,10 @@ struct MatCompiler {
       switch (d.op) {
         case PMC_OP_IMAGE_TEXTURE: I.param = d.variant;
           P.max_texture = std::max<int32_t>(P.max_texture, int32_t(d.variant)); break;
-        case PMC_OP_VALUE_NOISE: case PMC_OP_PERLIN_NOISE:
-          I.variant = uint8_t(d.octaves); I.param = d.seed; I.k[7] = d.freq; break;
+        case PMC_OP_VALUE_NOISE: case PMC_OP_PERLIN_NOISE: case PMC_OP_POSITION_NOISE:
+          I.variant = uint8_t(d.octaves); I.param = d.seed; I.k[7] = d.freq;
+          if (d.op == PMC_OP_POSITION_NOISE) P.uses_position = true;
+          break;
         case PMC_OP_MATH: I.variant = uint8_t(d.variant); break;
         case PMC_OP_COLOR_RAMP:
           I.param = uint32_t(P.pool.size());
@@ -531,6 +540,7 @@ struct MatCompiler {
       cd.node_sock = (uint32_t(i) << 16) | (uint32_t(s) << 8);
       cd.reg = uint16_t(reg[s][i]);
       cd.otype = out_type(nd[i].op, s);
+      cd.key = cls[i] == C_POS ? KEY_CELL : KEY_TEXEL;
       P.cach.push_back(cd);
     }
     P.headers.push_back(h);
@@ -548,6 +558,7 @@ struct MatCompiler {
       info.cacheable_socket[c] = uint32_t(cach[c].second);
       info.subgraph_nodes[c] = uint32_t(cach_sub[c]);
       info.cacheable_type[c] = out_type(nd[cach[c].first].op, cach[c].second) == OT_COLOR ? 1u : 0u;
+      info.cacheable_key[c] = cls[cach[c].first] == C_POS ? 1u : 0u;
     }
     P.max_regs = std::max(P.max_regs, n_regs);
     P.max_cach = std::max(P.max_cach, uint32_t(cach.size()));

@@ -19,6 +19,7 @@ struct Program {
   uint32_t max_regs = 0;
   uint32_t max_cach = 0;
   int32_t max_texture = -1;             // highest texture index referenced
+  bool uses_position = false;           // some live node reads the world position
 };
 
 // Compile every material.  On failure returns PMC_ERR_GRAPH (or INVALID) and sets err.

@@ -101,6 +101,45 @@ __device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float 
   return k;
 }
 
+// World-space cell of a position-dependent output (Sec. 3.1 names the world
+// position as other shading-point information a descriptor can use): the
+// level comes from the footprint width w as Eq. 1 takes it from min |g|
+// (m2 = w^2 in binary64), 2^L cells per world unit, indices floor(p 2^L) in
+// the int32 range, k0 marked by bit 7 of its low byte, k1 = 21 bits per axis.
+__device__ __forceinline__ Key make_key_cell(uint32_t mat, uint32_t node_sock, float3 p, float w,
+                                             int bias, int lmax, const CellMap& cells,
+                                             uint32_t h2mask) {
+  Key k;
+  k.cell = 0; k.hash2 = 1; k.level = 0; k.tx = 0; k.ty = 0; k.bypass = true;
+  if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(w))) return k;
+  const double m2 = (double)w * (double)w;
+  int L;
+  if (m2 == 0.0) {
+    L = lmax;
+  } else {
+    int e;
+    const double f = frexp(m2, &e);
+    const int F = (-e + (f == 0.5 ? 1 : 0)) >> 1;
+    L = F + bias;
+    L = L < 0 ? 0 : (L > lmax ? lmax : L);
+  }
+  const double x = ldexp((double)p.x, L), y = ldexp((double)p.y, L), z = ldexp((double)p.z, L);
+  const double lim = 2147483648.0;
+  if (!(x >= -lim && x < lim && y >= -lim && y < lim && z >= -lim && z < lim)) return k;
+  const int qx = (int)floor(x), qy = (int)floor(y), qz = (int)floor(z);
+  const uint64_t M = (1ull << 21) - 1ull;
+  const uint64_t k0 = ((uint64_t)mat << 32) | (uint64_t)node_sock | 0x80ull | (uint64_t)(uint32_t)L;
+  const uint64_t k1 = (((uint64_t)(uint32_t)qx & M) << 42) | (((uint64_t)(uint32_t)qy & M) << 21) |
+                      ((uint64_t)(uint32_t)qz & M);
+  const uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
+  const uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
+  k.cell = cell_of(cells, (uint32_t)(hc >> 32));
+  k.hash2 = (uint32_t)hv & h2mask;
+  if (k.hash2 == 0) k.hash2 = 1;
+  k.level = L; k.tx = qx; k.ty = qy; k.bypass = false;
+  return k;
+}
+
 // Descriptor hashes of raw descriptor words (Algorithm 1 surface).
 __device__ __forceinline__ void raw_hash(uint64_t k0, uint64_t k1, const CellMap& cells,
                                          uint32_t h2mask, uint32_t* cell, uint32_t* hash2) {

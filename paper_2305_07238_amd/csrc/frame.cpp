@@ -34,6 +34,8 @@ pmc_hits frame_hits(const pmc_frame_plan* p, uint32_t f) {
   h.duv = p->hits.duv + 4 * o;
   h.normal = p->hits.normal + 3 * o;
   h.bounce = p->hits.bounce ? p->hits.bounce + o : nullptr;
+  h.position = p->hits.position ? p->hits.position + 3 * o : nullptr;
+  h.width = p->hits.width ? p->hits.width + o : nullptr;
   h.n = p->hits_per_frame;
   return h;
 }

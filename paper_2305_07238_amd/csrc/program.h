@@ -71,11 +71,13 @@ struct MatHeader {          // 128 bytes
 };
 static_assert(sizeof(MatHeader) == 128, "MatHeader layout");
 
+enum : uint8_t { KEY_TEXEL = 0, KEY_CELL = 1 };   // UV texel, or world-space cell
+
 struct CachDesc {           // 16 bytes, one per cacheable output
   uint32_t node_sock;       // node << 16 | socket << 8 (low byte: level)
   uint16_t reg;             // register that holds the value
   uint8_t otype;            // OT_FLOAT (raw float code) or OT_COLOR (RGB9E5)
-  uint8_t pad;
+  uint8_t key;              // KEY_TEXEL or KEY_CELL
   uint32_t pad2[2];
 };
 static_assert(sizeof(CachDesc) == 16, "CachDesc layout");

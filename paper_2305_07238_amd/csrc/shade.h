@@ -38,6 +38,8 @@ struct ShadeArgs {
   const float* duv;
   const float* normal;
   const uint32_t* bounce;        // path depth per hit (PRIORITY policy), NULL = all 0
+  const float* position;         // [n][3] world positions, NULL when no graph reads them
+  const float* width;            // [n] world footprint widths (with position)
   const uint32_t* perm;          // processing order (material-sorted), NULL = identity
   uint32_t n;
   uint32_t mode;

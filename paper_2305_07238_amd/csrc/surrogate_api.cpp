@@ -101,6 +101,7 @@ pmc_status pmc_surrogate_setup(pmc_ctx* ctx, const pmc_surrogate_opts* opts, uin
     uint32_t used = 0, chan = 0;
     for (uint32_t c = 0; c < in.n_cacheable && c < 8; ++c) {
       if (in.subgraph_nodes[c] <= o.min_subgraph_nodes) continue;
+      if (in.cacheable_key[c] != 0u) continue;      // the networks read UV only
       const uint32_t w = in.cacheable_type[c] == 1u ? 3u : 1u;
       if (used + w > 4u) continue;
       sl.ordinal_mask |= 1u << c;

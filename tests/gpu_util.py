@@ -122,7 +122,9 @@ def substituted_outputs(materials, textures, hits, state, value, min_subgraph_no
                     else:
                         v = value[idx, c, 0].astype(np.float64)
                     subst[(node, sock)] = (rows, v)
-            o, _ = graph.evaluate(materials[m], hits.uv[idx], hits.normal[idx], textures, subst)
+            pos = None if getattr(hits, "position", None) is None else hits.position[idx]
+            o, _ = graph.evaluate(materials[m], hits.uv[idx], hits.normal[idx], textures, subst,
+                                  position=pos)
         for k in out:
             out[k][idx] = o[k]
     return out

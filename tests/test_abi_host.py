@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layouts_match_the_header():
-    assert B.pmc_abi_version() == 3
+    assert B.pmc_abi_version() == 4
     for i, st in enumerate([B.pmc_node_desc, B.pmc_input, B.pmc_texture_desc, B.pmc_compile_opts,
                             B.pmc_material_info, B.pmc_cache_params, B.pmc_shade_params,
                             B.pmc_stats, B.pmc_hits, B.pmc_bsdf_out, B.pmc_debug_out,
@@ -162,3 +162,25 @@ def test_surrogate_slots_follow_the_subgraph_rule():
         for c, ch in chans.items():
             assert sl["channel"][c] == ch
     ctx.close()
+
+
+def test_compiler_marks_world_keyed_outputs_like_the_oracle():
+    """Graphs with POSITION_NOISE leaves: the same cacheable outputs as the
+    oracle, keyed by a world cell exactly where the oracle's dependency class
+    is the world position, and no surrogate network over such an output."""
+    sc = scenes.spatial_scene(width=96, height=48, frames=1, n_mats=24)
+    ctx = _compile(sc.materials)
+    kinds = set()
+    for mi, m in enumerate(sc.materials):
+        cach = graph.cacheable_outputs(m)
+        assert ctx.cacheables(mi) == cach, mi
+        info = ctx.material_info(mi)
+        want = [1 if graph.key_kind(m, node) == graph.POS else 0 for node, _ in cach]
+        assert list(info.cacheable_key)[:len(cach)] == want, mi
+        kinds.update(want)
+    assert kinds == {0, 1}
+    n = ctx.surrogate_setup()
+    for k in range(n):
+        sl = ctx.surrogate_slot(k)
+        key = list(ctx.material_info(sl.material).cacheable_key)
+        assert all(key[c] == 0 for c in range(8) if (sl.ordinal_mask >> c) & 1)
