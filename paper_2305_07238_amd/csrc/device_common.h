@@ -58,79 +58,52 @@ struct Key {
   bool bypass;
 };
 
-// Level: floor(lambda) with lambda = -log2(min |g|) (Eq. 1), from the binary64
-// squared norms; frexp gives m2 = f 2^e, f in [1/2, 1), and then
-// floor(lambda) = floor((-e + [f == 1/2]) / 2).
+// Descriptor of a cacheable output (Sec. 3.1, Eq. 1), one routine for both
+// kinds so that a kernel carries a single copy of the arithmetic:
+//   texel (kind 0): coordinates (u, v), m2 = min(|g1|^2, |g2|^2) in binary64
+//     (the products are exact there);
+//   world cell (kind 1, the paper's other shading-point information): the
+//     world position (x, y, z), m2 = w^2 of the footprint width w.
+// Level: floor(lambda) with lambda = -log2(sqrt(m2)) (Eq. 1); frexp gives
+// m2 = f 2^e, f in [1/2, 1), and floor(lambda) = floor((-e + [f == 1/2]) / 2);
+// m2 = 0 takes the finest level.  Indices floor(c 2^L) must lie in the int32
+// range, else the hit bypasses.  Words: texel k0 = mat << 32 | node << 16 |
+// socket << 8 | L, k1 = (u32)tx << 32 | (u32)ty; cell k0 additionally has bit
+// 7 (never set by a texel level, L <= 20), k1 = qx << 42 | qy << 21 | qz with
+// each index mod 2^21.
 // h2mask keeps bits of the verification hash (all 32 in the method; fewer only
 // to force verification collisions in tests).
-__device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, float u, float v,
-                                        float4 g, int bias, int lmax, const CellMap& cells,
+__device__ __forceinline__ Key make_key(uint32_t mat, uint32_t node_sock, bool cell_kind,
+                                        float c0, float c1, float c2, double m2, bool finite,
+                                        int bias, int lmax, const CellMap& cells,
                                         uint32_t h2mask) {
   Key k;
   k.cell = 0; k.hash2 = 1; k.level = 0; k.tx = 0; k.ty = 0; k.bypass = true;
-  if (!(isfinite(u) && isfinite(v) && isfinite(g.x) && isfinite(g.y) && isfinite(g.z) &&
-        isfinite(g.w)))
-    return k;
-  double s1 = (double)g.x * (double)g.x + (double)g.y * (double)g.y;  // products exact
-  double s2 = (double)g.z * (double)g.z + (double)g.w * (double)g.w;
-  double m2 = s1 < s2 ? s1 : s2;
-  int L;
-  if (m2 == 0.0) {
-    L = lmax;
-  } else {
-    int e;
-    double f = frexp(m2, &e);
-    int t = -e + (f == 0.5 ? 1 : 0);
-    int F = t >> 1;                        // arithmetic shift = floor division by 2
-    L = F + bias;
-    L = L < 0 ? 0 : (L > lmax ? lmax : L);
-  }
-  double x = ldexp((double)u, L);
-  double y = ldexp((double)v, L);
-  const double lim = 2147483648.0;
-  if (!(x >= -lim && x < lim && y >= -lim && y < lim)) return k;
-  int tx = (int)floor(x), ty = (int)floor(y);
-  uint64_t k0 = ((uint64_t)mat << 32) | (uint64_t)node_sock | (uint64_t)(uint32_t)L;
-  uint64_t k1 = ((uint64_t)(uint32_t)tx << 32) | (uint64_t)(uint32_t)ty;
-  uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
-  uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
-  k.cell = cell_of(cells, (uint32_t)(hc >> 32));
-  k.hash2 = (uint32_t)hv & h2mask;
-  if (k.hash2 == 0) k.hash2 = 1;
-  k.level = L; k.tx = tx; k.ty = ty; k.bypass = false;
-  return k;
-}
-
-// World-space cell of a position-dependent output (Sec. 3.1 names the world
-// position as other shading-point information a descriptor can use): the
-// level comes from the footprint width w as Eq. 1 takes it from min |g|
-// (m2 = w^2 in binary64), 2^L cells per world unit, indices floor(p 2^L) in
-// the int32 range, k0 marked by bit 7 of its low byte, k1 = 21 bits per axis.
-__device__ __forceinline__ Key make_key_cell(uint32_t mat, uint32_t node_sock, float3 p, float w,
-                                             int bias, int lmax, const CellMap& cells,
-                                             uint32_t h2mask) {
-  Key k;
-  k.cell = 0; k.hash2 = 1; k.level = 0; k.tx = 0; k.ty = 0; k.bypass = true;
-  if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(w))) return k;
-  const double m2 = (double)w * (double)w;
+  if (!finite) return k;
   int L;
   if (m2 == 0.0) {
     L = lmax;
   } else {
     int e;
     const double f = frexp(m2, &e);
-    const int F = (-e + (f == 0.5 ? 1 : 0)) >> 1;
-    L = F + bias;
+    const int t = -e + (f == 0.5 ? 1 : 0);
+    L = (t >> 1) + bias;                   // arithmetic shift = floor division by 2
     L = L < 0 ? 0 : (L > lmax ? lmax : L);
   }
-  const double x = ldexp((double)p.x, L), y = ldexp((double)p.y, L), z = ldexp((double)p.z, L);
+  const double x = ldexp((double)c0, L), y = ldexp((double)c1, L), z = ldexp((double)c2, L);
   const double lim = 2147483648.0;
   if (!(x >= -lim && x < lim && y >= -lim && y < lim && z >= -lim && z < lim)) return k;
   const int qx = (int)floor(x), qy = (int)floor(y), qz = (int)floor(z);
-  const uint64_t M = (1ull << 21) - 1ull;
-  const uint64_t k0 = ((uint64_t)mat << 32) | (uint64_t)node_sock | 0x80ull | (uint64_t)(uint32_t)L;
-  const uint64_t k1 = (((uint64_t)(uint32_t)qx & M) << 42) | (((uint64_t)(uint32_t)qy & M) << 21) |
-                      ((uint64_t)(uint32_t)qz & M);
+  uint64_t k0 = ((uint64_t)mat << 32) | (uint64_t)node_sock | (uint64_t)(uint32_t)L;
+  uint64_t k1;
+  if (cell_kind) {
+    const uint64_t M = (1ull << 21) - 1ull;
+    k0 |= 0x80ull;
+    k1 = (((uint64_t)(uint32_t)qx & M) << 42) | (((uint64_t)(uint32_t)qy & M) << 21) |
+         ((uint64_t)(uint32_t)qz & M);
+  } else {
+    k1 = ((uint64_t)(uint32_t)qx << 32) | (uint64_t)(uint32_t)qy;
+  }
   const uint64_t hc = mix64(k1 ^ mix64(k0 ^ kSeedCell));
   const uint64_t hv = mix64(k1 ^ mix64(k0 ^ kSeedVerify));
   k.cell = cell_of(cells, (uint32_t)(hc >> 32));

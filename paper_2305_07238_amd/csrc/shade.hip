@@ -39,19 +39,34 @@ struct HitData {
   float u, v;
   float4 g;
   float3 n;
-  float3 p;            // world position and footprint width (zero when not supplied)
-  float w;
 };
 
-// Descriptor of cacheable output cd at a hit: a UV texel (Sec. 3.1, Eq. 1) or,
-// for outputs that depend on the world position, a world-space cell.
-__device__ __forceinline__ Key key_of(const ShadeArgs& a, uint32_t m, uint32_t node_sock,
-                                      uint8_t kind, const HitData& hd) {
-  if (kind == KEY_CELL)
-    return make_key_cell(m, node_sock, hd.p, hd.w, a.level_bias, a.level_max, a.cells,
-                         a.hash2_mask);
-  return make_key(m, node_sock, hd.u, hd.v, hd.g, a.level_bias, a.level_max, a.cells,
-                  a.hash2_mask);
+// Descriptor of cacheable output cd at hit h: a UV texel (Sec. 3.1, Eq. 1) or,
+// for outputs that depend on the world position, a world-space cell (the
+// position and width are read here only, so the UV-only path holds no
+// registers for them).
+__device__ __forceinline__ Key key_of(const ShadeArgs& a, uint32_t m, uint32_t h,
+                                      uint32_t node_sock, uint8_t kind, const HitData& hd) {
+  const bool cell = kind == KEY_CELL;
+  float c0 = hd.u, c1 = hd.v, c2 = 0.0f;
+  double m2;
+  bool finite;
+  if (cell) {
+    const float* p = a.position + (uint64_t)h * 3;
+    const float w = a.width[h];
+    c0 = p[0]; c1 = p[1]; c2 = p[2];
+    finite = isfinite(c0) && isfinite(c1) && isfinite(c2) && isfinite(w);
+    m2 = (double)w * (double)w;
+  } else {
+    const float4 g = hd.g;
+    finite = isfinite(c0) && isfinite(c1) && isfinite(g.x) && isfinite(g.y) && isfinite(g.z) &&
+             isfinite(g.w);
+    const double s1 = (double)g.x * (double)g.x + (double)g.y * (double)g.y;
+    const double s2 = (double)g.z * (double)g.z + (double)g.w * (double)g.w;
+    m2 = s1 < s2 ? s1 : s2;
+  }
+  return make_key(m, node_sock, cell, c0, c1, c2, m2, finite, a.level_bias, a.level_max,
+                  a.cells, a.hash2_mask);
 }
 
 __device__ __forceinline__ float read_f(uint32_t op, const PMC_CONST float* k, const LaneRegs& R,
@@ -149,33 +164,29 @@ __device__ float perlin_noise(float u, float v, float f0, int octaves, uint32_t 
 // Value noise of the world position: octave o at frequency f0 2^o, lattice
 // corner (i, j, k) valued lo32(mix64(((u32)i << 32 | (u32)j) ^
 // mix64((u32)k ^ (seed + o) G))) 2^-32, trilinear with smoothstep weights.
-__device__ float position_noise(float3 p, float f0, int octaves, uint32_t seed) {
+__device__ float position_noise(const ShadeArgs& a, uint32_t h, float f0, int octaves,
+                               uint32_t seed) {
+  const float* pp = a.position + (uint64_t)h * 3;
+  const float p0 = pp[0], p1 = pp[1], p2 = pp[2];
   float total = 0.0f, norm = 0.0f, amp = 1.0f, freq = f0;
+#pragma unroll 1
   for (int o = 0; o < octaves; ++o) {
     const uint64_t sg = (uint64_t)(seed + (uint32_t)o) * kGolden;
-    const float px = p.x * freq, py = p.y * freq, pz = p.z * freq;
+    const float px = p0 * freq, py = p1 * freq, pz = p2 * freq;
     const float fi = floorf(px), fj = floorf(py), fk = floorf(pz);
     const float fx = px - fi, fy = py - fj, fz = pz - fk;
     const int i = (int)fi, j = (int)fj, kk = (int)fk;
     const float wx = fx * fx * (3.0f - 2.0f * fx), wy = fy * fy * (3.0f - 2.0f * fy),
                 wz = fz * fz * (3.0f - 2.0f * fz);
-    const float s = 2.3283064365386963e-10f;  // 2^-32
     float val = 0.0f;
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz) {
+    // corners in the order dz, dy, dx (dx fastest)
+#pragma unroll 1
+    for (int c = 0; c < 8; ++c) {
+      const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
       const uint64_t kz = mix64((uint64_t)(uint32_t)(kk + dz) ^ sg);
-      const float cz = dz ? wz : 1.0f - wz;
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        const float cy = dy ? wy : 1.0f - wy;
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const uint64_t ij = ((uint64_t)(uint32_t)(i + dx) << 32) | (uint64_t)(uint32_t)(j + dy);
-          const float h = (float)(uint32_t)mix64(ij ^ kz) * s;
-          const float cx = dx ? wx : 1.0f - wx;
-          val += cx * cy * cz * h;
-        }
-      }
+      const uint64_t ij = ((uint64_t)(uint32_t)(i + dx) << 32) | (uint64_t)(uint32_t)(j + dy);
+      const float hv = (float)(uint32_t)mix64(ij ^ kz) * 2.3283064365386963e-10f;  // 2^-32
+      val += (dx ? wx : 1.0f - wx) * (dy ? wy : 1.0f - wy) * (dz ? wz : 1.0f - wz) * hv;
     }
     total += amp * val;
     norm += amp;
@@ -637,7 +648,7 @@ __device__ __forceinline__ void surrogate_substitute(const ShadeArgs& a, uint32_
       const bool is_c = cd.otype == OT_COLOR;
       bool want = isfinite(v0) && (!is_c || (isfinite(v1) && isfinite(v2)));
       const uint32_t code = is_c ? rgb9e5_encode(v0, v1, v2) : __float_as_uint(v0);
-      const Key k = key_of(a, m, cd.node_sock, cd.key, hd);
+      const Key k = key_of(a, m, h, cd.node_sock, cd.key, hd);
       want = want && !k.bypass;
       cnt.v[CNT_INS_TRIED] += (uint32_t)want;
       if (MODE == PMC_MODE_SNAPSHOT) {
@@ -709,7 +720,7 @@ __device__ __forceinline__ uint32_t probe_chunk(const ShadeArgs& a, bool active,
       } else {
         cd = a.cach[cbeg + c];
       }
-      k = key_of(a, m, cd.node_sock, cd.key, hd);
+      k = key_of(a, m, h, cd.node_sock, cd.key, hd);
     }
     const bool skipped = (skip >> c) & 1u;
     const uint32_t h2 = (has && !k.bypass && !skipped) ? k.hash2 : 0u;
@@ -800,7 +811,7 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
         o0.x = perlin_noise(hd.u, hd.v, K[7], I->variant, I->param);
         break;
       case PMC_OP_POSITION_NOISE:
-        o0.x = position_noise(hd.p, K[7], I->variant, I->param);
+        o0.x = position_noise(a, h, K[7], I->variant, I->param);
         break;
       case PMC_OP_MIX: {
         float t = clamp01f(read_f(I->src[0], K, R, hd));
@@ -854,7 +865,7 @@ __device__ __forceinline__ void run_program(const ShadeArgs& a, uint32_t m, uint
           {
             code = is_c ? rgb9e5_encode(val.x, val.y, val.z) : __float_as_uint(val.x);
             const PMC_CONST CachDesc* cd = as_const(a.cach) + cbeg + ord;
-            Key k = key_of(a, m, cd->node_sock, cd->key, hd);
+            Key k = key_of(a, m, h, cd->node_sock, cd->key, hd);
             cell = k.cell;
             hash2 = k.hash2;
           }
@@ -987,8 +998,6 @@ __device__ __forceinline__ LaneHit fetch_lane(const ShadeArgs& a, LaneIdx I) {
   L.hd.u = L.hd.v = 0.0f;
   L.hd.g = make_float4(0.f, 0.f, 0.f, 0.f);
   L.hd.n = make_float3(0.f, 0.f, 1.f);
-  L.hd.p = make_float3(0.f, 0.f, 0.f);
-  L.hd.w = 0.0f;
   if (L.active) {
     const uint32_t h = I.h;
     L.mat = a.material[h];
@@ -998,11 +1007,6 @@ __device__ __forceinline__ LaneHit fetch_lane(const ShadeArgs& a, LaneIdx I) {
     L.hd.g = reinterpret_cast<const float4*>(a.duv)[h];
     L.hd.n = make_float3(a.normal[(uint64_t)h * 3], a.normal[(uint64_t)h * 3 + 1],
                          a.normal[(uint64_t)h * 3 + 2]);
-    if (a.position) {
-      L.hd.p = make_float3(a.position[(uint64_t)h * 3], a.position[(uint64_t)h * 3 + 1],
-                           a.position[(uint64_t)h * 3 + 2]);
-      L.hd.w = a.width[h];
-    }
   }
   return L;
 }
@@ -1422,20 +1426,13 @@ __global__ void k_debug_keys(ShadeArgs a, pmc_key_record* out) {
   hd.v = uv.y;
   hd.g = reinterpret_cast<const float4*>(a.duv)[h];
   hd.n = make_float3(0.f, 0.f, 1.f);
-  hd.p = make_float3(0.f, 0.f, 0.f);
-  hd.w = 0.0f;
-  if (a.position) {
-    hd.p = make_float3(a.position[(uint64_t)h * 3], a.position[(uint64_t)h * 3 + 1],
-                       a.position[(uint64_t)h * 3 + 2]);
-    hd.w = a.width[h];
-  }
   uint32_t n_cach = m < a.n_mats ? a.hdr[m].n_cach : 0u;
   for (uint32_t c = 0; c < 8; ++c) {
     pmc_key_record r;
     r.cell = 0; r.hash2 = 0; r.level = 0; r.tx = 0; r.ty = 0; r.bypass = 2;
     if (c < n_cach) {
       const CachDesc cd = a.cach[a.hdr[m].cach_begin + c];
-      Key k = key_of(a, m, cd.node_sock, cd.key, hd);
+      Key k = key_of(a, m, h, cd.node_sock, cd.key, hd);
       r.bypass = k.bypass ? 1u : 0u;
       if (!k.bypass) {
         r.cell = k.cell; r.hash2 = k.hash2; r.level = k.level; r.tx = k.tx; r.ty = k.ty;
