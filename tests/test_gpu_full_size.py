@@ -133,3 +133,102 @@ def test_scale_workload_full_size():
     sc = scenes.scale_scene(frames=2)
     _run(sc, B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER | B.PMC_FLAG_PERSISTENT, B.PMC_POLICY_OVERWRITE,
          seed=1)
+
+
+def test_scale_workload_overwrite_evicts_like_the_oracle():
+    """OVERWRITE evictions at the scale workload's size: a 2^22-slot table
+    (2^19 cells of 8, a sixteenth of the benchmark's) overflows in frame 0, so
+    frame 1's misses displace frame-0 entries.  On sampled cells the table
+    after frame 1 equals the oracle's sequential apply of frame 1's candidates
+    (in (hit, ordinal) order) to the device's own table after frame 0: hash
+    halves and stamps bit-exact, value codes within one RGB9E5 step or the
+    scalar bar of the FP64 value at the entry's writer.
+
+    A key's writer in frame 1 is its first candidate: entries stamped in the
+    current frame are never displaced, so later candidates of the key find it
+    present or its cell full.  The candidates' values are all finite (the
+    device counts no non-finite value), so the simulation needs the FP64 values
+    of the writers only; a writer's value is its graph with the outputs it
+    found in the table (upstream of the written one, if any) substituted."""
+    from oracle import table as T
+    sc = scenes.scale_scene(frames=2)
+    n_cells, n_e = 1 << 19, 8
+    ctx = G.setup(sc)
+    cache = ctx.cache(n_cells, n_e, 16, B.PMC_POLICY_OVERWRITE)
+    kw = dict(mode=B.PMC_MODE_SNAPSHOT, flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER, chunk_waves=4,
+              defer_max=48)
+    _, _, _, st0 = G.shade(ctx, sc.frame(0), cache, frame=0, **kw)
+    w0 = cache.words().copy()
+    h1 = sc.frame(1)
+    _, _, _, st1 = G.shade(ctx, h1, cache, frame=1, **kw)
+    w1 = cache.words().copy()
+    ctx.close()
+    print("scale, 2^19 x 8 table: frame 0", st0, "frame 1", st1)
+    assert st0["cell_full"] > 0 and st1["overwrites"] > 10_000
+    assert st1["nonfinite"] == 0
+
+    rng = np.random.default_rng(3)
+    cells = np.sort(rng.choice(n_cells, 1000, replace=False))
+    slot_of = np.full(n_cells, -1, np.int64)
+    slot_of[cells] = np.arange(len(cells))
+    rows = (cells[:, None] * n_e + np.arange(n_e)).ravel()
+    ref = T.Table(len(cells), n_e, 16)
+    ref.word = [int(x) for x in w0[rows, 0]]
+    ref.stamp = [int(x) & 0xFFFFFFFF for x in w0[rows, 1]]
+    ref.aux = [int(x) >> 32 for x in w0[rows, 1]]
+
+    # frame 1's candidates in the sampled cells: keys that miss in the table after frame 0
+    order = np.argsort(h1.material, kind="stable")
+    bounds = np.searchsorted(h1.material[order], np.arange(len(sc.materials) + 1))
+    cand = []                                     # (hit, ordinal, slot, hash2, key, m, node, sock)
+    for m in range(len(sc.materials)):
+        idx = order[bounds[m]:bounds[m + 1]]
+        if len(idx) == 0:
+            continue
+        for c, (node, sock) in enumerate(graph.cacheable_outputs(sc.materials[m])):
+            ky = K.compute_keys(m, node, sock, h1.uv[idx], h1.duv[idx], n_cells)
+            for j in np.nonzero(~ky.bypass & (slot_of[ky.cell] >= 0))[0]:
+                hit, _, _ = _table_lookup(w0[:, 0], n_e, int(ky.cell[j]), int(ky.hash2[j]))
+                if not hit:
+                    cand.append((int(idx[j]), c, int(slot_of[ky.cell[j]]), int(ky.hash2[j]),
+                                 (int(ky.k0[j]), int(ky.k1[j])), m, node, sock))
+    cand.sort(key=lambda t: (t[0], t[1]))
+    first = {}
+    outcome = {}
+    for h, c, slot, h2, key, m, node, sock in cand:
+        first.setdefault(key, (h, m, node, sock))
+        r = ref.insert(slot, h2, 0, T.OVERWRITE, 1, key=key)
+        outcome[r] = outcome.get(r, 0) + 1
+    # the codes of the entries written in frame 1, from their writers' FP64 values
+    by_mat = {}
+    for e in range(len(ref.word)):
+        if ref.stamp[e] == 2:
+            h, m, node, sock = first[ref.key[e]]
+            by_mat.setdefault(m, []).append((e, h, node, sock))
+    for m, ents in by_mat.items():
+        mat = sc.materials[m]
+        hh = np.array(sorted({h for _, h, _, _ in ents}))
+        # the writer's other outputs found in the table after frame 0 stand in
+        # for their sub-graphs, as in the shading of frame 1
+        subst = {}
+        for node, sock in graph.cacheable_outputs(mat):
+            otype = graph.output_type(mat, node, sock)
+            ky = K.compute_keys(m, node, sock, h1.uv[hh], h1.duv[hh], n_cells)
+            found = np.zeros(len(hh), bool)
+            v = np.zeros((len(hh), 3)) if otype == "COLOR" else np.zeros(len(hh))
+            for j in np.nonzero(~ky.bypass)[0]:
+                hit, code, _ = _table_lookup(w0[:, 0], n_e, int(ky.cell[j]), int(ky.hash2[j]))
+                if hit:
+                    found[j] = True
+                    v[j] = render.decode(np.array([code], np.uint64), otype)[0]
+            if found.any():
+                subst[(node, sock)] = (found, v)
+        _, vals = graph.evaluate(mat, h1.uv[hh], h1.normal[hh], sc.textures, subst)
+        for e, h, node, sock in ents:
+            v = np.asarray(vals[(node, sock)][np.searchsorted(hh, h)])
+            enc = int(render.encode(v[None], graph.output_type(mat, node, sock))[0])
+            ref.word[e] = (ref.word[e] >> 32 << 32) | enc
+    print("sampled cells:", len(cells), "candidates", len(cand), outcome)
+    assert outcome.get("overwritten", 0) > 10
+    n_diff = G.table_parity(w1[rows], ref, sc.materials)
+    print("value codes differing within the bar:", n_diff)
