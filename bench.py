@@ -525,18 +525,22 @@ def cones_leg(args, n=3840 * 2160, reps=20):
 SURR_FLOP_PER_POINT = 2 * (32 * 64 + 64 * 64 + 64 * 4)     # 12,800 per network evaluation
 FP16_PEAK_TFLOPS = 2500.0
 TRAIN = dict(steps=8000, batch=1024, lr=2e-2, lr_end=1e-5, seed=0)
+LOG_TARGET = (1 << 20) - 64 * 64       # the log's 2^20 records, less a partly filled row of regions
 
 
 def surrogate_leg(args):
     """Learned surrogate on the mid workload: a progressive render (16 frames,
-    cached mode, insert log on) collects training pairs; every network is
-    trained (one launch) and trusted by its own held-out error; then the next
+    cached mode, insert log on) collects training pairs, topped up to the log's
+    2^20 records by the first frames of the same materials on other layouts;
+    every network is trained (one launch) and trusted by its own held-out
+    error; then the next
     pass (its first 2^20 hits) is shaded from the render's final table:
     uncached, cache only, and networks + cache.  Errors of every output
     against the uncached GPU path (held within 1e-5 of the FP64 graph by the
     parity tests)."""
     import torch
     from paper_2305_07238_amd import binding as B
+    from paper_2305_07238_amd import scenes
     sc, _ = workload("mid")
     n = sc.hits_per_frame
     hits = device_frames(sc, sc.frames)
@@ -554,7 +558,24 @@ def surrogate_leg(args):
         k["flags"] |= B.PMC_FLAG_LOG
         ctx.shade(views[f], out, cache, mode=B.PMC_MODE_CACHED, frame=f, **k)
     torch.cuda.synchronize()
-    n_log = len(ctx.log_read())
+    table = cache.export()
+    n_log_render = n_log = len(ctx.log_read())
+    # more training pairs, up to the log's 2^20 records: the first frames of the
+    # same materials on other screen layouts, each from an empty table
+    extra_frames = 0
+    for seed in range(1, 4):
+        if n_log >= LOG_TARGET:
+            break
+        sc2 = scenes.relayout(sc, seed)
+        cache.clear()
+        for f in range(4):
+            h2 = B.hits_to_device(sc2.frame(f))
+            ctx.shade(h2, out, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                      flags=B.PMC_FLAG_SORT | B.PMC_FLAG_DEFER | B.PMC_FLAG_LOG,
+                      chunk_waves=4, defer_max=48)
+            extra_frames += 1
+        torch.cuda.synchronize()
+        n_log = len(ctx.log_read())
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     ctx.surrogate_train(**TRAIN)
@@ -567,7 +588,6 @@ def surrogate_leg(args):
     log(f"surrogate: {n_slots} slots, {len(trained)} trained on {n_log} log records in "
         f"{train_ms:.1f} ms, {len(trusted)} trusted")
     train_flop = 3.0 * SURR_FLOP_PER_POINT * TRAIN["batch"] * TRAIN["steps"] * len(trained)
-    table = cache.export()
     n17 = min(1 << 20, n)
     h17 = sc.frame(sc.frames).take(np.arange(n17))
     d17 = B.hits_to_device(h17)
@@ -608,6 +628,7 @@ def surrogate_leg(args):
         "workload": "mid after its 16-frame render; next pass, first 2^20 hits",
         "slots": n_slots, "trusted": len(trusted),
         "trusted_materials": [int(rep[k]["material"]) for k in trusted], "log_records": n_log,
+        "log_records_render": n_log_render, "log_extra_frames": extra_frames,
         "train": dict(TRAIN, ms=train_ms, slots_trained=len(trained),
                       tflops=train_flop / (train_ms * 1e-3) / 1e12),
         "heldout_max_err": [r["max_err"] for r in rep],

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define PMC_ABI_VERSION 4u
+#define PMC_ABI_VERSION 5u
 
 typedef int32_t pmc_status;
 enum {
@@ -515,9 +515,15 @@ typedef struct pmc_train_params {
     float lr_end;                  /* > 0: the step size decays geometrically from lr to lr_end
                                       over the call's steps; 0 = constant lr */
     uint64_t seed;                 /* batch sampling */
+    uint32_t workgroups;           /* workgroups per slot, each taking a share of every step's
+                                      batch, their gradient sums added in a fixed order before
+                                      the step (data parallel, one cooperative launch); at most
+                                      64 and batch / 128; 0 = as many as can be resident at
+                                      once (at most 16), 1 = one workgroup per slot */
+    uint32_t reserved;
 } pmc_train_params;
-/* Train every slot on its records of the insert log, all slots at once (one
- * workgroup each): the log is grouped by slot, the last `holdout` records of
+/* Train every slot on its records of the insert log, all slots at once
+ * (`workgroups` workgroups each): the log is grouped by slot, the last `holdout` records of
  * each group are held out, `steps` Adam steps are taken on the rest, and the
  * held-out error decides the trust.  Asynchronous; read the outcome with
  * pmc_surrogate_report. */

@@ -147,7 +147,7 @@ class pmc_surrogate_slot(C.Structure):
 class pmc_train_params(C.Structure):
     _fields_ = [("steps", C.c_uint32), ("batch", C.c_uint32), ("lr", C.c_float),
                 ("holdout", C.c_uint32), ("min_records", C.c_uint32), ("lr_end", C.c_float),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("workgroups", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 SURROGATE_STAT_FIELDS = ("material", "trusted", "n_train", "n_heldout", "max_err", "mean_err",
@@ -236,7 +236,7 @@ for _name, (_res, _args) in _proto.items():
 
 EXPORTED = tuple(_proto)
 
-ABI_VERSION = 4                     # the layouts above follow this version of include/pmc.h
+ABI_VERSION = 5                     # the layouts above follow this version of include/pmc.h
 if pmc_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI {pmc_abi_version()}, the binding expects "
                       f"{ABI_VERSION}: rebuild it with __graft_entry__.build()")
@@ -470,15 +470,17 @@ class Context:
                                            _stream_ptr(stream)))
 
     def surrogate_train(self, steps: int = 0, batch: int = 0, lr: float = 0.0, holdout: int = 0,
-                        min_records: int = 0, seed: int = 0, lr_end: float = 0.0, stream=None):
-        p = pmc_train_params(steps, batch, lr, holdout, min_records, lr_end, seed)
+                        min_records: int = 0, seed: int = 0, lr_end: float = 0.0,
+                        workgroups: int = 0, stream=None):
+        p = pmc_train_params(steps, batch, lr, holdout, min_records, lr_end, seed, workgroups)
         self.check(pmc_surrogate_train(self.h, C.byref(p), _stream_ptr(stream)))
 
     def surrogate_train_records(self, slot: int, records, steps: int = 0, batch: int = 0,
-                                lr: float = 0.0, seed: int = 0, lr_end: float = 0.0, stream=None):
+                                lr: float = 0.0, seed: int = 0, lr_end: float = 0.0,
+                                workgroups: int = 0, stream=None):
         """records: torch uint8/int32 CUDA tensor holding n packed pmc_log_record."""
         n = records.numel() * records.element_size() // 32
-        p = pmc_train_params(steps, batch, lr, 0, 0, lr_end, seed)
+        p = pmc_train_params(steps, batch, lr, 0, 0, lr_end, seed, workgroups)
         self.check(pmc_surrogate_train_records(self.h, slot, _ptr(records), n, C.byref(p),
                                                _stream_ptr(stream)))
 

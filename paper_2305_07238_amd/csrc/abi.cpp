@@ -75,7 +75,8 @@ void destroy_context(pmc_ctx* ctx) {
                       &ctx->surr.w, &ctx->surr.master,
                       &ctx->surr.state, &ctx->surr.mat_slot_dev, &ctx->surr.log,
                       &ctx->surr.log_count, &ctx->surr.slot_count, &ctx->surr.slot_begin,
-                      &ctx->surr.slot_cursor, &ctx->surr.scan_sums, &ctx->surr.grouped})
+                      &ctx->surr.slot_cursor, &ctx->surr.scan_sums, &ctx->surr.grouped,
+                      &ctx->surr.partial, &ctx->surr.sync})
       free_buf(*b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   }

@@ -28,6 +28,7 @@ struct SurrHost {
   std::vector<uint32_t> mat_slot;           // per material, 0xFFFFFFFF = none
   DevBuf w, master, state, mat_slot_dev, log, log_count;
   DevBuf slot_count, slot_begin, slot_cursor, scan_sums, grouped;
+  DevBuf partial, sync;                     // data-parallel training exchange
 };
 
 struct pmc_ctx {

@@ -227,10 +227,21 @@ struct TrainArgs {
   uint32_t sample;             // 1: Adam steps on sampled batches; 0: one gradient pass
   float* grad_out;             // gradient pass: 6532 FP32
   float* loss_out;             // gradient pass: loss
+  // data parallel (replicas > 1, sample = 1 only): workgroups per slot, their
+  // published gradient sums [slot][replica][kPartial], and per slot two
+  // words, zero at launch: arrivals and the published step
+  uint32_t replicas;
+  float* partial;
+  uint32_t* sync;
+  uint32_t spin_limit;         // polls before a wait gives up
 };
+constexpr int kPartial = 6536;   // kParams gradient sums, loss, samples, padding
 
 size_t surr_train_lds_bytes();
+// n_blocks slots (replicas workgroups each, launched cooperatively when more than one)
 hipError_t launch_surr_train(const TrainArgs& a, uint32_t n_blocks, hipStream_t s);
+// training workgroups that can be resident at once on the current device
+uint32_t surr_train_capacity();
 hipError_t launch_surr_export(const float* master, SurrW* w, uint32_t n_slots, hipStream_t s);
 // held-out error -> trust, per slot (grouped records)
 hipError_t launch_surr_probe(const pmc_log_record* rec, const uint32_t* slot_begin,

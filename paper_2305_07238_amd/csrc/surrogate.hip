@@ -1,8 +1,9 @@
 // surrogate.hip - training, error probe and inference of the per-material
 // surrogate networks on the matrix cores (16x16x16 FP16 products, FP32 sums).
 //
-// Training: one workgroup (4 waves) per slot runs every Adam step of that
-// slot in one launch.  A wave takes 32 samples at a time (two 16-sample
+// Training: a slot's Adam steps all run in one launch, on one workgroup (4
+// waves) or, data parallel, on `replicas` workgroups that split every step's
+// batch (see below).  A wave takes 32 samples at a time (two 16-sample
 // tiles).  The forward and backward passes chain register to register (the
 // layout argument is in surrogate.h); the weight gradients contract over the
 // samples, which needs the activations with the sample index in the K
@@ -20,6 +21,7 @@ namespace pmc {
 namespace {
 
 constexpr int kTW = 4;                     // waves per training block
+constexpr int kMaxReplicas = 64;           // workgroups per slot (data parallel)
 constexpr int kRS = 40;                    // unit-major row stride (halves): 32 samples + pad
 constexpr int kS1 = 40, kS2 = 72, kS3T = 4;
 constexpr int OFF_W1 = 0;                              // [64][kS1]
@@ -53,9 +55,48 @@ __device__ __forceinline__ float nan_max(float a, float b) {   // NaN wins
   return (b > a || b != b) ? b : a;
 }
 
+// Data exchanged between the workgroups of a slot is written with stores
+// coherent at device scope (they write through the non-coherent cache
+// levels), so a barrier needs no writeback of whole caches: only that those
+// stores have completed before the arrival is counted, and, after the wait,
+// one invalidation of the workgroup's cached lines before plain loads read
+// what the others wrote.
+__device__ __forceinline__ void st_dev(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (one thread) until *w >= target; false after `limit` polls.
+__device__ __forceinline__ bool spin_until(uint32_t* w, uint32_t target, uint32_t limit) {
+  for (uint32_t i = 0; i < limit; ++i) {
+    if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
+}
+
+// Barrier of a slot's workgroups on one counter: every workgroup adds one per
+// barrier, so the b-th barrier of n workgroups ends when the counter reaches
+// n * b.  Each wave first waits for its own coherent stores to complete.
+// False when the wait gave up (the workgroup agrees through the LDS word `flag`).
+__device__ __forceinline__ bool group_barrier(uint32_t* counter, uint32_t target, uint32_t limit,
+                                              uint32_t* flag, int tid) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    flag[0] = spin_until(counter, target, limit) ? 0u : 1u;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");     // drop stale cached lines
+  }
+  __syncthreads();
+  const bool ok = flag[0] == 0u;
+  __syncthreads();                       // every thread has read the flag before it is reused
+  return ok;
+}
+
 struct Lds {
   _Float16 *w1, *w2, *w2t, *w3, *w3t;
   float *b, *g, *red;
+  uint32_t* flag;                        // one word: a wait of the step failed
   _Float16* act;
 };
 
@@ -69,6 +110,7 @@ __device__ __forceinline__ Lds lds_layout(unsigned char* base) {
   L.b = reinterpret_cast<float*>(base + OFF_B);
   L.g = reinterpret_cast<float*>(base + OFF_G);
   L.red = reinterpret_cast<float*>(base + OFF_RED);
+  L.flag = reinterpret_cast<uint32_t*>(base + OFF_RED + 8);
   L.act = reinterpret_cast<_Float16*>(base + OFF_ACT);
   return L;
 }
@@ -149,14 +191,24 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
   const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, g = lane >> 4;
 
+  // replicas > 1: the workgroups r = 0 .. replicas-1 of a slot take the
+  // chunks r*4 + wave, r*4 + wave + 4*replicas, ... of each step's batch (the
+  // single workgroup's samples, split) and publish their gradient sums; each
+  // workgroup then adds the sums of a 1/replicas share of the parameters in
+  // replica order and takes the Adam step there, and all read the new
+  // parameters back.  The launch is cooperative (every workgroup resident),
+  // and every wait is bounded: past its limit a workgroup marks the slot
+  // failed (loss NaN) and leaves.
+  const uint32_t nrep = a.replicas > 1u ? a.replicas : 1u;
+  const uint32_t rep = blockIdx.x % nrep;
   uint32_t slot, begin, n_train;
   if (a.slot_begin) {
-    slot = blockIdx.x;
+    slot = blockIdx.x / nrep;
     begin = a.slot_begin[slot];
     const uint32_t n_total = a.slot_count[slot];
     const uint32_t held = min(a.holdout, n_total / 4u);
     n_train = n_total - held;
-    if (tid == 0) {
+    if (tid == 0 && rep == 0u) {
       a.state[slot].n_train = n_train;
       a.state[slot].n_heldout = held;
     }
@@ -169,6 +221,8 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
   }
   SurrState* st = a.state + slot;
   const pmc_log_record* rec = a.rec + begin;
+  // the slot's place in the exchange buffers (one slot per launch without grouping)
+  const uint32_t xs = a.slot_begin ? slot : 0u;
   float* P = a.master + (size_t)slot * 3 * kParamStride;
   float* M1 = P + kParamStride;
   float* V1 = P + 2 * kParamStride;
@@ -217,11 +271,13 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
     };
     bool valid_next = false;
     pmc_log_record R_next;
-    if ((uint32_t)wave < n_chunks) R_next = load_record(rec + record_of((uint32_t)wave, &valid_next));
-    for (uint32_t c = (uint32_t)wave; c < n_chunks; c += kTW) {
+    if (rep * kTW + (uint32_t)wave < n_chunks)
+      R_next = load_record(rec + record_of(rep * kTW + (uint32_t)wave, &valid_next));
+    const uint32_t c_first = rep * kTW + (uint32_t)wave, c_step = kTW * nrep;
+    for (uint32_t c = c_first; c < n_chunks; c += c_step) {
       const pmc_log_record R = R_next;
       const bool valid = valid_next;
-      if (c + kTW < n_chunks) R_next = load_record(rec + record_of(c + kTW, &valid_next));
+      if (c + c_step < n_chunks) R_next = load_record(rec + record_of(c + c_step, &valid_next));
       float tg[4], mk[4];
       record_target(R, st, tg, mk);
       if (!valid) {
@@ -452,6 +508,49 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
     if (!a.sample) {
       for (int p = tid; p < kParams; p += 256) a.grad_out[p] = L.g[p] * inv;
       if (tid == 0) *a.loss_out = L.red[0] * inv;
+    } else if (nrep > 1u) {
+      // ---- data parallel: every workgroup publishes its sums; each then adds,
+      // in replica order, the sums of its own share of the parameters, takes
+      // the Adam step there, and reads the whole step back after all are done
+      const float lr = a.lr_end > 0.0f && steps > 1u
+                           ? a.lr * powf(a.lr_end / a.lr, (float)s / (float)(steps - 1u))
+                           : a.lr;
+      const float bc1 = 1.0f - powf(0.9f, (float)t_step);
+      const float bc2 = 1.0f - powf(0.999f, (float)t_step);
+      float* part = a.partial + ((size_t)xs * nrep + rep) * kPartial;
+      for (int p = tid; p < kParams; p += 256) st_dev(part + p, L.g[p]);
+      if (tid < 2) st_dev(part + kParams + tid, L.red[tid]);
+      if (!group_barrier(a.sync + 2 * xs, nrep * (2u * s + 1u), a.spin_limit, L.flag, tid)) {
+        if (tid == 0) st->loss = __int_as_float(0x7FC00000);
+        return;
+      }
+      const float* base = a.partial + (size_t)xs * nrep * kPartial;
+      float lsum = 0.0f, nsum = 0.0f;
+      for (uint32_t r = 0; r < nrep; ++r) {
+        lsum += base[(size_t)r * kPartial + kParams];
+        nsum += base[(size_t)r * kPartial + kParams + 1];
+      }
+      const float dinv = 1.0f / fmaxf(nsum, 1.0f);
+      const int per = (kParams + (int)nrep - 1) / (int)nrep;
+      const int p0 = (int)rep * per, p1 = min(kParams, p0 + per);
+      for (int p = p0 + tid; p < p1; p += 256) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int r = 0; r < kMaxReplicas; ++r)
+          if ((uint32_t)r < nrep) sum += base[(size_t)r * kPartial + p];
+        const float gr = sum * dinv;
+        const float m = 0.9f * M1[p] + 0.1f * gr;
+        const float v = 0.999f * V1[p] + 0.001f * gr * gr;
+        st_dev(P + p, P[p] - lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f));
+        M1[p] = m;
+        V1[p] = v;
+      }
+      last_loss = lsum * dinv;
+      if (!group_barrier(a.sync + 2 * xs, nrep * (2u * s + 2u), a.spin_limit, L.flag, tid)) {
+        if (tid == 0) st->loss = __int_as_float(0x7FC00000);
+        return;
+      }
+      for (int p = tid; p < kParams; p += 256) store_param(L, p, P[p]);
     } else {
       const float lr = a.lr_end > 0.0f && steps > 1u
                            ? a.lr * powf(a.lr_end / a.lr, (float)s / (float)(steps - 1u))
@@ -472,6 +571,9 @@ __global__ __launch_bounds__(256) void k_surr_train(TrainArgs a) {
     }
     __syncthreads();
   }
+  if (rep != 0u) return;
+  // the other workgroups' parameter stores: drop any stale cached copy first
+  if (nrep > 1u) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (a.sample) {
     export_params(P, a.w + slot, tid, 256);
     if (tid == 0) {
@@ -487,8 +589,26 @@ hipError_t prepare_surrogate_kernels() {
 }
 
 hipError_t launch_surr_train(const TrainArgs& a, uint32_t n_blocks, hipStream_t s) {
+  if (a.replicas > 1u) {
+    // every workgroup of a slot must be resident for its waits to end
+    TrainArgs args = a;
+    void* params[] = {&args};
+    return hipLaunchCooperativeKernel((const void*)k_surr_train, dim3(n_blocks * a.replicas),
+                                      dim3(256), params, LDS_TOTAL, s);
+  }
   hipLaunchKernelGGL(k_surr_train, dim3(n_blocks), dim3(256), LDS_TOTAL, s, a);
   return hipGetLastError();
+}
+
+uint32_t surr_train_capacity() {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0u;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0u;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_surr_train, 256,
+                                                   LDS_TOTAL) != hipSuccess)
+    return 0u;
+  return (uint32_t)(per_cu * cus);
 }
 
 __global__ __launch_bounds__(256) void k_surr_export(const float* master, SurrW* w) {

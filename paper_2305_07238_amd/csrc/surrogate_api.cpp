@@ -62,7 +62,34 @@ pmc_status check_train(pmc_ctx* ctx, const pmc_train_params* p, pmc_train_params
   if (!(q.lr > 0.0f) || !std::isfinite(q.lr)) return ctx->fail(PMC_ERR_INVALID, "bad lr");
   if (!(q.lr_end >= 0.0f) || !std::isfinite(q.lr_end))
     return ctx->fail(PMC_ERR_INVALID, "bad lr_end");
+  if (q.workgroups > 64u || q.workgroups > q.batch / 128u)
+    return ctx->fail(PMC_ERR_INVALID, "workgroups: at most 64 and batch / 128");
   *out = q;
+  return PMC_OK;
+}
+
+// Workgroups per slot for a launch over n_blocks slots: the caller's choice,
+// else as many as can be resident together (at most batch / 128 and 16); the
+// buffers of the data-parallel exchange are sized and the step words cleared.
+pmc_status train_replicas(pmc_ctx* ctx, const pmc_train_params& q, uint32_t n_blocks,
+                          TrainArgs& a, hipStream_t s) {
+  uint32_t r = q.workgroups;
+  if (r == 0u) {
+    const uint32_t cap = surr_train_capacity();
+    r = n_blocks ? cap / n_blocks : 1u;
+    r = std::min(r, std::min(q.batch / 128u, 16u));
+  }
+  if (r < 1u) r = 1u;
+  a.replicas = r;
+  if (r == 1u) return PMC_OK;
+  SurrHost& S = ctx->surr;
+  if (pmc_status st = ensure(ctx, S.partial, (size_t)n_blocks * r * kPartial * sizeof(float)))
+    return st;
+  if (pmc_status st = ensure(ctx, S.sync, (size_t)n_blocks * 2 * sizeof(uint32_t))) return st;
+  a.partial = (float*)S.partial.p;
+  a.sync = (uint32_t*)S.sync.p;
+  a.spin_limit = 1u << 22;
+  HIP_TRY(ctx, launch_fill_u32(a.sync, 0u, (uint64_t)n_blocks * 2, s));
   return PMC_OK;
 }
 
@@ -280,6 +307,7 @@ pmc_status pmc_surrogate_train(pmc_ctx* ctx, const pmc_train_params* params, voi
   a.lr_end = q.lr_end;
   a.seed = q.seed;
   a.sample = 1;
+  if (pmc_status st = train_replicas(ctx, q, S.n_slots, a, s)) return st;
   HIP_TRY(ctx, launch_surr_train(a, S.n_slots, s));
   HIP_TRY(ctx, launch_surr_probe(a.rec, a.slot_begin, a.slot_count, q.holdout, q.min_records,
                                  a.w, a.state, S.n_slots, s));
@@ -308,6 +336,7 @@ pmc_status pmc_surrogate_train_records(pmc_ctx* ctx, uint32_t slot, const pmc_lo
   a.lr_end = q.lr_end;
   a.seed = q.seed;
   a.sample = 1;
+  if (pmc_status st = train_replicas(ctx, q, 1, a, (hipStream_t)stream)) return st;
   HIP_TRY(ctx, launch_surr_train(a, 1, (hipStream_t)stream));
   return PMC_OK;
 }

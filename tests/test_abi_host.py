@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layouts_match_the_header():
-    assert B.pmc_abi_version() == 4
+    assert B.pmc_abi_version() == 5
     for i, st in enumerate([B.pmc_node_desc, B.pmc_input, B.pmc_texture_desc, B.pmc_compile_opts,
                             B.pmc_material_info, B.pmc_cache_params, B.pmc_shade_params,
                             B.pmc_stats, B.pmc_hits, B.pmc_bsdf_out, B.pmc_debug_out,

@@ -121,16 +121,20 @@ def test_gradients_match_reference(n):
     assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b)) >= 0.99
 
 
-def test_adam_steps_match_reference():
+@pytest.mark.parametrize("workgroups,batch", [(1, 256), (2, 256), (8, 1024)])
+def test_adam_steps_match_reference(workgroups, batch):
+    """Three Adam steps against the FP64 reference, on one workgroup and data
+    parallel (each step's batch split over workgroups, their gradient sums
+    added in a fixed order)."""
     sc = scenes.smooth_scene(frames=1)
     ctx, _ = _ctx_with_slots(sc)
     mat, om = _ordmap(ctx, sc, 0)
     flat = _params(23)
     ctx.surrogate_set_params(0, flat)
-    n, steps, batch, lr, seed = 3000, 3, 256, 1e-3, 99
+    n, steps, lr, seed = 3000, 3, 1e-3, 99
     rec = _records(np.random.default_rng(1), n, mat, om)
     ctx.surrogate_train_records(0, B.records_to_device(rec), steps=steps, batch=batch, lr=lr,
-                                seed=seed)
+                                seed=seed, workgroups=workgroups)
     torch.cuda.synchronize()
     got = ctx.surrogate_get_params(0).astype(np.float64)
     # the reference: same sampler, FP16 rounding points, FP64 Adam
