@@ -341,6 +341,22 @@ def path_leg(name, sc, desc, args, steps, warmup, ref=None, ref_frame=None,
     ms_step = ev0.elapsed_time(ev1) / steps
     log(f"{name}: {ms_step:.3f} ms/step (graph replay), {n_step / ms_step / 1e6:.3f} G samples/s")
     graph.close()
+    # the same render with the statistics counters on (every shade launch counts,
+    # and each frame ends with the reduction of its counters)
+    st_g = B.new_stats()
+    graph_s = ctx.frame_graph(use_cache, ctx.frame_plan(hits, n_frame, sc.frames, out, mode=mode,
+                                                        clear_cache=True, stats=st_g,
+                                                        late_frame=late_frame, late=late, **best))
+    graph_s.launch()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        graph_s.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_stats = ev0.elapsed_time(ev1) / steps
+    graph_s.close()
+    log(f"{name}: {ms_stats:.3f} ms/step with statistics")
     views = [{k: v[f * n_frame:(f + 1) * n_frame] for k, v in hits.items()}
              for f in range(sc.frames)]
 
@@ -365,6 +381,7 @@ def path_leg(name, sc, desc, args, steps, warmup, ref=None, ref_frame=None,
     st = B.stats_dict(stats)
     cached_last = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
     res = {"workload": desc, "samples_per_s": n_step / (ms_step * 1e-3), "ms_per_step": ms_step,
+           "ms_per_step_with_stats": ms_stats,
            "hits_per_step": n_step, "frames": sc.frames, "mode": args.mode,
            "launch": {"autotuned": best, "late_frame": late_frame, "autotuned_late": late,
                       "tuning": tune_info},
@@ -861,7 +878,7 @@ def main():
                    "launch": "one HIP graph per step (table clear + every frame)",
                    **head["launch"]},
     }
-    for k in ("cache_hit_rate", "found_per_sample", "deferred_fraction",
+    for k in ("ms_per_step_with_stats", "cache_hit_rate", "found_per_sample", "deferred_fraction",
               "nodes_executed_fraction", "uncached_samples_per_s", "speedup_vs_uncached",
               "bsdf_err_vs_fp64_oracle", "bsdf_err_vs_uncached_gpu", "stats",
               "phase_ms_per_step", "roofline"):

@@ -19,7 +19,7 @@ enum {
   kNumCounters
 };
 enum { KIND_FULL = 0, KIND_PROBE = 1 };   // shade kernel variants
-constexpr int kStatSlots = 64;       // counters are spread over slots to limit atomic contention
+constexpr int kStatSlots = 1024;     // counters are spread over slots to limit atomic contention
 constexpr int kStatStride = 32;      // u64 per slot (= sizeof(pmc_stats) / 8)
 
 struct ShadeArgs {

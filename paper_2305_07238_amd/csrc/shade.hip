@@ -1162,6 +1162,31 @@ __device__ __forceinline__ void flush_counters(const ShadeArgs& a, Counters& cnt
   }
 }
 
+// The shading kernels (every thread of the workgroup calls it once, at the
+// end): each wave leaves its counter sums in its LDS staging words, free by
+// now, and wave 0 adds the workgroup's and takes one atomic per counter, so
+// the counters' atomics do not pile up on a few addresses.
+__device__ __forceinline__ void flush_counters_block(const ShadeArgs& a, Counters& cnt,
+                                                     float* lds) {
+  if (!a.stat_slots) return;
+  const uint32_t stride = a.n_regs * 64u + 64u;          // floats per wave
+  const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t* mine = reinterpret_cast<uint32_t*>(lds + w * stride + a.n_regs * 64u);
+#pragma unroll
+  for (int q = 0; q < kNumCounters; ++q) {
+    const uint32_t s = wave_sum(cnt.v[q]);
+    if (lane_id() == 0) mine[q] = s;
+  }
+  __syncthreads();
+  if (w == 0 && lane_id() < kNumCounters) {
+    const int q = lane_id();
+    unsigned long long t = 0ull;
+    for (uint32_t k = 0; k < nw; ++k)
+      t += reinterpret_cast<const uint32_t*>(lds + k * stride + a.n_regs * 64u)[q];
+    if (t) atomicAdd(a.stat_slots + (uint64_t)(blockIdx.x % kStatSlots) * kStatStride + q, t);
+  }
+}
+
 // One run = `chunk_waves` consecutive chunks handled by one wave.
 template <int MODE, int KIND, bool SURR>
 __device__ __forceinline__ void do_run(const ShadeArgs& a, uint32_t first, uint32_t n_chunks,
@@ -1203,7 +1228,7 @@ __device__ __forceinline__ void shade_flat_body(const ShadeArgs& a) {
   const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint32_t first = w * a.chunk_waves;
   if (first < n_chunks) do_run<MODE, KIND, SURR>(a, first, n_chunks, R, cnt, B);
-  if (STATS) flush_counters(a, cnt);
+  if (STATS) flush_counters_block(a, cnt, lds);
 }
 
 // Persistent variant: a fixed grid of waves walks the runs with a static stride
@@ -1224,7 +1249,7 @@ __device__ __forceinline__ void shade_persistent_body(const ShadeArgs& a) {
   const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   for (uint32_t first = w * a.chunk_waves; first < n_chunks; first += waves * a.chunk_waves)
     do_run<MODE, KIND, SURR>(a, first, n_chunks, R, cnt, B);
-  if (STATS) flush_counters(a, cnt);
+  if (STATS) flush_counters_block(a, cnt, lds);
 }
 
 // Kernels.  The cached variants are compiled for 4 waves per SIMD (at most 128
@@ -1336,7 +1361,7 @@ __device__ __forceinline__ void shade_finish_body(const ShadeArgs& a) {
       }
     }
   }
-  if (STATS) flush_counters(a, cnt);
+  if (STATS) flush_counters_block(a, cnt, lds);
 }
 
 template <int MODE, bool STATS>

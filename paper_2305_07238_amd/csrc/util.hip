@@ -33,19 +33,33 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t value, uint64_t n, hipStream_t 
 }
 
 // slots[kStatSlots][kStatStride] -> out (+=), then clear the slots.
-__global__ void k_stats_reduce(unsigned long long* slots, unsigned long long* out) {
-  const int q = threadIdx.x;
-  if (q >= kStatStride) return;
-  unsigned long long s = 0;
-  for (int k = 0; k < kStatSlots; ++k) {
+// One workgroup of 1024 threads: thread t adds counter t % kStatStride over the
+// slots t / kStatStride, t / kStatStride + 32, ...; then 32 threads add the
+// 32 partial sums of each counter.
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceRows = kReduceThreads / kStatStride;     // 32
+static_assert(kReduceThreads % kStatStride == 0 && kStatSlots % kReduceRows == 0, "reduce layout");
+
+__global__ __launch_bounds__(kReduceThreads) void k_stats_reduce(unsigned long long* slots,
+                                                                unsigned long long* out) {
+  __shared__ unsigned long long part[kReduceThreads];
+  const int t = threadIdx.x, q = t % kStatStride, row = t / kStatStride;
+  unsigned long long s = 0ull;
+  for (int k = row; k < kStatSlots; k += kReduceRows) {
     s += slots[k * kStatStride + q];
     slots[k * kStatStride + q] = 0ull;
   }
-  if (out) out[q] += s;
+  part[t] = s;
+  __syncthreads();
+  if (t < kStatStride) {
+    unsigned long long tot = 0ull;
+    for (int r = 0; r < kReduceRows; ++r) tot += part[r * kStatStride + t];
+    if (out) out[t] += tot;
+  }
 }
 
 hipError_t launch_stats_reduce(unsigned long long* slots, pmc_stats* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kStatStride), 0, s, slots,
+  hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kReduceThreads), 0, s, slots,
                      reinterpret_cast<unsigned long long*>(out));
   return hipGetLastError();
 }
