@@ -539,6 +539,127 @@ def cones_leg(args, n=3840 * 2160, reps=20):
                          "frac": gbs / HBM_PEAK_GBS, "bytes_per_hit": 72}}
 
 
+def policies_leg(args, frames=8, n_cells=1 << 17):
+    """Priority insertion (after Sec. 5: prefer directly visible samples when
+    storage is short) on a path tracer's hits: each frame holds the mid
+    workload's 2,073,600 camera hits (depth 0) and as many secondary hits
+    (depth 1-3, footprints 2-16x wider), on a table of 2^17 cells x 8 entries
+    (2^20 slots, far fewer than the render's keys), cached mode.  Per policy:
+    the 8-frame render's samples/s, and the last frame's hit rates of the
+    depth-0 and the deeper lookups."""
+    import torch
+    from paper_2305_07238_amd import binding as B
+    from paper_2305_07238_amd import scenes
+    sc, _ = workload("mid", frames)
+    fr = [scenes.with_indirect(sc.frame(f), f) for f in range(frames)]
+    bounce = fr[-1].bounce.astype(np.int64)
+    dev = [B.hits_to_device(h) for h in fr]
+    n = len(fr[0])
+    out = B.alloc_outputs(n)
+    ctx = B.Context(0)
+    ctx.set_textures(sc.textures)
+    ctx.compile(sc.materials)
+    res = {"workload": "mid materials, %d frames x %d hits (camera + secondary), table "
+                       "2^17 cells x 8 entries x 16 B" % (frames, n)}
+    for name, pol in (("FIRST", B.PMC_POLICY_FIRST), ("OVERWRITE", B.PMC_POLICY_OVERWRITE),
+                      ("PRIORITY", B.PMC_POLICY_PRIORITY)):
+        cache = ctx.cache(n_cells, 8, 16, pol)
+
+        def run(pre, cache=cache):
+            if pre:
+                cache.clear()
+                torch.cuda.synchronize()
+                return
+            for f in range(frames):
+                ctx.shade(dev[f], out, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                          flags=B.PMC_FLAG_SORT)
+        ms = _median_ms(run)
+        run(True)
+        for f in range(frames - 1):
+            ctx.shade(dev[f], out, cache, mode=B.PMC_MODE_CACHED, frame=f, flags=B.PMC_FLAG_SORT)
+        state = torch.full((n, 8), 255, dtype=torch.uint8, device="cuda")
+        st = B.new_stats()
+        ctx.shade(dev[-1], out, cache, mode=B.PMC_MODE_CACHED, frame=frames - 1,
+                  flags=B.PMC_FLAG_SORT, stats=st, debug={"state": state})
+        torch.cuda.synchronize()
+        s_np = state.cpu().numpy()
+        probed = (s_np == 0) | (s_np == 1)
+        found = s_np == 1
+        d0 = bounce == 0
+        res[name] = {"samples_per_s": n * frames / (ms * 1e-3), "ms": ms,
+                     "hit_rate_depth0": float(found[d0].sum() / max(probed[d0].sum(), 1)),
+                     "hit_rate_deeper": float(found[~d0].sum() / max(probed[~d0].sum(), 1)),
+                     "overwrites_last_frame": int(B.stats_dict(st)["overwrites"])}
+        log(f"policies: {name} {res[name]}")
+        cache.close()
+    ctx.close()
+    return res
+
+
+def spatial_leg(args, frames=16):
+    """World-position descriptors (Sec. 3.1's other shading-point information):
+    the mid material mix with 35% of its UV leaves replaced by 3D value noise of
+    the world position, 1920x1080 x 16 frames of hits on planar patches in the
+    world carrying position and footprint width, table 2^24 slots.  Uncached;
+    cached with texel descriptors only (outputs of the world position are then
+    always evaluated); cached with world-cell descriptors as well.  Samples/s,
+    hit rate, interpreter work, the share of lookups keyed by world cells, and
+    the last frame's error against the uncached path."""
+    import torch
+    from paper_2305_07238_amd import binding as B
+    from paper_2305_07238_amd import scenes
+    sc = scenes.spatial_scene(width=1920, height=1080, frames=frames, slots=1 << 24)
+    fr = [sc.frame(f) for f in range(frames)]
+    dev = [B.hits_to_device(h) for h in fr]
+    n = len(fr[0])
+    out = B.alloc_outputs(n)
+    res = {"workload": "spatial: 64 materials (35%% of UV leaves -> world-position noise), "
+                       "1920x1080 x %d frames, table 2^24 slots x 16 B" % frames}
+    outs = {}
+    cnt = np.bincount(fr[-1].material, minlength=len(sc.materials))
+    for name, texel_only, cached in (("uncached", False, False), ("texel_keys", True, True),
+                                     ("world_cells", False, True)):
+        ctx = B.Context(0)
+        ctx.set_textures(sc.textures)
+        ctx.compile(sc.materials, texel_keys_only=texel_only)
+        cache = ctx.cache(sc.cache.n_cells, 8, 16) if cached else None
+        mode = B.PMC_MODE_CACHED if cached else B.PMC_MODE_UNCACHED
+
+        def run(pre, cache=cache, ctx=ctx, mode=mode):
+            if pre:
+                if cache is not None:
+                    cache.clear()
+                torch.cuda.synchronize()
+                return
+            for f in range(frames):
+                ctx.shade(dev[f], out, cache, mode=mode, frame=f, flags=B.PMC_FLAG_SORT)
+        ms = _median_ms(run)
+        outs[name] = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+        r = {"samples_per_s": n * frames / (ms * 1e-3), "ms": ms}
+        if cached:
+            st = B.new_stats()
+            run(True)
+            for f in range(frames):
+                ctx.shade(dev[f], out, cache, mode=mode, frame=f, flags=B.PMC_FLAG_SORT, stats=st)
+            torch.cuda.synchronize()
+            sd = B.stats_dict(st)
+            infos = [ctx.material_info(m) for m in range(len(sc.materials))]
+            cell = np.array([sum(i.cacheable_key[c] for c in range(i.n_cacheable)) for i in infos])
+            allk = np.array([i.n_cacheable for i in infos])
+            r.update(cache_hit_rate=sd["cache_hits"] / max(sd["probes"], 1),
+                     nodes_executed_fraction=sd["nodes_executed"] / max(sd["nodes_total"], 1),
+                     world_cell_share_of_lookups=float((cnt * cell).sum() /
+                                                       max((cnt * allk).sum(), 1)))
+        res[name] = r
+        ctx.close()
+    for name in ("texel_keys", "world_cells"):
+        res[name]["speedup_vs_uncached"] = res["uncached"]["ms"] / res[name]["ms"]
+        res[name]["err_vs_uncached"] = _abs_err(outs[name], outs["uncached"])
+    res["world_cells_vs_texel_keys"] = res["texel_keys"]["ms"] / res["world_cells"]["ms"]
+    log(f"spatial: {res}")
+    return res
+
+
 SURR_FLOP_PER_POINT = 2 * (32 * 64 + 64 * 64 + 64 * 4)     # 12,800 per network evaluation
 FP16_PEAK_TFLOPS = 2500.0
 TRAIN = dict(steps=8000, batch=1024, lr=2e-2, lr_end=1e-5, seed=0)
@@ -767,7 +888,7 @@ def surrogate_smooth_leg(args):
                                                     fine_res["surrogate_cache"]["ms"]))}
 
 
-LEGS = ("batching", "mid", "surrogate", "sweeps", "cones")
+LEGS = ("batching", "mid", "surrogate", "sweeps", "cones", "policies", "spatial")
 
 
 def main():
@@ -858,6 +979,10 @@ def main():
             out_legs["sweeps"] = sweeps_leg(args)
         elif leg == "cones":
             out_legs["cones"] = cones_leg(args)
+        elif leg == "policies":
+            out_legs["policies"] = policies_leg(args)
+        elif leg == "spatial":
+            out_legs["spatial"] = spatial_leg(args)
         log(f"leg {leg}: {time.perf_counter() - t0:.0f} s")
 
     res = {

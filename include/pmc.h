@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define PMC_ABI_VERSION 5u
+#define PMC_ABI_VERSION 6u
 
 typedef int32_t pmc_status;
 enum {
@@ -102,7 +102,9 @@ typedef struct pmc_texture_desc {
 typedef struct pmc_compile_opts {
     uint32_t min_subgraph_nodes;   /* smallest cacheable sub-graph (nodes besides UV inputs); 0 = 2 */
     uint32_t no_fold;              /* 1 = keep constant arithmetic nodes (no folding) */
-    uint32_t reserved[6];
+    uint32_t texel_keys_only;      /* 1 = descriptors are UV texels only (Sec. 3.1): outputs that
+                                      depend on the world position are not cached */
+    uint32_t reserved[5];
 } pmc_compile_opts;
 
 #define PMC_MAX_CACHEABLE 8    /* cacheable outputs per material kept by the compiler */

@@ -63,7 +63,7 @@ class pmc_texture_desc(C.Structure):
 
 class pmc_compile_opts(C.Structure):
     _fields_ = [("min_subgraph_nodes", C.c_uint32), ("no_fold", C.c_uint32),
-                ("reserved", C.c_uint32 * 6)]
+                ("texel_keys_only", C.c_uint32), ("reserved", C.c_uint32 * 5)]
 
 
 class pmc_material_info(C.Structure):
@@ -236,7 +236,7 @@ for _name, (_res, _args) in _proto.items():
 
 EXPORTED = tuple(_proto)
 
-ABI_VERSION = 5                     # the layouts above follow this version of include/pmc.h
+ABI_VERSION = 6                     # the layouts above follow this version of include/pmc.h
 if pmc_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI {pmc_abi_version()}, the binding expects "
                       f"{ABI_VERSION}: rebuild it with __graft_entry__.build()")
@@ -343,9 +343,11 @@ class Context:
             descs[i].height, descs[i].width = a.shape[0], a.shape[1]
         self.check(pmc_set_textures(self.h, descs, len(textures)))
 
-    def compile(self, materials, min_subgraph_nodes: int = 0, no_fold: bool = False):
+    def compile(self, materials, min_subgraph_nodes: int = 0, no_fold: bool = False,
+                texel_keys_only: bool = False):
         arr, offs = node_array(materials)
-        opts = pmc_compile_opts(min_subgraph_nodes, 1 if no_fold else 0)
+        opts = pmc_compile_opts(min_subgraph_nodes, 1 if no_fold else 0,
+                                1 if texel_keys_only else 0)
         self.check(pmc_compile_materials(self.h, arr, offs, len(materials), C.byref(opts)))
         self.n_mats = len(materials)
 

@@ -114,6 +114,7 @@ struct MatCompiler {
   uint32_t n;
   uint32_t min_nodes;
   bool fold;
+  bool world_keys = true;                 // outputs of the world position are cacheable
   std::string& err;
 
   std::vector<uint8_t> live, cls, folded;
@@ -366,9 +367,8 @@ struct MatCompiler {
     sock_ord[1].assign(n, -1);
     for (uint32_t i = 0; i < n; ++i) {
       uint32_t op = nd[i].op;
-      if (!live[i] || (cls[i] != C_UV && cls[i] != C_POS) || op == PMC_OP_UV_INPUT ||
-          op == PMC_OP_BSDF_OUTPUT)
-        continue;
+      const bool keyable = cls[i] == C_UV || (cls[i] == C_POS && world_keys);
+      if (!live[i] || !keyable || op == PMC_OP_UV_INPUT || op == PMC_OP_BSDF_OUTPUT) continue;
       int size = -1;
       for (int s = 0; s < kNumOut[op]; ++s) {
         bool boundary = false;
@@ -577,6 +577,7 @@ pmc_status compile_program(const pmc_node_desc* nodes, const uint32_t* node_offs
   }
   uint32_t min_nodes = (opts && opts->min_subgraph_nodes) ? opts->min_subgraph_nodes : 2;
   bool fold = !(opts && opts->no_fold);
+  const bool world_keys = !(opts && opts->texel_keys_only);
   out.info.resize(n_mats);
   for (uint32_t m = 0; m < n_mats; ++m) {
     if (node_offsets[m + 1] < node_offsets[m]) {
@@ -585,6 +586,7 @@ pmc_status compile_program(const pmc_node_desc* nodes, const uint32_t* node_offs
     }
     MatCompiler mc(m, nodes + node_offsets[m], node_offsets[m + 1] - node_offsets[m], min_nodes,
                    fold, err);
+    mc.world_keys = world_keys;
     if (!mc.validate()) return PMC_ERR_GRAPH;
     mc.analyse();
     mc.mark_cacheable();

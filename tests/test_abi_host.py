@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_layouts_match_the_header():
-    assert B.pmc_abi_version() == 5
+    assert B.pmc_abi_version() == 6
     for i, st in enumerate([B.pmc_node_desc, B.pmc_input, B.pmc_texture_desc, B.pmc_compile_opts,
                             B.pmc_material_info, B.pmc_cache_params, B.pmc_shade_params,
                             B.pmc_stats, B.pmc_hits, B.pmc_bsdf_out, B.pmc_debug_out,
@@ -184,3 +184,23 @@ def test_compiler_marks_world_keyed_outputs_like_the_oracle():
         sl = ctx.surrogate_slot(k)
         key = list(ctx.material_info(sl.material).cacheable_key)
         assert all(key[c] == 0 for c in range(8) if (sl.ordinal_mask >> c) & 1)
+
+
+def test_texel_keys_only_drops_the_world_keyed_outputs():
+    """With descriptors restricted to UV texels, the outputs of the world
+    position are not cached; the UV-keyed ones stay (where the 8-output cap
+    did not cut the list)."""
+    sc = scenes.spatial_scene(width=96, height=48, frames=1, n_mats=24)
+    ctx = _compile(sc.materials)
+    ctx2 = B.Context(-1)
+    ctx2.compile(sc.materials, texel_keys_only=True)
+    dropped = 0
+    for mi, m in enumerate(sc.materials):
+        cach = graph.cacheable_outputs(m)
+        uv_only = [c for c in cach if graph.key_kind(m, c[0]) != graph.POS]
+        info = ctx2.material_info(mi)
+        assert list(info.cacheable_key)[:info.n_cacheable] == [0] * info.n_cacheable
+        if len(cach) < 8:
+            assert ctx2.cacheables(mi) == uv_only, mi
+        dropped += len(cach) - len(uv_only)
+    assert dropped > 0
