@@ -124,10 +124,11 @@ uint32_t scan_blocks(uint32_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t n, uint32_t* out, uint32_t* out_copy,
                                  uint32_t* block_sums, uint32_t* total, hipStream_t s);
 
-// Tiled counting sort (no global atomics): buckets in rank order (rank[m] =
+// Counting sort over tiles of the batch: buckets in rank order (rank[m] =
 // position of material m by decreasing program length; invalid ids last).
-// mat_counts / offsets need (n_mats + 1) * sort_tiles(n) entries; scan_sums
-// scan_blocks(that) + 1.  reset[0..n_reset) is zeroed.
+// mat_counts / offsets need n_mats + 1 entries (the buffers are sized
+// (n_mats + 1) * sort_tiles(n)); scan_sums is unused.  reset[0..n_reset) is
+// zeroed.  At most 16383 materials and 1024 reset words.
 uint32_t sort_tiles(uint32_t n);
 // Kernel attributes (large dynamic LDS) set once per device, at context creation.
 hipError_t prepare_sort_kernels();

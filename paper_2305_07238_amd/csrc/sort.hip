@@ -9,22 +9,16 @@ namespace pmc {
 constexpr uint32_t kSortBatch = 8;    // material ids loaded per thread before they are used
 constexpr uint32_t kSortThreads = 1024;  // threads per tile (block)
 
-// Tiled counting sort without global atomics: tile k (a block) histograms
-// its hits in LDS and writes hist[rank(b)][k]; an exclusive scan over that
-// matrix (bucket rank major, tile minor) gives every (bucket, tile) its output
-// offset; each tile then scatters its hits, ranking them in LDS.  Buckets are
-// ranked by decreasing program length (invalid ids last), so longer programs
-// come first in the permutation.
-__global__ __launch_bounds__(kSortThreads) void k_tile_hist(const uint32_t* material, uint32_t n,
-                                                   uint32_t n_mats, uint32_t tile,
-                                                   uint32_t n_tiles, const uint32_t* rank,
-                                                   uint32_t* mat_counts) {
-  extern __shared__ uint32_t hist[];
-  const uint32_t nb = n_mats + 1;
-  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
-  __syncthreads();
-  const uint32_t beg = blockIdx.x * tile;
-  const uint32_t end = min(beg + tile, n);
+// Counting sort over tiles: tile k (a block) histograms its hits in LDS and
+// adds its non-zero bucket counts to the global counts of the buckets (a few
+// dozen atomics per tile: a tile covers a few screen regions, so few
+// materials); one block scans the counts (buckets ranked by decreasing
+// program length, invalid ids last, so longer programs come first in the
+// permutation); each tile then histograms again, reserves its ranges in the
+// buckets with one atomic per non-zero bucket, and scatters its hits, ranking
+// them in LDS.  The order of hits within a bucket carries no meaning.
+__device__ __forceinline__ void tile_histogram(const uint32_t* material, uint32_t beg,
+                                               uint32_t end, uint32_t n_mats, uint32_t* hist) {
   for (uint32_t g0 = beg; g0 < end; g0 += kSortBatch * kSortThreads) {
     uint32_t bb[kSortBatch];
 #pragma unroll
@@ -47,26 +41,43 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_hist(const uint32_t* mate
       }
     }
   }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_tile_hist(const uint32_t* material, uint32_t n,
+                                                   uint32_t n_mats, uint32_t tile,
+                                                   const uint32_t* rank, uint32_t* counts) {
+  extern __shared__ uint32_t hist[];
+  const uint32_t nb = n_mats + 1;
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
+  __syncthreads();
+  const uint32_t beg = blockIdx.x * tile;
+  tile_histogram(material, beg, min(beg + tile, n), n_mats, hist);
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
-    const uint32_t r = b < n_mats ? rank[b] : n_mats;
-    mat_counts[(uint64_t)r * n_tiles + blockIdx.x] = hist[b];
+    const uint32_t c = hist[b];
+    if (c) atomicAdd(&counts[b < n_mats ? rank[b] : n_mats], c);
   }
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_tile_scatter(const uint32_t* material, uint32_t n,
                                                       uint32_t n_mats, uint32_t tile,
-                                                      uint32_t n_tiles, const uint32_t* rank,
-                                                      const uint32_t* offsets, uint32_t* perm) {
+                                                      const uint32_t* rank, uint32_t* cursor,
+                                                      uint32_t* perm) {
   extern __shared__ uint32_t base[];
   const uint32_t nb = n_mats + 1;
-  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
-    const uint32_t r = b < n_mats ? rank[b] : n_mats;
-    base[b] = offsets[(uint64_t)r * n_tiles + blockIdx.x];
-  }
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) base[b] = 0u;
   __syncthreads();
   const uint32_t beg = blockIdx.x * tile;
   const uint32_t end = min(beg + tile, n);
+  tile_histogram(material, beg, end, n_mats, base);
+  __syncthreads();
+  // this tile's range in each of its buckets (the bucket cursors start at the
+  // buckets' first positions)
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    const uint32_t c = base[b];
+    if (c) base[b] = atomicAdd(&cursor[b < n_mats ? rank[b] : n_mats], c);
+  }
+  __syncthreads();
   for (uint32_t g0 = beg; g0 < end; g0 += kSortBatch * kSortThreads) {
     uint32_t bb[kSortBatch];
 #pragma unroll
@@ -75,8 +86,6 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_scatter(const uint32_t* m
       const uint32_t m = i < end ? material[i] : 0xFFFFFFFFu;
       bb[k] = i < end ? (m < n_mats ? m : n_mats) : 0xFFFFFFFFu;
     }
-    // ranks inside a bucket follow the order of the LDS atomics across the
-    // block's waves; the order of hits within a bucket carries no meaning
 #pragma unroll
     for (uint32_t k = 0; k < kSortBatch; ++k) {
       const uint32_t i = g0 + k * kSortThreads + threadIdx.x;
@@ -154,40 +163,36 @@ hipError_t prepare_sort_kernels() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, kSmallScanMax * 4);
 }
 
-// Tiles of at least 4096 hits, at most 256 of them: wide blocks over few tiles
-// keep the tile matrix (materials x tiles) small for its scan (measured on
-// 8.3 M hits over 4097 buckets: 256 threads x 512 tiles 163 us per sort,
-// 1024 threads x 256 tiles 93 us).
+// Buffer sizes: the bucket counts and cursors need n_mats + 1 entries each;
+// the sizing keeps the earlier tile-matrix bound (at least that).
 uint32_t sort_tiles(uint32_t n) {
   uint32_t t = (n + 4095) / 4096;
   return t < 1 ? 1 : (t > 256 ? 256 : t);
 }
 
+// Tiles of 8192 hits: the per-tile work (clearing and reading the LDS
+// histogram, a few atomics) is small against its 8192 ids, and 8.3 M hits give
+// about a thousand blocks.
+constexpr uint32_t kSortTile = 8192;
+
 hipError_t launch_material_sort_tiled(const uint32_t* material, uint32_t n, uint32_t n_mats,
                                       const uint32_t* rank, uint32_t* mat_counts,
                                       uint32_t* offsets, uint32_t* scan_sums, uint32_t* perm,
                                       uint32_t* reset, uint32_t n_reset, hipStream_t s) {
+  (void)scan_sums;
   const uint32_t nb = n_mats + 1;
-  const uint32_t n_tiles = sort_tiles(n);
-  const uint32_t tile = (n + n_tiles - 1) / n_tiles;
+  if (nb > kSmallScanMax || n_reset > kSmallScanThreads) return hipErrorInvalidValue;
+  const uint32_t n_tiles = (n + kSortTile - 1) / kSortTile;
   const size_t lds = (size_t)nb * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_tile_hist, dim3(n_tiles), dim3(kSortThreads), lds, s, material, n, n_mats, tile,
-                     n_tiles, rank, mat_counts);
-  const uint32_t cells = nb * n_tiles;
-  hipError_t e;
-  if (cells <= kSmallScanMax && n_reset <= kSmallScanThreads) {
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallScanThreads), (size_t)cells * 4, s,
-                       mat_counts, cells, offsets, reset, n_reset);
-  } else {
-    e = launch_exclusive_scan(mat_counts, cells, offsets, nullptr, scan_sums, nullptr, s);
-    if (e != hipSuccess) return e;
-    if (n_reset) {
-      e = launch_fill_u32(reset, 0u, n_reset, s);
-      if (e != hipSuccess) return e;
-    }
-  }
-  hipLaunchKernelGGL(k_tile_scatter, dim3(n_tiles), dim3(kSortThreads), lds, s, material, n, n_mats, tile,
-                     n_tiles, rank, offsets, perm);
+  hipError_t e = launch_fill_u32(mat_counts, 0u, nb, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_hist, dim3(n_tiles), dim3(kSortThreads), lds, s, material, n, n_mats,
+                     kSortTile, rank, mat_counts);
+  // bucket starts -> offsets (the cursors the scatter advances); also clears reset[]
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallScanThreads), (size_t)nb * 4, s,
+                     mat_counts, nb, offsets, reset, n_reset);
+  hipLaunchKernelGGL(k_tile_scatter, dim3(n_tiles), dim3(kSortThreads), lds, s, material, n,
+                     n_mats, kSortTile, rank, offsets, perm);
   return hipGetLastError();
 }
 
