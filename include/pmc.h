@@ -325,15 +325,15 @@ pmc_status pmc_shade(pmc_ctx* ctx, pmc_cache* cache, const pmc_hits* hits,
 
 /* For callers that cannot allocate device memory (code under their own HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc):
- * pmc_shade with the batch workspace (sorted order, the sort's tile matrix,
+ * pmc_shade with the batch workspace (sorted order, the sort's bucket counts,
  * batch counters, statistics slots) in a fixed device array of
  * PMC_STATIC_SCRATCH_BYTES that every device the library runs on holds from
  * its first context until the process ends.  Same arguments, kernels and
  * results as pmc_shade, for modes UNCACHED and CACHED with flags SORT,
  * PERSISTENT and DEFER.  PMC_ERR_UNSUPPORTED, before anything is enqueued,
  * for SNAPSHOT mode, LOG or SURROGATE flags, more than PMC_STATIC_MAX_HITS
- * hits, or a sorted batch whose tile matrix ((materials + 1) x ceil(n / 4096)
- * words, twice) does not fit the array.  Calls no hipMalloc or hipFree (the
+ * hits, or a sorted batch whose order and bucket counts (n + 2 (materials + 1)
+ * words) do not fit the array.  Calls no hipMalloc or hipFree (the
  * caller passes inputs, outputs, stats and the table) and records no phase
  * timing.  All calls on one device share the array and each one overwrites
  * it: calls that overlap on one device (several streams, threads or

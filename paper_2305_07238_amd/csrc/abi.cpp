@@ -464,7 +464,7 @@ pmc_status reserve_batch(pmc_ctx* ctx, pmc_cache* cache, uint32_t n, uint32_t mo
   if (flags & PMC_FLAG_SORT) {
     if (n_mats + 1 > 16384)
       return ctx->fail(PMC_ERR_UNSUPPORTED, "material sort handles at most 16383 materials");
-    const size_t cells = (size_t)(n_mats + 1) * sort_tiles(n);
+    const size_t cells = (size_t)n_mats + 1;                      // bucket counts
     if ((st = ensure(ctx, ctx->perm, (size_t)n * 4)) ||
         (all_sets && (st = ensure(ctx, ctx->perm2, (size_t)n * 4 * (kWorkSets - 1)))) ||
         (st = ensure(ctx, ctx->sort_counts, cells * 4)) ||

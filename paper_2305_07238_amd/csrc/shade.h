@@ -126,10 +126,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t n, uint32_t* out, 
 
 // Counting sort over tiles of the batch: buckets in rank order (rank[m] =
 // position of material m by decreasing program length; invalid ids last).
-// mat_counts / offsets need n_mats + 1 entries (the buffers are sized
-// (n_mats + 1) * sort_tiles(n)); scan_sums is unused.  reset[0..n_reset) is
-// zeroed.  At most 16383 materials and 1024 reset words.
-uint32_t sort_tiles(uint32_t n);
+// mat_counts / offsets need n_mats + 1 entries; scan_sums is unused.
+// reset[0..n_reset) is zeroed.  At most 16383 materials and 1024 reset words.
 // Kernel attributes (large dynamic LDS) set once per device, at context creation.
 hipError_t prepare_sort_kernels();
 hipError_t prepare_surrogate_kernels();

@@ -163,13 +163,6 @@ hipError_t prepare_sort_kernels() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, kSmallScanMax * 4);
 }
 
-// Buffer sizes: the bucket counts and cursors need n_mats + 1 entries each;
-// the sizing keeps the earlier tile-matrix bound (at least that).
-uint32_t sort_tiles(uint32_t n) {
-  uint32_t t = (n + 4095) / 4096;
-  return t < 1 ? 1 : (t > 256 ? 256 : t);
-}
-
 // Tiles of 8192 hits: the per-tile work (clearing and reading the LDS
 // histogram, a few atomics) is small against its 8192 ids, and 8.3 M hits give
 // about a thousand blocks.

@@ -40,7 +40,7 @@ size_t carve(unsigned char* base, uint32_t n, uint32_t n_mats, bool sort, pmc::W
     ws->misc = misc;
   }
   if (sort) {
-    const size_t cells = (size_t)(n_mats + 1) * pmc::sort_tiles(n);
+    const size_t cells = (size_t)n_mats + 1;                      // bucket counts
     auto* perm = (uint32_t*)take((size_t)n * 4);
     auto* counts = (uint32_t*)take(cells * 4);
     auto* offsets = (uint32_t*)take(cells * 4);
