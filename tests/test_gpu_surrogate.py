@@ -297,6 +297,54 @@ def test_untrained_network_is_not_trusted_and_not_used():
     assert st["surrogate_used"] == 0
 
 
+def test_library_trust_decision_holds_on_the_graph():
+    """pmc_surrogate_train's own decision (log grouped per network, the last
+    records of each group held out, trust at the configured 5e-3): the held-out
+    errors it reports sit on the right side of the threshold, and every value a
+    network it trusted supplies in a render is within 1e-2 of the FP64 graph.
+    (How many networks pass varies with the racing log's order; the bench
+    records 1-3 of 4 on this kind of scene.)"""
+    sc = scenes.smooth_scene(frames=4)
+    ctx, n_slots = _ctx_with_slots(sc, seed=7, max_err=5e-3)
+    cache = ctx.cache(sc.cache.n_cells, 8, 16)
+    ctx.log_clear()
+    for f in range(4):
+        G.shade(ctx, sc.frame(f), cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                flags=B.PMC_FLAG_SORT | B.PMC_FLAG_LOG)
+    ctx.surrogate_train(steps=48000, batch=512, lr=2e-2, lr_end=2e-6, seed=0, min_records=256)
+    torch.cuda.synchronize()
+    rep = ctx.surrogate_report()
+    trained = [r for r in rep if r["n_heldout"] > 0]
+    assert trained
+    for r in trained:
+        assert bool(r["trusted"]) == (r["max_err"] <= 5e-3), r
+    print("held-out max errors", [r["max_err"] for r in rep], "trusted",
+          [bool(r["trusted"]) for r in rep])
+    h = sc.frame(0)
+    cache.clear()
+    out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=0,
+                                    flags=B.PMC_FLAG_SORT | B.PMC_FLAG_SURROGATE, debug=True)
+    net_err, n_used = 0.0, 0
+    for k in range(n_slots):
+        mat, om = _ordmap(ctx, sc, k)
+        rows = np.nonzero((h.material == mat) & (state == 4).any(1))[0]
+        if len(rows) == 0:
+            continue
+        assert rep[k]["trusted"]
+        _, vals = graph.evaluate(sc.materials[mat], h.uv[rows], h.normal[rows], sc.textures)
+        cach = graph.cacheable_outputs(sc.materials[mat])
+        for c, (base, w) in om.items():
+            sel = state[rows, c] == 4
+            if sel.any():
+                n_used += int(sel.sum())
+                ref_c = np.asarray(vals[cach[c]], dtype=np.float64).reshape(len(rows), -1)
+                e = np.abs(value[rows[sel], c, :w] - ref_c[sel, :w]).max()
+                net_err = max(net_err, float(e))
+    print("network values used", n_used, "max abs error vs FP64 graph", net_err)
+    assert n_used == st["surrogate_used"]
+    assert net_err <= 1e-2
+
+
 def test_training_on_the_log_gains_over_cache_only():
     """End to end on a scene of low-frequency sub-graphs, made deterministic:
     snapshot frames with the log on collect training pairs (a deterministic
