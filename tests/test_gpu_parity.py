@@ -250,6 +250,44 @@ def test_snapshot_mid_two_frames_matches_oracle():
     print("mid snapshot stats", st)
 
 
+@pytest.mark.parametrize("mode", ["snapshot", "cached"])
+def test_eight_byte_entries(mode):
+    """The paper's 8-byte entries (the word alone, no stamp), 16 per 128-byte
+    cell, keep-first: the per-lane probe scan and the insert on that layout.
+    Snapshot mode matches the oracle (hit pattern, found values, outputs,
+    table); cached (racing) mode passes the invariant checker."""
+    sc = G.small_mid_scene(frames=2)
+    ctx = G.setup(sc)
+    n_cells = 1 << 12                                  # small table: cells overflow
+    cache = ctx.cache(n_cells, 16, 8)
+    ref_t = table.Table(n_cells, 16, 8)
+    log, vals, prev = check.KeyLog(), {}, None
+    for f in range(2):
+        h = sc.frame(f)
+        if mode == "snapshot":
+            ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f)
+            out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                            flags=B.PMC_FLAG_SORT, debug=True)
+            _snapshot_frame_parity(sc, h, ref, out, state, value)
+            assert st["cache_hits"] == ref.stats["hits"]
+            assert st["cell_full"] == ref.stats.get("full", 0)
+            assert st["inserts"] == ref.stats.get("inserted", 0)
+            words = cache.words()
+            assert words.shape[1] == 1
+            G.table_parity(words, ref_t, sc.materials)
+        else:
+            out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                                            flags=B.PMC_FLAG_SORT, debug=True)
+            bad = check.check_frame(sc.materials, sc.textures, h, f, state, value, out, n_cells,
+                                    log, vals)
+            words = cache.words()[:, 0]
+            bad += check.table_structure(words, 16, prev)
+            bad += check.check_entries_come_from_keys(words, 16, log)
+            assert not bad, (f, bad[:5])
+            prev = words
+    assert st["cache_hits"] > 0
+
+
 @pytest.mark.parametrize("n_cells,n_entries", [(512, 8), (1000, 5)])
 def test_snapshot_overwrite_matches_oracle(n_cells, n_entries):
     """OVERWRITE: a full cell evicts its oldest-stamped entry; the deterministic
