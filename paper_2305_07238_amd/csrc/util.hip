@@ -44,10 +44,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_stats_reduce(unsigned long l
                                                                 unsigned long long* out) {
   __shared__ unsigned long long part[kReduceThreads];
   const int t = threadIdx.x, q = t % kStatStride, row = t / kStatStride;
+  constexpr int kPer = kStatSlots / kReduceRows;
+  unsigned long long v[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) v[j] = slots[(row + j * kReduceRows) * kStatStride + q];
   unsigned long long s = 0ull;
-  for (int k = row; k < kStatSlots; k += kReduceRows) {
-    s += slots[k * kStatStride + q];
-    slots[k * kStatStride + q] = 0ull;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {            // all loads above are in flight before the clears
+    s += v[j];
+    slots[(row + j * kReduceRows) * kStatStride + q] = 0ull;
   }
   part[t] = s;
   __syncthreads();
