@@ -146,16 +146,20 @@ def subgraph(material, i) -> set:
 MAX_CACHEABLE = 8
 
 
-def cacheable_outputs(material, min_subgraph_nodes: int = 2) -> List[Tuple[int, int]]:
+def cacheable_outputs(material, min_subgraph_nodes: int = 2,
+                      texel_only: bool = False) -> List[Tuple[int, int]]:
     """Ordered list of cacheable (node, socket) pairs (ordinal = list index); at
     most MAX_CACHEABLE per material, the first in (node, socket) order (the
-    rest are evaluated every time, as if not cacheable)."""
+    rest are evaluated every time, as if not cacheable).  texel_only: the
+    descriptor is the UV texel alone, as Sec. 3.1 defines it, so outputs of
+    the world position are not cacheable."""
     nodes = material.nodes
     live = reachable(material)
     cls = dependency_classes(material)
+    keyed = (UV,) if texel_only else (UV, POS)
     out = []
     for i, n in enumerate(nodes):
-        if not live[i] or cls[i] not in (UV, POS) or n.op == "UV_INPUT" or n.op == "BSDF_OUTPUT":
+        if not live[i] or cls[i] not in keyed or n.op == "UV_INPUT" or n.op == "BSDF_OUTPUT":
             continue
         size = sum(1 for j in subgraph(material, i) if nodes[j].op != "UV_INPUT")
         if size < min_subgraph_nodes:

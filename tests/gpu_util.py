@@ -73,7 +73,8 @@ def small_mid_scene(seed=0, frames=2, **kw):
     return scenes.mid_scene(seed=seed, width=480, height=240, frames=frames, **kw)
 
 
-def found_values_parity(materials, hits, state, value, ref_found_value, min_subgraph_nodes=2):
+def found_values_parity(materials, hits, state, value, ref_found_value, min_subgraph_nodes=2,
+                        cacheables=None):
     """Values the device found in the table against the oracle's found values:
     COLOR within one RGB9E5 step of the oracle's decoded code, FLOAT at the
     scalar bar.  Returns the number of (hit, ordinal) pairs compared."""
@@ -83,8 +84,9 @@ def found_values_parity(materials, hits, state, value, ref_found_value, min_subg
         if m >= len(materials):
             continue
         idx = np.nonzero(mat == m)[0]
-        for c, (node, sock) in enumerate(graph.cacheable_outputs(materials[m],
-                                                                 min_subgraph_nodes)):
+        cach = (cacheables[m] if cacheables is not None
+                else graph.cacheable_outputs(materials[m], min_subgraph_nodes))
+        for c, (node, sock) in enumerate(cach):
             rows = idx[state[idx, c] == 1]
             if len(rows) == 0:
                 continue
@@ -100,7 +102,7 @@ def found_values_parity(materials, hits, state, value, ref_found_value, min_subg
 
 
 def substituted_outputs(materials, textures, hits, state, value, min_subgraph_nodes=2,
-                        states=(1,)):
+                        states=(1,), cacheables=None):
     """FP64 evaluation of every hit with the device's values substituted at the
     cacheable outputs whose state is in ``states`` (1 = found in the table,
     4 = supplied by a network)."""
@@ -113,8 +115,9 @@ def substituted_outputs(materials, textures, hits, state, value, min_subgraph_no
             o = graph.default_outputs(hits.normal[idx])
         else:
             subst = {}
-            for c, (node, sock) in enumerate(graph.cacheable_outputs(materials[m],
-                                                                     min_subgraph_nodes)):
+            cach = (cacheables[m] if cacheables is not None
+                    else graph.cacheable_outputs(materials[m], min_subgraph_nodes))
+            for c, (node, sock) in enumerate(cach):
                 rows = np.isin(state[idx, c], states)
                 if rows.any():
                     if graph.output_type(materials[m], node, sock) == "COLOR":

@@ -200,6 +200,7 @@ def test_texel_keys_only_drops_the_world_keyed_outputs():
         uv_only = [c for c in cach if graph.key_kind(m, c[0]) != graph.POS]
         info = ctx2.material_info(mi)
         assert list(info.cacheable_key)[:info.n_cacheable] == [0] * info.n_cacheable
+        assert ctx2.cacheables(mi) == graph.cacheable_outputs(m, texel_only=True), mi
         if len(cach) < 8:
             assert ctx2.cacheables(mi) == uv_only, mi
         dropped += len(cach) - len(uv_only)

@@ -115,3 +115,31 @@ def test_position_required_when_the_graphs_read_it():
     with pytest.raises(B.PmcError) as e:
         ctx.shade(d, out, None, mode=B.PMC_MODE_UNCACHED)
     assert "world position" in str(e.value)
+
+
+def test_texel_keys_only_snapshot_matches_oracle():
+    """Descriptors restricted to UV texels (the comparison the benchmark draws):
+    the compiler's cacheable outputs equal the oracle's texel-only ones, and a
+    two-frame snapshot render matches the oracle with those outputs."""
+    sc = _scene(2)
+    ctx = G.setup(sc, texel_keys_only=True)
+    cach = [graph.cacheable_outputs(m, texel_only=True) for m in sc.materials]
+    for mi in range(len(sc.materials)):
+        assert ctx.cacheables(mi) == cach[mi], mi
+    n_cells = 1 << 16
+    cache = ctx.cache(n_cells, 8, 16)
+    ref_t = table.Table(n_cells, 8, 16)
+    for f in range(2):
+        h = sc.frame(f)
+        ref = render.shade_snapshot_frame(sc.materials, sc.textures, h, ref_t, f, cacheables=cach)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_SNAPSHOT, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        assert np.array_equal(state == 1, ref.found)
+        assert np.array_equal(state == 2, ref.bypass & ref.valid)
+        G.found_values_parity(sc.materials, h, state, value, ref.found_value, cacheables=cach)
+        o = G.substituted_outputs(sc.materials, sc.textures, h, state, value, cacheables=cach)
+        G.assert_outputs(out, o)
+        assert st["cache_hits"] == ref.stats["hits"]
+        assert st["inserts"] == ref.stats.get("inserted", 0)
+        G.table_parity(cache.words(), ref_t, sc.materials)
+    assert st["cache_hits"] > 0

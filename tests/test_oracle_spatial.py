@@ -126,3 +126,20 @@ def test_spatial_snapshot_values_are_earlier_samples():
     unc = render.shade_uncached(sc.materials, sc.textures, f1)
     assert r0.stats["hits"] == 0 and checked > 0
     assert np.all(np.isfinite(unc["base_color"]))
+
+
+def test_texel_only_marking():
+    """Texel-only descriptors drop exactly the outputs of the world position
+    (while the 8-output cap does not bind) and change nothing where no node
+    reads the position."""
+    from paper_2305_07238_amd import scenes as S
+    sc = S.spatial_scene(width=96, height=48, frames=1, n_mats=24)
+    for m in sc.materials:
+        full = graph.cacheable_outputs(m)
+        tex = graph.cacheable_outputs(m, texel_only=True)
+        assert all(graph.key_kind(m, node) == graph.UV for node, _ in tex)
+        if len(full) < graph.MAX_CACHEABLE:
+            assert tex == [c for c in full if graph.key_kind(m, c[0]) == graph.UV]
+    mid = S.mid_scene(frames=1, width=64, height=32)
+    for m in mid.materials:
+        assert graph.cacheable_outputs(m, texel_only=True) == graph.cacheable_outputs(m)
