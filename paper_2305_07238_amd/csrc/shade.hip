@@ -1252,10 +1252,10 @@ __device__ __forceinline__ void shade_persistent_body(const ShadeArgs& a) {
   if (STATS) flush_counters_block(a, cnt, lds);
 }
 
-// Kernels.  The cached variants are compiled for 4 waves per SIMD (at most 128
-// VGPRs): the probe-heavy path is latency bound and gains more from the extra
-// wave than it loses to a few spilled registers.  The uncached variants keep
-// the compiler's own register budget.
+// Kernels.  The cached variants without counters are compiled for 4 waves per
+// SIMD (at most 128 VGPRs): the probe-heavy path is latency bound and gains
+// more from the extra wave than it loses to a few spilled registers.  The
+// uncached and the counting variants keep the compiler's own register budget.
 template <int MODE, int KIND, bool STATS, bool SURR>
 __global__ __launch_bounds__(256) void k_shade_flat(ShadeArgs a) {
   shade_flat_body<MODE, KIND, STATS, SURR>(a);
@@ -1397,15 +1397,20 @@ size_t shade_lds_bytes(uint32_t n_regs, uint32_t waves) {
 template <int MODE, int KIND, bool STATS, bool SURR>
 static void launch_one(const ShadeArgs& a, bool persistent, dim3 grid, dim3 block, size_t lds,
                        hipStream_t s) {
-  constexpr bool w4 = MODE != PMC_MODE_UNCACHED;
-  if (w4 && persistent)
-    hipLaunchKernelGGL((k_shade_persistent_w4<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
-  else if (w4)
-    hipLaunchKernelGGL((k_shade_flat_w4<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
-  else if (persistent)
-    hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
-  else
-    hipLaunchKernelGGL((k_shade_flat<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
+  // the counting variants keep the compiler's register budget: their 23
+  // per-lane counters would spill under the 4-wave cap
+  constexpr bool w4 = MODE != PMC_MODE_UNCACHED && !STATS;
+  if constexpr (w4) {
+    if (persistent)
+      hipLaunchKernelGGL((k_shade_persistent_w4<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
+    else
+      hipLaunchKernelGGL((k_shade_flat_w4<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
+  } else {
+    if (persistent)
+      hipLaunchKernelGGL((k_shade_persistent<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
+    else
+      hipLaunchKernelGGL((k_shade_flat<MODE, KIND, STATS, SURR>), grid, block, lds, s, a);
+  }
 }
 
 template <int KIND, bool STATS>
