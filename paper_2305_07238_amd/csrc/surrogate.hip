@@ -716,17 +716,21 @@ __global__ __launch_bounds__(256) void k_surr_infer(const SurrW* w, const float*
   const uint32_t j = threadIdx.x & 15u;
   const bool lead = (threadIdx.x & 63u) < 16u;
   const float2* uv2 = reinterpret_cast<const float2*>(uv);
-  uint32_t i = t * 16u + j;
-  float2 p = i < n ? uv2[i] : make_float2(0.f, 0.f);
+  // two tiles per step (t and t + waves): their products and the vector work
+  // of their features and activations are independent, so the matrix core
+  // works on one tile while the vector ALU works on the other
+  const uint32_t step = 2u * waves;
 #pragma unroll 1
-  for (; t < tiles; t += waves) {
-    // the next tile's coordinates load while this tile is computed
-    const uint32_t i_next = (t + waves) * 16u + j;
-    const float2 p_next = (t + waves < tiles && i_next < n) ? uv2[i_next] : make_float2(0.f, 0.f);
-    const f4 Y = net_tile(N, p.x, p.y);
-    if (lead && i < n) reinterpret_cast<float4*>(y)[i] = make_float4(Y.x, Y.y, Y.z, Y.w);
-    i = i_next;
-    p = p_next;
+  for (; t < tiles; t += step) {
+    const uint32_t ia = t * 16u + j, ib = (t + waves) * 16u + j;
+    const bool has_b = t + waves < tiles;
+    const float2 pa = ia < n ? uv2[ia] : make_float2(0.f, 0.f);
+    const float2 pb = has_b && ib < n ? uv2[ib] : make_float2(0.f, 0.f);
+    const f4 Ya = net_tile(N, pa.x, pa.y);
+    const f4 Yb = net_tile(N, pb.x, pb.y);
+    if (lead && ia < n) reinterpret_cast<float4*>(y)[ia] = make_float4(Ya.x, Ya.y, Ya.z, Ya.w);
+    if (lead && has_b && ib < n)
+      reinterpret_cast<float4*>(y)[ib] = make_float4(Yb.x, Yb.y, Yb.z, Yb.w);
   }
 }
 
