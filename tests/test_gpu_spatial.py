@@ -143,3 +143,37 @@ def test_texel_keys_only_snapshot_matches_oracle():
         assert st["inserts"] == ref.stats.get("inserted", 0)
         G.table_parity(cache.words(), ref_t, sc.materials)
     assert st["cache_hits"] > 0
+
+
+def test_frame_graph_carries_positions():
+    """A captured snapshot render of the spatial scene (each frame's positions
+    and widths taken at the frame's offset) equals the frames launched one by
+    one, bit for bit, on two replays."""
+    F = 3
+    sc = _scene(F)
+    ctx = G.setup(sc)
+    n = sc.hits_per_frame
+    hits = B.hits_to_device(scenes.Hits.concat([sc.frame(f) for f in range(F)]))
+    assert "position" in hits and "width" in hits
+    out_g, out_s = B.alloc_outputs(n * F), B.alloc_outputs(n * F)
+    cache_g, cache_s = ctx.cache(1 << 14), ctx.cache(1 << 14)
+    plan = ctx.frame_plan(hits, n, F, out_g, mode=B.PMC_MODE_SNAPSHOT, out_per_frame=True,
+                          clear_cache=True, flags=B.PMC_FLAG_SORT)
+    graph = ctx.frame_graph(cache_g, plan)
+    for f in range(F):
+        sl = {k: v[f * n:(f + 1) * n] for k, v in hits.items()}
+        ctx.shade(sl, {k: v[f * n:(f + 1) * n] for k, v in out_s.items()}, cache_s,
+                  mode=B.PMC_MODE_SNAPSHOT, frame=f, flags=B.PMC_FLAG_SORT)
+    torch.cuda.synchronize()
+    ref = G.to_numpy(out_s)
+    ref_table = cache_s.export()
+    for rep in range(2):
+        for v in out_g.values():
+            v.fill_(-1.0)
+        graph.launch()
+        torch.cuda.synchronize()
+        got = G.to_numpy(out_g)
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (rep, k)
+        assert np.array_equal(cache_g.export(), ref_table), rep
+    graph.close()
