@@ -192,3 +192,37 @@ def test_autotune_of_the_late_frames():
     bad = ctx.frame_plan(hits, n, F, out, mode=B.PMC_MODE_CACHED, late_frame=F)
     with pytest.raises(B.PmcError):
         ctx.autotune(cache, bad)
+
+
+def test_frame_graph_carries_path_depths():
+    """PRIORITY over frames of camera and secondary hits: a captured snapshot
+    render (each frame's path depths taken at the frame's offset) equals the
+    frames launched one by one, bit for bit."""
+    F = 3
+    sc = G.small_mid_scene(frames=F)
+    ctx = G.setup(sc)
+    fr = [scenes.with_indirect(sc.frame(f), f) for f in range(F)]
+    n = len(fr[0])
+    hits = B.hits_to_device(scenes.Hits.concat(fr))
+    assert "bounce" in hits
+    out_g, out_s = B.alloc_outputs(n * F), B.alloc_outputs(n * F)
+    cache_g = ctx.cache(1 << 12, 8, 16, B.PMC_POLICY_PRIORITY)
+    cache_s = ctx.cache(1 << 12, 8, 16, B.PMC_POLICY_PRIORITY)
+    plan = ctx.frame_plan(hits, n, F, out_g, mode=B.PMC_MODE_SNAPSHOT, out_per_frame=True,
+                          clear_cache=True, flags=B.PMC_FLAG_SORT)
+    graph = ctx.frame_graph(cache_g, plan)
+    st = B.new_stats()
+    for f in range(F):
+        ctx.shade(_slice(hits, f, n), _slice(out_s, f, n), cache_s, mode=B.PMC_MODE_SNAPSHOT,
+                  frame=f, flags=B.PMC_FLAG_SORT, stats=st)
+    torch.cuda.synchronize()
+    assert B.stats_dict(st)["overwrites"] > 0          # the table overflows: depths decide
+    ref = G.to_numpy(out_s)
+    ref_table = cache_s.export()
+    graph.launch()
+    torch.cuda.synchronize()
+    got = G.to_numpy(out_g)
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.array_equal(cache_g.export(), ref_table)
+    graph.close()
