@@ -177,3 +177,29 @@ def test_frame_graph_carries_positions():
             assert np.array_equal(got[k], ref[k]), (rep, k)
         assert np.array_equal(cache_g.export(), ref_table), rep
     graph.close()
+
+
+def test_surrogates_beside_world_keys():
+    """Networks (untrained, trusted by a huge threshold) on graphs that also
+    hold world-keyed outputs: no network stands for a world-keyed output (they
+    read UV only), and in racing mode every output equals the FP64 graph with
+    the device's found and network values substituted."""
+    sc = _scene(2)
+    ctx = G.setup(sc)
+    n_slots = ctx.surrogate_setup(min_subgraph_nodes=4, seed=3, max_err=1e6)
+    assert n_slots > 0
+    for k in range(n_slots):
+        sl = ctx.surrogate_slot(k)
+        info = ctx.material_info(sl["material"])
+        assert all(info.cacheable_key[c] == 0 for c in range(8) if (sl["ordinal_mask"] >> c) & 1)
+        ctx.surrogate_set_trust(k, True)
+    cache = ctx.cache(1 << 16, 8, 16)
+    used = 0
+    for f in range(2):
+        h = sc.frame(f)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                                        flags=B.PMC_FLAG_SORT | B.PMC_FLAG_SURROGATE, debug=True)
+        o = G.substituted_outputs(sc.materials, sc.textures, h, state, value, states=(1, 4))
+        G.assert_outputs(out, o)
+        used += st["surrogate_used"]
+    assert used > 0
