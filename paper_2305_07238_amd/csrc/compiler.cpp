@@ -108,6 +108,19 @@ void ramp_eval(const pmc_node_desc& n, float fac, float out[4]) {
   }
 }
 
+// Integer hash (C. Wellons' "lowbias32" finalizer) for scrambled visiting orders.
+inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+constexpr uint32_t kOrderVariants = 32;   // alternative emission orders tried per material
+constexpr uint32_t kRegsGoal = 24;        // registers at which no further order is tried
+
 struct MatCompiler {
   uint32_t mat;
   const pmc_node_desc* nd;
@@ -119,6 +132,8 @@ struct MatCompiler {
 
   std::vector<uint8_t> live, cls, folded;
   std::vector<int> order;                 // emission order (node ids)
+  std::vector<int> need;                  // Sethi-Ullman register need per node
+  std::vector<std::array<int, 3>> child_order;   // inputs in visiting order
   std::vector<int> pos;                   // emission position, -1 if not emitted
   std::vector<std::vector<std::pair<int, int>>> consumers;  // per (node): (consumer, input slot)
   std::vector<Val> fval[2];               // folded value per socket
@@ -233,8 +248,9 @@ struct MatCompiler {
         }
       }
     }
-    std::vector<int> need(n, 0), width(n, 0);
-    std::vector<std::array<int, 3>> child_order(n);
+    std::vector<int> width(n, 0);
+    need.assign(n, 0);
+    child_order.assign(n, {-1, -1, -1});
     for (int i : topo) {
       const pmc_node_desc& d = nd[i];
       int w = 0;
@@ -406,7 +422,7 @@ struct MatCompiler {
     }
   }
 
-  bool socket_used(int i, int s) {
+  bool socket_used(int i, int s) const {
     if (sock_ord[s][i] >= 0) return true;
     for (auto& ck : consumers[i])
       if (int(nd[ck.first].in[ck.second].socket) == s && (ck.first == sink || pos[ck.first] >= 0))
@@ -414,7 +430,80 @@ struct MatCompiler {
     return false;
   }
 
+  // Emission order: post-order of a depth-first walk from the sink that visits
+  // each node's inputs in the order co gives.
+  std::vector<int> emission_order(const std::vector<std::array<int, 3>>& co) const {
+    std::vector<uint8_t> done(n, 0);
+    std::vector<std::pair<int, int>> stack{{sink, 0}};
+    std::vector<int> out;
+    done[sink] = 1;
+    while (!stack.empty()) {
+      auto& top = stack.back();
+      if (top.second < 3) {
+        int j = co[top.first][top.second++];
+        if (j >= 0 && !done[j]) {
+          done[j] = 1;
+          stack.push_back({j, 0});
+        }
+      } else {
+        const int i = top.first;
+        stack.pop_back();
+        if (i != sink && nd[i].op != PMC_OP_UV_INPUT && !folded[i]) out.push_back(i);
+      }
+    }
+    return out;
+  }
+
+  // Sethi-Ullman order is a heuristic on a DAG: shared values can stay live
+  // across long stretches.  Variants of it that break ties between equally
+  // needy inputs differently, or visit inputs in a scrambled order, are tried
+  // too (a fixed number, with a fixed hash: the result is deterministic), and
+  // the order whose allocation needs the fewest registers is emitted.
   bool allocate_registers() {
+    const std::string err0 = err;
+    bool ok = assign_registers();
+    std::string best_err = err;
+    std::vector<int> best_order = order, best_reg[2] = {reg[0], reg[1]};
+    uint32_t best_regs = n_regs;
+    if (ok && n_regs <= kRegsGoal) return true;
+    for (uint32_t v = 1; v <= kOrderVariants; ++v) {
+      std::vector<std::array<int, 3>> co = child_order;
+      for (uint32_t i = 0; i < n; ++i) {
+        auto& ch = co[i];
+        int nc = 0;
+        while (nc < 3 && ch[nc] >= 0) ++nc;
+        auto key = [&](int j) { return mix32(v * 0x9E3779B9u ^ (uint32_t(i) << 12) ^ uint32_t(j)); };
+        if (v & 1u)      // scrambled visiting order
+          std::sort(ch.begin(), ch.begin() + nc, [&](int a, int b) { return key(a) < key(b); });
+        else             // by need, ties scrambled
+          std::sort(ch.begin(), ch.begin() + nc, [&](int a, int b) {
+            return need[a] != need[b] ? need[a] > need[b] : key(a) < key(b);
+          });
+      }
+      order = emission_order(co);
+      for (size_t p = 0; p < order.size(); ++p) pos[order[p]] = int(p);
+      n_regs = 0;
+      const bool ok_v = assign_registers();
+      if (ok_v && (!ok || n_regs < best_regs)) {
+        ok = true;
+        best_err = err0;
+        best_order = order;
+        best_reg[0] = reg[0];
+        best_reg[1] = reg[1];
+        best_regs = n_regs;
+      }
+      if (ok && best_regs <= kRegsGoal) break;
+    }
+    err = ok ? err0 : best_err;
+    order = best_order;
+    for (size_t p = 0; p < order.size(); ++p) pos[order[p]] = int(p);
+    reg[0] = best_reg[0];
+    reg[1] = best_reg[1];
+    n_regs = best_regs;
+    return ok;
+  }
+
+  bool assign_registers() {
     struct V { int node, sock, width, def, last; };
     std::vector<V> vals;
     int end = int(order.size());
@@ -427,7 +516,9 @@ struct MatCompiler {
           last = std::max(last, ck.first == sink ? end : pos[ck.first]);
         }
         bool cachd = sock_ord[s][i] >= 0;
-        if (cachd) last = std::max(last, pos[i]);
+        // a cached value is written by its own instruction: it stays busy
+        // there even when nothing reads it later
+        if (cachd) last = std::max(last, pos[i] + 1);
         vals.push_back({i, s, width_of(out_type(nd[i].op, s)), cachd ? -1 : pos[i], last});
       }
     }
@@ -439,8 +530,11 @@ struct MatCompiler {
       int base = -1;
       for (int r = 0; r + v.width <= kMaxRegs && base < 0; ++r) {
         bool ok = true;
+        // a register whose value is last read by the defining instruction is
+        // free for its result: the interpreter reads all operands of an
+        // instruction before it writes any output
         for (int w = 0; w < v.width; ++w)
-          if (owner_last[r + w] >= v.def) { ok = false; break; }  // busy (strictly overlapping)
+          if (owner_last[r + w] > v.def) { ok = false; break; }
         if (ok) base = r;
       }
       if (base < 0) {

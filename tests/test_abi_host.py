@@ -113,6 +113,25 @@ def test_constant_folding_and_min_subgraph_option():
     assert ctx3.cacheables(0) == graph.cacheable_outputs(m, 1) == [(3, 0), (4, 0)]
 
 
+def test_a_result_takes_the_register_its_operand_frees():
+    """A chain noise -> 8 MATH nodes -> roughness: each MATH node reads the one
+    before it for the last time, so its result can take that register (the
+    interpreter reads all operands before it writes).  The chain's end is the
+    cacheable output, held from the start for a found value: two registers in
+    all, where a rule that keeps the operand's register busy through its last
+    reader needs three."""
+    N, L, Cn = scenes.Node, scenes.Input.link, scenes.Input.const
+    nodes = [N("UV_INPUT"), N("PERLIN_NOISE", [L(0)], freq=4, octaves=2, seed=3)]
+    for k in range(8):
+        nodes.append(N("MATH", [L(len(nodes) - 1), Cn(0.5 + k)], math_op="ADD" if k % 2 else "MUL"))
+    nodes.append(N("BSDF_OUTPUT", [Cn(0.2, 0.3, 0.4), L(len(nodes) - 1), Cn()]))
+    m = scenes.Material(nodes)
+    ctx = _compile([m])
+    assert ctx.cacheables(0) == graph.cacheable_outputs(m) == [(9, 0)]
+    info = ctx.material_info(0)
+    assert info.n_instr == 9 and info.n_regs == 2
+
+
 @pytest.mark.parametrize("bad", ["cycle", "type", "no_sink", "link", "ramp"])
 def test_compiler_rejects_bad_graphs(bad):
     N, L, Cn = scenes.Node, scenes.Input.link, scenes.Input.const
