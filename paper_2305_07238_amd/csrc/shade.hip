@@ -377,20 +377,28 @@ __device__ __forceinline__ void store_stamp(const ShadeArgs& a, uint64_t* p, uin
   if (a.policy == PMC_POLICY_PRIORITY) ((uint32_t*)p)[3] = bounce;
 }
 
+// The entry of the cell a key may take: the first one that holds the key or
+// is empty (entries fill front to back and are never emptied singly, so a
+// key never sits behind an empty entry); n_entries when the cell is full of
+// other keys.
+__device__ __forceinline__ uint32_t claimable_entry(const ShadeArgs& a, uint32_t cell,
+                                                    uint32_t hash2) {
+  uint32_t e = 0u;
+  for (; e < a.n_entries; ++e) {
+    const uint32_t h = (uint32_t)(load_relaxed(entry_word(a, cell, e)) >> 32);
+    if (h == hash2 || h == 0u) break;
+  }
+  return e;
+}
+
 __device__ __forceinline__ int cache_insert(const ShadeArgs& a, uint32_t cell, uint32_t hash2,
                                             uint32_t code, uint32_t bounce = 0u) {
   const uint64_t neu = ((uint64_t)hash2 << 32) | code;
-  int idx = -1;
-  for (uint32_t i = 0; i < a.n_entries; ++i) {
-    uint64_t cur = load_relaxed(entry_word(a, cell, i));
-    uint32_t h = (uint32_t)(cur >> 32);
-    if (h == hash2 || h == 0u) {
-      idx = (int)i;
-      break;
-    }
-  }
-  if (idx >= 0) {
-    uint64_t* p = entry_word(a, cell, (uint32_t)idx);
+  const uint32_t e = claimable_entry(a, cell, hash2);
+  if (e < a.n_entries) {
+    // one compare-and-swap from the empty word; it fails if the entry holds
+    // the key already or another key took it meanwhile
+    uint64_t* p = entry_word(a, cell, e);
     uint64_t expected = 0ull;
     bool ok = __hip_atomic_compare_exchange_strong(p, &expected, neu, __ATOMIC_RELAXED,
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

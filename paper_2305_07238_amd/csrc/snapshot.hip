@@ -35,13 +35,13 @@ __device__ __forceinline__ int apply_one(uint64_t* w0, const SnapshotArgs& a, ui
                                          uint32_t code, uint32_t stamp, uint32_t bounce) {
   const uint64_t neu = ((uint64_t)hash2 << 32) | code;
   const bool prio = a.policy == PMC_POLICY_PRIORITY;
-  int idx = -1;
-  for (uint32_t i = 0; i < a.n_entries; ++i) {
-    uint32_t h = (uint32_t)(w0[(uint64_t)i * a.entry_words] >> 32);
-    if (h == hash2 || h == 0u) { idx = (int)i; break; }
-  }
-  if (idx >= 0) {
-    uint64_t* p = w0 + (uint64_t)idx * a.entry_words;
+  // the first entry holding the key or empty (entries fill front to back)
+  uint32_t e = 0u;
+  while (e < a.n_entries && (uint32_t)(w0[(uint64_t)e * a.entry_words] >> 32) != hash2 &&
+         (uint32_t)(w0[(uint64_t)e * a.entry_words] >> 32) != 0u)
+    ++e;
+  if (e < a.n_entries) {
+    uint64_t* p = w0 + (uint64_t)e * a.entry_words;
     if (*p != 0ull) return 1;
     *p = neu;
     if (a.entry_words == 2) {
