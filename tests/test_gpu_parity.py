@@ -371,6 +371,41 @@ def test_cached_mid_frames_invariants():
     print("mid cached frame stats", st)
 
 
+def test_register_heavy_materials_match_oracle():
+    """400-node graphs with shared values: the compiler searches other
+    depth-first orders for them and lets a result take the register its
+    operand frees.  Uncached outputs against the FP64 graph, then two cached
+    frames through the oracle's frame checker."""
+    rng = np.random.default_rng(5)
+    mats = [scenes.random_material(rng, 400, 8) for _ in range(12)]
+    tex = scenes.texture_pool(7, 8, 64)
+    frame_fn, n = scenes._object_screen(3, len(mats), 320, 160, 40, 2, name="heavy")
+    sc = scenes.Scene("heavy", mats, tex, 2, n, scenes.CacheConfig(1 << 14), 3, frame_fn)
+    ctx = G.setup(sc)
+    regs = [ctx.material_info(m).n_regs for m in range(len(mats))]
+    assert max(regs) > 24, regs                  # beyond the point where the search stops
+    h = sc.frame(0)
+    assert len(np.unique(h.material)) >= 6
+    out, _, _, _ = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED)
+    G.assert_outputs(out, render.shade_uncached(mats, tex, h), what="uncached")
+    n_cells = (1 << 14) // 8
+    cache = ctx.cache(n_cells, 8, 16)
+    log, vals = check.KeyLog(), {}
+    prev = None
+    for f in range(2):
+        h = sc.frame(f)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        bad = check.check_frame(mats, tex, h, f, state, value, out, n_cells, log, vals)
+        words = cache.words()[:, 0]
+        bad += check.table_structure(words, 8, prev)
+        bad += check.check_entries_come_from_keys(words, 8, log)
+        assert not bad, (f, bad[:5])
+        prev = words
+    assert st["cache_hits"] > 0
+    print("register-heavy materials: registers", sorted(regs), "frame-1 stats", st)
+
+
 # -------------------------------------------------- Algorithm 1 surface -------
 
 def test_raw_insert_same_key_contention():
