@@ -91,6 +91,12 @@ def test_large_networks_fit_the_register_file():
     for mi in range(len(mats)):
         assert ctx.cacheables(mi) == graph.cacheable_outputs(mats[mi])
         assert ctx.material_info(mi).n_regs <= 64
+    # the order search (materials above 24 registers) is deterministic: a second
+    # compile in a new context gives the same register counts
+    regs = [ctx.material_info(mi).n_regs for mi in range(len(mats))]
+    assert max(regs) > 24
+    ctx2 = _compile(mats)
+    assert [ctx2.material_info(mi).n_regs for mi in range(len(mats))] == regs
 
 
 def test_constant_folding_and_min_subgraph_option():
