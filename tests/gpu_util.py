@@ -73,6 +73,26 @@ def small_mid_scene(seed=0, frames=2, **kw):
     return scenes.mid_scene(seed=seed, width=480, height=240, frames=frames, **kw)
 
 
+def crossed_chains(n_tex):
+    """n_tex textures read by a forward MIX chain and again by a reverse one:
+    whichever texture any order computes last, every texture is still awaited
+    by one of the chains then, so at least 3 n_tex registers are live
+    (3 n_tex + 6 as compiled).  Textures 0-3 of the scene."""
+    N, L, Cn = scenes.Node, scenes.Input.link, scenes.Input.const
+    nodes = [N("UV_INPUT")] + [N("IMAGE_TEXTURE", [L(0)], texture=t % 4) for t in range(n_tex)]
+    fwd = 1
+    for t in range(2, n_tex + 1):
+        nodes.append(N("MIX", [Cn(0.5), L(fwd), L(t)]))
+        fwd = len(nodes) - 1
+    rev = n_tex
+    for t in range(n_tex - 1, 0, -1):
+        nodes.append(N("MIX", [Cn(0.25), L(rev), L(t)]))
+        rev = len(nodes) - 1
+    nodes.append(N("MIX", [Cn(0.5), L(fwd), L(rev)]))
+    nodes.append(N("BSDF_OUTPUT", [L(len(nodes) - 1), Cn(0.5), Cn()]))
+    return scenes.Material(nodes)
+
+
 def found_values_parity(materials, hits, state, value, ref_found_value, min_subgraph_nodes=2,
                         cacheables=None):
     """Values the device found in the table against the oracle's found values:

@@ -11,6 +11,7 @@ import pytest
 from oracle import graph
 from paper_2305_07238_amd import binding as B
 from paper_2305_07238_amd import scenes
+from tests import gpu_util as G
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -138,32 +139,13 @@ def test_a_result_takes_the_register_its_operand_frees():
     assert info.n_instr == 9 and info.n_regs == 2
 
 
-def _crossed_chains(n_tex):
-    """n_tex textures read by a forward MIX chain and again by a reverse one:
-    whichever texture any order computes last, every texture is still awaited
-    by one of the chains then, so at least 3 n_tex registers are live."""
-    N, L, Cn = scenes.Node, scenes.Input.link, scenes.Input.const
-    nodes = [N("UV_INPUT")] + [N("IMAGE_TEXTURE", [L(0)], texture=t % 4) for t in range(n_tex)]
-    fwd = 1
-    for t in range(2, n_tex + 1):
-        nodes.append(N("MIX", [Cn(0.5), L(fwd), L(t)]))
-        fwd = len(nodes) - 1
-    rev = n_tex
-    for t in range(n_tex - 1, 0, -1):
-        nodes.append(N("MIX", [Cn(0.25), L(rev), L(t)]))
-        rev = len(nodes) - 1
-    nodes.append(N("MIX", [Cn(0.5), L(fwd), L(rev)]))
-    nodes.append(N("BSDF_OUTPUT", [L(len(nodes) - 1), Cn(0.5), Cn()]))
-    return scenes.Material(nodes)
-
-
 def test_register_need_beyond_the_limit_is_refused():
-    ctx = _compile([_crossed_chains(16)])
+    ctx = _compile([G.crossed_chains(16)])
     assert 48 <= ctx.material_info(0).n_regs <= 64
     ctx.close()
     ctx = B.Context(-1)
     with pytest.raises(B.PmcError) as e:
-        ctx.compile([_crossed_chains(24)])
+        ctx.compile([G.crossed_chains(24)])
     assert e.value.code == B.PMC_ERR_UNSUPPORTED
     assert "registers" in str(e.value)
     ctx.compile([scenes.tiny_material()])      # the context stays usable

@@ -406,6 +406,37 @@ def test_register_heavy_materials_match_oracle():
     print("register-heavy materials: registers", sorted(regs), "frame-1 stats", st)
 
 
+def test_material_at_the_register_limit_matches_oracle():
+    """A material needing 63 of the 64 registers (LDS register file of 16 KB
+    per wave) beside the tiny material: uncached and two cached frames against
+    the FP64 graph."""
+    mats = [G.crossed_chains(19), scenes.tiny_material()]
+    tex = scenes.texture_pool(11, 4, 64)
+    frame_fn, n = scenes._object_screen(4, len(mats), 320, 160, 40, 2, name="limit")
+    sc = scenes.Scene("limit", mats, tex, 2, n, scenes.CacheConfig(1 << 14), 4, frame_fn)
+    ctx = G.setup(sc)
+    assert ctx.material_info(0).n_regs == 63
+    h = sc.frame(0)
+    assert np.count_nonzero(h.material == 0) > 1000
+    out, _, _, _ = G.shade(ctx, h, None, mode=B.PMC_MODE_UNCACHED)
+    G.assert_outputs(out, render.shade_uncached(mats, tex, h), what="uncached")
+    n_cells = (1 << 14) // 8
+    cache = ctx.cache(n_cells, 8, 16)
+    log, vals = check.KeyLog(), {}
+    prev = None
+    for f in range(2):
+        h = sc.frame(f)
+        out, state, value, st = G.shade(ctx, h, cache, mode=B.PMC_MODE_CACHED, frame=f,
+                                        flags=B.PMC_FLAG_SORT, debug=True)
+        bad = check.check_frame(mats, tex, h, f, state, value, out, n_cells, log, vals)
+        words = cache.words()[:, 0]
+        bad += check.table_structure(words, 8, prev)
+        bad += check.check_entries_come_from_keys(words, 8, log)
+        assert not bad, (f, bad[:5])
+        prev = words
+    assert st["cache_hits"] > 0
+
+
 # -------------------------------------------------- Algorithm 1 surface -------
 
 def test_raw_insert_same_key_contention():
